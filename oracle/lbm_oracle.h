@@ -1,0 +1,60 @@
+/*
+ * lbm_oracle.h -- plain FP64 CPU reference of the D3Q19 TRT moving-particle
+ * lattice Boltzmann step (Bartuschat & Ruede, "A Scalable Multiphysics
+ * Algorithm for Massively Parallel Direct Numerical Simulations of
+ * Electrophoresis", arXiv:1708.08741, Sec. 3.1 "Lattice Boltzmann Method"
+ * and Sec. 3.2 "Momentum Exchange Approach").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker of the GPU library:
+ * only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no source with the GPU path.
+ *
+ * State layout: populations f[q * N + c] with c = x + nx * (y + ny * z).
+ * The stored state is post-stream / pre-collide ("ready"): after every step
+ * the particle map of the new time level is already applied (newly
+ * uncovered cells refilled), so macroscopic read-outs are consistent.
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_lattice orc_lattice;
+
+/* flag values returned by orc_get_map */
+enum { ORC_FLUID = 0, ORC_WALL = 1, ORC_OBST = 2, ORC_NEAR = 3 };
+
+orc_lattice *orc_create(int nx, int ny, int nz, const int periodic[3],
+                        double nu, double magic);
+void orc_destroy(orc_lattice *L);
+/* relaxation rates derived from nu and the TRT magic parameter */
+void orc_get_rates(const orc_lattice *L, double out[3]); /* tau, lambda_e, lambda_o */
+int orc_set_flags(orc_lattice *L, const uint8_t *flags);  /* 0 fluid, 1 wall */
+int orc_set_particles(orc_lattice *L, int n, const double *X, const double *R,
+                      const double *U, const double *W, int moving);
+int orc_set_force(orc_lattice *L, const double *fb);      /* 3*N SoA */
+void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]);
+void orc_set_pdfs(orc_lattice *L, const double *f);       /* 19*N */
+void orc_get_pdfs(const orc_lattice *L, double *f);
+void orc_step(orc_lattice *L, int nsteps);
+long orc_get_step(const orc_lattice *L);
+void orc_get_macro(const orc_lattice *L, double *rho, double *u);
+void orc_get_ft(const orc_lattice *L, double *F, double *M);
+void orc_get_map(const orc_lattice *L, uint8_t *flags, int32_t *owner);
+void orc_get_invariants(const orc_lattice *L, double out[4]);
+/* bookkeeping of the last step's re-mapping:
+ * out[0] = number of uncovered cells, out[1..3] = sum rho0*u_s over them,
+ * out[4] = sum rho over newly covered cells, out[5..7] = sum j over them,
+ * out[8..10] = sum of f_b over the fluid cells of the streamed step */
+void orc_get_bookkeeping(const orc_lattice *L, double out[11]);
+/* particle centres of the current time level (wrapped) */
+void orc_get_positions(const orc_lattice *L, double *X);
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
