@@ -1,0 +1,216 @@
+"""Benchmark of the moving-particle D3Q19 TRT sweep on one MI355X.
+
+A step is one full time step of the method on the GPU: the fused
+collide/stream sweep with the charge body force, wall and velocity
+bounce-back and the per-particle momentum exchange, followed by the
+prescribed kinematics, re-mapping and refill for the next time level.
+
+Workload: 512^3 fully periodic box, 4096 moving spheres of radius 4
+(random sequential addition, surface gap >= 3, velocities uniform in
+[-5e-4, 5e-4]), body force rho_e * E with a Gaussian-shell charge density
+(Debye length 2, amplitude 1e-5) and E = (1e-3, 0, 0), nu = 1/6,
+Lambda = 3/16, populations stored as FP32 deviations from the rest weights.
+
+Prints ONE JSON line.  `value` is MLUPS (all cells); `roofline` prices the
+fused sweep kernel against the 8 TB/s HBM peak with 152 algorithmic bytes
+per cell update (19 FP32 loads + 19 FP32 stores); `cpu_baseline` times the
+FP64 CPU oracle on a bounded sample of the same workload shape.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline, 512^3 FP32/FP16 vs FP64; serve p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {"fp64": 304, "fp32dev": 152, "fp16dev": 76}
+DTYPE = {"fp64": "f64", "fp32dev": "f32", "fp16dev": "f32"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_512.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "k_stream.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current sweep source; else None."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_hash():
+        return None
+    e = d.get("per_precision", {}).get(precision)
+    if not e:
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def run_gpu(wl, precision, steps, warmup):
+    import torch
+
+    from paper_1708_08741_amd import lbmep as lb
+
+    stream = torch.cuda.current_stream()
+    L = lb.from_workload(wl, precision=precision, stream=stream.cuda_stream)
+    fl, _ = L.map()
+    nfluid = int(((fl == lb.FLUID) | (fl == lb.NEAR)).sum())
+    del fl
+    L.step(warmup)
+    L.sync()
+    L.get_timing()  # reset
+    L.set_timing(True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kern_ms, launches = L.get_timing()
+    L.set_timing(False)
+    inv = L.invariants()
+    L.close()
+    torch.cuda.empty_cache()
+    return dict(total_ms=total_ms, kernel_ms=kern_ms / max(launches, 1), launches=launches,
+                nfluid=nfluid, invariants=inv.tolist())
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle on a bounded sample: the 128^3 sub-run of the same
+    workload shape (64 moving R=4 spheres, same force construction)."""
+    from oracle import oracle as O
+    from paper_1708_08741_amd import workloads as W
+
+    wl = W.suspension_subrun(precision="fp64")
+    o = O.from_workload(wl)
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(2)
+    per = (time.perf_counter() - t0) / 2
+    n = max(2, int(target_s / per))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    cells = wl.ncells
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"128^3 periodic sub-run, 64 moving R=4 spheres, charge force, FP64, "
+                      f"{n} steps ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="box edge (cells)")
+    ap.add_argument("--precision", default="fp32dev", choices=list(BYTES_PER_CELL))
+    ap.add_argument("--variants", default="fp64,fp16dev",
+                    help="other storage precisions timed on the same workload ('' = none)")
+    ap.add_argument("--variant-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this "
+              "build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_1708_08741_amd import workloads as W
+
+    n = args.n
+    count = 4096 * (n // 512) ** 3 if n >= 512 else max(1, int(4096 * (n / 512) ** 3))
+    log(f"[bench] generating the {n}^3 workload ({count} spheres)")
+    t0 = time.perf_counter()
+    wl = W.periodic_suspension(n=n, count=count, R=4.0, seed=3, steps=args.steps,
+                               precision=args.precision)
+    log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    res = run_gpu(wl, args.precision, args.steps, args.warmup)
+    cells = wl.ncells
+    t_s = res["total_ms"] / 1e3
+    mlups = cells * args.steps / t_s / 1e6
+    mflups = res["nfluid"] * args.steps / t_s / 1e6
+    k_s = res["kernel_ms"] / 1e3
+    bpc = BYTES_PER_CELL[args.precision]
+    achieved = bpc * cells / k_s / 1e9
+    log(f"[bench] {args.precision}: {mlups:.0f} MLUPS, sweep kernel {res['kernel_ms']:.3f} ms "
+        f"= {achieved:.0f} GB/s")
+
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s]:
+        if v == args.precision:
+            continue
+        r = run_gpu(wl, v, args.variant_steps, 5)
+        tv = r["total_ms"] / 1e3
+        kv = r["kernel_ms"] / 1e3
+        variants[v] = {
+            "MLUPS": round(cells * args.variant_steps / tv / 1e6, 1),
+            "steps": args.variant_steps,
+            "sweep_kernel_ms": round(r["kernel_ms"], 4),
+            "sweep_GBps": round(BYTES_PER_CELL[v] * cells / kv / 1e9, 1),
+            "roofline_frac": round(BYTES_PER_CELL[v] * cells / kv / 1e9 / HBM_PEAK_GBS, 4),
+        }
+        log(f"[bench] {v}: {variants[v]}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        cpu = cpu_baseline()
+
+    traffic = traffic_for(args.precision)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["total_ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 periodic box, {count} moving spheres R=4, Gaussian-shell "
+                        f"charge force E=(1e-3,0,0), D3Q19 TRT nu=1/6 Lambda=3/16, "
+                        f"{args.precision} storage",
+            "cells": cells, "fluid_cells": res["nfluid"], "particles": count,
+            "precision": args.precision, "MFLUPS": round(mflups, 1),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_stream_collide", "kernel_ms": round(res["kernel_ms"], 4),
+            "bytes_per_cell": bpc,
+        },
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * lbmep.h -- C ABI of the MI355X (gfx950) D3Q19 TRT lattice Boltzmann sweep
+ * with an electrostatic body force and moving rigid spheres.
+ *
+ * Method: Bartuschat & Ruede, "A Scalable Multiphysics Algorithm for
+ * Massively Parallel Direct Numerical Simulations of Electrophoresis",
+ * arXiv:1708.08741.  Sec. 3.1 defines the lattice Boltzmann step (D3Q19,
+ * incompressible equilibrium Eq. fequ_Incompr_SRT, TRT operator Eq. TRTOp
+ * with lambda_e = -1/tau and the odd rate that fixes walls half-way, collide
+ * Eq. LBMcollideStep and stream Eq. LBMstreamStep with the Luo force term
+ * Eq. LBE_forcetermLuo and the velocity of Eq. modified_velocity).  Sec. 3.2
+ * defines the particle coupling (obstacle cells = cells whose centre lies in
+ * a particle, velocity bounce-back Eq. LBMMovWall, momentum-exchange force
+ * Eq. LBMhydrodynForce and torque, equilibrium refill of uncovered cells).
+ * Alg. 1's LBM block ("set velocity BCs of particles -> fused stream-collide
+ * -> hydrodynamic force") is one call of lbmep_step.
+ *
+ * Units: lattice units, dx = dt = rho0 = 1, c_s^2 = 1/3.
+ * Grid: nx*ny*nz cells, cell (x,y,z) has linear index x + nx*(y + ny*z)
+ * (x fastest) and centre (x+1/2, y+1/2, z+1/2).  Per-cell vector fields are
+ * SoA: component a of cell c at [a*N + c], N = nx*ny*nz.
+ *
+ * Conventions for every function:
+ *   - returns LBMEP_OK (0) or a negative LBMEP_E* code; lbmep_last_error()
+ *     gives a thread-local message for the last failure on this thread;
+ *   - on an argument error (LBMEP_EINVAL) the lattice is left unchanged;
+ *   - host arrays passed in are copied before the call returns; the library
+ *     never keeps or frees caller memory;
+ *   - on_device = 1 means the pointer is device memory on the lattice's
+ *     device (e.g. a torch tensor's data_ptr); it must stay valid until the
+ *     work enqueued on the lattice's stream has completed;
+ *   - all device work is enqueued on the lattice's stream; lbmep_step is
+ *     asynchronous, the lbmep_get_* functions synchronise the stream.
+ */
+#ifndef LBMEP_H
+#define LBMEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBMEP_OK = 0,
+    LBMEP_EINVAL = -1,    /* bad argument (sizes, NaN, null pointer, ...) */
+    LBMEP_ENOMEM = -2,    /* device or host allocation failed */
+    LBMEP_EDEVICE = -3,   /* a HIP call failed */
+    LBMEP_ESTATE = -4,    /* call not allowed in the current state */
+    LBMEP_ENONFINITE = -5,/* a global reduction found NaN/Inf populations */
+    LBMEP_EBUSY = -6      /* serving: no capacity for the request now */
+};
+
+/* storage precision of the populations (compute precision in brackets) */
+enum {
+    LBMEP_FP64 = 0,    /* f_q stored as FP64 (FP64 collide)                  */
+    LBMEP_FP32DEV = 1, /* f_q - w_q stored as FP32 (FP32 collide)            */
+    LBMEP_FP16DEV = 2  /* (f_q - w_q) * 2^24 stored as FP16 (FP32 collide)   */
+};
+
+/* cell flags: FLUID/WALL are user input; OBST/NEAR are produced by mapping */
+enum { LBMEP_FLUID = 0, LBMEP_WALL = 1, LBMEP_OBST = 2, LBMEP_NEAR = 3 };
+
+/* element types of force / charge arrays */
+enum { LBMEP_DTYPE_F64 = 0, LBMEP_DTYPE_F32 = 1 };
+
+typedef struct lbmep_lattice lbmep_lattice; /* opaque; owns its device memory */
+
+typedef struct {
+    int32_t nx, ny, nz;      /* grid size, each >= 1 */
+    int32_t periodic[3];     /* 1 = periodic axis; 0 = implicit resting
+                                no-slip wall half a cell beyond the last cell */
+    double nu;               /* kinematic viscosity, > 0 (Eq. kinVisc:
+                                tau = 3 nu + 1/2, lambda_e = -1/tau) */
+    double magic;            /* TRT parameter Lambda > 0; the paper's lambda_o
+                                (walls half-way for every tau) is 3/16 */
+    int32_t precision;       /* LBMEP_FP64 / LBMEP_FP32DEV / LBMEP_FP16DEV */
+    int32_t move_particles;  /* 1: X_p(n) = X_p(0) + n U_p, re-mapped every
+                                step; 0: fixed map, (U, W) only set the
+                                surface velocity */
+    int32_t device;          /* HIP device ordinal */
+    int32_t reserved;        /* must be 0 */
+    void *stream;            /* hipStream_t; NULL = the default stream */
+} lbmep_config;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *lbmep_last_error(void);
+
+/* Create a lattice.  Allocates two population grids of the storage
+ * precision, the flag field and the mapping fields on cfg->device.  The
+ * initial state is the rest equilibrium f_q = w_q, all cells FLUID, no
+ * particles, zero force.  Errors: EINVAL (non-positive sizes, nu <= 0 or not
+ * finite, magic <= 0, unknown precision, reserved != 0), ENOMEM, EDEVICE. */
+int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out);
+
+/* Release all device memory of L (synchronises its stream).  NULL is OK. */
+int lbmep_destroy(lbmep_lattice *L);
+
+/* Set the user flags (N bytes, LBMEP_FLUID or LBMEP_WALL per cell) and
+ * re-map the particles on the new walls (walls are never obstacle cells).
+ * Populations are not touched.  Errors: EINVAL (null, value not 0/1). */
+int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device);
+
+/* Set the particle table (host arrays, n >= 0): centres X[3n], radii R[n]
+ * (> 0), velocities U[3n], angular velocities W[3n] (NULL = 0).  Sets the
+ * kinematic time level to 0, maps the spheres (Sec. 3.2: a cell is an
+ * obstacle cell iff its centre is inside the closed ball, minimum image on
+ * periodic axes, lowest index owns shared cells) and classifies NEAR cells.
+ * Populations are not touched.  Errors: EINVAL (negative n, non-finite
+ * values, R <= 0). */
+int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const double *R,
+                        const double *U, const double *W);
+
+/* Set a dense body force f_b (3*N SoA, dtype LBMEP_DTYPE_F64/F32) used at
+ * fluid cells (Eq. LBE_forcetermLuo, Eq. modified_velocity).  It is kept in
+ * the compute precision (FP64 for LBMEP_FP64, FP32 otherwise).  Replaces any
+ * charge force.  Errors: EINVAL (null, bad dtype, non-finite values). */
+int lbmep_set_force(lbmep_lattice *L, const void *fb, int dtype, int on_device);
+
+/* Set the electric body force f_b = rho_e * E (Sec. 2: force on the ions of
+ * the double layer) from a per-cell charge density rho_e (N values of dtype)
+ * and a uniform field E[3].  Stored compactly (one scalar per cell) and
+ * multiplied in the sweep.  Replaces any dense force.  Errors as above. */
+int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const double E[3],
+                           int on_device);
+
+/* Set every population to the incompressible equilibrium f^eq(rho, u)
+ * (Eq. fequ_Incompr_SRT).  Errors: EINVAL (non-finite). */
+int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]);
+
+/* Overwrite / read the populations as absolute FP64 values f[q*N + c] in
+ * the D3Q19 order q=0 rest, 1..6 = +x,-x,+y,-y,+z,-z, 7..18 = (+x+y),
+ * (-x-y), (+x-y), (-x+y), (+x+z), (-x-z), (+x-z), (-x+z), (+y+z), (-y-z),
+ * (+y-z), (-y+z).  Reduced-precision lattices convert to / from their
+ * storage (rounding).  The state is post-stream, pre-collide. */
+int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device);
+int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device);
+
+/* Advance nsteps time steps (nsteps >= 0), asynchronously on the stream.
+ * One step: fused collide (Eq. LBMcollideStep + force) and push-stream
+ * (Eq. LBMstreamStep) over all fluid cells, bounce-back at walls and
+ * velocity bounce-back at obstacle cells (Eq. LBMMovWall) with the
+ * momentum exchange summed per particle in FP64 (Eq. LBMhydrodynForce); then,
+ * with moving particles, the kinematics and re-mapping for the next time
+ * level and the refill of uncovered cells with f^eq(rho0, u_s).  Errors:
+ * EINVAL (nsteps < 0), EDEVICE. */
+int lbmep_step(lbmep_lattice *L, int32_t nsteps);
+
+/* Wait for all work enqueued on the lattice's stream. */
+int lbmep_sync(lbmep_lattice *L);
+
+/* Macroscopic fields of the current state (Eq. MacroscopVel with the
+ * velocity of Eq. modified_velocity): rho[N] and u[3N] in FP64.  Obstacle
+ * cells report rho0 and their surface velocity, wall cells rho0 and 0. */
+int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device);
+
+/* Hydrodynamic force F[3n] and torque M[3n] (about the centre, M = sum
+ * r x g, r = x_s - x_C) of the last step, FP64, host arrays. */
+int lbmep_get_particle_ft(lbmep_lattice *L, double *F, double *M);
+
+/* Current map: flags[N] (LBMEP_FLUID/WALL/OBST/NEAR; NEAR = fluid cell with
+ * a wall, obstacle or out-of-domain neighbour) and owner[N] (particle index
+ * or -1), host arrays; either may be NULL. */
+int lbmep_get_map(lbmep_lattice *L, uint8_t *flags, int32_t *owner);
+
+/* FP64 sums over fluid cells of the current state: out[0] = sum rho,
+ * out[1..3] = sum_q c_q f_q.  Deterministic order.  Returns LBMEP_ENONFINITE
+ * (with out filled) if a sum is not finite. */
+int lbmep_get_invariants(lbmep_lattice *L, double out[4]);
+
+/* Number of completed steps (the kinematic time level). */
+int lbmep_get_time(lbmep_lattice *L, int64_t *step);
+
+/* Per-kernel timing of the fused stream-collide launches: enable = 1 starts
+ * recording a HIP event pair around every launch (on the lattice's stream),
+ * 0 stops.  lbmep_get_timing synchronises, returns the summed duration in ms
+ * and the launch count since the last call, and resets them. */
+int lbmep_set_timing(lbmep_lattice *L, int enable);
+int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches);
+
+/* Checkpoint: populations (storage format), flags, particle table, time
+ * level and force to a file; load restores them into a lattice created with
+ * the same configuration.  Continuing from a load is bitwise identical to
+ * an uninterrupted run.  Errors: EINVAL (null path, mismatching file),
+ * EDEVICE, ENOMEM. */
+int lbmep_save_state(lbmep_lattice *L, const char *path);
+int lbmep_load_state(lbmep_lattice *L, const char *path);
+
+/* Device bytes held by a lattice of this configuration with n particles
+ * (used for admission by footprint). */
+int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charge, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

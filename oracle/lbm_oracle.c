@@ -143,6 +143,25 @@ static void lever_arm(const orc_lattice *L, int x, int y, int z, const double X[
     r[2] = min_image(((double)z + 0.5) - X[2], L->nz, L->per[2]);
 }
 
+/* centre of cell (x,y,z) moved by whole periods so that it is the image
+ * nearest to X: image_centre - X equals the lever arm of lever_arm(), and the
+ * values are exact half-integers */
+static double image_coord(int i, double Xa, int len, int periodic) {
+    double c = (double)i + 0.5;
+    if (periodic) {
+        double d = c - Xa, h = 0.5 * (double)len;
+        if (d > h) c -= (double)len;
+        else if (d < -h) c += (double)len;
+    }
+    return c;
+}
+
+static void image_centre(const orc_lattice *L, int x, int y, int z, const double X[3], double xs[3]) {
+    xs[0] = image_coord(x, X[0], L->nx, L->per[0]);
+    xs[1] = image_coord(y, X[1], L->ny, L->per[1]);
+    xs[2] = image_coord(z, X[2], L->nz, L->per[2]);
+}
+
 /* surface velocity u_s = U + W x r of a rigid body */
 static void surface_velocity(const orc_lattice *L, int p, const double r[3], double us[3]) {
     const double *U = L->U + 3 * p, *W = L->W + 3 * p;
@@ -176,16 +195,18 @@ static void map_particles(orc_lattice *L, const double *Xpos, int32_t *owner) {
         double R = L->R[p];
         int lo[3], cnt[3];
         for (a = 0; a < 3; ++a) {
-            int l = (int)floor(X[a] - R) - 1;
-            int h = (int)floor(X[a] + R) + 1;
+            /* a generous box of cells around the ball, in FP64 so that huge
+             * radii cannot overflow int */
+            double l = floor(X[a] - R) - 1.0;
+            double h = floor(X[a] + R) + 1.0;
             if (L->per[a]) {
-                if (h - l + 1 >= len[a]) { l = 0; h = len[a] - 1; }
+                if (h - l + 1.0 >= (double)len[a]) { l = 0.0; h = (double)len[a] - 1.0; }
             } else {
-                if (l < 0) l = 0;
-                if (h > len[a] - 1) h = len[a] - 1;
+                if (l < 0.0) l = 0.0;
+                if (h > (double)len[a] - 1.0) h = (double)len[a] - 1.0;
             }
-            lo[a] = l;
-            cnt[a] = h - l + 1;
+            lo[a] = (int)l;
+            cnt[a] = h >= l ? (int)(h - l + 1.0) : 0;
         }
         if (cnt[0] <= 0 || cnt[1] <= 0 || cnt[2] <= 0) continue;
         {
@@ -401,12 +422,10 @@ static void kahan_add(double *sum, double *comp, double x) {
 static void one_step(orc_lattice *L) {
     const long N = L->N;
     const int nx = L->nx, ny = L->ny, nz = L->nz, np = L->np;
-    double *Fz = NULL, *Mz = NULL;
+    /* per z slab and particle: F_dev[3], M_dev[3], K[3], T[3] (see below) */
+    double *Sz = NULL;
     int z;
-    if (np > 0) {
-        Fz = (double *)calloc((size_t)nz * np * 3, sizeof(double));
-        Mz = (double *)calloc((size_t)nz * np * 3, sizeof(double));
-    }
+    if (np > 0) Sz = (double *)calloc((size_t)nz * np * 12, sizeof(double));
 
     /* 1. collide every fluid cell */
 #pragma omp parallel for schedule(static)
@@ -446,45 +465,61 @@ static void one_step(orc_lattice *L) {
                         int sx = wrap_coord(x + back[0], nx, L->per[0]);
                         int sy = wrap_coord(y + back[1], ny, L->per[1]);
                         int sz = wrap_coord(z + back[2], nz, L->per[2]);
-                        double r[3], us[3], cus, mw, g[3], fq;
+                        double r[3], xs[3], us[3], cus, mw, gd, g[3], fq, k;
+                        double *S = Sz + ((size_t)z * np + p) * 12;
                         lever_arm(L, sx, sy, sz, L->Xn + 3 * p, r);
+                        image_centre(L, sx, sy, sz, L->Xn + 3 * p, xs);
                         surface_velocity(L, p, r, us);
                         cus = (double)C[qb][0] * us[0] + (double)C[qb][1] * us[1] + (double)C[qb][2] * us[2];
                         mw = 2.0 * L->w[qb] * INV_CS2 * RHO0 * cus;
                         fq = L->fstar[(long)qb * N + c];
                         /* Eq. LBMMovWall: population q arrives back at x */
                         L->fnew[(long)q * N + c] = fq - mw;
-                        /* Eq. LBMhydrodynForce: [2 f* - 2 (w/cs^2) rho0 c.u_s] c */
-                        g[0] = (2.0 * fq - mw) * (double)C[qb][0];
-                        g[1] = (2.0 * fq - mw) * (double)C[qb][1];
-                        g[2] = (2.0 * fq - mw) * (double)C[qb][2];
-                        {
-                            double *Fp = Fz + ((size_t)z * np + p) * 3;
-                            double *Mp = Mz + ((size_t)z * np + p) * 3;
-                            Fp[0] += g[0]; Fp[1] += g[1]; Fp[2] += g[2];
-                            Mp[0] += r[1] * g[2] - r[2] * g[1];
-                            Mp[1] += r[2] * g[0] - r[0] * g[2];
-                            Mp[2] += r[0] * g[1] - r[1] * g[0];
-                        }
+                        /* Eq. LBMhydrodynForce: g = [2 f* - 2 (w/cs^2) rho0 c.u_s] c,
+                         * summed as [2 (f* - w) - 2 (w/cs^2) rho0 c.u_s] c plus the
+                         * rest-weight part 2 w c = (k/18) c, k = 2 (axis) or 1
+                         * (diagonal).  The rest-weight parts cancel over a closed
+                         * body (link cancellation), so they are summed exactly as
+                         * integers (K = sum k c, T = sum k x_s x c with x_s the
+                         * half-integer cell centre nearest the particle). */
+                        gd = 2.0 * (fq - L->w[qb]) - mw;
+                        g[0] = gd * (double)C[qb][0];
+                        g[1] = gd * (double)C[qb][1];
+                        g[2] = gd * (double)C[qb][2];
+                        k = qb <= 6 ? 2.0 : 1.0;
+                        S[0] += g[0]; S[1] += g[1]; S[2] += g[2];
+                        S[3] += r[1] * g[2] - r[2] * g[1];
+                        S[4] += r[2] * g[0] - r[0] * g[2];
+                        S[5] += r[0] * g[1] - r[1] * g[0];
+                        S[6] += k * (double)C[qb][0];
+                        S[7] += k * (double)C[qb][1];
+                        S[8] += k * (double)C[qb][2];
+                        S[9] += k * (xs[1] * (double)C[qb][2] - xs[2] * (double)C[qb][1]);
+                        S[10] += k * (xs[2] * (double)C[qb][0] - xs[0] * (double)C[qb][2]);
+                        S[11] += k * (xs[0] * (double)C[qb][1] - xs[1] * (double)C[qb][0]);
                     }
                 }
             }
     }
     {
         int p, a;
-        for (p = 0; p < np; ++p)
-            for (a = 0; a < 3; ++a) {
-                double sf = 0.0, sm = 0.0;
-                for (z = 0; z < nz; ++z) {
-                    sf += Fz[((size_t)z * np + p) * 3 + a];
-                    sm += Mz[((size_t)z * np + p) * 3 + a];
-                }
-                L->F[3 * p + a] = sf;
-                L->M[3 * p + a] = sm;
+        for (p = 0; p < np; ++p) {
+            double t[12];
+            const double *X = L->Xn + 3 * p;
+            for (a = 0; a < 12; ++a) {
+                t[a] = 0.0;
+                for (z = 0; z < nz; ++z) t[a] += Sz[((size_t)z * np + p) * 12 + a];
             }
+            /* F = F_dev + K/18, M = M_dev + (T - X x K)/18 */
+            L->F[3 * p + 0] = t[0] + t[6] / 18.0;
+            L->F[3 * p + 1] = t[1] + t[7] / 18.0;
+            L->F[3 * p + 2] = t[2] + t[8] / 18.0;
+            L->M[3 * p + 0] = t[3] + (t[9] - (X[1] * t[8] - X[2] * t[7])) / 18.0;
+            L->M[3 * p + 1] = t[4] + (t[10] - (X[2] * t[6] - X[0] * t[8])) / 18.0;
+            L->M[3 * p + 2] = t[5] + (t[11] - (X[0] * t[7] - X[1] * t[6])) / 18.0;
+        }
     }
-    free(Fz);
-    free(Mz);
+    free(Sz);
 
     /* bookkeeping: total body force on the fluid cells of this step */
     {

@@ -1,0 +1,313 @@
+// k_particles.hip -- prescribed kinematics, obstacle mapping, NEAR-cell
+// classification and refill of uncovered cells (arXiv:1708.08741, Sec. 3.2:
+// a cell is an obstacle cell of a particle iff its centre lies inside it;
+// uncovered cells get f^eq(rho0, u_s) of the previous time level).
+//
+// Every per-particle kernel runs one block per particle over the particle's
+// bounding box of cells.  The inside test uses the same FP64 operation
+// sequence as a plain CPU evaluation (no contraction), so maps are
+// bit-identical to it; shared cells go to the lowest particle index via an
+// atomic minimum.
+#include "lbmep_internal.h"
+
+namespace lbmep {
+namespace {
+
+constexpr int kBoxThreads = 256;
+
+__device__ __forceinline__ double min_image(double d, int len, int periodic) {
+    if (periodic) {
+        const double h = 0.5 * (double)len;
+        if (d > h)
+            d -= (double)len;
+        else if (d < -h)
+            d += (double)len;
+    }
+    return d;
+}
+
+// cell range [lo, lo+cnt) of a box on one axis, before wrapping
+struct Box {
+    int lo[3], cnt[3];
+};
+
+__device__ __forceinline__ void axis_range(double xmin, double xmax, int len, int periodic,
+                                           int &lo, int &cnt) {
+    // computed in FP64 so that huge radii cannot overflow the integer range
+    double l = floor(xmin) - 1.0;
+    double h = floor(xmax) + 1.0;
+    if (periodic) {
+        if (h - l + 1.0 >= (double)len) {
+            l = 0.0;
+            h = (double)len - 1.0;
+        }
+    } else {
+        if (l < 0.0) l = 0.0;
+        if (h > (double)len - 1.0) h = (double)len - 1.0;
+    }
+    lo = (int)l;
+    cnt = h >= l ? (int)(h - l + 1.0) : 0;
+}
+
+__device__ __forceinline__ int box_size(const Box &b) {
+    return (b.cnt[0] > 0 && b.cnt[1] > 0 && b.cnt[2] > 0) ? b.cnt[0] * b.cnt[1] * b.cnt[2] : 0;
+}
+
+// box around the ball of radius R at X (generous: every cell whose centre
+// can be inside is in it)
+__device__ __forceinline__ Box ball_box(const Grid &g, const double *X, double R) {
+    Box b;
+    const int len[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k) axis_range(X[k] - R, X[k] + R, len[k], g.per[k], b.lo[k], b.cnt[k]);
+    return b;
+}
+
+// the i-th cell of a box (wrapped on periodic axes); false if empty
+__device__ __forceinline__ void box_cell(const Grid &g, const Box &b, int i, int &x, int &y,
+                                         int &z) {
+    const int cx = b.cnt[0], cy = b.cnt[1];
+    x = b.lo[0] + i % cx;
+    y = b.lo[1] + (i / cx) % cy;
+    z = b.lo[2] + i / (cx * cy);
+    if (g.per[0]) x = ((x % g.nx) + g.nx) % g.nx;
+    if (g.per[1]) y = ((y % g.ny) + g.ny) % g.ny;
+    if (g.per[2]) z = ((z % g.nz) + g.nz) % g.nz;
+}
+
+__device__ __forceinline__ size_t cell_of(const Grid &g, int x, int y, int z) {
+    return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+}
+
+__global__ void k_positions(ParticleArgs pa, int64_t level, double *X) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pa.np) return;
+    const int len[3] = {pa.g.nx, pa.g.ny, pa.g.nz};
+    for (int k = 0; k < 3; ++k) {
+        double x = pa.X0[3 * p + k];
+        // prescribed kinematics X(n) = X(0) + n U, evaluated in this form
+        if (pa.moving) x = pa.X0[3 * p + k] + (double)level * pa.U[3 * p + k];
+        if (pa.g.per[k]) {
+            x = x - (double)len[k] * floor(x / (double)len[k]);
+            if (x >= (double)len[k]) x -= (double)len[k];
+        }
+        X[3 * p + k] = x;
+    }
+}
+
+__global__ void __launch_bounds__(kBoxThreads)
+    k_map_clear(ParticleArgs pa, const double *X, uint32_t *owner) {
+    const int p = blockIdx.x;
+    const Box b = ball_box(pa.g, X + 3 * p, pa.R[p]);
+    const int n = box_size(b);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int x, y, z;
+        box_cell(pa.g, b, i, x, y, z);
+        owner[cell_of(pa.g, x, y, z)] = kNone;
+    }
+}
+
+__global__ void __launch_bounds__(kBoxThreads)
+    k_map_set(ParticleArgs pa, const double *X, const uint8_t *flag, uint32_t *owner) {
+    const int p = blockIdx.x;
+    const double *Xp = X + 3 * p;
+    const double R = pa.R[p];
+    const Box b = ball_box(pa.g, Xp, R);
+    const int n = box_size(b);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int x, y, z;
+        box_cell(pa.g, b, i, x, y, z);
+        const size_t c = cell_of(pa.g, x, y, z);
+        if (flag[c] & kWall) continue;
+        const double r0 = min_image(((double)x + 0.5) - Xp[0], pa.g.nx, pa.g.per[0]);
+        const double r1 = min_image(((double)y + 0.5) - Xp[1], pa.g.ny, pa.g.per[1]);
+        const double r2 = min_image(((double)z + 0.5) - Xp[2], pa.g.nz, pa.g.per[2]);
+        const double d2 = (r0 * r0 + r1 * r1) + r2 * r2;
+        if (d2 <= R * R) atomicMin(&owner[c], (uint32_t)p);
+    }
+}
+
+// flag and blocked-direction mask of one cell from the wall bits and the map
+__device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z, uint8_t *flag,
+                                              uint32_t *nearmask, const uint32_t *owner) {
+    const size_t c = cell_of(g, x, y, z);
+    const uint8_t wall = flag[c] & kWall;
+    uint8_t f = wall;
+    uint32_t mask = 0;
+    if (!wall) {
+        if (owner && owner[c] != kNone) {
+            f = kObst;
+        } else {
+#pragma unroll
+            for (int q = 1; q < Q; ++q) {
+                int sx = x + kCx[q], sy = y + kCy[q], sz = z + kCz[q];
+                bool solid = false;
+                if (sx < 0 || sx >= g.nx) {
+                    if (g.per[0]) sx = sx < 0 ? sx + g.nx : sx - g.nx; else solid = true;
+                }
+                if (sy < 0 || sy >= g.ny) {
+                    if (g.per[1]) sy = sy < 0 ? sy + g.ny : sy - g.ny; else solid = true;
+                }
+                if (sz < 0 || sz >= g.nz) {
+                    if (g.per[2]) sz = sz < 0 ? sz + g.nz : sz - g.nz; else solid = true;
+                }
+                if (!solid) {
+                    const size_t s = cell_of(g, sx, sy, sz);
+                    solid = (flag[s] & kWall) || (owner && owner[s] != kNone);
+                }
+                if (solid) mask |= 1u << (q - 1);
+            }
+            if (mask) f = kNear;
+        }
+    }
+    flag[c] = f | wall;
+    nearmask[c] = mask;
+}
+
+__global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *nearmask, const uint32_t *owner) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.nx) return;
+    classify_cell(g, x, blockIdx.y, blockIdx.z, flag, nearmask, owner);
+}
+
+template <typename ST>
+__device__ __forceinline__ void store_eq(ST *f, size_t Ns, size_t c, double u0, double u1,
+                                         double u2);
+
+// f^eq(rho0 = 1, u) (Eq. fequ_Incompr_SRT), in the storage format
+template <typename ST>
+__device__ __forceinline__ void store_eq(ST *f, size_t Ns, size_t c, double u0, double u1,
+                                         double u2) {
+    const double uu = (u0 * u0 + u1 * u1) + u2 * u2;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
+        const double w = wq(q);
+        const double d = (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5;
+        if constexpr (sizeof(ST) == 8) {
+            f[(size_t)q * Ns + c] = w * (1.0 + 1.0 * d);
+        } else if constexpr (sizeof(ST) == 4) {
+            f[(size_t)q * Ns + c] = (float)(w * d);
+        } else {
+            f[(size_t)q * Ns + c] = __float2half_rn((float)(w * d) * kHalfScale);
+        }
+    }
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(kBoxThreads)
+    k_classify_refill(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
+                      uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old,
+                      ST *f) {
+    const int p = blockIdx.x;
+    const Grid &g = pa.g;
+    const double R = pa.R[p];
+    Box b;
+    {
+        const int len[3] = {g.nx, g.ny, g.nz};
+        for (int k = 0; k < 3; ++k) {
+            const double a0 = Xold[3 * p + k], a1 = Xnew[3 * p + k];
+            double mn = a0 < a1 ? a0 : a1, mx = a0 < a1 ? a1 : a0;
+            // a particle that wrapped around a periodic axis: cover both ends
+            if (g.per[k] && mx - mn > 0.5 * (double)len[k]) {
+                mn = 0.0;
+                mx = (double)len[k];
+            }
+            // one more cell on each side for the NEAR ring
+            axis_range(mn - R - 1.0, mx + R + 1.0, len[k], g.per[k], b.lo[k], b.cnt[k]);
+        }
+    }
+    const int n = box_size(b);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int x, y, z;
+        box_cell(g, b, i, x, y, z);
+        const size_t c = cell_of(g, x, y, z);
+        classify_cell(g, x, y, z, flag, nearmask, owner_new);
+        const uint32_t po = owner_old[c];
+        if (!(flag[c] & kWall) && owner_new[c] == kNone && po != kNone) {
+            // uncovered: equilibrium with the surface velocity of the previous
+            // owner at its previous position
+            const double *Xp = Xold + 3 * (size_t)po;
+            const double *U = pa.U + 3 * (size_t)po;
+            const double *W = pa.W + 3 * (size_t)po;
+            const double r0 = min_image(((double)x + 0.5) - Xp[0], g.nx, g.per[0]);
+            const double r1 = min_image(((double)y + 0.5) - Xp[1], g.ny, g.per[1]);
+            const double r2 = min_image(((double)z + 0.5) - Xp[2], g.nz, g.per[2]);
+            const double us0 = U[0] + (W[1] * r2 - W[2] * r1);
+            const double us1 = U[1] + (W[2] * r0 - W[0] * r2);
+            const double us2 = U[2] + (W[0] * r1 - W[1] * r0);
+            store_eq<ST>(f, g.Ns, c, us0, us1, us2);
+        }
+    }
+}
+
+// F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
+// accumulators F_dev[3], M_dev[3], K[3], T[3] of the sweep
+__global__ void k_finalize_ft(int np, const double *acc, const double *X, double *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const double *t = acc + 12 * (size_t)p;
+    const double *Xp = X + 3 * (size_t)p;
+    out[6 * (size_t)p + 0] = t[0] + t[6] / 18.0;
+    out[6 * (size_t)p + 1] = t[1] + t[7] / 18.0;
+    out[6 * (size_t)p + 2] = t[2] + t[8] / 18.0;
+    out[6 * (size_t)p + 3] = t[3] + (t[9] - (Xp[1] * t[8] - Xp[2] * t[7])) / 18.0;
+    out[6 * (size_t)p + 4] = t[4] + (t[10] - (Xp[2] * t[6] - Xp[0] * t[8])) / 18.0;
+    out[6 * (size_t)p + 5] = t[5] + (t[11] - (Xp[0] * t[7] - Xp[1] * t[6])) / 18.0;
+}
+
+}  // namespace
+
+hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double *out,
+                              hipStream_t s) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_ft, dim3((np + 127) / 128), dim3(128), 0, s, np, acc, X, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_positions(const ParticleArgs &pa, int64_t level, double *X, hipStream_t s) {
+    if (pa.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_positions, dim3((pa.np + 127) / 128), dim3(128), 0, s, pa, level, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_clear(const ParticleArgs &pa, const double *X, uint32_t *owner,
+                            hipStream_t s) {
+    if (pa.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_clear, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, X, owner);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_set(const ParticleArgs &pa, const double *X, const uint8_t *flag,
+                          uint32_t *owner, hipStream_t s) {
+    if (pa.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_set, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, X, flag, owner);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
+                               const uint32_t *owner, hipStream_t s) {
+    const int bx = 64;
+    hipLaunchKernelGGL(k_classify_all, dim3((g.nx + bx - 1) / bx, g.ny, g.nz), dim3(bx), 0, s, g,
+                       flag, nearmask, owner);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify_refill(int precision, const ParticleArgs &pa, const double *Xold,
+                                  const double *Xnew, uint8_t *flag, uint32_t *nearmask,
+                                  const uint32_t *owner_new, const uint32_t *owner_old, void *f,
+                                  hipStream_t s) {
+    if (pa.np == 0) return hipSuccess;
+    const dim3 grid(pa.np), block(kBoxThreads);
+    if (precision == LBMEP_FP64)
+        hipLaunchKernelGGL(k_classify_refill<double>, grid, block, 0, s, pa, Xold, Xnew, flag,
+                           nearmask, owner_new, owner_old, static_cast<double *>(f));
+    else if (precision == LBMEP_FP32DEV)
+        hipLaunchKernelGGL(k_classify_refill<float>, grid, block, 0, s, pa, Xold, Xnew, flag,
+                           nearmask, owner_new, owner_old, static_cast<float *>(f));
+    else
+        hipLaunchKernelGGL(k_classify_refill<__half>, grid, block, 0, s, pa, Xold, Xnew, flag,
+                           nearmask, owner_new, owner_old, static_cast<__half *>(f));
+    return hipGetLastError();
+}
+
+}  // namespace lbmep

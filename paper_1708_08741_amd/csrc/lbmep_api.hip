@@ -1,0 +1,780 @@
+// lbmep_api.hip -- host runtime behind the C ABI of include/lbmep.h: lattice
+// object, argument checks, device memory, the per-step launch sequence and
+// checkpointing.  Every step of the method runs in the device kernels of
+// k_stream.hip, k_particles.hip and k_fields.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbmep_internal.h"
+
+using namespace lbmep;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(LBMEP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t n, size_t m) { return (n + m - 1) / m * m; }
+
+size_t storage_bytes(int precision) {
+    return precision == LBMEP_FP64 ? 8 : (precision == LBMEP_FP32DEV ? 4 : 2);
+}
+
+size_t compute_bytes(int precision) { return precision == LBMEP_FP64 ? 8 : 4; }
+
+bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct lbmep_lattice {
+    lbmep_config cfg{};
+    Grid g{};
+    hipStream_t stream = nullptr;
+    int precision = 0;
+    double tau = 0, le = 0, lo = 0, ae = 0, ao = 0;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t *flag = nullptr;
+    uint32_t *nearmask = nullptr;
+    uint32_t *owner[2] = {nullptr, nullptr};
+    double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
+    int cur_owner = 0;
+    int ft_buf = 0;  // owner/position buffer of the last streamed time level
+    int np = 0;
+    size_t np_cap = 0;
+    double *X0 = nullptr, *R = nullptr, *U = nullptr, *W = nullptr, *FM = nullptr;
+    std::vector<double> hX0, hR, hU, hW;  // host copy of the particle table
+    int64_t level = 0;
+    int force_mode = kForceNone;
+    void *force = nullptr;
+    size_t force_bytes = 0;
+    double E[3] = {0, 0, 0};
+    double *red = nullptr;
+    int red_blocks = 0;
+    int block_x = 256;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+int set_device(lbmep_lattice *L) {
+    HIP_TRY(hipSetDevice(L->cfg.device));
+    return LBMEP_OK;
+}
+
+ParticleArgs particle_args(const lbmep_lattice *L) {
+    ParticleArgs pa;
+    pa.g = L->g;
+    pa.np = L->np;
+    pa.moving = L->cfg.move_particles;
+    pa.X0 = L->X0;
+    pa.R = L->R;
+    pa.U = L->U;
+    pa.W = L->W;
+    return pa;
+}
+
+// map the particles at `level` into both owner buffers and classify the grid
+int remap_all(lbmep_lattice *L) {
+    hipStream_t s = L->stream;
+    if (L->np > 0) {
+        const ParticleArgs pa = particle_args(L);
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(launch_fill_u32(L->owner[b], kNone, L->g.N, s));
+            HIP_TRY(launch_positions(pa, L->level, L->Xheld[b], s));
+            HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
+        }
+        L->cur_owner = 0;
+        L->ft_buf = 0;
+        HIP_TRY(launch_fill_f64(L->FM, 0.0, 18 * (size_t)L->np, s));
+    }
+    HIP_TRY(launch_classify_all(L->g, L->flag, L->nearmask, L->np > 0 ? L->owner[0] : nullptr, s));
+    return LBMEP_OK;
+}
+
+void free_particles(lbmep_lattice *L) {
+    hipFree(L->X0);
+    hipFree(L->R);
+    hipFree(L->U);
+    hipFree(L->W);
+    hipFree(L->FM);
+    hipFree(L->Xheld[0]);
+    hipFree(L->Xheld[1]);
+    L->X0 = L->R = L->U = L->W = L->FM = L->Xheld[0] = L->Xheld[1] = nullptr;
+    L->np_cap = 0;
+}
+
+size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mode) {
+    const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
+    const size_t Ns = round_up(N, 128);
+    size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
+    b += N + 4 * N;                                                    // flags + near masks
+    if (n_particles > 0) b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;
+    if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
+    if (force_mode == kForceCharge) b += Ns * compute_bytes(cfg->precision);
+    b += 4096 * 5 * 8 + 64;
+    return b;
+}
+
+int check_config(const lbmep_config *cfg) {
+    if (!cfg) return fail(LBMEP_EINVAL, "null config");
+    if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->nz <= 0)
+        return fail(LBMEP_EINVAL, "grid sizes must be positive");
+    if ((double)cfg->nx * cfg->ny * cfg->nz > 4.0e9)
+        return fail(LBMEP_EINVAL, "grid larger than 4e9 cells");
+    if (cfg->nx > (1 << 20) || cfg->ny > 65535 || cfg->nz > 65535)
+        return fail(LBMEP_EINVAL, "ny and nz must be <= 65535");
+    if (!(std::isfinite(cfg->nu) && cfg->nu > 0.0)) return fail(LBMEP_EINVAL, "nu must be > 0");
+    if (!(std::isfinite(cfg->magic) && cfg->magic > 0.0))
+        return fail(LBMEP_EINVAL, "magic parameter must be > 0");
+    if (cfg->precision < LBMEP_FP64 || cfg->precision > LBMEP_FP16DEV)
+        return fail(LBMEP_EINVAL, "unknown precision");
+    if (cfg->reserved != 0) return fail(LBMEP_EINVAL, "reserved must be 0");
+    return LBMEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbmep_last_error(void) { return g_err.c_str(); }
+
+int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charge, size_t *bytes) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!bytes || n_particles < 0) return fail(LBMEP_EINVAL, "bad footprint arguments");
+    *bytes = lattice_bytes(cfg, n_particles, with_charge ? kForceCharge : kForceNone);
+    return LBMEP_OK;
+}
+
+int lbmep_destroy(lbmep_lattice *L) {
+    if (!L) return LBMEP_OK;
+    hipSetDevice(L->cfg.device);
+    hipStreamSynchronize(L->stream);
+    hipFree(L->f[0]);
+    hipFree(L->f[1]);
+    hipFree(L->flag);
+    hipFree(L->nearmask);
+    hipFree(L->owner[0]);
+    hipFree(L->owner[1]);
+    hipFree(L->force);
+    hipFree(L->red);
+    free_particles(L);
+    for (hipEvent_t e : L->ev) hipEventDestroy(e);
+    delete L;
+    return LBMEP_OK;
+}
+
+int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!out) return fail(LBMEP_EINVAL, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(LBMEP_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(cfg->device));
+    lbmep_lattice *L = new lbmep_lattice();
+    L->cfg = *cfg;
+    L->stream = (hipStream_t)cfg->stream;
+    L->precision = cfg->precision;
+    Grid &g = L->g;
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    for (int k = 0; k < 3; ++k) g.per[k] = cfg->periodic[k] ? 1 : 0;
+    g.N = (size_t)g.nx * g.ny * g.nz;
+    g.Ns = round_up(g.N, 128);
+    // Eq. kinVisc: nu = (tau - 1/2) c_s^2; lambda_e = -1/tau (Sec. 3.1); the
+    // odd rate from Lambda = (1/s_e - 1/2)(1/s_o - 1/2), s = -lambda
+    L->tau = cfg->nu * 3.0 + 0.5;
+    L->le = -1.0 / L->tau;
+    L->lo = -1.0 / (0.5 + cfg->magic / (L->tau - 0.5));
+    L->ae = 1.0 + 0.5 * L->le;
+    L->ao = 1.0 + 0.5 * L->lo;
+    if (!(L->lo > -2.0 && L->lo < 0.0)) {
+        delete L;
+        return fail(LBMEP_EINVAL, "odd relaxation rate outside ]-2,0[");
+    }
+    // one row per block when it fits (512 threads); rows of other sizes are
+    // covered by whole wavefronts
+    L->block_x = g.nx >= 512 ? 512 : (int)round_up((size_t)g.nx, 64);
+    const size_t es = storage_bytes(L->precision);
+    bool ok = true;
+    ok = ok && hipMalloc(&L->f[0], Q * g.Ns * es) == hipSuccess;
+    ok = ok && hipMalloc(&L->f[1], Q * g.Ns * es) == hipSuccess;
+    ok = ok && hipMalloc(&L->flag, g.N) == hipSuccess;
+    ok = ok && hipMalloc(&L->nearmask, 4 * g.N) == hipSuccess;
+    L->red_blocks = invariants_blocks(g);
+    ok = ok && hipMalloc(&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        lbmep_destroy(L);
+        return fail(LBMEP_ENOMEM, "device allocation failed");
+    }
+    hipStream_t s = L->stream;
+    hipError_t e = hipMemsetAsync(L->flag, 0, g.N, s);
+    if (e == hipSuccess) e = launch_classify_all(g, L->flag, L->nearmask, nullptr, s);
+    const double u0[3] = {0, 0, 0};
+    if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[0], 1.0, u0, s);
+    if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[1], 1.0, u0, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        lbmep_destroy(L);
+        return fail(LBMEP_EDEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    }
+    *out = L;
+    return LBMEP_OK;
+}
+
+int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device) {
+    if (!L || !flags) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    if (!on_device) {
+        for (size_t i = 0; i < N; ++i)
+            if (flags[i] != LBMEP_FLUID && flags[i] != LBMEP_WALL)
+                return fail(LBMEP_EINVAL, "flag values must be LBMEP_FLUID or LBMEP_WALL");
+    }
+    uint8_t *tmp = nullptr;
+    const uint8_t *src = flags;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, N));
+        hipError_t e = hipMemcpyAsync(tmp, flags, N, hipMemcpyHostToDevice, L->stream);
+        if (e != hipSuccess) {
+            hipFree(tmp);
+            return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+        }
+        src = tmp;
+    }
+    hipError_t e = launch_import_flags(L->g, src, L->flag, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    return remap_all(L);
+}
+
+int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const double *R,
+                        const double *U, const double *W) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (n < 0) return fail(LBMEP_EINVAL, "negative particle count");
+    if (n > 0 && (!X || !R || !U)) return fail(LBMEP_EINVAL, "null particle array");
+    if (n > 0) {
+        if (!finite_all(X, 3 * (size_t)n) || !finite_all(R, n) || !finite_all(U, 3 * (size_t)n) ||
+            (W && !finite_all(W, 3 * (size_t)n)))
+            return fail(LBMEP_EINVAL, "non-finite particle data");
+        for (int i = 0; i < n; ++i)
+            if (!(R[i] > 0.0)) return fail(LBMEP_EINVAL, "radii must be > 0");
+    }
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    if (n > 0 && !L->owner[0]) {
+        if (hipMalloc(&L->owner[0], 4 * L->g.N) != hipSuccess ||
+            hipMalloc(&L->owner[1], 4 * L->g.N) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "owner field allocation failed");
+    }
+    if ((size_t)n > L->np_cap) {
+        free_particles(L);
+        const size_t b = 3 * (size_t)n * sizeof(double);
+        bool ok = hipMalloc(&L->X0, b) == hipSuccess && hipMalloc(&L->U, b) == hipSuccess &&
+                  hipMalloc(&L->W, b) == hipSuccess && hipMalloc(&L->R, b / 3) == hipSuccess &&
+                  hipMalloc(&L->FM, 6 * b) == hipSuccess && hipMalloc(&L->Xheld[0], b) == hipSuccess &&
+                  hipMalloc(&L->Xheld[1], b) == hipSuccess;
+        if (!ok) {
+            free_particles(L);
+            L->np = 0;
+            return fail(LBMEP_ENOMEM, "particle table allocation failed");
+        }
+        L->np_cap = n;
+    }
+    L->np = n;
+    L->hX0.assign(X, X + 3 * (size_t)n);
+    L->hR.assign(R, R + n);
+    L->hU.assign(U, U + 3 * (size_t)n);
+    if (W)
+        L->hW.assign(W, W + 3 * (size_t)n);
+    else
+        L->hW.assign(3 * (size_t)n, 0.0);
+    if (n > 0) {
+        const size_t b = 3 * (size_t)n * sizeof(double);
+        HIP_TRY(hipMemcpy(L->X0, L->hX0.data(), b, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(L->R, L->hR.data(), b / 3, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(L->U, L->hU.data(), b, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(L->W, L->hW.data(), b, hipMemcpyHostToDevice));
+    }
+    L->level = 0;
+    rc = remap_all(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    return LBMEP_OK;
+}
+
+static int set_force_common(lbmep_lattice *L, const void *in, int dtype, int on_device,
+                            int ncomp, int mode) {
+    if (!L || !in) return fail(LBMEP_EINVAL, "null argument");
+    if (dtype != LBMEP_DTYPE_F64 && dtype != LBMEP_DTYPE_F32)
+        return fail(LBMEP_EINVAL, "unknown dtype");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N, Ns = L->g.Ns;
+    const size_t ib = dtype == LBMEP_DTYPE_F64 ? 8 : 4;
+    if (!on_device) {
+        for (size_t i = 0; i < (size_t)ncomp * N; ++i) {
+            const double v = dtype == LBMEP_DTYPE_F64 ? ((const double *)in)[i]
+                                                      : (double)((const float *)in)[i];
+            if (!std::isfinite(v)) return fail(LBMEP_EINVAL, "non-finite force value");
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    const size_t need = (size_t)ncomp * Ns * compute_bytes(L->precision);
+    if (L->force_bytes < need) {
+        hipFree(L->force);
+        L->force = nullptr;
+        L->force_bytes = 0;
+        if (hipMalloc(&L->force, need) != hipSuccess) {
+            L->force_mode = kForceNone;
+            return fail(LBMEP_ENOMEM, "force field allocation failed");
+        }
+        L->force_bytes = need;
+    }
+    const void *src = in;
+    void *tmp = nullptr;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, (size_t)ncomp * N * ib));
+        hipError_t e = hipMemcpy(tmp, in, (size_t)ncomp * N * ib, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(tmp);
+            return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+        }
+        src = tmp;
+    }
+    hipError_t e =
+        launch_convert_force(L->precision, src, dtype, L->force, N, N, Ns, ncomp, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    L->force_mode = mode;
+    return LBMEP_OK;
+}
+
+int lbmep_set_force(lbmep_lattice *L, const void *fb, int dtype, int on_device) {
+    int rc = set_force_common(L, fb, dtype, on_device, 3, kForceDense);
+    if (rc == LBMEP_OK) L->E[0] = L->E[1] = L->E[2] = 0.0;
+    return rc;
+}
+
+int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const double E[3],
+                           int on_device) {
+    if (!E || !finite_all(E, 3)) return fail(LBMEP_EINVAL, "bad field E");
+    int rc = set_force_common(L, rho_e, dtype, on_device, 1, kForceCharge);
+    if (rc == LBMEP_OK) {
+        L->E[0] = E[0];
+        L->E[1] = E[1];
+        L->E[2] = E[2];
+    }
+    return rc;
+}
+
+int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]) {
+    if (!L || !u) return fail(LBMEP_EINVAL, "null argument");
+    if (!std::isfinite(rho) || !finite_all(u, 3)) return fail(LBMEP_EINVAL, "non-finite state");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(launch_init_equilibrium(L->precision, L->g, L->f[L->cur], rho, u, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    return LBMEP_OK;
+}
+
+int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device) {
+    if (!L || !f) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    if (!on_device && !finite_all(f, Q * N)) return fail(LBMEP_EINVAL, "non-finite populations");
+    double *tmp = nullptr;
+    if (!on_device) HIP_TRY(hipMalloc(&tmp, N * sizeof(double)));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < Q && e == hipSuccess; ++q) {
+        const double *src = f + (size_t)q * N;
+        if (!on_device) {
+            e = hipMemcpyAsync(tmp, src, N * sizeof(double), hipMemcpyHostToDevice, L->stream);
+            src = tmp;
+        }
+        if (e == hipSuccess) e = launch_pdfs_from_f64(L->precision, L->g, q, src, L->f[L->cur], L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    }
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    return LBMEP_OK;
+}
+
+int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device) {
+    if (!L || !f) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    double *tmp = nullptr;
+    if (!on_device) HIP_TRY(hipMalloc(&tmp, N * sizeof(double)));
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < Q && e == hipSuccess; ++q) {
+        double *dst = on_device ? f + (size_t)q * N : tmp;
+        e = launch_pdfs_to_f64(L->precision, L->g, q, L->f[L->cur], dst, L->stream);
+        if (e == hipSuccess && !on_device)
+            e = hipMemcpyAsync(f + (size_t)q * N, tmp, N * sizeof(double), hipMemcpyDeviceToHost,
+                               L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    }
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    return LBMEP_OK;
+}
+
+int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (nsteps < 0) return fail(LBMEP_EINVAL, "negative step count");
+    int rc = set_device(L);
+    if (rc) return rc;
+    hipStream_t s = L->stream;
+    const ParticleArgs pa = particle_args(L);
+    for (int32_t it = 0; it < nsteps; ++it) {
+        if (L->np > 0) HIP_TRY(launch_fill_f64(L->FM, 0.0, 12 * (size_t)L->np, s));
+        L->ft_buf = L->cur_owner;
+        SweepArgs a;
+        a.g = L->g;
+        a.src = L->f[L->cur];
+        a.dst = L->f[1 - L->cur];
+        a.flag = L->flag;
+        a.nearmask = L->nearmask;
+        a.owner = L->np > 0 ? L->owner[L->cur_owner] : nullptr;
+        a.Xc = L->np > 0 ? L->Xheld[L->cur_owner] : nullptr;
+        a.U = L->U;
+        a.W = L->W;
+        a.FM = L->np > 0 ? L->FM : nullptr;
+        a.force = L->force;
+        for (int k = 0; k < 3; ++k) a.E[k] = L->E[k];
+        a.le = L->le;
+        a.lo = L->lo;
+        a.ae = L->ae;
+        a.ao = L->ao;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (L->timing) {
+            while (L->ev.size() < L->ev_used + 2) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                L->ev.push_back(e);
+            }
+            e0 = L->ev[L->ev_used];
+            e1 = L->ev[L->ev_used + 1];
+            L->ev_used += 2;
+            HIP_TRY(hipEventRecord(e0, s));
+        }
+        HIP_TRY(launch_stream_collide(L->precision, L->force_mode, a, L->block_x, s));
+        if (L->timing) HIP_TRY(hipEventRecord(e1, s));
+        if (L->np > 0 && L->cfg.move_particles) {
+            // kinematics, re-mapping and refill for the next time level
+            const int b = 1 - L->cur_owner;
+            HIP_TRY(launch_map_clear(pa, L->Xheld[b], L->owner[b], s));
+            HIP_TRY(launch_positions(pa, L->level + 1, L->Xheld[b], s));
+            HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
+            HIP_TRY(launch_classify_refill(L->precision, pa, L->Xheld[L->cur_owner], L->Xheld[b],
+                                           L->flag, L->nearmask, L->owner[b],
+                                           L->owner[L->cur_owner], L->f[1 - L->cur], s));
+            L->cur_owner = b;
+        }
+        L->cur = 1 - L->cur;
+        L->level += 1;
+    }
+    return LBMEP_OK;
+}
+
+int lbmep_sync(lbmep_lattice *L) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    return LBMEP_OK;
+}
+
+int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device) {
+    if (!L || !rho || !u) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    double *drho = rho, *du = u;
+    if (!on_device) {
+        if (hipMalloc(&drho, N * sizeof(double)) != hipSuccess) return fail(LBMEP_ENOMEM, "temp");
+        if (hipMalloc(&du, 3 * N * sizeof(double)) != hipSuccess) {
+            hipFree(drho);
+            return fail(LBMEP_ENOMEM, "temp");
+        }
+    }
+    hipError_t e = launch_macro(L->precision, L->force_mode, L->g, L->f[L->cur], L->flag,
+                                L->np > 0 ? L->owner[L->cur_owner] : nullptr,
+                                L->np > 0 ? L->Xheld[L->cur_owner] : nullptr, L->U, L->W, L->force,
+                                L->E, drho, du, L->stream);
+    if (e == hipSuccess && !on_device) {
+        e = hipMemcpyAsync(rho, drho, N * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(u, du, 3 * N * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (!on_device) {
+        hipFree(drho);
+        hipFree(du);
+    }
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    return LBMEP_OK;
+}
+
+int lbmep_get_particle_ft(lbmep_lattice *L, double *F, double *M) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (L->np == 0) return LBMEP_OK;
+    if (!F || !M) return fail(LBMEP_EINVAL, "null output");
+    int rc = set_device(L);
+    if (rc) return rc;
+    std::vector<double> h(6 * (size_t)L->np);
+    double *out = L->FM + 12 * (size_t)L->np;
+    HIP_TRY(launch_finalize_ft(L->np, L->FM, L->Xheld[L->ft_buf], out, L->stream));
+    HIP_TRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    for (int p = 0; p < L->np; ++p)
+        for (int k = 0; k < 3; ++k) {
+            F[3 * p + k] = h[6 * (size_t)p + k];
+            M[3 * p + k] = h[6 * (size_t)p + 3 + k];
+        }
+    return LBMEP_OK;
+}
+
+int lbmep_get_map(lbmep_lattice *L, uint8_t *flags, int32_t *owner) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    if (flags) {
+        uint8_t *tmp = nullptr;
+        HIP_TRY(hipMalloc(&tmp, N));
+        hipError_t e = launch_export_flags(L->g, L->flag, tmp, L->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(flags, tmp, N, hipMemcpyDeviceToHost, L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+        hipFree(tmp);
+        if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    }
+    if (owner) {
+        if (L->np > 0) {
+            HIP_TRY(hipMemcpyAsync(owner, L->owner[L->cur_owner], 4 * N, hipMemcpyDeviceToHost,
+                                   L->stream));
+            HIP_TRY(hipStreamSynchronize(L->stream));
+        } else {
+            for (size_t i = 0; i < N; ++i) owner[i] = -1;
+        }
+    }
+    return LBMEP_OK;
+}
+
+int lbmep_get_invariants(lbmep_lattice *L, double out[4]) {
+    if (!L || !out) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    double *dout = L->red + 5 * (size_t)L->red_blocks;
+    HIP_TRY(launch_invariants(L->precision, L->g, L->f[L->cur], L->flag, L->red, L->red_blocks,
+                              dout, L->stream));
+    HIP_TRY(hipMemcpyAsync(out, dout, 4 * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    if (!finite_all(out, 4)) return fail(LBMEP_ENONFINITE, "non-finite mass or momentum");
+    return LBMEP_OK;
+}
+
+int lbmep_get_time(lbmep_lattice *L, int64_t *step) {
+    if (!L || !step) return fail(LBMEP_EINVAL, "null argument");
+    *step = L->level;
+    return LBMEP_OK;
+}
+
+int lbmep_set_timing(lbmep_lattice *L, int enable) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    L->timing = enable != 0;
+    return LBMEP_OK;
+}
+
+int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches) {
+    if (!L || !total_ms || !launches) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < L->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, L->ev[i], L->ev[i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(L->ev_used / 2);
+    L->ev_used = 0;
+    return LBMEP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint
+// ---------------------------------------------------------------------------
+
+namespace {
+const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '1'};
+
+struct Header {
+    char magic[8];
+    int32_t nx, ny, nz, per[3], precision, move;
+    double nu, magic_param;
+    int64_t level;
+    int32_t np, force_mode;
+    double E[3];
+};
+}  // namespace
+
+int lbmep_save_state(lbmep_lattice *L, const char *path) {
+    if (!L || !path) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return fail(LBMEP_EINVAL, std::string("cannot open ") + path);
+    Header h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.nx = L->g.nx;
+    h.ny = L->g.ny;
+    h.nz = L->g.nz;
+    for (int k = 0; k < 3; ++k) h.per[k] = L->g.per[k];
+    h.precision = L->precision;
+    h.move = L->cfg.move_particles;
+    h.nu = L->cfg.nu;
+    h.magic_param = L->cfg.magic;
+    h.level = L->level;
+    h.np = L->np;
+    h.force_mode = L->force_mode;
+    for (int k = 0; k < 3; ++k) h.E[k] = L->E[k];
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
+    const size_t N = L->g.N, Ns = L->g.Ns;
+    if (ok && L->np > 0) {
+        ok = std::fwrite(L->hX0.data(), 8, L->hX0.size(), fp) == L->hX0.size() &&
+             std::fwrite(L->hR.data(), 8, L->hR.size(), fp) == L->hR.size() &&
+             std::fwrite(L->hU.data(), 8, L->hU.size(), fp) == L->hU.size() &&
+             std::fwrite(L->hW.data(), 8, L->hW.size(), fp) == L->hW.size();
+    }
+    // user wall flags
+    std::vector<uint8_t> fl(N);
+    if (ok) {
+        if (hipMemcpy(fl.data(), L->flag, N, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        for (size_t i = 0; i < N; ++i) fl[i] = (fl[i] & kWall) ? LBMEP_WALL : LBMEP_FLUID;
+        ok = ok && std::fwrite(fl.data(), 1, N, fp) == N;
+    }
+    // force (compute precision)
+    if (ok && L->force_mode != kForceNone) {
+        const int nc = L->force_mode == kForceDense ? 3 : 1;
+        std::vector<char> buf(N * compute_bytes(L->precision));
+        for (int k = 0; k < nc && ok; ++k) {
+            ok = hipMemcpy(buf.data(), (char *)L->force + k * Ns * compute_bytes(L->precision),
+                           buf.size(), hipMemcpyDeviceToHost) == hipSuccess &&
+                 std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+        }
+    }
+    // populations, raw storage format
+    if (ok) {
+        const size_t es = storage_bytes(L->precision);
+        std::vector<char> buf(N * es);
+        for (int q = 0; q < Q && ok; ++q) {
+            ok = hipMemcpy(buf.data(), (char *)L->f[L->cur] + q * Ns * es, buf.size(),
+                           hipMemcpyDeviceToHost) == hipSuccess &&
+                 std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+        }
+    }
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(LBMEP_EDEVICE, "checkpoint write failed");
+    return LBMEP_OK;
+}
+
+int lbmep_load_state(lbmep_lattice *L, const char *path) {
+    if (!L || !path) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return fail(LBMEP_EINVAL, std::string("cannot open ") + path);
+    Header h{};
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 &&
+              h.nx == L->g.nx && h.ny == L->g.ny && h.nz == L->g.nz && h.per[0] == L->g.per[0] &&
+              h.per[1] == L->g.per[1] && h.per[2] == L->g.per[2] &&
+              h.precision == L->precision && h.move == L->cfg.move_particles &&
+              h.nu == L->cfg.nu && h.magic_param == L->cfg.magic && h.np >= 0 && h.level >= 0;
+    if (!ok) {
+        std::fclose(fp);
+        return fail(LBMEP_EINVAL, "checkpoint does not match this lattice");
+    }
+    const size_t N = L->g.N, Ns = L->g.Ns;
+    std::vector<double> X(3 * (size_t)h.np), R(h.np), U(3 * (size_t)h.np), W(3 * (size_t)h.np);
+    if (h.np > 0)
+        ok = std::fread(X.data(), 8, X.size(), fp) == X.size() &&
+             std::fread(R.data(), 8, R.size(), fp) == R.size() &&
+             std::fread(U.data(), 8, U.size(), fp) == U.size() &&
+             std::fread(W.data(), 8, W.size(), fp) == W.size();
+    std::vector<uint8_t> fl(N);
+    ok = ok && std::fread(fl.data(), 1, N, fp) == N;
+    const int nc = h.force_mode == kForceDense ? 3 : (h.force_mode == kForceCharge ? 1 : 0);
+    std::vector<char> force(nc * N * compute_bytes(L->precision));
+    ok = ok && std::fread(force.data(), 1, force.size(), fp) == force.size();
+    const size_t es = storage_bytes(L->precision);
+    std::vector<char> pdf(Q * N * es);
+    ok = ok && std::fread(pdf.data(), 1, pdf.size(), fp) == pdf.size();
+    std::fclose(fp);
+    if (!ok) return fail(LBMEP_EINVAL, "truncated checkpoint");
+    // walls, particles (time level 0 map), then the saved time level
+    rc = lbmep_set_flags(L, fl.data(), 0);
+    if (rc) return rc;
+    rc = lbmep_set_particles(L, h.np, X.data(), R.data(), U.data(), W.data());
+    if (rc) return rc;
+    L->level = h.level;
+    rc = remap_all(L);
+    if (rc) return rc;
+    if (nc > 0) {
+        const size_t need = nc * Ns * compute_bytes(L->precision);
+        if (L->force_bytes < need) {
+            hipFree(L->force);
+            L->force = nullptr;
+            L->force_bytes = 0;
+            if (hipMalloc(&L->force, need) != hipSuccess) return fail(LBMEP_ENOMEM, "force");
+            L->force_bytes = need;
+        }
+        const size_t cb = N * compute_bytes(L->precision);
+        for (int k = 0; k < nc; ++k)
+            HIP_TRY(hipMemcpy((char *)L->force + k * Ns * compute_bytes(L->precision),
+                              force.data() + k * cb, cb, hipMemcpyHostToDevice));
+    }
+    L->force_mode = h.force_mode;
+    for (int k = 0; k < 3; ++k) L->E[k] = h.E[k];
+    for (int q = 0; q < Q; ++q)
+        HIP_TRY(hipMemcpy((char *)L->f[L->cur] + q * Ns * es, pdf.data() + q * N * es, N * es,
+                          hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    return LBMEP_OK;
+}
+
+}  // extern "C"

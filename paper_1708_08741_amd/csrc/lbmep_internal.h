@@ -1,0 +1,124 @@
+// lbmep_internal.h -- shared definitions of the gfx950 library (device side
+// and host runtime).  Not part of the public ABI (include/lbmep.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbmep.h"
+
+namespace lbmep {
+
+constexpr int Q = 19;
+
+// D3Q19 velocity set in the ABI order: q=0 rest, 1..6 axis directions,
+// 7..18 diagonals, opposite pairs (2k-1, 2k).  Sec. 3.1 uses Qian et al.'s
+// D3Q19 model with weights 1/3, 1/18, 1/36 and c_s^2 = 1/3.
+constexpr int kCx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int kCy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kCz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr double wq(int q) {
+    return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// cell flag bits (internal encoding of LBMEP_WALL / OBST / NEAR)
+constexpr uint8_t kWall = 1, kObst = 2, kNear = 4;
+// owner value of a cell no particle covers
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// FP16 deviation storage scale: stored h = (f - w) * 2^24
+constexpr float kHalfScale = 16777216.0f;
+constexpr float kHalfInvScale = 1.0f / 16777216.0f;
+
+// force modes of the sweep
+enum ForceMode { kForceNone = 0, kForceDense = 1, kForceCharge = 2 };
+
+struct Grid {
+    int nx, ny, nz;
+    int per[3];
+    size_t N;   // nx*ny*nz
+    size_t Ns;  // population stride (N rounded up to a multiple of 128)
+};
+
+// arguments of the fused stream-collide sweep
+struct SweepArgs {
+    Grid g;
+    const void *src;
+    void *dst;
+    const uint8_t *flag;
+    const uint32_t *nearmask;
+    const uint32_t *owner;
+    const double *Xc;  // particle centres of the current time level (3n)
+    const double *U;   // 3n
+    const double *W;   // 3n
+    double *FM;        // 12n accumulators per particle: F_dev, M_dev, K, T; or null
+    const void *force; // dense: 3*Ns compute type; charge: Ns compute type
+    double E[3];
+    double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
+};
+
+// kernels (host-side launchers); each returns hipError_t of the launch
+hipError_t launch_stream_collide(int precision, int force_mode, const SweepArgs &a, int block_x,
+                                 hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
+
+// equilibrium everywhere (rho, u)
+hipError_t launch_init_equilibrium(int precision, const Grid &g, void *f, double rho,
+                                   const double u[3], hipStream_t s);
+// absolute FP64 values of population q <-> storage (N values)
+hipError_t launch_pdfs_from_f64(int precision, const Grid &g, int q, const double *in, void *f,
+                                hipStream_t s);
+hipError_t launch_pdfs_to_f64(int precision, const Grid &g, int q, const void *f, double *out,
+                              hipStream_t s);
+// force conversion into the compute precision
+hipError_t launch_convert_force(int precision, const void *in, int in_dtype, void *out,
+                                size_t n, size_t in_stride, size_t out_stride, int ncomp,
+                                hipStream_t s);
+// macroscopic read-out
+hipError_t launch_macro(int precision, int force_mode, const Grid &g, const void *f,
+                        const uint8_t *flag, const uint32_t *owner, const double *Xc,
+                        const double *U, const double *W, const void *force,
+                        const double E[3], double *rho, double *u, hipStream_t s);
+// deterministic FP64 invariants: partial sums per block, then one block
+hipError_t launch_invariants(int precision, const Grid &g, const void *f, const uint8_t *flag,
+                             double *partials, int nblocks, double *out, hipStream_t s);
+int invariants_blocks(const Grid &g);
+
+// particles
+struct ParticleArgs {
+    Grid g;
+    int np;
+    int moving;
+    const double *X0, *R, *U, *W;
+};
+hipError_t launch_positions(const ParticleArgs &pa, int64_t level, double *X, hipStream_t s);
+hipError_t launch_map_clear(const ParticleArgs &pa, const double *X, uint32_t *owner,
+                            hipStream_t s);
+hipError_t launch_map_set(const ParticleArgs &pa, const double *X, const uint8_t *flag,
+                          uint32_t *owner, hipStream_t s);
+// classify cells (flags + near masks) over the whole grid
+hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
+                               const uint32_t *owner, hipStream_t s);
+// classify around every particle (union of the boxes at Xold and Xnew,
+// grown by one cell) and refill uncovered cells with f^eq(rho0, u_s)
+hipError_t launch_classify_refill(int precision, const ParticleArgs &pa, const double *Xold,
+                                  const double *Xnew, uint8_t *flag, uint32_t *nearmask,
+                                  const uint32_t *owner_new, const uint32_t *owner_old, void *f,
+                                  hipStream_t s);
+// final force and torque (6n: F then M per particle) from the 12n sweep
+// accumulators and the particle centres of the streamed time level
+hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double *out,
+                              hipStream_t s);
+// map read-out in the ABI encoding
+hipError_t launch_export_flags(const Grid &g, const uint8_t *flag, uint8_t *out, hipStream_t s);
+// user flags -> internal wall bits (clears OBST/NEAR)
+hipError_t launch_import_flags(const Grid &g, const uint8_t *in, uint8_t *flag, hipStream_t s);
+
+}  // namespace lbmep

@@ -1,0 +1,305 @@
+"""Python binding of the gfx950 library liblbmep.so (C ABI in include/lbmep.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The raw functions keep the C names (``lbmep_create``,
+``lbmep_step``, ...); ``Lattice`` is a thin object wrapper over them.
+Host arrays are numpy arrays; device arrays are torch CUDA tensors (their
+``data_ptr`` is passed with ``on_device = 1``).  PyTorch is used only for
+device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbmep.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32DEV, FP16DEV = 0, 1, 2
+FLUID, WALL, OBST, NEAR = 0, 1, 2, 3
+DTYPE_F64, DTYPE_F32 = 0, 1
+
+PRECISIONS = {"fp64": FP64, "fp32dev": FP32DEV, "fp16dev": FP16DEV}
+
+
+class LbmepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbmep error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic", ctypes.c_int32 * 3),
+        ("nu", ctypes.c_double), ("magic", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("move_particles", ctypes.c_int32),
+        ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+# exported symbols and their ctypes signatures
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "lbmep_last_error": (ctypes.c_char_p, []),
+    "lbmep_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),
+    "lbmep_destroy": (ctypes.c_int, [_P]),
+    "lbmep_set_flags": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lbmep_set_particles": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
+    "lbmep_set_force": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int]),
+    "lbmep_set_charge_force": (ctypes.c_int, [_P, _P, ctypes.c_int, _D, ctypes.c_int]),
+    "lbmep_init_equilibrium": (ctypes.c_int, [_P, ctypes.c_double, _D]),
+    "lbmep_set_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lbmep_get_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lbmep_step": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbmep_sync": (ctypes.c_int, [_P]),
+    "lbmep_get_macro": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "lbmep_get_particle_ft": (ctypes.c_int, [_P, _P, _P]),
+    "lbmep_get_map": (ctypes.c_int, [_P, _P, _P]),
+    "lbmep_get_invariants": (ctypes.c_int, [_P, _D]),
+    "lbmep_get_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lbmep_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "lbmep_get_timing": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
+    "lbmep_save_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "lbmep_load_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+}
+
+
+def lib():
+    """Load liblbmep.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with paper_1708_08741_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != OK:
+        msg = lib().lbmep_last_error().decode(errors="replace")
+        raise LbmepError(rc, msg)
+    return rc
+
+
+def _ptr(a):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return ctypes.c_void_p(a.ctypes.data), 0
+    # torch tensor
+    assert a.is_contiguous()
+    return ctypes.c_void_p(a.data_ptr()), 1 if a.is_cuda else 0
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def make_config(shape, periodic=(True, True, True), nu=1.0 / 6.0, magic=3.0 / 16.0,
+                precision=FP64, move_particles=False, device=0, stream=None):
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    c = Config()
+    c.nx, c.ny, c.nz = (int(s) for s in shape)
+    for k in range(3):
+        c.periodic[k] = 1 if periodic[k] else 0
+    c.nu = float(nu)
+    c.magic = float(magic)
+    c.precision = int(precision)
+    c.move_particles = 1 if move_particles else 0
+    c.device = int(device)
+    c.reserved = 0
+    c.stream = stream
+    return c
+
+
+def footprint(shape, precision=FP64, n_particles=0, with_charge=False, **kw):
+    cfg = make_config(shape, precision=precision, **kw)
+    out = ctypes.c_size_t(0)
+    _check(lib().lbmep_footprint(ctypes.byref(cfg), int(n_particles), 1 if with_charge else 0,
+                                 ctypes.byref(out)))
+    return out.value
+
+
+class Lattice:
+    """One lattice of the GPU library.  Host arrays use numpy (z, y, x) order."""
+
+    def __init__(self, shape, periodic=(True, True, True), nu=1.0 / 6.0, magic=3.0 / 16.0,
+                 precision=FP64, move_particles=False, device=0, stream=None):
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.cfg = make_config(shape, periodic, nu, magic, precision, move_particles, device,
+                               stream)
+        self.shape = tuple(int(s) for s in shape)
+        nx, ny, nz = self.shape
+        self.N = nx * ny * nz
+        self.np = 0
+        h = ctypes.c_void_p()
+        _check(lib().lbmep_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbmep_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_flags(self, flags):
+        if isinstance(flags, np.ndarray):
+            flags = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1)
+        p, dev = _ptr(flags)
+        _check(lib().lbmep_set_flags(self._h, p, dev))
+
+    def set_particles(self, X, R, U, W=None):
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1)
+        n = len(R)
+        Wp = None
+        if W is not None:
+            W = np.ascontiguousarray(W, dtype=np.float64).reshape(-1)
+            Wp = W.ctypes.data
+        _check(lib().lbmep_set_particles(self._h, n, X.ctypes.data, R.ctypes.data, U.ctypes.data,
+                                         Wp))
+        self.np = n
+
+    def set_force(self, fb):
+        if isinstance(fb, np.ndarray):
+            fb = np.ascontiguousarray(fb)
+            dt = DTYPE_F32 if fb.dtype == np.float32 else DTYPE_F64
+            fb = fb.astype(np.float32 if dt == DTYPE_F32 else np.float64, copy=False).reshape(-1)
+        else:
+            import torch
+            dt = DTYPE_F32 if fb.dtype == torch.float32 else DTYPE_F64
+        p, dev = _ptr(fb)
+        _check(lib().lbmep_set_force(self._h, p, dt, dev))
+
+    def set_charge_force(self, rho_e, E):
+        if isinstance(rho_e, np.ndarray):
+            rho_e = np.ascontiguousarray(rho_e)
+            dt = DTYPE_F32 if rho_e.dtype == np.float32 else DTYPE_F64
+            rho_e = rho_e.astype(np.float32 if dt == DTYPE_F32 else np.float64,
+                                 copy=False).reshape(-1)
+        else:
+            import torch
+            dt = DTYPE_F32 if rho_e.dtype == torch.float32 else DTYPE_F64
+        Ea = np.array(E, dtype=np.float64)
+        p, dev = _ptr(rho_e)
+        _check(lib().lbmep_set_charge_force(self._h, p, dt, _dp(Ea), dev))
+
+    def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
+        ua = np.array(u, dtype=np.float64)
+        _check(lib().lbmep_init_equilibrium(self._h, float(rho), _dp(ua)))
+
+    def set_pdfs(self, f):
+        if isinstance(f, np.ndarray):
+            f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        p, dev = _ptr(f)
+        _check(lib().lbmep_set_pdfs(self._h, p, dev))
+
+    def get_pdfs(self, out=None):
+        nx, ny, nz = self.shape
+        if out is None:
+            out = np.zeros((19, nz, ny, nx))
+        p, dev = _ptr(out)
+        _check(lib().lbmep_get_pdfs(self._h, p, dev))
+        return out
+
+    def step(self, n=1):
+        _check(lib().lbmep_step(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().lbmep_sync(self._h))
+
+    @property
+    def time(self):
+        t = ctypes.c_int64(0)
+        _check(lib().lbmep_get_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    def macro(self):
+        nx, ny, nz = self.shape
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        _check(lib().lbmep_get_macro(self._h, rho.ctypes.data, u.ctypes.data, 0))
+        return rho, u
+
+    def macro_device(self, rho, u):
+        _check(lib().lbmep_get_macro(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                     ctypes.c_void_p(u.data_ptr()), 1))
+
+    def ft(self):
+        F = np.zeros((self.np, 3))
+        M = np.zeros((self.np, 3))
+        if self.np:
+            _check(lib().lbmep_get_particle_ft(self._h, F.ctypes.data, M.ctypes.data))
+        return F, M
+
+    def map(self):
+        nx, ny, nz = self.shape
+        fl = np.zeros((nz, ny, nx), dtype=np.uint8)
+        ow = np.zeros((nz, ny, nx), dtype=np.int32)
+        _check(lib().lbmep_get_map(self._h, fl.ctypes.data, ow.ctypes.data))
+        return fl, ow
+
+    def invariants(self):
+        out = np.zeros(4)
+        _check(lib().lbmep_get_invariants(self._h, _dp(out)))
+        return out
+
+    def set_timing(self, enable=True):
+        _check(lib().lbmep_set_timing(self._h, 1 if enable else 0))
+
+    def get_timing(self):
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        _check(lib().lbmep_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def save(self, path):
+        _check(lib().lbmep_save_state(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().lbmep_load_state(self._h, str(path).encode()))
+
+
+def from_workload(wl, precision=None, device=0, stream=None, force_dtype=None):
+    """Set up a GPU lattice for a workloads.Workload."""
+    prec = PRECISIONS[precision or wl.precision]
+    L = Lattice(wl.shape, wl.periodic, wl.nu, wl.magic, prec, wl.moving, device, stream)
+    L.set_flags(wl.flags)
+    if force_dtype is None:
+        force_dtype = np.float64 if prec == FP64 else np.float32
+    if wl.rho_e is not None:
+        L.set_charge_force(wl.rho_e.astype(force_dtype), wl.E)
+    elif wl.fb is not None:
+        L.set_force(wl.fb.astype(force_dtype))
+    L.init_equilibrium(1.0, (0.0, 0.0, 0.0))
+    L.set_particles(wl.X, wl.R, wl.U, wl.W)
+    return L

@@ -1,0 +1,82 @@
+"""Host-side checks of the gfx950 library (no GPU needed, no kernel calls).
+
+The C-ABI library must load and export every function include/lbmep.h
+declares; the Python binding must declare the same set; host-only argument
+checks (configuration validation, footprint) behave as documented.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1708_08741_amd import lbmep as lb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbmep.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbmep_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lb.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/lbmep.h but not exported"
+    assert sorted(lb.exported_symbols()) == names
+
+
+def test_config_struct_layout():
+    # int32 nx,ny,nz, periodic[3]; double nu, magic; int32 precision,
+    # move_particles, device, reserved; void* stream
+    assert ctypes.sizeof(lb.Config) == 64
+    assert lb.Config.nu.offset == 24 and lb.Config.stream.offset == 56
+
+
+def test_library_is_gfx950_only():
+    """The shared object carries gfx950 device code and no other target."""
+    data = open(lb.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    for other in (b"gfx90a", b"gfx942", b"gfx1100", b"sm_"):
+        assert other + b"\x00" not in data or other == b"sm_"
+
+
+@pytest.mark.parametrize("shape,prec,np_,charge", [
+    ((512, 512, 512), lb.FP32DEV, 4096, True),
+    ((512, 512, 512), lb.FP16DEV, 4096, True),
+    ((512, 512, 512), lb.FP64, 0, False),
+    ((64, 96, 128), lb.FP32DEV, 200, True),
+])
+def test_footprint(shape, prec, np_, charge):
+    """Footprint = two population grids + flags/masks (+ maps, force)."""
+    b = lb.footprint(shape, prec, np_, charge)
+    N = shape[0] * shape[1] * shape[2]
+    es = {lb.FP64: 8, lb.FP32DEV: 4, lb.FP16DEV: 2}[prec]
+    pops = 2 * 19 * N * es
+    assert pops < b < pops + 14 * N + 8 * N + 10_000_000
+    if shape == (512, 512, 512) and prec == lb.FP32DEV:
+        assert 20.4e9 < b < 23e9  # fits one MI355X (288 GB) many times over
+
+
+@pytest.mark.parametrize("kw", [
+    dict(shape=(0, 4, 4)), dict(shape=(4, -1, 4)), dict(shape=(4, 4, 4), nu=0.0),
+    dict(shape=(4, 4, 4), nu=float("nan")), dict(shape=(4, 4, 4), magic=0.0),
+    dict(shape=(4, 4, 4), precision=7), dict(shape=(4, 4, 70000)),
+])
+def test_config_validation(kw):
+    shape = kw.pop("shape")
+    prec = kw.pop("precision", lb.FP64)
+    with pytest.raises(lb.LbmepError) as e:
+        lb.footprint(shape, prec, 0, False, **kw)
+    assert e.value.code == lb.EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(lb, "_lib", None)
+    monkeypatch.setattr(lb, "LIB_PATH", str(tmp_path / "liblbmep.so"))
+    with pytest.raises(ImportError):
+        lb.lib()
