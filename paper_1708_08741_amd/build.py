@@ -16,15 +16,19 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbmep.so")
 
-SOURCES = ["k_stream.hip", "k_particles.hip", "k_fields.hip", "lbmep_api.hip"]
+SOURCES = ["k_stream_f64.hip", "k_stream_lp.hip", "k_particles.hip", "k_fields.hip",
+           "lbmep_api.hip"]
+
+# floating-point contraction per source: the FP64 sweep, the particle mapping
+# and the field kernels evaluate plain operation sequences (no fused
+# multiply-add); the reduced-precision sweep may contract
+CONTRACT = {"k_stream_lp.hip": "-ffp-contract=fast"}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# -ffp-contract=off: the FP64 sweep and the particle mapping evaluate the same
-# operation sequence as a plain CPU implementation, without fused multiply-adds.
 # -target-feature -packed-fp32-ops: no packed FP32 instructions.
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-ffp-contract=off",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC,
 ]
@@ -32,7 +36,8 @@ FLAGS = [
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + [CONTRACT.get(src, "-ffp-contract=off"), "-c",
+                             os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -1,7 +1,7 @@
-// k_particles.hip -- prescribed kinematics, obstacle mapping, NEAR-cell
-// classification and refill of uncovered cells (arXiv:1708.08741, Sec. 3.2:
-// a cell is an obstacle cell of a particle iff its centre lies inside it;
-// uncovered cells get f^eq(rho0, u_s) of the previous time level).
+// k_particles.hip -- prescribed kinematics, obstacle mapping and NEAR /
+// uncovered cell classification (arXiv:1708.08741, Sec. 3.2: a cell is an
+// obstacle cell of a particle iff its centre lies inside it; uncovered cells
+// are refilled with f^eq(rho0, u_s) by the sweep).
 //
 // Every per-particle kernel runs one block per particle over the particle's
 // bounding box of cells.  The inside test uses the same FP64 operation
@@ -126,9 +126,11 @@ __global__ void __launch_bounds__(kBoxThreads)
     }
 }
 
-// flag and blocked-direction mask of one cell from the wall bits and the map
+// flag and blocked-direction mask of one cell from the wall bits and the map;
+// with owner_old, a fluid cell that was an obstacle cell is marked uncovered
 __device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z, uint8_t *flag,
-                                              uint32_t *nearmask, const uint32_t *owner) {
+                                              uint32_t *nearmask, const uint32_t *owner,
+                                              const uint32_t *owner_old) {
     const size_t c = cell_of(g, x, y, z);
     const uint8_t wall = flag[c] & kWall;
     uint8_t f = wall;
@@ -156,7 +158,8 @@ __device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z
                 }
                 if (solid) mask |= 1u << (q - 1);
             }
-            if (mask) f = kNear;
+            f = mask ? kNear : 0;
+            if (owner_old && owner_old[c] != kNone) f |= kUncov;
         }
     }
     flag[c] = f | wall;
@@ -166,38 +169,12 @@ __device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z
 __global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *nearmask, const uint32_t *owner) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= g.nx) return;
-    classify_cell(g, x, blockIdx.y, blockIdx.z, flag, nearmask, owner);
+    classify_cell(g, x, blockIdx.y, blockIdx.z, flag, nearmask, owner, nullptr);
 }
 
-template <typename ST>
-__device__ __forceinline__ void store_eq(ST *f, size_t Ns, size_t c, double u0, double u1,
-                                         double u2);
-
-// f^eq(rho0 = 1, u) (Eq. fequ_Incompr_SRT), in the storage format
-template <typename ST>
-__device__ __forceinline__ void store_eq(ST *f, size_t Ns, size_t c, double u0, double u1,
-                                         double u2) {
-    const double uu = (u0 * u0 + u1 * u1) + u2 * u2;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
-        const double w = wq(q);
-        const double d = (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5;
-        if constexpr (sizeof(ST) == 8) {
-            f[(size_t)q * Ns + c] = w * (1.0 + 1.0 * d);
-        } else if constexpr (sizeof(ST) == 4) {
-            f[(size_t)q * Ns + c] = (float)(w * d);
-        } else {
-            f[(size_t)q * Ns + c] = __float2half_rn((float)(w * d) * kHalfScale);
-        }
-    }
-}
-
-template <typename ST>
 __global__ void __launch_bounds__(kBoxThreads)
-    k_classify_refill(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
-                      uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old,
-                      ST *f) {
+    k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
+                     uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old) {
     const int p = blockIdx.x;
     const Grid &g = pa.g;
     const double R = pa.R[p];
@@ -212,7 +189,8 @@ __global__ void __launch_bounds__(kBoxThreads)
                 mn = 0.0;
                 mx = (double)len[k];
             }
-            // one more cell on each side for the NEAR ring
+            // one more cell on each side for the NEAR ring and for the
+            // uncovered marks of the previous level (motion < 1 cell/step)
             axis_range(mn - R - 1.0, mx + R + 1.0, len[k], g.per[k], b.lo[k], b.cnt[k]);
         }
     }
@@ -220,23 +198,7 @@ __global__ void __launch_bounds__(kBoxThreads)
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         int x, y, z;
         box_cell(g, b, i, x, y, z);
-        const size_t c = cell_of(g, x, y, z);
-        classify_cell(g, x, y, z, flag, nearmask, owner_new);
-        const uint32_t po = owner_old[c];
-        if (!(flag[c] & kWall) && owner_new[c] == kNone && po != kNone) {
-            // uncovered: equilibrium with the surface velocity of the previous
-            // owner at its previous position
-            const double *Xp = Xold + 3 * (size_t)po;
-            const double *U = pa.U + 3 * (size_t)po;
-            const double *W = pa.W + 3 * (size_t)po;
-            const double r0 = min_image(((double)x + 0.5) - Xp[0], g.nx, g.per[0]);
-            const double r1 = min_image(((double)y + 0.5) - Xp[1], g.ny, g.per[1]);
-            const double r2 = min_image(((double)z + 0.5) - Xp[2], g.nz, g.per[2]);
-            const double us0 = U[0] + (W[1] * r2 - W[2] * r1);
-            const double us1 = U[1] + (W[2] * r0 - W[0] * r2);
-            const double us2 = U[2] + (W[0] * r1 - W[1] * r0);
-            store_eq<ST>(f, g.Ns, c, us0, us1, us2);
-        }
+        classify_cell(g, x, y, z, flag, nearmask, owner_new, owner_old);
     }
 }
 
@@ -292,21 +254,12 @@ hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
     return hipGetLastError();
 }
 
-hipError_t launch_classify_refill(int precision, const ParticleArgs &pa, const double *Xold,
-                                  const double *Xnew, uint8_t *flag, uint32_t *nearmask,
-                                  const uint32_t *owner_new, const uint32_t *owner_old, void *f,
-                                  hipStream_t s) {
+hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, const double *Xnew,
+                                 uint8_t *flag, uint32_t *nearmask, const uint32_t *owner_new,
+                                 const uint32_t *owner_old, hipStream_t s) {
     if (pa.np == 0) return hipSuccess;
-    const dim3 grid(pa.np), block(kBoxThreads);
-    if (precision == LBMEP_FP64)
-        hipLaunchKernelGGL(k_classify_refill<double>, grid, block, 0, s, pa, Xold, Xnew, flag,
-                           nearmask, owner_new, owner_old, static_cast<double *>(f));
-    else if (precision == LBMEP_FP32DEV)
-        hipLaunchKernelGGL(k_classify_refill<float>, grid, block, 0, s, pa, Xold, Xnew, flag,
-                           nearmask, owner_new, owner_old, static_cast<float *>(f));
-    else
-        hipLaunchKernelGGL(k_classify_refill<__half>, grid, block, 0, s, pa, Xold, Xnew, flag,
-                           nearmask, owner_new, owner_old, static_cast<__half *>(f));
+    hipLaunchKernelGGL(k_classify_boxes, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, Xold, Xnew,
+                       flag, nearmask, owner_new, owner_old);
     return hipGetLastError();
 }
 

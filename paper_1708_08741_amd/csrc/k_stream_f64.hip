@@ -1,0 +1,14 @@
+// k_stream_f64.hip -- FP64 instantiation of the fused sweep (sweep_impl.h).
+// Built without floating-point contraction: the collision, forcing and
+// bounce-back evaluate the same operation sequence as a plain FP64 CPU
+// implementation of Sec. 3.1-3.2 of arXiv:1708.08741.
+#include "sweep_impl.h"
+
+namespace lbmep {
+
+hipError_t launch_sweep_f64(int mode, int force_mode, const SweepArgs &a, int block_x,
+                            hipStream_t s) {
+    return sweep::launch_typed<double>(mode, force_mode, a, block_x, s);
+}
+
+}  // namespace lbmep

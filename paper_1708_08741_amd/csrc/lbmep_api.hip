@@ -4,6 +4,7 @@
 // k_stream.hip, k_particles.hip and k_fields.hip.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -52,6 +53,11 @@ struct lbmep_lattice {
     double tau = 0, le = 0, lo = 0, ae = 0, ao = 0;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
+    // false: f[cur] holds the post-stream state of the current level (as set
+    // by init / set_pdfs / load); true: f[cur] holds the post-collision
+    // populations of the previous level plus the bounce-back slots, from
+    // which the sweep (or a read-out) gathers the current state
+    bool pmode = false;
     uint8_t *flag = nullptr;
     uint32_t *nearmask = nullptr;
     uint32_t *owner[2] = {nullptr, nullptr};
@@ -70,6 +76,7 @@ struct lbmep_lattice {
     double *red = nullptr;
     int red_blocks = 0;
     int block_x = 256;
+    int xcd_swizzle = 1;
     bool timing = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -109,6 +116,44 @@ int remap_all(lbmep_lattice *L) {
         HIP_TRY(launch_fill_f64(L->FM, 0.0, 18 * (size_t)L->np, s));
     }
     HIP_TRY(launch_classify_all(L->g, L->flag, L->nearmask, L->np > 0 ? L->owner[0] : nullptr, s));
+    return LBMEP_OK;
+}
+
+SweepArgs sweep_args(const lbmep_lattice *L) {
+    SweepArgs a;
+    a.g = L->g;
+    a.src = L->f[L->cur];
+    a.dst = L->f[1 - L->cur];
+    a.flag = L->flag;
+    a.nearmask = L->nearmask;
+    const bool parts = L->np > 0;
+    a.owner = parts ? L->owner[L->cur_owner] : nullptr;
+    a.owner_old = parts ? L->owner[1 - L->cur_owner] : nullptr;
+    a.Xc = parts ? L->Xheld[L->cur_owner] : nullptr;
+    a.Xold = parts ? L->Xheld[1 - L->cur_owner] : nullptr;
+    a.U = L->U;
+    a.W = L->W;
+    a.FM = parts ? L->FM : nullptr;
+    a.force = L->force;
+    for (int k = 0; k < 3; ++k) a.E[k] = L->E[k];
+    a.le = L->le;
+    a.lo = L->lo;
+    a.ae = L->ae;
+    a.ao = L->ao;
+    a.nxb = 0;
+    a.xcd_swizzle = L->xcd_swizzle;
+    return a;
+}
+
+// bring the grid to the post-stream state of the current level (gather from
+// the post-collision state), so that it can be read or modified in place
+int materialize(lbmep_lattice *L) {
+    if (!L->pmode) return LBMEP_OK;
+    SweepArgs a = sweep_args(L);
+    a.FM = nullptr;
+    HIP_TRY(launch_sweep(L->precision, kSweepReadout, kForceNone, a, L->block_x, L->stream));
+    L->cur = 1 - L->cur;
+    L->pmode = false;
     return LBMEP_OK;
 }
 
@@ -216,9 +261,15 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
         delete L;
         return fail(LBMEP_EINVAL, "odd relaxation rate outside ]-2,0[");
     }
-    // one row per block when it fits (512 threads); rows of other sizes are
-    // covered by whole wavefronts
-    L->block_x = g.nx >= 512 ? 512 : (int)round_up((size_t)g.nx, 64);
+    // launch shape of the sweep: x-segments of block_x threads (whole
+    // wavefronts), dealt onto XCDs in contiguous runs; LBMEP_BLOCK_X and
+    // LBMEP_XCD_SWIZZLE override the defaults for launch-shape sweeps
+    L->block_x = 256;
+    if (const char *e = std::getenv("LBMEP_BLOCK_X")) {
+        const int b = std::atoi(e);
+        if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
+    }
+    if (const char *e = std::getenv("LBMEP_XCD_SWIZZLE")) L->xcd_swizzle = std::atoi(e) != 0;
     const size_t es = storage_bytes(L->precision);
     bool ok = true;
     ok = ok && hipMalloc(&L->f[0], Q * g.Ns * es) == hipSuccess;
@@ -256,6 +307,8 @@ int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device) {
             if (flags[i] != LBMEP_FLUID && flags[i] != LBMEP_WALL)
                 return fail(LBMEP_EINVAL, "flag values must be LBMEP_FLUID or LBMEP_WALL");
     }
+    rc = materialize(L);
+    if (rc) return rc;
     uint8_t *tmp = nullptr;
     const uint8_t *src = flags;
     if (!on_device) {
@@ -285,8 +338,16 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
             return fail(LBMEP_EINVAL, "non-finite particle data");
         for (int i = 0; i < n; ++i)
             if (!(R[i] > 0.0)) return fail(LBMEP_EINVAL, "radii must be > 0");
+        // the re-mapping of a step covers the boxes of two consecutive
+        // positions grown by one cell: a body may move less than one cell
+        if (L->cfg.move_particles)
+            for (size_t i = 0; i < 3 * (size_t)n; ++i)
+                if (!(std::fabs(U[i]) < 1.0))
+                    return fail(LBMEP_EINVAL, "particles must move less than one cell per step");
     }
     int rc = set_device(L);
+    if (rc) return rc;
+    rc = materialize(L);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(L->stream));
     if (n > 0 && !L->owner[0]) {
@@ -403,6 +464,7 @@ int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]) {
     if (rc) return rc;
     HIP_TRY(launch_init_equilibrium(L->precision, L->g, L->f[L->cur], rho, u, L->stream));
     HIP_TRY(hipStreamSynchronize(L->stream));
+    L->pmode = false;
     return LBMEP_OK;
 }
 
@@ -426,12 +488,15 @@ int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device) {
     }
     hipFree(tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    L->pmode = false;
     return LBMEP_OK;
 }
 
 int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device) {
     if (!L || !f) return fail(LBMEP_EINVAL, "null argument");
     int rc = set_device(L);
+    if (rc) return rc;
+    rc = materialize(L);
     if (rc) return rc;
     const size_t N = L->g.N;
     double *tmp = nullptr;
@@ -460,23 +525,7 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     for (int32_t it = 0; it < nsteps; ++it) {
         if (L->np > 0) HIP_TRY(launch_fill_f64(L->FM, 0.0, 12 * (size_t)L->np, s));
         L->ft_buf = L->cur_owner;
-        SweepArgs a;
-        a.g = L->g;
-        a.src = L->f[L->cur];
-        a.dst = L->f[1 - L->cur];
-        a.flag = L->flag;
-        a.nearmask = L->nearmask;
-        a.owner = L->np > 0 ? L->owner[L->cur_owner] : nullptr;
-        a.Xc = L->np > 0 ? L->Xheld[L->cur_owner] : nullptr;
-        a.U = L->U;
-        a.W = L->W;
-        a.FM = L->np > 0 ? L->FM : nullptr;
-        a.force = L->force;
-        for (int k = 0; k < 3; ++k) a.E[k] = L->E[k];
-        a.le = L->le;
-        a.lo = L->lo;
-        a.ae = L->ae;
-        a.ao = L->ao;
+        const SweepArgs a = sweep_args(L);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {
             while (L->ev.size() < L->ev_used + 2) {
@@ -489,20 +538,23 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
             L->ev_used += 2;
             HIP_TRY(hipEventRecord(e0, s));
         }
-        HIP_TRY(launch_stream_collide(L->precision, L->force_mode, a, L->block_x, s));
+        // gather + refill + collide + bounce-back slots (or, right after the
+        // state was set, collide the stored post-stream state in place)
+        HIP_TRY(launch_sweep(L->precision, L->pmode ? kSweepPull : kSweepLocal, L->force_mode, a,
+                             L->block_x, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
+        L->cur = 1 - L->cur;
+        L->pmode = true;
         if (L->np > 0 && L->cfg.move_particles) {
-            // kinematics, re-mapping and refill for the next time level
+            // kinematics, re-mapping and classification of the next level
             const int b = 1 - L->cur_owner;
             HIP_TRY(launch_map_clear(pa, L->Xheld[b], L->owner[b], s));
             HIP_TRY(launch_positions(pa, L->level + 1, L->Xheld[b], s));
             HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
-            HIP_TRY(launch_classify_refill(L->precision, pa, L->Xheld[L->cur_owner], L->Xheld[b],
-                                           L->flag, L->nearmask, L->owner[b],
-                                           L->owner[L->cur_owner], L->f[1 - L->cur], s));
+            HIP_TRY(launch_classify_boxes(pa, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
+                                          L->nearmask, L->owner[b], L->owner[L->cur_owner], s));
             L->cur_owner = b;
         }
-        L->cur = 1 - L->cur;
         L->level += 1;
     }
     return LBMEP_OK;
@@ -519,6 +571,8 @@ int lbmep_sync(lbmep_lattice *L) {
 int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device) {
     if (!L || !rho || !u) return fail(LBMEP_EINVAL, "null argument");
     int rc = set_device(L);
+    if (rc) return rc;
+    rc = materialize(L);
     if (rc) return rc;
     const size_t N = L->g.N;
     double *drho = rho, *du = u;
@@ -597,6 +651,8 @@ int lbmep_get_invariants(lbmep_lattice *L, double out[4]) {
     if (!L || !out) return fail(LBMEP_EINVAL, "null argument");
     int rc = set_device(L);
     if (rc) return rc;
+    rc = materialize(L);
+    if (rc) return rc;
     double *dout = L->red + 5 * (size_t)L->red_blocks;
     HIP_TRY(launch_invariants(L->precision, L->g, L->f[L->cur], L->flag, L->red, L->red_blocks,
                               dout, L->stream));
@@ -655,6 +711,8 @@ struct Header {
 int lbmep_save_state(lbmep_lattice *L, const char *path) {
     if (!L || !path) return fail(LBMEP_EINVAL, "null argument");
     int rc = set_device(L);
+    if (rc) return rc;
+    rc = materialize(L);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(L->stream));
     FILE *fp = std::fopen(path, "wb");
@@ -774,6 +832,7 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
         HIP_TRY(hipMemcpy((char *)L->f[L->cur] + q * Ns * es, pdf.data() + q * N * es, N * es,
                           hipMemcpyHostToDevice));
     HIP_TRY(hipStreamSynchronize(L->stream));
+    L->pmode = false;
     return LBMEP_OK;
 }
 

@@ -26,8 +26,9 @@ __host__ __device__ constexpr double wq(int q) {
     return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-// cell flag bits (internal encoding of LBMEP_WALL / OBST / NEAR)
-constexpr uint8_t kWall = 1, kObst = 2, kNear = 4;
+// cell flag bits (internal encoding of LBMEP_WALL / OBST / NEAR); kUncov
+// marks a fluid cell that was an obstacle cell at the previous time level
+constexpr uint8_t kWall = 1, kObst = 2, kNear = 4, kUncov = 8;
 // owner value of a cell no particle covers
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -52,19 +53,26 @@ struct SweepArgs {
     void *dst;
     const uint8_t *flag;
     const uint32_t *nearmask;
-    const uint32_t *owner;
+    const uint32_t *owner;      // map of the current time level
+    const uint32_t *owner_old;  // map of the previous time level (refill)
     const double *Xc;  // particle centres of the current time level (3n)
+    const double *Xold; // particle centres of the previous time level (3n)
     const double *U;   // 3n
     const double *W;   // 3n
     double *FM;        // 12n accumulators per particle: F_dev, M_dev, K, T; or null
     const void *force; // dense: 3*Ns compute type; charge: Ns compute type
     double E[3];
     double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
+    int nxb;                // x-segments per row (set by the launcher)
+    int xcd_swizzle;        // 1: map consecutive segments onto one XCD
 };
 
+// sweep modes: gather + collide, collide in place, gather only (read-out)
+enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2 };
+
 // kernels (host-side launchers); each returns hipError_t of the launch
-hipError_t launch_stream_collide(int precision, int force_mode, const SweepArgs &a, int block_x,
-                                 hipStream_t s);
+hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs &a, int block_x,
+                        hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
@@ -107,11 +115,10 @@ hipError_t launch_map_set(const ParticleArgs &pa, const double *X, const uint8_t
 hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
                                const uint32_t *owner, hipStream_t s);
 // classify around every particle (union of the boxes at Xold and Xnew,
-// grown by one cell) and refill uncovered cells with f^eq(rho0, u_s)
-hipError_t launch_classify_refill(int precision, const ParticleArgs &pa, const double *Xold,
-                                  const double *Xnew, uint8_t *flag, uint32_t *nearmask,
-                                  const uint32_t *owner_new, const uint32_t *owner_old, void *f,
-                                  hipStream_t s);
+// grown by one cell), marking uncovered cells for the refill in the sweep
+hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, const double *Xnew,
+                                 uint8_t *flag, uint32_t *nearmask, const uint32_t *owner_new,
+                                 const uint32_t *owner_old, hipStream_t s);
 // final force and torque (6n: F then M per particle) from the 12n sweep
 // accumulators and the particle centres of the streamed time level
 hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double *out,

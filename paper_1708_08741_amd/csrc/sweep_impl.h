@@ -1,0 +1,525 @@
+// sweep_impl.h -- fused collide + push-stream sweep of the D3Q19 TRT lattice
+// Boltzmann method with a body force and moving-obstacle bounce-back
+// (arXiv:1708.08741, Sec. 3.1 Eq. LBMcollideStep / Eq. LBMstreamStep with
+// Eq. LBE_forcetermLuo and Eq. modified_velocity; Sec. 3.2 Eq. LBMMovWall and
+// Eq. LBMhydrodynForce).
+//
+// Pull scheme with post-collision storage.  The grid holds f*, the
+// post-collision populations (with the forcing term) of the previous time
+// level.  One thread per cell; a workgroup covers a segment of an x-row and
+// consecutive segments are dealt onto one XCD.  A thread gathers f*_q from
+// x - e_q (reads shifted by at most one element along x; this completes the
+// stream of Eq. LBMstreamStep), refills the cell if it has just been
+// uncovered, collides, and writes its 19 new values aligned to its own cell.
+// Bounce-back needs no look-up at gather time: a fluid cell next to a solid
+// cell s writes the bounced value f*_q - 2 w_q rho0 c_q.u_s / c_s^2
+// (Eq. LBMMovWall) into the slot of s that the fluid cell will gather from
+// at the next step, and adds the momentum-exchange terms (Eq.
+// LBMhydrodynForce), summed per particle in FP64 (per lane, across the
+// wavefront by shuffles, then one FP64 atomic per particle and wavefront).
+// Only the edge of a non-periodic axis is resolved at gather time, from the
+// cell coordinates.
+//
+// The template is instantiated in two translation units: k_stream_f64.hip
+// (FP64, compiled without floating-point contraction so that it evaluates
+// exactly the operation sequence of a plain CPU implementation) and
+// k_stream_lp.hip (FP32 / FP16 deviation storage, FMA contraction allowed).
+// Byte offsets are 32-bit (global loads/stores with a scalar base) whenever a
+// population array is smaller than 4 GiB.
+#pragma once
+#include "lbmep_internal.h"
+
+namespace lbmep {
+namespace sweep {
+
+template <typename ST>
+struct Storage;
+
+// FP64: absolute populations
+template <>
+struct Storage<double> {
+    using CT = double;
+    static __device__ __forceinline__ double load(const double *p) { return *p; }
+    static __device__ __forceinline__ void store(double *p, double v) { *p = v; }
+    // deviation f - w_q of a computed population q, in FP64
+    static __device__ __forceinline__ double devval(double v, int q) { return v - wq(q); }
+    // f^eq(rho0 = 1, u) of population q (Eq. fequ_Incompr_SRT) as stored
+    static __device__ __forceinline__ double feq(int q, double d) { return wq(q) * (1.0 + 1.0 * d); }
+};
+
+// FP32: deviations f - w_q
+template <>
+struct Storage<float> {
+    using CT = float;
+    static __device__ __forceinline__ float load(const float *p) { return *p; }
+    static __device__ __forceinline__ void store(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ double devval(float v, int q) { return (double)v; }
+    static __device__ __forceinline__ float feq(int q, double d) { return (float)(wq(q) * d); }
+};
+
+// FP16: deviations scaled by 2^24
+template <>
+struct Storage<__half> {
+    using CT = float;
+    static __device__ __forceinline__ float load(const __half *p) {
+        return __half2float(*p) * kHalfInvScale;
+    }
+    static __device__ __forceinline__ void store(__half *p, float v) {
+        *p = __float2half_rn(v * kHalfScale);
+    }
+    static __device__ __forceinline__ double devval(float v, int q) { return (double)v; }
+    // rounded to the storage format, as a stored and re-loaded value would be
+    static __device__ __forceinline__ float feq(int q, double d) {
+        return __half2float(__float2half_rn((float)(wq(q) * d) * kHalfScale)) * kHalfInvScale;
+    }
+};
+
+// a . c_q for a lattice direction, with the zero terms of
+// ((c_x a_x + c_y a_y) + c_z a_z) dropped (same value, same rounding)
+template <int q, typename T>
+__device__ __forceinline__ T cdot(T ax, T ay, T az) {
+    constexpr int a = kCx[q], b = kCy[q], c = kCz[q];
+    T r = T(0);
+    if constexpr (a != 0 && b != 0) {
+        r = (a > 0 ? ax : -ax) + (b > 0 ? ay : -ay);
+    } else if constexpr (a != 0) {
+        r = (a > 0 ? ax : -ax);
+    } else if constexpr (b != 0) {
+        r = (b > 0 ? ay : -ay);
+    }
+    if constexpr (c != 0) {
+        if constexpr (a != 0 || b != 0)
+            r = r + (c > 0 ? az : -az);
+        else
+            r = (c > 0 ? az : -az);
+    }
+    return r;
+}
+
+__device__ __forceinline__ double min_image(double d, int len, int periodic) {
+    if (periodic) {
+        const double h = 0.5 * (double)len;
+        if (d > h)
+            d -= (double)len;
+        else if (d < -h)
+            d += (double)len;
+    }
+    return d;
+}
+
+// nearest periodic image of the half-integer cell coordinate c to X (exact)
+__device__ __forceinline__ double image_coord(double c, double X, int len, int periodic) {
+    if (periodic) {
+        const double d = c - X, h = 0.5 * (double)len;
+        if (d > h)
+            c -= (double)len;
+        else if (d < -h)
+            c += (double)len;
+    }
+    return c;
+}
+
+// per-particle accumulators: F_dev[3], M_dev[3], K[3], T[3]
+constexpr int kAcc = 12;
+
+__device__ __forceinline__ void flush_particle(double *FM, uint32_t p, const double acc[kAcc]) {
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) unsafeAtomicAdd(&FM[kAcc * (size_t)p + k], acc[k]);
+}
+
+// address of element `off` (bytes) of the array starting at the uniform
+// `base`; with OFF = uint32_t this becomes a global access with a scalar base
+// register and a 32-bit vector offset
+template <typename ST, typename OFF>
+__device__ __forceinline__ ST *at(void *base, OFF off) {
+    return reinterpret_cast<ST *>(static_cast<char *>(base) + off);
+}
+template <typename ST, typename OFF>
+__device__ __forceinline__ const ST *at(const void *base, OFF off) {
+    return reinterpret_cast<const ST *>(static_cast<const char *>(base) + off);
+}
+
+// sweep modes
+enum { kPull = 0,     // gather f* of the previous level, refill, collide
+       kLocal = 1,    // collide the post-stream state held in the grid
+       kReadout = 2   // gather and refill only: write the post-stream state
+};
+
+// Bounce-back of population q of a fluid cell whose neighbour s = x + e_q is
+// solid: the value that comes back to the cell as population opp(q) at the
+// next gather is written into slot opp(q) of s, with the momentum exchange.
+template <int q, typename ST, typename OFF>
+__device__ __forceinline__ void bounce(const SweepArgs &a, int x, int y, int z,
+                                       typename Storage<ST>::CT fq, uint32_t &pp,
+                                       double acc[kAcc]) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
+    const Grid &g = a.g;
+    int sx = x + cx, sy = y + cy, sz = z + cz;
+    bool inside = true;
+    if (sx < 0 || sx >= g.nx) {
+        if (g.per[0]) sx = sx < 0 ? sx + g.nx : sx - g.nx; else inside = false;
+    }
+    if (sy < 0 || sy >= g.ny) {
+        if (g.per[1]) sy = sy < 0 ? sy + g.ny : sy - g.ny; else inside = false;
+    }
+    if (sz < 0 || sz >= g.nz) {
+        if (g.per[2]) sz = sz < 0 ? sz + g.nz : sz - g.nz; else inside = false;
+    }
+    // beyond a non-periodic edge: resolved by the next gather
+    if (!inside) return;
+    const OFF s = (OFF)sx + (OFF)g.nx * ((OFF)sy + (OFF)g.ny * (OFF)sz);
+    double mw = 0.0;
+    const uint32_t p = a.owner ? a.owner[s] : kNone;
+    if (p != kNone) {
+        const double *X = a.Xc + 3 * (size_t)p;
+        const double *U = a.U + 3 * (size_t)p;
+        const double *W = a.W + 3 * (size_t)p;
+        // lever arm r = x_s - x_C (minimum image) and u_s = U + W x r
+        const double r0 = min_image(((double)sx + 0.5) - X[0], g.nx, g.per[0]);
+        const double r1 = min_image(((double)sy + 0.5) - X[1], g.ny, g.per[1]);
+        const double r2 = min_image(((double)sz + 0.5) - X[2], g.nz, g.per[2]);
+        const double us0 = U[0] + (W[1] * r2 - W[2] * r1);
+        const double us1 = U[1] + (W[2] * r0 - W[0] * r2);
+        const double us2 = U[2] + (W[0] * r1 - W[1] * r0);
+        const double cus = cdot<q>(us0, us1, us2);
+        // 2 (w_q / c_s^2) rho0 c_q . u_s (Eq. LBMMovWall)
+        mw = 2.0 * wq(q) * 3.0 * cus;
+        // [2 f*_q - 2 (w_q/c_s^2) rho0 c_q . u_s] c_q (Eq. LBMhydrodynForce),
+        // summed as [2 (f*_q - w_q) - ...] c_q plus the rest-weight part
+        // 2 w_q c_q = (k/18) c_q (k = 2 axis, 1 diagonal), whose sum cancels
+        // over a closed body and is accumulated exactly as integers:
+        // K = sum k c_q, T = sum k x_s x c_q (x_s the exact half-integer
+        // image of the cell centre)
+        const double gm = 2.0 * T::devval(fq, q) - mw;
+        const double g0 = cx == 0 ? 0.0 : (cx > 0 ? gm : -gm);
+        const double g1 = cy == 0 ? 0.0 : (cy > 0 ? gm : -gm);
+        const double g2 = cz == 0 ? 0.0 : (cz > 0 ? gm : -gm);
+        constexpr double k = q <= 6 ? 2.0 : 1.0;
+        const double xs0 = image_coord((double)sx + 0.5, X[0], g.nx, g.per[0]);
+        const double xs1 = image_coord((double)sy + 0.5, X[1], g.ny, g.per[1]);
+        const double xs2 = image_coord((double)sz + 0.5, X[2], g.nz, g.per[2]);
+        if (pp != p) {
+            if (pp != kNone) flush_particle(a.FM, pp, acc);
+            pp = p;
+#pragma unroll
+            for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        }
+        acc[0] += g0;
+        acc[1] += g1;
+        acc[2] += g2;
+        acc[3] += r1 * g2 - r2 * g1;
+        acc[4] += r2 * g0 - r0 * g2;
+        acc[5] += r0 * g1 - r1 * g0;
+        acc[6] += k * (double)cx;
+        acc[7] += k * (double)cy;
+        acc[8] += k * (double)cz;
+        acc[9] += k * (xs1 * (double)cz - xs2 * (double)cy);
+        acc[10] += k * (xs2 * (double)cx - xs0 * (double)cz);
+        acc[11] += k * (xs0 * (double)cy - xs1 * (double)cx);
+    }
+    constexpr int qb = opp(q);
+    void *slot = static_cast<char *>(a.dst) + (size_t)qb * a.g.Ns * sizeof(ST);
+    if constexpr (sizeof(CT) == 8) {
+        T::store(at<ST>(slot, s * (OFF)sizeof(ST)), fq - mw);
+    } else {
+        T::store(at<ST>(slot, s * (OFF)sizeof(ST)), (CT)((double)fq - mw));
+    }
+}
+
+// the TRT collision of one opposite pair (q, q+1) with the forcing term
+template <int q, typename CT>
+__device__ __forceinline__ void collide_pair(CT (&v)[Q], CT rho, CT ux, CT uy, CT uz, CT uu,
+                                             CT ufb, CT fb0, CT fb1, CT fb2, CT le, CT lo, CT ae,
+                                             CT ao, bool forced) {
+    constexpr int qb = q + 1;
+    const CT w = (CT)wq(q);
+    const CT cu = cdot<q>(ux, uy, uz);
+    // equilibrium halves (Eq. EqPDF_TRT), rho0 = 1, 1/c_s^2 = 3, 1/c_s^4 = 9
+    const CT feq_e = w * ((rho - uu * CT(1.5)) + (cu * cu) * CT(4.5));
+    const CT feq_o = w * (CT(3.0) * cu);
+    const CT fe = CT(0.5) * (v[q] + v[qb]);
+    const CT fo = CT(0.5) * (v[q] - v[qb]);
+    const CT A = le * (fe - feq_e);
+    const CT B = lo * (fo - feq_o);
+    CT fq = (v[q] + A) + B;
+    CT fqb = (v[qb] + A) - B;
+    if (forced) {
+        // Luo term split into even / odd parts, weighted (1 + lambda/2)
+        const CT cf = cdot<q>(fb0, fb1, fb2);
+        const CT Fe = w * ((-ufb * CT(3.0)) + (cu * cf) * CT(9.0));
+        const CT Fo = w * (cf * CT(3.0));
+        fq = (fq + ae * Fe) + ao * Fo;
+        fqb = (fqb + ae * Fe) - ao * Fo;
+    }
+    v[q] = fq;
+    v[qb] = fqb;
+}
+
+#define LBMEP_FOR_Q18(M) \
+    M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) M(17) M(18)
+
+// gather population q of the cell from x - e_q; beyond the edge of a
+// non-periodic axis the population bounces at the (resting) edge: it is the
+// cell's own opposite population
+template <int q, typename ST, typename OFF>
+__device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF pst, OFF es,
+                                                           OFF cb, const OFF rows[3][3],
+                                                           const bool rok[3][3], const OFF xs[3],
+                                                           const bool xok[3]) {
+    constexpr int qb = opp(q);
+    constexpr int lo = q < qb ? q : qb;
+    const void *base = static_cast<const char *>(src) + (size_t)lo * pst;
+    const bool ok = rok[kCy[q] + 1][kCz[q] + 1] && xok[kCx[q] + 1];
+    const OFF nb = (OFF)(q - lo) * pst + xs[kCx[q] + 1] + rows[kCy[q] + 1][kCz[q] + 1];
+    const OFF own = (OFF)(qb - lo) * pst + cb;
+    return Storage<ST>::load(at<ST>(base, ok ? nb : own));
+}
+
+template <typename ST, int FMODE, typename OFF, int MODE>
+__global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    // 1-D grid of x-segments; workgroups are dealt to the 8 XCDs round-robin,
+    // so consecutive segments (which share cache lines through the +-1
+    // gathers along x) are remapped onto the same XCD and its L2
+    const uint32_t nblk = gridDim.x;
+    uint32_t lb = blockIdx.x;
+    if (a.xcd_swizzle) {
+        const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
+        lb = (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
+    }
+    const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
+    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
+    const int x = (int)xb * blockDim.x + threadIdx.x;
+
+    const OFF es = (OFF)sizeof(ST);
+    const OFF pst = (OFF)a.g.Ns * es;
+    const bool inx = x < nx;
+    const int xc = inx ? x : 0;
+    const OFF ci = (OFF)xc + (OFF)nx * ((OFF)y + (OFF)ny * (OFF)z);
+    const OFF cb = ci * es;
+
+    // every load of the cell is issued at once (solid cells load and drop
+    // their values), so that the flag and the populations share one latency
+    const uint8_t fl0 = *at<uint8_t>((const void *)a.flag, ci);
+    CT v[Q];
+    if constexpr (MODE == kLocal) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            v[q] = T::load(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
+    } else {
+        // source rows (y - c_y, z - c_z) and columns x - c_x, wrapped on
+        // periodic axes; beyond a non-periodic edge: not ok
+        OFF rows[3][3];
+        bool rok[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                int ys = y - (j - 1), zs = z - (k - 1);
+                bool ok = true;
+                if (ys < 0 || ys >= ny) {
+                    if (a.g.per[1]) ys = ys < 0 ? ys + ny : ys - ny; else { ok = false; ys = y; }
+                }
+                if (zs < 0 || zs >= nz) {
+                    if (a.g.per[2]) zs = zs < 0 ? zs + nz : zs - nz; else { ok = false; zs = z; }
+                }
+                rows[j][k] = (OFF)nx * ((OFF)ys + (OFF)ny * (OFF)zs) * es;
+                rok[j][k] = ok;
+            }
+        OFF xs[3];
+        bool xok[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            int xq = xc - (i - 1);
+            bool ok = true;
+            if (xq < 0 || xq >= nx) {
+                if (a.g.per[0]) xq = xq < 0 ? xq + nx : xq - nx; else { ok = false; xq = xc; }
+            }
+            xs[i] = (OFF)xq * es;
+            xok[i] = ok;
+        }
+        v[0] = T::load(at<ST>(a.src, cb));
+#define LBMEP_GATHER(q) v[q] = gather<q, ST, OFF>(a.src, pst, es, cb, rows, rok, xs, xok);
+        LBMEP_FOR_Q18(LBMEP_GATHER)
+#undef LBMEP_GATHER
+    }
+    CT fb0 = CT(0), fb1 = CT(0), fb2 = CT(0);
+    if constexpr (MODE != kReadout) {
+        if constexpr (FMODE == kForceDense) {
+            const OFF fo = ci * (OFF)sizeof(CT), fs = (OFF)a.g.Ns * (OFF)sizeof(CT);
+            fb0 = *at<CT>(a.force, fo);
+            fb1 = *at<CT>(a.force, fo + fs);
+            fb2 = *at<CT>(a.force, fo + 2 * fs);
+        } else if constexpr (FMODE == kForceCharge) {
+            const CT re = *at<CT>(a.force, ci * (OFF)sizeof(CT));
+            fb0 = re * (CT)a.E[0];
+            fb1 = re * (CT)a.E[1];
+            fb2 = re * (CT)a.E[2];
+        }
+    }
+    const uint8_t fl = inx ? fl0 : kWall;
+    const bool act = inx && !(fl & (kWall | kObst));
+    // blocked directions of NEAR cells; this load waits only for the flag
+    uint32_t mask = 0u;
+    if constexpr (MODE != kReadout)
+        mask = (act && (fl & kNear)) ? *at<uint32_t>((const void *)a.nearmask, ci * (OFF)4) : 0u;
+
+    // refill of a cell uncovered at this level: f^eq(rho0, u_s) with the
+    // surface velocity of its previous owner at its previous place (Sec. 3.2)
+    if constexpr (MODE != kLocal) {
+        if (act && (fl & kUncov)) {
+            const uint32_t po = a.owner_old[ci];
+            const double *Xp = a.Xold + 3 * (size_t)po;
+            const double *U = a.U + 3 * (size_t)po;
+            const double *W = a.W + 3 * (size_t)po;
+            const double r0 = min_image(((double)x + 0.5) - Xp[0], nx, a.g.per[0]);
+            const double r1 = min_image(((double)y + 0.5) - Xp[1], ny, a.g.per[1]);
+            const double r2 = min_image(((double)z + 0.5) - Xp[2], nz, a.g.per[2]);
+            const double u0 = U[0] + (W[1] * r2 - W[2] * r1);
+            const double u1 = U[1] + (W[2] * r0 - W[0] * r2);
+            const double u2 = U[2] + (W[0] * r1 - W[1] * r0);
+            const double uu = (u0 * u0 + u1 * u1) + u2 * u2;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
+                v[q] = (CT)T::feq(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5);
+            }
+        }
+    }
+
+    if constexpr (MODE == kReadout) {
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+        }
+        return;
+    } else {
+        // the collision runs on every lane; only the stores are restricted
+        // to fluid cells
+
+        // moments (Eq. MacroscopVel), in q order
+        CT rho = CT(0), jx = CT(0), jy = CT(0), jz = CT(0);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rho += v[q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (kCx[q] > 0) jx += v[q];
+            if (kCx[q] < 0) jx -= v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (kCy[q] > 0) jy += v[q];
+            if (kCy[q] < 0) jy -= v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (kCz[q] > 0) jz += v[q];
+            if (kCz[q] < 0) jz -= v[q];
+        }
+        // Eq. modified_velocity: u = (sum c f + f_b / 2) / rho0
+        const bool forced = FMODE != kForceNone;
+        const CT ux = forced ? jx + CT(0.5) * fb0 : jx;
+        const CT uy = forced ? jy + CT(0.5) * fb1 : jy;
+        const CT uz = forced ? jz + CT(0.5) * fb2 : jz;
+        const CT uu = (ux * ux + uy * uy) + uz * uz;
+        const CT ufb = forced ? (ux * fb0 + uy * fb1) + uz * fb2 : CT(0);
+        const CT le = (CT)a.le, lo = (CT)a.lo, ae = (CT)a.ae, ao = (CT)a.ao;
+
+        // rest population
+        {
+            const CT w0 = (CT)wq(0);
+            const CT feq_e = w0 * (rho - uu * CT(1.5));
+            CT f0 = v[0] + le * (v[0] - feq_e);
+            if (forced) f0 = f0 + ae * (w0 * (-ufb * CT(3.0)));
+            v[0] = f0;
+        }
+        collide_pair<1>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<3>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<5>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<7>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<9>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<11>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<13>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<15>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        collide_pair<17>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+
+        uint32_t pp = kNone;
+        double acc[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        if (act) {
+            // aligned store of the post-collision state
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+            if (mask) {
+#define LBMEP_BOUNCE(q) \
+    if (mask & (1u << ((q)-1))) bounce<q, ST, OFF>(a, x, y, z, v[q], pp, acc);
+                LBMEP_FOR_Q18(LBMEP_BOUNCE)
+#undef LBMEP_BOUNCE
+            }
+        }
+
+        // per-particle sums across the wavefront: one FP64 atomic per
+        // particle, component and wavefront (every lane of the wave takes part)
+        if (a.FM) {
+            unsigned long long pend = __ballot(pp != kNone);
+            while (pend) {
+                const int leader = __ffsll((unsigned long long)pend) - 1;
+                const uint32_t lp = (uint32_t)__shfl((int)pp, leader);
+                const bool mine = pp == lp;
+                double t[kAcc];
+#pragma unroll
+                for (int k = 0; k < kAcc; ++k) t[k] = mine ? acc[k] : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                    for (int k = 0; k < kAcc; ++k) t[k] += __shfl_xor(t[k], off);
+                }
+                if ((int)__lane_id() == leader) flush_particle(a.FM, lp, t);
+                if (mine) pp = kNone;
+                pend = __ballot(pp != kNone);
+            }
+        }
+    }
+}
+
+// host launcher for one storage type
+template <typename ST>
+hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, hipStream_t s) {
+    a.nxb = (a.g.nx + block_x - 1) / block_x;
+    const size_t nblocks = (size_t)a.nxb * a.g.ny * a.g.nz;
+    const dim3 block(block_x, 1, 1);
+    const dim3 grid((unsigned)nblocks, 1, 1);
+    // 32-bit byte offsets when two population arrays fit in 4 GiB (the
+    // gather addresses an opposite pair from one base)
+    const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
+#define LBMEP_LAUNCH(MD, FM, OFF) \
+    hipLaunchKernelGGL((k_sweep<ST, FM, OFF, MD>), grid, block, 0, s, a)
+#define LBMEP_BY_FORCE(MD, OFF)                                     \
+    do {                                                           \
+        if (force_mode == kForceNone) LBMEP_LAUNCH(MD, kForceNone, OFF);   \
+        else if (force_mode == kForceDense) LBMEP_LAUNCH(MD, kForceDense, OFF); \
+        else LBMEP_LAUNCH(MD, kForceCharge, OFF);                    \
+    } while (0)
+    if (small) {
+        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint32_t);
+        else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint32_t);
+        else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t);
+    } else {
+        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint64_t);
+        else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint64_t);
+        else LBMEP_LAUNCH(kReadout, kForceNone, uint64_t);
+    }
+#undef LBMEP_BY_FORCE
+#undef LBMEP_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace sweep
+}  // namespace lbmep
