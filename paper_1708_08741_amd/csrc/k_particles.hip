@@ -172,9 +172,15 @@ __global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *nearmask, const 
     classify_cell(g, x, blockIdx.y, blockIdx.z, flag, nearmask, owner, nullptr);
 }
 
+// solid bits of a box plus a one-cell halo, staged in LDS for the
+// classification (boxes up to kHaloCells cells; larger ones use the global
+// path)
+constexpr int kHaloCells = 32768;
+
 __global__ void __launch_bounds__(kBoxThreads)
     k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
                      uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old) {
+    __shared__ uint8_t solid[kHaloCells];
     const int p = blockIdx.x;
     const Grid &g = pa.g;
     const double R = pa.R[p];
@@ -195,11 +201,143 @@ __global__ void __launch_bounds__(kBoxThreads)
         }
     }
     const int n = box_size(b);
+    if (n == 0) return;
+    const int hx = b.cnt[0] + 2, hy = b.cnt[1] + 2, hz = b.cnt[2] + 2;
+    const int hn = hx * hy * hz;
+    if (hn > kHaloCells) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            int x, y, z;
+            box_cell(g, b, i, x, y, z);
+            classify_cell(g, x, y, z, flag, nearmask, owner_new, owner_old);
+        }
+        return;
+    }
+    // stage: solid = wall, obstacle of the new map, or beyond a non-periodic edge
+    const int len[3] = {g.nx, g.ny, g.nz};
+    for (int i = threadIdx.x; i < hn; i += blockDim.x) {
+        int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy, b.lo[2] - 1 + i / (hx * hy)};
+        bool out = false;
+        for (int k = 0; k < 3; ++k) {
+            if (v[k] < 0 || v[k] >= len[k]) {
+                if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
+            }
+        }
+        uint8_t sv = 1;
+        if (!out) {
+            const size_t c = cell_of(g, v[0], v[1], v[2]);
+            sv = (flag[c] & kWall) || owner_new[c] != kNone;
+        }
+        solid[i] = sv;
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ix = i % b.cnt[0], iy = (i / b.cnt[0]) % b.cnt[1], iz = i / (b.cnt[0] * b.cnt[1]);
         int x, y, z;
         box_cell(g, b, i, x, y, z);
-        classify_cell(g, x, y, z, flag, nearmask, owner_new, owner_old);
+        const size_t c = cell_of(g, x, y, z);
+        const uint8_t wall = flag[c] & kWall;
+        uint8_t f = wall;
+        uint32_t mask = 0;
+        if (!wall) {
+            if (owner_new[c] != kNone) {
+                f = kObst;
+            } else {
+                const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
+#pragma unroll
+                for (int q = 1; q < Q; ++q)
+                    if (solid[h + kCx[q] + hx * (kCy[q] + hy * kCz[q])]) mask |= 1u << (q - 1);
+                f = mask ? kNear : 0;
+                if (owner_old[c] != kNone) f |= kUncov;
+            }
+        }
+        flag[c] = f | wall;
+        nearmask[c] = mask;
     }
+}
+
+// compact list of the fluid cells with a blocked direction, in cell order,
+// by a three-kernel scan (no contended atomics): per-block counts, one block
+// scanning the counts, then each block writing its cells from its offset.  A
+// thread reads the flags of 16 consecutive cells at once (the flag array is
+// padded to a multiple of kListChunk).
+constexpr int kListCells = 16;
+constexpr int kListChunk = 256 * kListCells;
+
+__device__ __forceinline__ uint32_t near_bits(const Grid &g, const uint8_t *flag, size_t c0) {
+    const uint4 raw = *reinterpret_cast<const uint4 *>(flag + c0);
+    const uint32_t words[4] = {raw.x, raw.y, raw.z, raw.w};
+    uint32_t take = 0;  // bit k: cell c0 + k is a fluid NEAR cell
+#pragma unroll
+    for (int k = 0; k < kListCells; ++k) {
+        const uint8_t f = (uint8_t)(words[k / 4] >> (8 * (k % 4)));
+        if ((f & kNear) && !(f & (kWall | kObst)) && c0 + k < g.N) take |= 1u << k;
+    }
+    return take;
+}
+
+// exclusive prefix of `mine` over the block (256 threads); returns the
+// block total in *total
+__device__ __forceinline__ uint32_t block_scan(uint32_t mine, uint32_t *wsum, uint32_t *total) {
+    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t pre = incl - mine;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    return pre;
+}
+
+__global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag, uint32_t *bcount) {
+    __shared__ uint32_t wsum[4];
+    const size_t c0 = (size_t)blockIdx.x * kListChunk + (size_t)threadIdx.x * kListCells;
+    uint32_t total;
+    block_scan((uint32_t)__popc(near_bits(g, flag, c0)), wsum, &total);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = total;
+}
+
+// exclusive scan of the block counts in place (one block of 1024 threads,
+// each owning a contiguous run of counts); count = total
+__global__ void __launch_bounds__(1024) k_near_offsets(uint32_t *bcount, int nb, uint32_t *count) {
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
+    const int per = (nb + 1023) / 1024;
+    const int i0 = tid * per, i1 = min(nb, i0 + per);
+    uint32_t mine = 0;
+    for (int i = i0; i < i1; ++i) mine += bcount[i];
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - mine;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t v = bcount[i];
+        bcount[i] = run;
+        run += v;
+    }
+    if (tid == 1023) *count = run;
+}
+
+__global__ void __launch_bounds__(256) k_near_write(Grid g, const uint8_t *flag,
+                                                    const uint32_t *boff, uint32_t *list) {
+    __shared__ uint32_t wsum[4];
+    const size_t c0 = (size_t)blockIdx.x * kListChunk + (size_t)threadIdx.x * kListCells;
+    const uint32_t take = near_bits(g, flag, c0);
+    uint32_t total;
+    uint32_t pos = boff[blockIdx.x] + block_scan((uint32_t)__popc(take), wsum, &total);
+#pragma unroll
+    for (int k = 0; k < kListCells; ++k)
+        if (take & (1u << k)) list[pos++] = (uint32_t)(c0 + k);
 }
 
 // F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
@@ -218,6 +356,17 @@ __global__ void k_finalize_ft(int np, const double *acc, const double *X, double
 }
 
 }  // namespace
+
+int near_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kListChunk); }
+
+hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
+                            uint32_t *bcount, hipStream_t s) {
+    const int nb = near_list_blocks(g);
+    hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(256), 0, s, g, flag, bcount);
+    hipLaunchKernelGGL(k_near_offsets, dim3(1), dim3(1024), 0, s, bcount, nb, count);
+    hipLaunchKernelGGL(k_near_write, dim3(nb), dim3(256), 0, s, g, flag, bcount, list);
+    return hipGetLastError();
+}
 
 hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double *out,
                               hipStream_t s) {

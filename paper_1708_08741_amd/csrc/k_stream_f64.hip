@@ -7,8 +7,13 @@
 namespace lbmep {
 
 hipError_t launch_sweep_f64(int mode, int force_mode, const SweepArgs &a, int block_x,
-                            hipStream_t s) {
-    return sweep::launch_typed<double>(mode, force_mode, a, block_x, s);
+                            int cpt, hipStream_t s) {
+    return sweep::launch_typed<double>(mode, force_mode, a, block_x, cpt, s);
+}
+
+hipError_t launch_near_f64(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
+                           hipStream_t s) {
+    return sweep::launch_near_typed<double>(a, list, count, s);
 }
 
 }  // namespace lbmep

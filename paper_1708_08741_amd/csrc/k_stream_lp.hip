@@ -6,14 +6,24 @@
 namespace lbmep {
 
 hipError_t launch_sweep_f64(int mode, int force_mode, const SweepArgs &a, int block_x,
-                            hipStream_t s);
+                            int cpt, hipStream_t s);
 
 hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs &a, int block_x,
-                        hipStream_t s) {
-    if (precision == LBMEP_FP64) return launch_sweep_f64(mode, force_mode, a, block_x, s);
+                        int cpt, hipStream_t s) {
+    if (precision == LBMEP_FP64) return launch_sweep_f64(mode, force_mode, a, block_x, cpt, s);
     if (precision == LBMEP_FP32DEV)
-        return sweep::launch_typed<float>(mode, force_mode, a, block_x, s);
-    return sweep::launch_typed<__half>(mode, force_mode, a, block_x, s);
+        return sweep::launch_typed<float>(mode, force_mode, a, block_x, cpt, s);
+    return sweep::launch_typed<__half>(mode, force_mode, a, block_x, cpt, s);
+}
+
+hipError_t launch_near_f64(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
+                           hipStream_t s);
+
+hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
+                       const uint32_t *count, hipStream_t s) {
+    if (precision == LBMEP_FP64) return launch_near_f64(a, list, count, s);
+    if (precision == LBMEP_FP32DEV) return sweep::launch_near_typed<float>(a, list, count, s);
+    return sweep::launch_near_typed<__half>(a, list, count, s);
 }
 
 }  // namespace lbmep

@@ -60,6 +60,9 @@ struct lbmep_lattice {
     bool pmode = false;
     uint8_t *flag = nullptr;
     uint32_t *nearmask = nullptr;
+    uint32_t *near_list = nullptr;   // fluid cells with a blocked direction
+    uint32_t *near_count = nullptr;  // their number (device)
+    uint32_t *near_bcount = nullptr; // per-block counts of the list scan
     uint32_t *owner[2] = {nullptr, nullptr};
     double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
     int cur_owner = 0;
@@ -75,7 +78,8 @@ struct lbmep_lattice {
     double E[3] = {0, 0, 0};
     double *red = nullptr;
     int red_blocks = 0;
-    int block_x = 256;
+    int block_x = 128;
+    int cpt = 1;  // cells per thread of the sweep (consecutive rows)
     int xcd_swizzle = 1;
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -101,6 +105,13 @@ ParticleArgs particle_args(const lbmep_lattice *L) {
     return pa;
 }
 
+// rebuild the list of fluid cells next to a solid cell from the flags
+int rebuild_near_list(lbmep_lattice *L) {
+    HIP_TRY(launch_near_list(L->g, L->flag, L->near_list, L->near_count, L->near_bcount,
+                             L->stream));
+    return LBMEP_OK;
+}
+
 // map the particles at `level` into both owner buffers and classify the grid
 int remap_all(lbmep_lattice *L) {
     hipStream_t s = L->stream;
@@ -116,7 +127,7 @@ int remap_all(lbmep_lattice *L) {
         HIP_TRY(launch_fill_f64(L->FM, 0.0, 18 * (size_t)L->np, s));
     }
     HIP_TRY(launch_classify_all(L->g, L->flag, L->nearmask, L->np > 0 ? L->owner[0] : nullptr, s));
-    return LBMEP_OK;
+    return rebuild_near_list(L);
 }
 
 SweepArgs sweep_args(const lbmep_lattice *L) {
@@ -151,7 +162,7 @@ int materialize(lbmep_lattice *L) {
     if (!L->pmode) return LBMEP_OK;
     SweepArgs a = sweep_args(L);
     a.FM = nullptr;
-    HIP_TRY(launch_sweep(L->precision, kSweepReadout, kForceNone, a, L->block_x, L->stream));
+    HIP_TRY(launch_sweep(L->precision, kSweepReadout, kForceNone, a, L->block_x, 1, L->stream));
     L->cur = 1 - L->cur;
     L->pmode = false;
     return LBMEP_OK;
@@ -173,7 +184,7 @@ size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mod
     const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
     const size_t Ns = round_up(N, 128);
     size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
-    b += N + 4 * N;                                                    // flags + near masks
+    b += N + 4 * N + 4 * N;                                    // flags, near masks, near list
     if (n_particles > 0) b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;
     if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
     if (force_mode == kForceCharge) b += Ns * compute_bytes(cfg->precision);
@@ -220,6 +231,9 @@ int lbmep_destroy(lbmep_lattice *L) {
     hipFree(L->f[1]);
     hipFree(L->flag);
     hipFree(L->nearmask);
+    hipFree(L->near_list);
+    hipFree(L->near_count);
+    hipFree(L->near_bcount);
     hipFree(L->owner[0]);
     hipFree(L->owner[1]);
     hipFree(L->force);
@@ -262,9 +276,15 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
         return fail(LBMEP_EINVAL, "odd relaxation rate outside ]-2,0[");
     }
     // launch shape of the sweep: x-segments of block_x threads (whole
-    // wavefronts), dealt onto XCDs in contiguous runs; LBMEP_BLOCK_X and
-    // LBMEP_XCD_SWIZZLE override the defaults for launch-shape sweeps
-    L->block_x = 256;
+    // wavefronts), cpt cells per thread on consecutive rows, dealt onto XCDs
+    // in contiguous runs; LBMEP_BLOCK_X, LBMEP_CPT and LBMEP_XCD_SWIZZLE
+    // override the defaults for launch-shape sweeps
+    L->block_x = 128;
+    L->cpt = 1;
+    if (const char *e = std::getenv("LBMEP_CPT")) {
+        const int c = std::atoi(e);
+        if (c == 1 || c == 2) L->cpt = c;
+    }
     if (const char *e = std::getenv("LBMEP_BLOCK_X")) {
         const int b = std::atoi(e);
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
@@ -274,8 +294,12 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
     bool ok = true;
     ok = ok && hipMalloc(&L->f[0], Q * g.Ns * es) == hipSuccess;
     ok = ok && hipMalloc(&L->f[1], Q * g.Ns * es) == hipSuccess;
-    ok = ok && hipMalloc(&L->flag, g.N) == hipSuccess;
+    // flags padded for the 16-byte reads of the NEAR-list compaction
+    ok = ok && hipMalloc(&L->flag, round_up(g.N, 4096)) == hipSuccess;
     ok = ok && hipMalloc(&L->nearmask, 4 * g.N) == hipSuccess;
+    ok = ok && hipMalloc(&L->near_list, 4 * g.N) == hipSuccess;
+    ok = ok && hipMalloc(&L->near_count, 256) == hipSuccess;
+    ok = ok && hipMalloc(&L->near_bcount, 4 * (size_t)near_list_blocks(g) + 256) == hipSuccess;
     L->red_blocks = invariants_blocks(g);
     ok = ok && hipMalloc(&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
     if (!ok) {
@@ -283,8 +307,10 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
         return fail(LBMEP_ENOMEM, "device allocation failed");
     }
     hipStream_t s = L->stream;
-    hipError_t e = hipMemsetAsync(L->flag, 0, g.N, s);
+    hipError_t e = hipMemsetAsync(L->flag, 0, round_up(g.N, 4096), s);
     if (e == hipSuccess) e = launch_classify_all(g, L->flag, L->nearmask, nullptr, s);
+    if (e == hipSuccess)
+        e = launch_near_list(g, L->flag, L->near_list, L->near_count, L->near_bcount, s);
     const double u0[3] = {0, 0, 0};
     if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[0], 1.0, u0, s);
     if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[1], 1.0, u0, s);
@@ -541,8 +567,10 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         // gather + refill + collide + bounce-back slots (or, right after the
         // state was set, collide the stored post-stream state in place)
         HIP_TRY(launch_sweep(L->precision, L->pmode ? kSweepPull : kSweepLocal, L->force_mode, a,
-                             L->block_x, s));
+                             L->block_x, L->cpt, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
+        // bounce-back slots and momentum exchange next to solid cells
+        HIP_TRY(launch_near(L->precision, a, L->near_list, L->near_count, s));
         L->cur = 1 - L->cur;
         L->pmode = true;
         if (L->np > 0 && L->cfg.move_particles) {
@@ -554,6 +582,8 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
             HIP_TRY(launch_classify_boxes(pa, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
                                           L->nearmask, L->owner[b], L->owner[L->cur_owner], s));
             L->cur_owner = b;
+            int rc2 = rebuild_near_list(L);
+            if (rc2) return rc2;
         }
         L->level += 1;
     }

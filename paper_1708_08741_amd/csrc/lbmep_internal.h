@@ -72,7 +72,17 @@ enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2 };
 
 // kernels (host-side launchers); each returns hipError_t of the launch
 hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs &a, int block_x,
-                        hipStream_t s);
+                        int cpt, hipStream_t s);
+
+// bounce-back slots and momentum exchange of the listed NEAR cells, after a
+// sweep (count read on the device)
+hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
+                       const uint32_t *count, hipStream_t s);
+// compact list of the fluid NEAR cells in cell order; bcount is scratch of
+// near_list_blocks(g) entries
+int near_list_blocks(const Grid &g);
+hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
+                            uint32_t *bcount, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);

@@ -11,14 +11,14 @@
 // x - e_q (reads shifted by at most one element along x; this completes the
 // stream of Eq. LBMstreamStep), refills the cell if it has just been
 // uncovered, collides, and writes its 19 new values aligned to its own cell.
-// Bounce-back needs no look-up at gather time: a fluid cell next to a solid
-// cell s writes the bounced value f*_q - 2 w_q rho0 c_q.u_s / c_s^2
-// (Eq. LBMMovWall) into the slot of s that the fluid cell will gather from
-// at the next step, and adds the momentum-exchange terms (Eq.
-// LBMhydrodynForce), summed per particle in FP64 (per lane, across the
-// wavefront by shuffles, then one FP64 atomic per particle and wavefront).
-// Only the edge of a non-periodic axis is resolved at gather time, from the
-// cell coordinates.
+// Bounce-back needs no look-up at gather time: after the sweep, a second
+// kernel visits the fluid cells next to a solid cell s (a compact list, ~1%
+// of the cells) and writes the bounced value f*_q - 2 w_q rho0 c_q.u_s/c_s^2
+// (Eq. LBMMovWall) into the slot of s that the fluid cell gathers from at the
+// next step, with the momentum-exchange terms (Eq. LBMhydrodynForce) summed
+// per particle in FP64 (per lane, across the wavefront by shuffles, then one
+// FP64 atomic per particle and wavefront).  Only the edge of a non-periodic
+// axis is resolved at gather time, from the cell coordinates.
 //
 // The template is instantiated in two translation units: k_stream_f64.hip
 // (FP64, compiled without floating-point contraction so that it evaluates
@@ -145,18 +145,14 @@ enum { kPull = 0,     // gather f* of the previous level, refill, collide
        kReadout = 2   // gather and refill only: write the post-stream state
 };
 
-// Bounce-back of population q of a fluid cell whose neighbour s = x + e_q is
-// solid: the value that comes back to the cell as population opp(q) at the
-// next gather is written into slot opp(q) of s, with the momentum exchange.
-template <int q, typename ST, typename OFF>
-__device__ __forceinline__ void bounce(const SweepArgs &a, int x, int y, int z,
-                                       typename Storage<ST>::CT fq, uint32_t &pp,
-                                       double acc[kAcc]) {
-    using T = Storage<ST>;
-    using CT = typename T::CT;
-    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
-    const Grid &g = a.g;
-    int sx = x + cx, sy = y + cy, sz = z + cz;
+// neighbour s = x + e_q of a cell: its coordinates (wrapped on periodic
+// axes) and false if it lies beyond the edge of a non-periodic axis
+template <int q>
+__device__ __forceinline__ bool neighbour(const Grid &g, int x, int y, int z, int &sx, int &sy,
+                                          int &sz) {
+    sx = x + kCx[q];
+    sy = y + kCy[q];
+    sz = z + kCz[q];
     bool inside = true;
     if (sx < 0 || sx >= g.nx) {
         if (g.per[0]) sx = sx < 0 ? sx + g.nx : sx - g.nx; else inside = false;
@@ -167,15 +163,26 @@ __device__ __forceinline__ void bounce(const SweepArgs &a, int x, int y, int z,
     if (sz < 0 || sz >= g.nz) {
         if (g.per[2]) sz = sz < 0 ? sz + g.nz : sz - g.nz; else inside = false;
     }
-    // beyond a non-periodic edge: resolved by the next gather
-    if (!inside) return;
+    return inside;
+}
+
+// Bounce-back of population q of a fluid cell whose neighbour s = x + e_q is
+// solid: the value that comes back to the cell as population opp(q) at the
+// next gather is written into slot opp(q) of s; for an obstacle cell of
+// particle p (p != kNone; its centre, velocity and angular velocity given)
+// the momentum exchange is added to the lane's accumulators.
+template <int q, typename ST, typename OFF>
+__device__ __forceinline__ void bounce_apply(const SweepArgs &a, int sx, int sy, int sz,
+                                             typename Storage<ST>::CT fq, uint32_t p,
+                                             const double *X, const double *U, const double *W,
+                                             uint32_t &pp, double acc[kAcc]) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
+    const Grid &g = a.g;
     const OFF s = (OFF)sx + (OFF)g.nx * ((OFF)sy + (OFF)g.ny * (OFF)sz);
     double mw = 0.0;
-    const uint32_t p = a.owner ? a.owner[s] : kNone;
     if (p != kNone) {
-        const double *X = a.Xc + 3 * (size_t)p;
-        const double *U = a.U + 3 * (size_t)p;
-        const double *W = a.W + 3 * (size_t)p;
         // lever arm r = x_s - x_C (minimum image) and u_s = U + W x r
         const double r0 = min_image(((double)sx + 0.5) - X[0], g.nx, g.per[0]);
         const double r1 = min_image(((double)sy + 0.5) - X[1], g.ny, g.per[1]);
@@ -277,39 +284,34 @@ __device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF 
     return Storage<ST>::load(at<ST>(base, ok ? nb : own));
 }
 
+// loaded inputs of one cell
+template <typename CT>
+struct CellIn {
+    CT v[Q];
+    CT fb0, fb1, fb2;
+    uint8_t fl;
+};
+
+// issue every load of cell (x, y, z) (solid cells and cells beyond the grid
+// load in-range values and drop them), so that the flag and the populations
+// share one memory latency
 template <typename ST, int FMODE, typename OFF, int MODE>
-__global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
+__device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int z, bool valid,
+                                          CellIn<typename Storage<ST>::CT> &c) {
     using T = Storage<ST>;
     using CT = typename T::CT;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    // 1-D grid of x-segments; workgroups are dealt to the 8 XCDs round-robin,
-    // so consecutive segments (which share cache lines through the +-1
-    // gathers along x) are remapped onto the same XCD and its L2
-    const uint32_t nblk = gridDim.x;
-    uint32_t lb = blockIdx.x;
-    if (a.xcd_swizzle) {
-        const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
-        lb = (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
-    }
-    const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
-    const int y = (int)(row % (uint32_t)ny), z = (int)(row / (uint32_t)ny);
-    const int x = (int)xb * blockDim.x + threadIdx.x;
-
     const OFF es = (OFF)sizeof(ST);
     const OFF pst = (OFF)a.g.Ns * es;
-    const bool inx = x < nx;
-    const int xc = inx ? x : 0;
-    const OFF ci = (OFF)xc + (OFF)nx * ((OFF)y + (OFF)ny * (OFF)z);
+    const int xc = valid ? x : 0, yc = valid ? y : 0;
+    const OFF ci = (OFF)xc + (OFF)nx * ((OFF)yc + (OFF)ny * (OFF)z);
     const OFF cb = ci * es;
-
-    // every load of the cell is issued at once (solid cells load and drop
-    // their values), so that the flag and the populations share one latency
-    const uint8_t fl0 = *at<uint8_t>((const void *)a.flag, ci);
-    CT v[Q];
+    const uint8_t fl = *at<uint8_t>((const void *)a.flag, ci);
+    c.fl = valid ? fl : kWall;
     if constexpr (MODE == kLocal) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            v[q] = T::load(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
+            c.v[q] = T::load(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
     } else {
         // source rows (y - c_y, z - c_z) and columns x - c_x, wrapped on
         // periodic axes; beyond a non-periodic edge: not ok
@@ -319,10 +321,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                int ys = y - (j - 1), zs = z - (k - 1);
+                int ys = yc - (j - 1), zs = z - (k - 1);
                 bool ok = true;
                 if (ys < 0 || ys >= ny) {
-                    if (a.g.per[1]) ys = ys < 0 ? ys + ny : ys - ny; else { ok = false; ys = y; }
+                    if (a.g.per[1]) ys = ys < 0 ? ys + ny : ys - ny; else { ok = false; ys = yc; }
                 }
                 if (zs < 0 || zs >= nz) {
                     if (a.g.per[2]) zs = zs < 0 ? zs + nz : zs - nz; else { ok = false; zs = z; }
@@ -342,36 +344,46 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
             xs[i] = (OFF)xq * es;
             xok[i] = ok;
         }
-        v[0] = T::load(at<ST>(a.src, cb));
-#define LBMEP_GATHER(q) v[q] = gather<q, ST, OFF>(a.src, pst, es, cb, rows, rok, xs, xok);
+        c.v[0] = T::load(at<ST>(a.src, cb));
+#define LBMEP_GATHER(q) c.v[q] = gather<q, ST, OFF>(a.src, pst, es, cb, rows, rok, xs, xok);
         LBMEP_FOR_Q18(LBMEP_GATHER)
 #undef LBMEP_GATHER
     }
-    CT fb0 = CT(0), fb1 = CT(0), fb2 = CT(0);
+    c.fb0 = c.fb1 = c.fb2 = CT(0);
     if constexpr (MODE != kReadout) {
         if constexpr (FMODE == kForceDense) {
             const OFF fo = ci * (OFF)sizeof(CT), fs = (OFF)a.g.Ns * (OFF)sizeof(CT);
-            fb0 = *at<CT>(a.force, fo);
-            fb1 = *at<CT>(a.force, fo + fs);
-            fb2 = *at<CT>(a.force, fo + 2 * fs);
+            c.fb0 = *at<CT>(a.force, fo);
+            c.fb1 = *at<CT>(a.force, fo + fs);
+            c.fb2 = *at<CT>(a.force, fo + 2 * fs);
         } else if constexpr (FMODE == kForceCharge) {
             const CT re = *at<CT>(a.force, ci * (OFF)sizeof(CT));
-            fb0 = re * (CT)a.E[0];
-            fb1 = re * (CT)a.E[1];
-            fb2 = re * (CT)a.E[2];
+            c.fb0 = re * (CT)a.E[0];
+            c.fb1 = re * (CT)a.E[1];
+            c.fb2 = re * (CT)a.E[2];
         }
     }
-    const uint8_t fl = inx ? fl0 : kWall;
-    const bool act = inx && !(fl & (kWall | kObst));
-    // blocked directions of NEAR cells; this load waits only for the flag
-    uint32_t mask = 0u;
-    if constexpr (MODE != kReadout)
-        mask = (act && (fl & kNear)) ? *at<uint32_t>((const void *)a.nearmask, ci * (OFF)4) : 0u;
+}
+
+// refill (if uncovered), collide, store, bounce-back slots and momentum
+// exchange of one loaded cell
+template <typename ST, int FMODE, typename OFF, int MODE>
+__device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, int z,
+                                            CellIn<typename Storage<ST>::CT> &c) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const OFF es = (OFF)sizeof(ST);
+    const OFF pst = (OFF)a.g.Ns * es;
+    const bool act = !(c.fl & (kWall | kObst));
+    const OFF ci = act ? (OFF)x + (OFF)nx * ((OFF)y + (OFF)ny * (OFF)z) : (OFF)0;
+    const OFF cb = ci * es;
+    CT(&v)[Q] = c.v;
 
     // refill of a cell uncovered at this level: f^eq(rho0, u_s) with the
     // surface velocity of its previous owner at its previous place (Sec. 3.2)
     if constexpr (MODE != kLocal) {
-        if (act && (fl & kUncov)) {
+        if (act && (c.fl & kUncov)) {
             const uint32_t po = a.owner_old[ci];
             const double *Xp = a.Xold + 3 * (size_t)po;
             const double *U = a.U + 3 * (size_t)po;
@@ -397,10 +409,10 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
             for (int q = 0; q < Q; ++q)
                 T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
         }
-        return;
     } else {
         // the collision runs on every lane; only the stores are restricted
         // to fluid cells
+        const CT fb0 = c.fb0, fb1 = c.fb1, fb2 = c.fb2;
 
         // moments (Eq. MacroscopVel), in q order
         CT rho = CT(0), jx = CT(0), jy = CT(0), jz = CT(0);
@@ -448,25 +460,122 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
         collide_pair<15>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
         collide_pair<17>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
 
-        uint32_t pp = kNone;
-        double acc[kAcc];
-#pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
         if (act) {
             // aligned store of the post-collision state
 #pragma unroll
             for (int q = 0; q < Q; ++q)
                 T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
-            if (mask) {
-#define LBMEP_BOUNCE(q) \
-    if (mask & (1u << ((q)-1))) bounce<q, ST, OFF>(a, x, y, z, v[q], pp, acc);
-                LBMEP_FOR_Q18(LBMEP_BOUNCE)
-#undef LBMEP_BOUNCE
-            }
         }
+    }
+}
 
-        // per-particle sums across the wavefront: one FP64 atomic per
-        // particle, component and wavefront (every lane of the wave takes part)
+// CPT cells per thread, on consecutive rows y (their loads are all issued
+// before the first collision, for more memory-level parallelism per wave)
+template <typename ST, int FMODE, typename OFF, int MODE, int CPT>
+__global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    const int nx = a.g.nx, ny = a.g.ny;
+    // 1-D grid of x-segments; workgroups are dealt to the 8 XCDs round-robin,
+    // so consecutive segments (which share cache lines through the +-1
+    // gathers along x) are remapped onto the same XCD and its L2
+    const uint32_t nblk = gridDim.x;
+    uint32_t lb = blockIdx.x;
+    if (a.xcd_swizzle) {
+        const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
+        lb = (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
+    }
+    const uint32_t nyb = (uint32_t)((ny + CPT - 1) / CPT);
+    const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
+    const int y0 = (int)(row % nyb) * CPT, z = (int)(row / nyb);
+    const int x = (int)xb * blockDim.x + threadIdx.x;
+
+    CellIn<CT> c[CPT];
+#pragma unroll
+    for (int r = 0; r < CPT; ++r)
+        load_cell<ST, FMODE, OFF, MODE>(a, x, y0 + r, z, x < nx && y0 + r < ny, c[r]);
+#pragma unroll
+    for (int r = 0; r < CPT; ++r) finish_cell<ST, FMODE, OFF, MODE>(a, x, y0 + r, z, c[r]);
+}
+
+// Bounce-back slots and momentum exchange of the cells next to a solid cell
+// (the list built after every re-mapping), run after the sweep on the
+// post-collision state it wrote.  Each wavefront takes 64 consecutive list
+// entries (neighbouring cells, mostly of one particle) at a time and sums
+// their momentum exchange per particle across the wavefront before one
+// FP64 atomic per particle and component.  The count is read on the device,
+// so the launch needs no host synchronisation.
+template <typename ST, typename OFF>
+__global__ void __launch_bounds__(256) k_near(SweepArgs a, const uint32_t *list,
+                                              const uint32_t *count) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    const uint32_t n = *count;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const OFF pst = (OFF)a.g.Ns * (OFF)sizeof(ST);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        uint32_t pp = kNone;
+        double acc[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+        const uint32_t i = base + threadIdx.x;
+        if (i < n) {
+            const uint32_t c = list[i];
+            const int x = (int)(c % (uint32_t)nx);
+            const int y = (int)((c / (uint32_t)nx) % (uint32_t)ny);
+            const int z = (int)(c / ((uint32_t)nx * (uint32_t)ny));
+            const uint32_t mask = a.nearmask[c];
+            const OFF cb = (OFF)c * (OFF)sizeof(ST);
+            // phase 1: every load of the blocked links at once (the cell's
+            // post-collision value and the owner of the solid neighbour)
+            CT fq[Q];
+            uint32_t own[Q];
+#define LBMEP_NEAR_LOAD(q)                                                                     \
+    fq[q] = CT(0);                                                                             \
+    own[q] = kNone;                                                                            \
+    if (mask & (1u << ((q)-1))) {                                                              \
+        int sx, sy, sz;                                                                        \
+        const bool in = neighbour<q>(a.g, x, y, z, sx, sy, sz);                                \
+        fq[q] = T::load(at<ST>(static_cast<const char *>(a.dst) + (size_t)(q) * pst, cb));     \
+        if (in && a.owner)                                                                     \
+            own[q] = a.owner[(size_t)sx + (size_t)nx * ((size_t)sy + (size_t)ny * (size_t)sz)]; \
+    }
+            LBMEP_FOR_Q18(LBMEP_NEAR_LOAD)
+#undef LBMEP_NEAR_LOAD
+            // phase 2: the particle of the cell's first particle link (most
+            // cells touch one particle)
+            uint32_t p0 = kNone;
+#pragma unroll
+            for (int q = Q - 1; q >= 1; --q)
+                if (own[q] != kNone) p0 = own[q];
+            double X0[3] = {0, 0, 0}, U0[3] = {0, 0, 0}, W0[3] = {0, 0, 0};
+            if (p0 != kNone) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    X0[k] = a.Xc[3 * (size_t)p0 + k];
+                    U0[k] = a.U[3 * (size_t)p0 + k];
+                    W0[k] = a.W[3 * (size_t)p0 + k];
+                }
+            }
+            // phase 3: bounce-back slots and momentum exchange
+#define LBMEP_NEAR_APPLY(q)                                                                     \
+    if (mask & (1u << ((q)-1))) {                                                               \
+        int sx, sy, sz;                                                                         \
+        if (neighbour<q>(a.g, x, y, z, sx, sy, sz)) {                                           \
+            const uint32_t p = own[q];                                                          \
+            if (p == p0 || p == kNone) {                                                        \
+                bounce_apply<q, ST, OFF>(a, sx, sy, sz, fq[q], p, X0, U0, W0, pp, acc);         \
+            } else {                                                                            \
+                bounce_apply<q, ST, OFF>(a, sx, sy, sz, fq[q], p, a.Xc + 3 * (size_t)p,         \
+                                         a.U + 3 * (size_t)p, a.W + 3 * (size_t)p, pp, acc);    \
+            }                                                                                   \
+        }                                                                                       \
+    }
+            LBMEP_FOR_Q18(LBMEP_NEAR_APPLY)
+#undef LBMEP_NEAR_APPLY
+        }
+        // per-particle sums across the wavefront (every lane takes part)
         if (a.FM) {
             unsigned long long pend = __ballot(pp != kNone);
             while (pend) {
@@ -489,33 +598,58 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
     }
 }
 
-// host launcher for one storage type
 template <typename ST>
-hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, hipStream_t s) {
-    a.nxb = (a.g.nx + block_x - 1) / block_x;
-    const size_t nblocks = (size_t)a.nxb * a.g.ny * a.g.nz;
-    const dim3 block(block_x, 1, 1);
-    const dim3 grid((unsigned)nblocks, 1, 1);
+hipError_t launch_near_typed(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
+                             hipStream_t s) {
+    // enough wavefronts for a list of a few per cent of the cells in one pass
+    size_t blocks = (a.g.N / 32 + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    if (blocks < 1) blocks = 1;
+    const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
+    if (small)
+        hipLaunchKernelGGL((k_near<ST, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                           list, count);
+    else
+        hipLaunchKernelGGL((k_near<ST, uint64_t>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                           list, count);
+    return hipGetLastError();
+}
+
+// host launcher for one storage type; cpt = cells per thread (1 or 2)
+template <typename ST>
+hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int cpt,
+                        hipStream_t s) {
     // 32-bit byte offsets when two population arrays fit in 4 GiB (the
     // gather addresses an opposite pair from one base)
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
-#define LBMEP_LAUNCH(MD, FM, OFF) \
-    hipLaunchKernelGGL((k_sweep<ST, FM, OFF, MD>), grid, block, 0, s, a)
-#define LBMEP_BY_FORCE(MD, OFF)                                     \
-    do {                                                           \
-        if (force_mode == kForceNone) LBMEP_LAUNCH(MD, kForceNone, OFF);   \
-        else if (force_mode == kForceDense) LBMEP_LAUNCH(MD, kForceDense, OFF); \
-        else LBMEP_LAUNCH(MD, kForceCharge, OFF);                    \
+    if (!small || mode == kReadout) cpt = 1;
+    a.nxb = (a.g.nx + block_x - 1) / block_x;
+    const size_t nblocks = (size_t)a.nxb * ((a.g.ny + cpt - 1) / cpt) * a.g.nz;
+    const dim3 block(block_x, 1, 1);
+    const dim3 grid((unsigned)nblocks, 1, 1);
+#define LBMEP_LAUNCH(MD, FM, OFF, C) \
+    hipLaunchKernelGGL((k_sweep<ST, FM, OFF, MD, C>), grid, block, 0, s, a)
+#define LBMEP_BY_FORCE(MD, OFF, C)                                           \
+    do {                                                                     \
+        if (force_mode == kForceNone) LBMEP_LAUNCH(MD, kForceNone, OFF, C);      \
+        else if (force_mode == kForceDense) LBMEP_LAUNCH(MD, kForceDense, OFF, C); \
+        else LBMEP_LAUNCH(MD, kForceCharge, OFF, C);                           \
+    } while (0)
+#define LBMEP_BY_CPT(MD)                                    \
+    do {                                                    \
+        if (cpt == 2) LBMEP_BY_FORCE(MD, uint32_t, 2);      \
+        else LBMEP_BY_FORCE(MD, uint32_t, 1);               \
     } while (0)
     if (small) {
-        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint32_t);
-        else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint32_t);
-        else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t);
+        if (mode == kPull) LBMEP_BY_CPT(kPull);
+        else if (mode == kLocal) LBMEP_BY_CPT(kLocal);
+        else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t, 1);
     } else {
-        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint64_t);
-        else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint64_t);
-        else LBMEP_LAUNCH(kReadout, kForceNone, uint64_t);
+        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint64_t, 1);
+        else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint64_t, 1);
+        else LBMEP_LAUNCH(kReadout, kForceNone, uint64_t, 1);
     }
+#undef LBMEP_BY_CPT
 #undef LBMEP_BY_FORCE
 #undef LBMEP_LAUNCH
     return hipGetLastError();
