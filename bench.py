@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"fp64": 304, "fp32dev": 152, "fp16dev": 76}
 DTYPE = {"fp64": "f64", "fp32dev": "f32", "fp16dev": "f32"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_512.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "k_stream.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "sweep_impl.h")
 
 
 def log(*a):
@@ -95,25 +95,55 @@ def run_gpu(wl, precision, steps, warmup):
 
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on a bounded sample: the 128^3 sub-run of the same
-    workload shape (64 moving R=4 spheres, same force construction)."""
+    workload shape (64 moving R=4 spheres, same force construction).
+    Returns the baseline record and the oracle state (for the error check)."""
     from oracle import oracle as O
     from paper_1708_08741_amd import workloads as W
 
     wl = W.suspension_subrun(precision="fp64")
     o = O.from_workload(wl)
-    o.step(1)
     t0 = time.perf_counter()
-    o.step(2)
-    per = (time.perf_counter() - t0) / 2
+    o.step(3)
+    per = (time.perf_counter() - t0) / 3
     n = max(2, int(target_s / per))
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
     cells = wl.ncells
-    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"128^3 periodic sub-run, 64 moving R=4 spheres, charge force, FP64, "
-                      f"{n} steps ({dt:.1f} s)"}
+    rec = {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
+           "kind": "oracle",
+           "sample": f"128^3 periodic sub-run, 64 moving R=4 spheres, charge force, FP64, "
+                     f"{n} steps timed ({dt:.1f} s) after 3 untimed"}
+    return rec, wl, o, n + 3
+
+
+def precision_errors(wl, o, steps):
+    """Errors of the GPU FP64 / FP32-dev / FP16-dev runs of the oracle's
+    sub-run after the same number of steps (relative to max |u| over fluid
+    cells and max |F_p|; |drho| absolute; torque relative to max|F| R)."""
+    from oracle import oracle as O
+    from paper_1708_08741_amd import lbmep as lb
+
+    rho_o, u_o = o.macro()
+    F_o, M_o = o.ft()
+    fl, _ = o.map()
+    fluid = (fl == O.FLUID) | (fl == O.NEAR)
+    umax = np.abs(u_o[:, fluid]).max()
+    sF = np.linalg.norm(F_o, axis=1).max()
+    out = {"steps": steps, "workload": "128^3 sub-run (64 moving R=4 spheres)"}
+    for p in ("fp64", "fp32dev", "fp16dev"):
+        g = lb.from_workload(wl, precision=p)
+        g.step(steps)
+        rho_g, u_g = g.macro()
+        F_g, M_g = g.ft()
+        out[p] = {
+            "u_rel": float(np.abs(u_g - u_o)[:, fluid].max() / umax),
+            "rho_abs": float(np.abs(rho_g - rho_o)[fluid].max()),
+            "F_rel": float(np.linalg.norm(F_g - F_o, axis=1).max() / sF),
+            "M_rel": float(np.linalg.norm(M_g - M_o, axis=1).max() / (sF * 4.0)),
+        }
+        g.close()
+    return out
 
 
 def main():
@@ -174,9 +204,13 @@ def main():
         log(f"[bench] {v}: {variants[v]}")
 
     cpu = None
+    errors = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
-        cpu = cpu_baseline()
+        cpu, swl, o, n_o = cpu_baseline()
+        log("[bench] GPU precisions against the oracle sample")
+        errors = precision_errors(swl, o, n_o)
+        log(f"[bench] errors: {errors}")
 
     traffic = traffic_for(args.precision)
     out = {
@@ -208,6 +242,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "variants": variants,
+        "errors_vs_fp64_oracle": errors,
     }
     print(json.dumps(out), flush=True)
 

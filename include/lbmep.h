@@ -56,7 +56,8 @@ enum {
 enum {
     LBMEP_FP64 = 0,    /* f_q stored as FP64 (FP64 collide)                  */
     LBMEP_FP32DEV = 1, /* f_q - w_q stored as FP32 (FP32 collide)            */
-    LBMEP_FP16DEV = 2  /* (f_q - w_q) * 2^24 stored as FP16 (FP32 collide)   */
+    LBMEP_FP16DEV = 2  /* (f_q - w_q) * 2^22 stored as FP16 (FP32 collide);
+                          deviations up to 1.56e-2, i.e. |u| <~ 0.04 */
 };
 
 /* cell flags: FLUID/WALL are user input; OBST/NEAR are produced by mapping */
@@ -133,17 +134,19 @@ int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]);
  * the D3Q19 order q=0 rest, 1..6 = +x,-x,+y,-y,+z,-z, 7..18 = (+x+y),
  * (-x-y), (+x-y), (-x+y), (+x+z), (-x-z), (+x-z), (-x+z), (+y+z), (-y-z),
  * (+y-z), (-y+z).  Reduced-precision lattices convert to / from their
- * storage (rounding).  The state is post-stream, pre-collide. */
+ * storage (rounding).  The state is post-stream, pre-collide.  After a step,
+ * solid cells read as the rest state (walls) or f^eq(rho0, u_s) of their
+ * particle (obstacle cells); their values never enter the fluid update. */
 int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device);
 int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device);
 
 /* Advance nsteps time steps (nsteps >= 0), asynchronously on the stream.
- * One step: fused collide (Eq. LBMcollideStep + force) and push-stream
- * (Eq. LBMstreamStep) over all fluid cells, bounce-back at walls and
- * velocity bounce-back at obstacle cells (Eq. LBMMovWall) with the
- * momentum exchange summed per particle in FP64 (Eq. LBMhydrodynForce); then,
- * with moving particles, the kinematics and re-mapping for the next time
- * level and the refill of uncovered cells with f^eq(rho0, u_s).  Errors:
+ * One step: fused collide (Eq. LBMcollideStep + force) and stream
+ * (Eq. LBMstreamStep) of all fluid cells, bounce-back at walls and velocity
+ * bounce-back at obstacle cells (Eq. LBMMovWall) with the momentum exchange
+ * summed per particle in FP64 (Eq. LBMhydrodynForce); then, with moving
+ * particles, the kinematics and re-mapping for the next time level; cells
+ * uncovered there are refilled with f^eq(rho0, u_s) (Sec. 3.2).  Errors:
  * EINVAL (nsteps < 0), EDEVICE. */
 int lbmep_step(lbmep_lattice *L, int32_t nsteps);
 

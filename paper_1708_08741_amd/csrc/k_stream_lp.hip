@@ -1,6 +1,6 @@
 // k_stream_lp.hip -- FP32 and FP16 deviation-storage instantiations of the
-// fused sweep (sweep_impl.h), FP32 arithmetic with FMA contraction, and the
-// precision dispatch of the sweep launch.
+// fused sweep (sweep_impl.h), FP32 arithmetic, and the precision dispatch of
+// the sweep launch.
 #include "sweep_impl.h"
 
 namespace lbmep {

@@ -32,9 +32,13 @@ constexpr uint8_t kWall = 1, kObst = 2, kNear = 4, kUncov = 8;
 // owner value of a cell no particle covers
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// FP16 deviation storage scale: stored h = (f - w) * 2^24
-constexpr float kHalfScale = 16777216.0f;
-constexpr float kHalfInvScale = 1.0f / 16777216.0f;
+// FP16 deviation storage scale: stored h = (f - w) * 2^22.  Deviations
+// between 1.5e-11 (smallest normal FP16 / 2^22) and 1.56e-2 (largest FP16 /
+// 2^22) keep 11 significant bits; the largest deviations of a flow are the
+// moving-wall terms 2 w_q c_q.u_s / c_s^2 (|u_s| / 3 on axis links), so
+// velocities up to ~0.04 lattice units fit.
+constexpr float kHalfScale = 4194304.0f;
+constexpr float kHalfInvScale = 1.0f / 4194304.0f;
 
 // force modes of the sweep
 enum ForceMode { kForceNone = 0, kForceDense = 1, kForceCharge = 2 };

@@ -20,10 +20,11 @@
 // FP64 atomic per particle and wavefront).  Only the edge of a non-periodic
 // axis is resolved at gather time, from the cell coordinates.
 //
-// The template is instantiated in two translation units: k_stream_f64.hip
-// (FP64, compiled without floating-point contraction so that it evaluates
-// exactly the operation sequence of a plain CPU implementation) and
-// k_stream_lp.hip (FP32 / FP16 deviation storage, FMA contraction allowed).
+// The template is instantiated in two translation units, k_stream_f64.hip
+// (FP64) and k_stream_lp.hip (FP32 / FP16 deviation storage), both compiled
+// without floating-point contraction: the FP64 sweep evaluates exactly the
+// operation sequence of a plain CPU implementation, and every sweep mode
+// rounds identically.
 // Byte offsets are 32-bit (global loads/stores with a scalar base) whenever a
 // population array is smaller than 4 GiB.
 #pragma once
@@ -57,7 +58,7 @@ struct Storage<float> {
     static __device__ __forceinline__ float feq(int q, double d) { return (float)(wq(q) * d); }
 };
 
-// FP16: deviations scaled by 2^24
+// FP16: deviations scaled by 2^22
 template <>
 struct Storage<__half> {
     using CT = float;
@@ -404,6 +405,31 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
     }
 
     if constexpr (MODE == kReadout) {
+        // solid cells get defined values: the rest state at walls and
+        // f^eq(rho0, u_s) of the owning particle at obstacle cells
+        if (!act && (c.fl & (kWall | kObst)) && x < nx && y < ny) {
+            const OFF si = (OFF)x + (OFF)nx * ((OFF)y + (OFF)ny * (OFF)z);
+            double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+            if (!(c.fl & kWall)) {
+                const uint32_t po = a.owner[si];
+                const double *Xp = a.Xc + 3 * (size_t)po;
+                const double *U = a.U + 3 * (size_t)po;
+                const double *W = a.W + 3 * (size_t)po;
+                const double r0 = min_image(((double)x + 0.5) - Xp[0], nx, a.g.per[0]);
+                const double r1 = min_image(((double)y + 0.5) - Xp[1], ny, a.g.per[1]);
+                const double r2 = min_image(((double)z + 0.5) - Xp[2], nz, a.g.per[2]);
+                u0 = U[0] + (W[1] * r2 - W[2] * r1);
+                u1 = U[1] + (W[2] * r0 - W[0] * r2);
+                u2 = U[2] + (W[0] * r1 - W[1] * r0);
+            }
+            const double uu = (u0 * u0 + u1 * u1) + u2 * u2;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
+                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, si * es),
+                         (CT)T::feq(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5));
+            }
+        }
         if (act) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
