@@ -157,6 +157,9 @@ def main():
                     help="other storage precisions timed on the same workload ('' = none)")
     ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (the reference "
+                         "kernel that scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this "
@@ -175,6 +178,19 @@ def main():
     wl = W.periodic_suspension(n=n, count=count, R=4.0, seed=3, steps=args.steps,
                                precision=args.precision)
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
+
+    if args.copy_calibration > 0:
+        # an elementwise copy (y = x + 1) of 1 GiB float32 arrays: 1 GiB
+        # read and 1 GiB written per launch
+        nbytes = int(args.copy_calibration * 2 ** 30) // 16 * 16
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read and written per launch")
+        del src, dst
+        torch.cuda.empty_cache()
 
     res = run_gpu(wl, args.precision, args.steps, args.warmup)
     cells = wl.ncells
@@ -237,7 +253,7 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_stream_collide", "kernel_ms": round(res["kernel_ms"], 4),
+            "kernel": "k_sweep", "kernel_ms": round(res["kernel_ms"], 4),
             "bytes_per_cell": bpc,
         },
         "cpu_baseline": cpu,
