@@ -146,6 +146,100 @@ def precision_errors(wl, o, steps):
     return out
 
 
+def _serving_inputs(r):
+    """Request r of the serving mix with its charge density (FP32)."""
+    from paper_1708_08741_amd import workloads as W
+    q = W.serving_request(r)
+    q["rho_e"] = W.gaussian_shell_rho_e(q["shape"], q["periodic"], q["X"], q["R"]).astype(
+        np.float32)
+    return q
+
+
+def serving_bench(n_load, n_sat, load, budget_gib, slots, chunk):
+    """Continuous batching of the serving mix (FP32-dev, moving spheres,
+    charge force): saturated throughput with a full queue of n_sat requests,
+    then n_load requests arriving as a Poisson process at `load` times that
+    throughput; latency = completion - arrival (server clock)."""
+    import multiprocessing as mp
+
+    from paper_1708_08741_amd import lbmep as lb
+
+    total = n_sat + n_load
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        reqs = pool.map(_serving_inputs, range(total))
+    log(f"[serve] {total} requests generated in {time.perf_counter() - t0:.1f} s")
+    dropped = sum(q["requested"] - len(q["R"]) for q in reqs)
+
+    def work(q):
+        nx, ny, nz = q["shape"]
+        return nx * ny * nz * q["steps"]
+
+    def submit(srv, q):
+        return srv.submit(q["shape"], X=q["X"], R=q["R"], U=q["U"], W=q["W"], steps=q["steps"],
+                          rho_e=q["rho_e"], E=q["E"], periodic=q["periodic"],
+                          precision=lb.FP32DEV, moving=True)
+
+    srv = lb.Server(hbm_budget=int(budget_gib * 2 ** 30), max_slots=slots, chunk_steps=chunk)
+    # saturation: everything queued at once
+    sat = reqs[:n_sat]
+    t_a = srv.now()
+    ids = [submit(srv, q) for q in sat]
+    srv.wait_all(ids, timeout=900)
+    t_sat = srv.now() - t_a
+    for i in ids:
+        srv.release(i)
+    sat_rate = sum(work(q) for q in sat) / t_sat
+    log(f"[serve] saturated: {n_sat} requests in {t_sat:.2f} s = {sat_rate / 1e6:.0f} MLUPS")
+
+    # Poisson arrivals at `load` of the saturated rate
+    mix = reqs[n_sat:]
+    mean_work = float(np.mean([work(q) for q in reqs]))
+    lam = load * sat_rate / mean_work
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(mix)))
+    start = srv.now()
+    ids = []
+    k = 0
+    done = set()
+    max_res = 0
+    while len(done) < len(mix):
+        now = srv.now() - start
+        while k < len(mix) and arrivals[k] <= now:
+            ids.append(submit(srv, mix[k]))
+            k += 1
+        for i in srv.poll():
+            done.add(i)
+        max_res = max(max_res, srv.stats()["resident"])
+        if srv.now() - start > 1800:
+            raise TimeoutError("serving run did not finish")
+        time.sleep(2e-4)
+    lat, t_end = [], 0.0
+    for i in ids:
+        _, _, _, t = srv.result(i)
+        lat.append(t[2] - t[0])
+        t_end = max(t_end, t[2])
+    span = t_end - start
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    cells_work = sum(work(q) for q in mix)
+    return {
+        "requests": len(mix), "saturation_requests": n_sat,
+        "throughput_req_per_s": round(len(mix) / span, 3),
+        "aggregate_MLUPS": round(cells_work / span / 1e6, 1),
+        "saturated_MLUPS": round(sat_rate / 1e6, 1),
+        "offered_load": load, "arrival_rate_per_s": round(lam, 4),
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+        "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+        "latency_max_s": round(float(lat.max()), 3),
+        "max_resident": max_res, "slots": slots, "chunk_steps": chunk,
+        "hbm_budget_GiB": budget_gib, "packed_launches": st["packed_launches"],
+        "spheres_dropped_by_rsa": int(dropped),
+        "mix": "edges {64,96,128,192,256}^3, 1-200 spheres R 3-8, 500-5000 steps, FP32-dev",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +251,14 @@ def main():
                     help="other storage precisions timed on the same workload ('' = none)")
     ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the Poisson-arrival serving run (0 = no serving leg)")
+    ap.add_argument("--serve-sat-requests", type=int, default=24,
+                    help="requests of the saturated-throughput serving run")
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-chunk", type=int, default=20)
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (the reference "
                          "kernel that scales HBM byte counters)")
@@ -228,6 +330,13 @@ def main():
         errors = precision_errors(swl, o, n_o)
         log(f"[bench] errors: {errors}")
 
+    serving = None
+    if args.serve_requests > 0:
+        log("[bench] serving leg")
+        serving = serving_bench(args.serve_requests, args.serve_sat_requests, args.serve_load,
+                                args.serve_budget_gib, args.serve_slots, args.serve_chunk)
+        log(f"[bench] serving: {serving}")
+
     traffic = traffic_for(args.precision)
     out = {
         "metric": METRIC,
@@ -259,6 +368,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "errors_vs_fp64_oracle": errors,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -194,6 +194,105 @@ int lbmep_load_state(lbmep_lattice *L, const char *path);
  * (used for admission by footprint). */
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charge, size_t *bytes);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of independent simulations on one GPU.
+ *
+ * Each request is a complete simulation (grid, walls, particles, charge force,
+ * number of steps) starting from the rest equilibrium.  Requests are queued on
+ * submit and admitted first-in first-out while a slot is free and the sum of
+ * the resident requests' device footprints stays within the budget; all of
+ * their device memory comes from one arena of `hbm_budget` bytes allocated at
+ * creation.  Resident simulations advance together: every kernel of a time
+ * step is one packed launch over all of them, enqueued in chunks of
+ * `chunk_steps` steps; requests that arrive meanwhile join at the next chunk.
+ * Each request computes exactly what a lattice created with the same
+ * configuration and stepped `steps` times computes (Sec. 3.1-3.2, as for
+ * lbmep_step): its fields are bitwise identical alone or in any mix; forces
+ * and torques differ only by the order of FP64 atomic additions.
+ *
+ * All lbmep_server_* calls on one server must come from one thread at a time.
+ * Progress (completion, admission, enqueueing) happens inside
+ * lbmep_server_poll, which never waits for the GPU except for the set-up of a
+ * newly admitted request (which overlaps the resident requests' steps).
+ * ------------------------------------------------------------------------ */
+
+typedef struct lbmep_server lbmep_server; /* opaque; owns its arena and streams */
+
+typedef struct {
+    int32_t device;       /* HIP device ordinal */
+    int32_t max_slots;    /* resident simulations at once, 1..64 */
+    int32_t chunk_steps;  /* steps enqueued per chunk, >= 1 */
+    int32_t max_queue;    /* queued requests before submit returns LBMEP_EBUSY */
+    size_t hbm_budget;    /* bytes of the device arena, >= 1 MiB */
+} lbmep_server_config;
+
+typedef struct {
+    lbmep_config cfg;        /* grid, periodic, nu, magic, precision, move_particles;
+                                device / stream are the server's; reserved = 0 */
+    const uint8_t *flags;    /* N user flags (LBMEP_FLUID / LBMEP_WALL) or NULL */
+    int32_t n;               /* particles, >= 0 */
+    int32_t steps;           /* time steps, >= 1 */
+    const double *X, *R, *U; /* 3n, n, 3n (as lbmep_set_particles) */
+    const double *W;         /* 3n angular velocities or NULL */
+    const void *rho_e;       /* N charge densities (force rho_e E) or NULL */
+    int32_t rho_e_dtype;     /* LBMEP_DTYPE_F64 / LBMEP_DTYPE_F32 */
+    int32_t keep_fields;     /* 1: keep rho, u of the final state */
+    double E[3];             /* uniform field (used with rho_e) */
+} lbmep_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, failed;
+    int32_t queued, resident;
+    uint64_t chunks, steps, packed_launches;
+    double cell_updates;     /* lattice cells advanced (all cells of every step) */
+    size_t bytes_reserved;   /* footprints of the resident requests */
+    size_t bytes_in_use;     /* arena bytes allocated */
+    size_t budget;           /* arena size */
+} lbmep_server_stats;
+
+/* Create a server: allocates the arena and two streams (default priority)
+ * on cfg->device.  Errors: EINVAL (ranges), ENOMEM (arena), EDEVICE. */
+int lbmep_server_create(const lbmep_server_config *cfg, lbmep_server **out);
+
+/* Wait for the server's device work, free everything (also requests that are
+ * queued or resident).  NULL is OK. */
+int lbmep_server_destroy(lbmep_server *srv);
+
+/* Device bytes a request holds while resident (its admission footprint). */
+int lbmep_server_request_footprint(const lbmep_request *req, size_t *bytes);
+
+/* Queue a request; every input array is copied before the call returns.
+ * *id identifies it from then on.  Errors: EINVAL (bad configuration or
+ * arrays, steps < 1, footprint above the budget, a grid whose two population
+ * arrays reach 4 GiB), EBUSY (queue full). */
+int lbmep_server_submit(lbmep_server *srv, const lbmep_request *req, uint64_t *id);
+
+/* Make progress (retire finished requests, admit queued ones, enqueue the
+ * next chunk) and return up to cap ids of requests finished since the last
+ * poll (including requests whose set-up failed).  Errors: EINVAL, EDEVICE. */
+int lbmep_server_poll(lbmep_server *srv, uint64_t *done_ids, int32_t cap, int32_t *ndone);
+
+/* Results of a finished request: F[3n], M[3n] of its last step (either may be
+ * NULL), inv[4] = FP64 mass and momentum sums of its final state (as
+ * lbmep_get_invariants), times[3] = submit, admission and completion times in
+ * seconds of the server's clock (may be NULL).  Errors: ESTATE (not finished
+ * or unknown id); the request's own error code if its set-up failed. */
+int lbmep_server_result(lbmep_server *srv, uint64_t id, double *F, double *M, double inv[4],
+                        double times[3]);
+
+/* Final fields rho[N], u[3N] (as lbmep_get_macro) of a request submitted with
+ * keep_fields = 1.  Errors: ESTATE. */
+int lbmep_server_fields(lbmep_server *srv, uint64_t id, double *rho, double *u);
+
+/* Forget a finished request's results. */
+int lbmep_server_release(lbmep_server *srv, uint64_t id);
+
+/* Counters of the server. */
+int lbmep_server_get_stats(lbmep_server *srv, lbmep_server_stats *out);
+
+/* The server's clock (seconds since creation). */
+int lbmep_server_now(lbmep_server *srv, double *t);
+
 #ifdef __cplusplus
 }
 #endif

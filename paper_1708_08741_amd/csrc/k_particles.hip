@@ -78,25 +78,16 @@ __device__ __forceinline__ size_t cell_of(const Grid &g, int x, int y, int z) {
     return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
 }
 
+__device__ __forceinline__ double position(const ParticleArgs &pa, int p, int k, int64_t level);
+
 __global__ void k_positions(ParticleArgs pa, int64_t level, double *X) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= pa.np) return;
-    const int len[3] = {pa.g.nx, pa.g.ny, pa.g.nz};
-    for (int k = 0; k < 3; ++k) {
-        double x = pa.X0[3 * p + k];
-        // prescribed kinematics X(n) = X(0) + n U, evaluated in this form
-        if (pa.moving) x = pa.X0[3 * p + k] + (double)level * pa.U[3 * p + k];
-        if (pa.g.per[k]) {
-            x = x - (double)len[k] * floor(x / (double)len[k]);
-            if (x >= (double)len[k]) x -= (double)len[k];
-        }
-        X[3 * p + k] = x;
-    }
+    for (int k = 0; k < 3; ++k) X[3 * p + k] = position(pa, p, k, level);
 }
 
-__global__ void __launch_bounds__(kBoxThreads)
-    k_map_clear(ParticleArgs pa, const double *X, uint32_t *owner) {
-    const int p = blockIdx.x;
+__device__ __forceinline__ void map_clear_particle(const ParticleArgs &pa, int p,
+                                                   const double *X, uint32_t *owner) {
     const Box b = ball_box(pa.g, X + 3 * p, pa.R[p]);
     const int n = box_size(b);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -107,8 +98,40 @@ __global__ void __launch_bounds__(kBoxThreads)
 }
 
 __global__ void __launch_bounds__(kBoxThreads)
-    k_map_set(ParticleArgs pa, const double *X, const uint8_t *flag, uint32_t *owner) {
-    const int p = blockIdx.x;
+    k_map_clear(ParticleArgs pa, const double *X, uint32_t *owner) {
+    map_clear_particle(pa, blockIdx.x, X, owner);
+}
+
+// X_p(level) of the prescribed kinematics, component k, wrapped into [0, L)
+// on periodic axes
+__device__ __forceinline__ double position(const ParticleArgs &pa, int p, int k, int64_t level) {
+    const int len[3] = {pa.g.nx, pa.g.ny, pa.g.nz};
+    double x = pa.X0[3 * p + k];
+    // prescribed kinematics X(n) = X(0) + n U, evaluated in this form
+    if (pa.moving) x = pa.X0[3 * p + k] + (double)level * pa.U[3 * p + k];
+    if (pa.g.per[k]) {
+        x = x - (double)len[k] * floor(x / (double)len[k]);
+        if (x >= (double)len[k]) x -= (double)len[k];
+    }
+    return x;
+}
+
+// one particle of the step's kinematics: clear its cells of the map that the
+// buffer held (two levels back), then store its position at `level`
+__device__ __forceinline__ void advance_particle(const ParticleArgs &pa, int p, int64_t level,
+                                                 double *X, uint32_t *owner) {
+    map_clear_particle(pa, p, X, owner);
+    __syncthreads();  // every thread has read the old position
+    if (threadIdx.x < 3) X[3 * p + threadIdx.x] = position(pa, p, threadIdx.x, level);
+}
+
+__global__ void __launch_bounds__(kBoxThreads)
+    k_advance(ParticleArgs pa, int64_t level, double *X, uint32_t *owner) {
+    advance_particle(pa, blockIdx.x, level, X, owner);
+}
+
+__device__ __forceinline__ void map_set_particle(const ParticleArgs &pa, int p, const double *X,
+                                                 const uint8_t *flag, uint32_t *owner) {
     const double *Xp = X + 3 * p;
     const double R = pa.R[p];
     const Box b = ball_box(pa.g, Xp, R);
@@ -124,6 +147,11 @@ __global__ void __launch_bounds__(kBoxThreads)
         const double d2 = (r0 * r0 + r1 * r1) + r2 * r2;
         if (d2 <= R * R) atomicMin(&owner[c], (uint32_t)p);
     }
+}
+
+__global__ void __launch_bounds__(kBoxThreads)
+    k_map_set(ParticleArgs pa, const double *X, const uint8_t *flag, uint32_t *owner) {
+    map_set_particle(pa, blockIdx.x, X, flag, owner);
 }
 
 // flag and blocked-direction mask of one cell from the wall bits and the map;
@@ -177,11 +205,11 @@ __global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *nearmask, const 
 // path)
 constexpr int kHaloCells = 32768;
 
-__global__ void __launch_bounds__(kBoxThreads)
-    k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
-                     uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old) {
-    __shared__ uint8_t solid[kHaloCells];
-    const int p = blockIdx.x;
+__device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
+                                                  const double *Xold, const double *Xnew,
+                                                  uint8_t *flag, uint32_t *nearmask,
+                                                  const uint32_t *owner_new,
+                                                  const uint32_t *owner_old, uint8_t *solid) {
     const Grid &g = pa.g;
     const double R = pa.R[p];
     Box b;
@@ -255,6 +283,13 @@ __global__ void __launch_bounds__(kBoxThreads)
     }
 }
 
+__global__ void __launch_bounds__(kBoxThreads)
+    k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
+                     uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old) {
+    __shared__ uint8_t solid[kHaloCells];
+    classify_particle(pa, blockIdx.x, Xold, Xnew, flag, nearmask, owner_new, owner_old, solid);
+}
+
 // compact list of the fluid cells with a blocked direction, in cell order,
 // by a three-kernel scan (no contended atomics): per-block counts, one block
 // scanning the counts, then each block writing its cells from its offset.  A
@@ -293,17 +328,22 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t mine, uint32_t *wsum, ui
     return pre;
 }
 
-__global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag, uint32_t *bcount) {
+__device__ __forceinline__ void near_count_block(const Grid &g, const uint8_t *flag,
+                                                 uint32_t *bcount, uint32_t blk) {
     __shared__ uint32_t wsum[4];
-    const size_t c0 = (size_t)blockIdx.x * kListChunk + (size_t)threadIdx.x * kListCells;
+    const size_t c0 = (size_t)blk * kListChunk + (size_t)threadIdx.x * kListCells;
     uint32_t total;
     block_scan((uint32_t)__popc(near_bits(g, flag, c0)), wsum, &total);
-    if (threadIdx.x == 0) bcount[blockIdx.x] = total;
+    if (threadIdx.x == 0) bcount[blk] = total;
+}
+
+__global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag, uint32_t *bcount) {
+    near_count_block(g, flag, bcount, blockIdx.x);
 }
 
 // exclusive scan of the block counts in place (one block of 1024 threads,
 // each owning a contiguous run of counts); count = total
-__global__ void __launch_bounds__(1024) k_near_offsets(uint32_t *bcount, int nb, uint32_t *count) {
+__device__ __forceinline__ void near_offsets_block(uint32_t *bcount, int nb, uint32_t *count) {
     __shared__ uint32_t wsum[16];
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
     const int per = (nb + 1023) / 1024;
@@ -328,16 +368,75 @@ __global__ void __launch_bounds__(1024) k_near_offsets(uint32_t *bcount, int nb,
     if (tid == 1023) *count = run;
 }
 
-__global__ void __launch_bounds__(256) k_near_write(Grid g, const uint8_t *flag,
-                                                    const uint32_t *boff, uint32_t *list) {
+__global__ void __launch_bounds__(1024) k_near_offsets(uint32_t *bcount, int nb, uint32_t *count) {
+    near_offsets_block(bcount, nb, count);
+}
+
+__device__ __forceinline__ void near_write_block(const Grid &g, const uint8_t *flag,
+                                                 const uint32_t *boff, uint32_t *list,
+                                                 uint32_t blk) {
     __shared__ uint32_t wsum[4];
-    const size_t c0 = (size_t)blockIdx.x * kListChunk + (size_t)threadIdx.x * kListCells;
+    const size_t c0 = (size_t)blk * kListChunk + (size_t)threadIdx.x * kListCells;
     const uint32_t take = near_bits(g, flag, c0);
     uint32_t total;
-    uint32_t pos = boff[blockIdx.x] + block_scan((uint32_t)__popc(take), wsum, &total);
+    uint32_t pos = boff[blk] + block_scan((uint32_t)__popc(take), wsum, &total);
 #pragma unroll
     for (int k = 0; k < kListCells; ++k)
         if (take & (1u << k)) list[pos++] = (uint32_t)(c0 + k);
+}
+
+__global__ void __launch_bounds__(256) k_near_write(Grid g, const uint8_t *flag,
+                                                    const uint32_t *boff, uint32_t *list) {
+    near_write_block(g, flag, boff, list, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// packed forms: one dispatch for several lattices (entry by binary search);
+// the particle kernels use the map / position buffer the step writes,
+// b = 1 - cur_owner
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBoxThreads) k_advance_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    const ParticleArgs pa = d->pa;
+    const int b = 1 - (int)(t.state[e] >> 1);
+    advance_particle(pa, (int)(blockIdx.x - t.start[e]), t.level[e], d->Xheld[b], d->owner[b]);
+}
+
+__global__ void __launch_bounds__(kBoxThreads) k_map_set_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    const ParticleArgs pa = d->pa;
+    const int b = 1 - (int)(t.state[e] >> 1);
+    map_set_particle(pa, (int)(blockIdx.x - t.start[e]), d->Xheld[b], d->flag, d->owner[b]);
+}
+
+__global__ void __launch_bounds__(kBoxThreads) k_classify_packed(PackTable t) {
+    __shared__ uint8_t solid[kHaloCells];
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    const ParticleArgs pa = d->pa;
+    const int co = (int)(t.state[e] >> 1), b = 1 - co;
+    classify_particle(pa, (int)(blockIdx.x - t.start[e]), d->Xheld[co], d->Xheld[b], d->flag,
+                      d->nearmask, d->owner[b], d->owner[co], solid);
+}
+
+__global__ void __launch_bounds__(256) k_near_count_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    near_count_block(d->pa.g, d->flag, d->near_bcount, blockIdx.x - t.start[e]);
+}
+
+__global__ void __launch_bounds__(1024) k_near_offsets_packed(PackTable t) {
+    const LatticeDev *d = t.d[blockIdx.x];
+    near_offsets_block(d->near_bcount, d->list_blocks, d->near_count);
+}
+
+__global__ void __launch_bounds__(256) k_near_write_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    near_write_block(d->pa.g, d->flag, d->near_bcount, d->near_list, blockIdx.x - t.start[e]);
 }
 
 // F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
@@ -373,6 +472,43 @@ hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize_ft, dim3((np + 127) / 128), dim3(128), 0, s, np, acc, X, out);
     return hipGetLastError();
+}
+
+hipError_t launch_advance(const ParticleArgs &pa, int64_t level, double *X, uint32_t *owner,
+                          hipStream_t s) {
+    if (pa.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, level, X, owner);
+    return hipGetLastError();
+}
+
+namespace {
+template <typename K>
+hipError_t launch_packed(K kernel, const PackTable &t, int threads, hipStream_t s) {
+    const uint32_t total = t.start[t.n];
+    if (t.n == 0 || total == 0) return hipSuccess;
+    hipLaunchKernelGGL(kernel, dim3(total), dim3(threads), 0, s, t);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_advance_packed(const PackTable &t, hipStream_t s) {
+    return launch_packed(k_advance_packed, t, kBoxThreads, s);
+}
+
+hipError_t launch_map_set_packed(const PackTable &t, hipStream_t s) {
+    return launch_packed(k_map_set_packed, t, kBoxThreads, s);
+}
+
+hipError_t launch_classify_packed(const PackTable &t, hipStream_t s) {
+    return launch_packed(k_classify_packed, t, kBoxThreads, s);
+}
+
+hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_one,
+                                   hipStream_t s) {
+    hipError_t e = launch_packed(k_near_count_packed, t_cells, 256, s);
+    if (e == hipSuccess) e = launch_packed(k_near_offsets_packed, t_one, 1024, s);
+    if (e == hipSuccess) e = launch_packed(k_near_write_packed, t_cells, 256, s);
+    return e;
 }
 
 hipError_t launch_positions(const ParticleArgs &pa, int64_t level, double *X, hipStream_t s) {

@@ -16,4 +16,14 @@ hipError_t launch_near_f64(const SweepArgs &a, const uint32_t *list, const uint3
     return sweep::launch_near_typed<double>(a, list, count, s);
 }
 
+hipError_t launch_sweep_packed_f64(int force_mode, const PackTable &t, hipStream_t s) {
+    return sweep::launch_sweep_packed_typed<double>(force_mode, t, s);
+}
+
+hipError_t launch_near_packed_f64(const PackTable &t, hipStream_t s) {
+    return sweep::launch_near_packed_typed<double>(t, s);
+}
+
+int near_blocks(const Grid &g) { return sweep::near_blocks_for(g.N); }
+
 }  // namespace lbmep

@@ -26,4 +26,19 @@ hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
     return sweep::launch_near_typed<__half>(a, list, count, s);
 }
 
+hipError_t launch_sweep_packed_f64(int force_mode, const PackTable &t, hipStream_t s);
+hipError_t launch_near_packed_f64(const PackTable &t, hipStream_t s);
+
+hipError_t launch_sweep_packed(int precision, int force_mode, const PackTable &t, hipStream_t s) {
+    if (precision == LBMEP_FP64) return launch_sweep_packed_f64(force_mode, t, s);
+    if (precision == LBMEP_FP32DEV) return sweep::launch_sweep_packed_typed<float>(force_mode, t, s);
+    return sweep::launch_sweep_packed_typed<__half>(force_mode, t, s);
+}
+
+hipError_t launch_near_packed(int precision, const PackTable &t, hipStream_t s) {
+    if (precision == LBMEP_FP64) return launch_near_packed_f64(t, s);
+    if (precision == LBMEP_FP32DEV) return sweep::launch_near_packed_typed<float>(t, s);
+    return sweep::launch_near_packed_typed<__half>(t, s);
+}
+
 }  // namespace lbmep

@@ -1,0 +1,105 @@
+// lattice.h -- the lattice object behind the C ABI and the host-runtime
+// helpers shared by the single-lattice API (lbmep_api.hip) and the request
+// server (lbmep_server.hip).  Not part of the public ABI.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "lbmep_internal.h"
+
+namespace lbmep {
+
+// source of a lattice's device memory: hipMalloc / hipFree, or a server's
+// pre-allocated arena (whose release never synchronises the device)
+struct DevHeap {
+    virtual ~DevHeap() = default;
+    virtual void *alloc(size_t bytes) = 0;  // nullptr when it does not fit
+    virtual void release(void *p) = 0;
+};
+
+}  // namespace lbmep
+
+struct lbmep_lattice {
+    lbmep_config cfg{};
+    lbmep::Grid g{};
+    hipStream_t stream = nullptr;
+    int precision = 0;
+    double tau = 0, le = 0, lo = 0, ae = 0, ao = 0;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    // false: f[cur] holds the post-stream state of the current level (as set
+    // by init / set_pdfs / load); true: f[cur] holds the post-collision
+    // populations of the previous level plus the bounce-back slots, from
+    // which the sweep (or a read-out) gathers the current state
+    bool pmode = false;
+    uint8_t *flag = nullptr;
+    uint32_t *nearmask = nullptr;
+    uint32_t *near_list = nullptr;   // fluid cells with a blocked direction
+    uint32_t *near_count = nullptr;  // their number (device)
+    uint32_t *near_bcount = nullptr; // per-block counts of the list scan
+    uint32_t *owner[2] = {nullptr, nullptr};
+    double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
+    int cur_owner = 0;
+    int ft_buf = 0;  // owner/position buffer of the last streamed time level
+    int np = 0;
+    size_t np_cap = 0;
+    double *X0 = nullptr, *R = nullptr, *U = nullptr, *W = nullptr, *FM = nullptr;
+    std::vector<double> hX0, hR, hU, hW;  // host copy of the particle table
+    int64_t level = 0;
+    int force_mode = lbmep::kForceNone;
+    void *force = nullptr;
+    size_t force_bytes = 0;
+    double E[3] = {0, 0, 0};
+    double *red = nullptr;
+    int red_blocks = 0;
+    int block_x = 128;
+    int cpt = 1;  // cells per thread of the sweep (consecutive rows)
+    int xcd_swizzle = 1;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    // source of device memory (nullptr: hipMalloc / hipFree)
+    lbmep::DevHeap *heap = nullptr;
+};
+
+namespace lbmep {
+namespace rt {
+
+// records the message of the last failure of the calling thread
+int fail(int code, const std::string &msg);
+
+#define LBMEP_HIP_TRY(expr)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::lbmep::rt::fail(LBMEP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t round_up(size_t n, size_t m);
+size_t storage_bytes(int precision);
+size_t compute_bytes(int precision);
+bool finite_all(const double *p, size_t n);
+int check_config(const lbmep_config *cfg);
+// device bytes of a lattice (what lbmep_footprint reports)
+size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mode);
+
+hipError_t dev_alloc(lbmep_lattice *L, void **p, size_t bytes);
+void dev_free(lbmep_lattice *L, void *p);
+
+// create / destroy with a given memory source; destroy without sync assumes
+// the caller knows that no work of the lattice is pending
+int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out);
+int destroy_lattice(lbmep_lattice *L, bool sync);
+
+ParticleArgs particle_args(const lbmep_lattice *L);
+// sweep arguments for a given (cur, cur_owner) state
+SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int cur_owner);
+SweepArgs sweep_args(const lbmep_lattice *L);
+// gather the post-stream state into the spare grid (after a step)
+int materialize(lbmep_lattice *L);
+// host bookkeeping of one completed step (the grid / map buffers flip)
+void advance_state(lbmep_lattice *L);
+
+}  // namespace rt
+}  // namespace lbmep

@@ -9,25 +9,24 @@
 #include <string>
 #include <vector>
 
-#include "lbmep_internal.h"
+#include "lattice.h"
 
 using namespace lbmep;
+using namespace lbmep::rt;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace lbmep {
+namespace rt {
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
     return code;
 }
 
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(LBMEP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+#define HIP_TRY(expr) LBMEP_HIP_TRY(expr)
 
 size_t round_up(size_t n, size_t m) { return (n + m - 1) / m * m; }
 
@@ -43,50 +42,26 @@ bool finite_all(const double *p, size_t n) {
     return true;
 }
 
-}  // namespace
+hipError_t dev_alloc(lbmep_lattice *L, void **p, size_t bytes) {
+    if (!L->heap) return hipMalloc(p, bytes);
+    *p = L->heap->alloc(bytes);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
 
-struct lbmep_lattice {
-    lbmep_config cfg{};
-    Grid g{};
-    hipStream_t stream = nullptr;
-    int precision = 0;
-    double tau = 0, le = 0, lo = 0, ae = 0, ao = 0;
-    void *f[2] = {nullptr, nullptr};
-    int cur = 0;
-    // false: f[cur] holds the post-stream state of the current level (as set
-    // by init / set_pdfs / load); true: f[cur] holds the post-collision
-    // populations of the previous level plus the bounce-back slots, from
-    // which the sweep (or a read-out) gathers the current state
-    bool pmode = false;
-    uint8_t *flag = nullptr;
-    uint32_t *nearmask = nullptr;
-    uint32_t *near_list = nullptr;   // fluid cells with a blocked direction
-    uint32_t *near_count = nullptr;  // their number (device)
-    uint32_t *near_bcount = nullptr; // per-block counts of the list scan
-    uint32_t *owner[2] = {nullptr, nullptr};
-    double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
-    int cur_owner = 0;
-    int ft_buf = 0;  // owner/position buffer of the last streamed time level
-    int np = 0;
-    size_t np_cap = 0;
-    double *X0 = nullptr, *R = nullptr, *U = nullptr, *W = nullptr, *FM = nullptr;
-    std::vector<double> hX0, hR, hU, hW;  // host copy of the particle table
-    int64_t level = 0;
-    int force_mode = kForceNone;
-    void *force = nullptr;
-    size_t force_bytes = 0;
-    double E[3] = {0, 0, 0};
-    double *red = nullptr;
-    int red_blocks = 0;
-    int block_x = 128;
-    int cpt = 1;  // cells per thread of the sweep (consecutive rows)
-    int xcd_swizzle = 1;
-    bool timing = false;
-    std::vector<hipEvent_t> ev;
-    size_t ev_used = 0;
-};
+void dev_free(lbmep_lattice *L, void *p) {
+    if (!p) return;
+    if (!L->heap)
+        hipFree(p);
+    else
+        L->heap->release(p);
+}
 
-namespace {
+}  // namespace rt
+}  // namespace lbmep
+
+
+namespace lbmep {
+namespace rt {
 
 int set_device(lbmep_lattice *L) {
     HIP_TRY(hipSetDevice(L->cfg.device));
@@ -130,18 +105,18 @@ int remap_all(lbmep_lattice *L) {
     return rebuild_near_list(L);
 }
 
-SweepArgs sweep_args(const lbmep_lattice *L) {
+SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     SweepArgs a;
     a.g = L->g;
-    a.src = L->f[L->cur];
-    a.dst = L->f[1 - L->cur];
+    a.src = L->f[cur];
+    a.dst = L->f[1 - cur];
     a.flag = L->flag;
     a.nearmask = L->nearmask;
     const bool parts = L->np > 0;
-    a.owner = parts ? L->owner[L->cur_owner] : nullptr;
-    a.owner_old = parts ? L->owner[1 - L->cur_owner] : nullptr;
-    a.Xc = parts ? L->Xheld[L->cur_owner] : nullptr;
-    a.Xold = parts ? L->Xheld[1 - L->cur_owner] : nullptr;
+    a.owner = parts ? L->owner[co] : nullptr;
+    a.owner_old = parts ? L->owner[1 - co] : nullptr;
+    a.Xc = parts ? L->Xheld[co] : nullptr;
+    a.Xold = parts ? L->Xheld[1 - co] : nullptr;
     a.U = L->U;
     a.W = L->W;
     a.FM = parts ? L->FM : nullptr;
@@ -154,6 +129,16 @@ SweepArgs sweep_args(const lbmep_lattice *L) {
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
     return a;
+}
+
+SweepArgs sweep_args(const lbmep_lattice *L) { return sweep_args_state(L, L->cur, L->cur_owner); }
+
+void advance_state(lbmep_lattice *L) {
+    L->ft_buf = L->cur_owner;
+    L->cur = 1 - L->cur;
+    L->pmode = true;
+    if (L->np > 0 && L->cfg.move_particles) L->cur_owner = 1 - L->cur_owner;
+    L->level += 1;
 }
 
 // bring the grid to the post-stream state of the current level (gather from
@@ -169,13 +154,13 @@ int materialize(lbmep_lattice *L) {
 }
 
 void free_particles(lbmep_lattice *L) {
-    hipFree(L->X0);
-    hipFree(L->R);
-    hipFree(L->U);
-    hipFree(L->W);
-    hipFree(L->FM);
-    hipFree(L->Xheld[0]);
-    hipFree(L->Xheld[1]);
+    dev_free(L, L->X0);
+    dev_free(L, L->R);
+    dev_free(L, L->U);
+    dev_free(L, L->W);
+    dev_free(L, L->FM);
+    dev_free(L, L->Xheld[0]);
+    dev_free(L, L->Xheld[1]);
     L->X0 = L->R = L->U = L->W = L->FM = L->Xheld[0] = L->Xheld[1] = nullptr;
     L->np_cap = 0;
 }
@@ -209,7 +194,8 @@ int check_config(const lbmep_config *cfg) {
     return LBMEP_OK;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace lbmep
 
 extern "C" {
 
@@ -223,28 +209,39 @@ int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charg
     return LBMEP_OK;
 }
 
-int lbmep_destroy(lbmep_lattice *L) {
+int lbmep_destroy(lbmep_lattice *L) { return destroy_lattice(L, true); }
+
+int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
+    return create_lattice(cfg, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace lbmep {
+namespace rt {
+
+int destroy_lattice(lbmep_lattice *L, bool sync) {
     if (!L) return LBMEP_OK;
     hipSetDevice(L->cfg.device);
-    hipStreamSynchronize(L->stream);
-    hipFree(L->f[0]);
-    hipFree(L->f[1]);
-    hipFree(L->flag);
-    hipFree(L->nearmask);
-    hipFree(L->near_list);
-    hipFree(L->near_count);
-    hipFree(L->near_bcount);
-    hipFree(L->owner[0]);
-    hipFree(L->owner[1]);
-    hipFree(L->force);
-    hipFree(L->red);
+    if (sync) hipStreamSynchronize(L->stream);
+    dev_free(L, L->f[0]);
+    dev_free(L, L->f[1]);
+    dev_free(L, L->flag);
+    dev_free(L, L->nearmask);
+    dev_free(L, L->near_list);
+    dev_free(L, L->near_count);
+    dev_free(L, L->near_bcount);
+    dev_free(L, L->owner[0]);
+    dev_free(L, L->owner[1]);
+    dev_free(L, L->force);
+    dev_free(L, L->red);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
     delete L;
     return LBMEP_OK;
 }
 
-int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
+int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) {
     int rc = check_config(cfg);
     if (rc) return rc;
     if (!out) return fail(LBMEP_EINVAL, "null output pointer");
@@ -254,6 +251,7 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
     if (cfg->device < 0 || cfg->device >= ndev) return fail(LBMEP_EINVAL, "no such device");
     HIP_TRY(hipSetDevice(cfg->device));
     lbmep_lattice *L = new lbmep_lattice();
+    L->heap = heap;
     L->cfg = *cfg;
     L->stream = (hipStream_t)cfg->stream;
     L->precision = cfg->precision;
@@ -292,18 +290,18 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
     if (const char *e = std::getenv("LBMEP_XCD_SWIZZLE")) L->xcd_swizzle = std::atoi(e) != 0;
     const size_t es = storage_bytes(L->precision);
     bool ok = true;
-    ok = ok && hipMalloc(&L->f[0], Q * g.Ns * es) == hipSuccess;
-    ok = ok && hipMalloc(&L->f[1], Q * g.Ns * es) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->f[0], Q * g.Ns * es) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->f[1], Q * g.Ns * es) == hipSuccess;
     // flags padded for the 16-byte reads of the NEAR-list compaction
-    ok = ok && hipMalloc(&L->flag, round_up(g.N, 4096)) == hipSuccess;
-    ok = ok && hipMalloc(&L->nearmask, 4 * g.N) == hipSuccess;
-    ok = ok && hipMalloc(&L->near_list, 4 * g.N) == hipSuccess;
-    ok = ok && hipMalloc(&L->near_count, 256) == hipSuccess;
-    ok = ok && hipMalloc(&L->near_bcount, 4 * (size_t)near_list_blocks(g) + 256) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->flag, round_up(g.N, 4096)) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->nearmask, 4 * g.N) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->near_list, 4 * g.N) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->near_count, 256) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->near_bcount, 4 * (size_t)near_list_blocks(g) + 256) == hipSuccess;
     L->red_blocks = invariants_blocks(g);
-    ok = ok && hipMalloc(&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
     if (!ok) {
-        lbmep_destroy(L);
+        destroy_lattice(L, true);
         return fail(LBMEP_ENOMEM, "device allocation failed");
     }
     hipStream_t s = L->stream;
@@ -316,12 +314,17 @@ int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
     if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[1], 1.0, u0, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        lbmep_destroy(L);
+        destroy_lattice(L, true);
         return fail(LBMEP_EDEVICE, std::string("initialisation: ") + hipGetErrorString(e));
     }
     *out = L;
     return LBMEP_OK;
 }
+
+}  // namespace rt
+}  // namespace lbmep
+
+extern "C" {
 
 int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device) {
     if (!L || !flags) return fail(LBMEP_EINVAL, "null argument");
@@ -338,17 +341,17 @@ int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device) {
     uint8_t *tmp = nullptr;
     const uint8_t *src = flags;
     if (!on_device) {
-        HIP_TRY(hipMalloc(&tmp, N));
+        HIP_TRY(dev_alloc(L, (void **)&tmp, N));
         hipError_t e = hipMemcpyAsync(tmp, flags, N, hipMemcpyHostToDevice, L->stream);
         if (e != hipSuccess) {
-            hipFree(tmp);
+            dev_free(L, tmp);
             return fail(LBMEP_EDEVICE, hipGetErrorString(e));
         }
         src = tmp;
     }
     hipError_t e = launch_import_flags(L->g, src, L->flag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    hipFree(tmp);
+    dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     return remap_all(L);
 }
@@ -377,17 +380,17 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(L->stream));
     if (n > 0 && !L->owner[0]) {
-        if (hipMalloc(&L->owner[0], 4 * L->g.N) != hipSuccess ||
-            hipMalloc(&L->owner[1], 4 * L->g.N) != hipSuccess)
+        if (dev_alloc(L, (void **)&L->owner[0], 4 * L->g.N) != hipSuccess ||
+            dev_alloc(L, (void **)&L->owner[1], 4 * L->g.N) != hipSuccess)
             return fail(LBMEP_ENOMEM, "owner field allocation failed");
     }
     if ((size_t)n > L->np_cap) {
         free_particles(L);
         const size_t b = 3 * (size_t)n * sizeof(double);
-        bool ok = hipMalloc(&L->X0, b) == hipSuccess && hipMalloc(&L->U, b) == hipSuccess &&
-                  hipMalloc(&L->W, b) == hipSuccess && hipMalloc(&L->R, b / 3) == hipSuccess &&
-                  hipMalloc(&L->FM, 6 * b) == hipSuccess && hipMalloc(&L->Xheld[0], b) == hipSuccess &&
-                  hipMalloc(&L->Xheld[1], b) == hipSuccess;
+        bool ok = dev_alloc(L, (void **)&L->X0, b) == hipSuccess && dev_alloc(L, (void **)&L->U, b) == hipSuccess &&
+                  dev_alloc(L, (void **)&L->W, b) == hipSuccess && dev_alloc(L, (void **)&L->R, b / 3) == hipSuccess &&
+                  dev_alloc(L, (void **)&L->FM, 6 * b) == hipSuccess && dev_alloc(L, (void **)&L->Xheld[0], b) == hipSuccess &&
+                  dev_alloc(L, (void **)&L->Xheld[1], b) == hipSuccess;
         if (!ok) {
             free_particles(L);
             L->np = 0;
@@ -436,10 +439,10 @@ static int set_force_common(lbmep_lattice *L, const void *in, int dtype, int on_
     HIP_TRY(hipStreamSynchronize(L->stream));
     const size_t need = (size_t)ncomp * Ns * compute_bytes(L->precision);
     if (L->force_bytes < need) {
-        hipFree(L->force);
+        dev_free(L, L->force);
         L->force = nullptr;
         L->force_bytes = 0;
-        if (hipMalloc(&L->force, need) != hipSuccess) {
+        if (dev_alloc(L, (void **)&L->force, need) != hipSuccess) {
             L->force_mode = kForceNone;
             return fail(LBMEP_ENOMEM, "force field allocation failed");
         }
@@ -448,10 +451,10 @@ static int set_force_common(lbmep_lattice *L, const void *in, int dtype, int on_
     const void *src = in;
     void *tmp = nullptr;
     if (!on_device) {
-        HIP_TRY(hipMalloc(&tmp, (size_t)ncomp * N * ib));
+        HIP_TRY(dev_alloc(L, (void **)&tmp, (size_t)ncomp * N * ib));
         hipError_t e = hipMemcpy(tmp, in, (size_t)ncomp * N * ib, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            hipFree(tmp);
+            dev_free(L, tmp);
             return fail(LBMEP_EDEVICE, hipGetErrorString(e));
         }
         src = tmp;
@@ -459,7 +462,7 @@ static int set_force_common(lbmep_lattice *L, const void *in, int dtype, int on_
     hipError_t e =
         launch_convert_force(L->precision, src, dtype, L->force, N, N, Ns, ncomp, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    hipFree(tmp);
+    dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     L->force_mode = mode;
     return LBMEP_OK;
@@ -501,7 +504,7 @@ int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device) {
     const size_t N = L->g.N;
     if (!on_device && !finite_all(f, Q * N)) return fail(LBMEP_EINVAL, "non-finite populations");
     double *tmp = nullptr;
-    if (!on_device) HIP_TRY(hipMalloc(&tmp, N * sizeof(double)));
+    if (!on_device) HIP_TRY(dev_alloc(L, (void **)&tmp, N * sizeof(double)));
     hipError_t e = hipSuccess;
     for (int q = 0; q < Q && e == hipSuccess; ++q) {
         const double *src = f + (size_t)q * N;
@@ -512,7 +515,7 @@ int lbmep_set_pdfs(lbmep_lattice *L, const double *f, int on_device) {
         if (e == hipSuccess) e = launch_pdfs_from_f64(L->precision, L->g, q, src, L->f[L->cur], L->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     }
-    hipFree(tmp);
+    dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     L->pmode = false;
     return LBMEP_OK;
@@ -526,7 +529,7 @@ int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device) {
     if (rc) return rc;
     const size_t N = L->g.N;
     double *tmp = nullptr;
-    if (!on_device) HIP_TRY(hipMalloc(&tmp, N * sizeof(double)));
+    if (!on_device) HIP_TRY(dev_alloc(L, (void **)&tmp, N * sizeof(double)));
     hipError_t e = hipSuccess;
     for (int q = 0; q < Q && e == hipSuccess; ++q) {
         double *dst = on_device ? f + (size_t)q * N : tmp;
@@ -536,7 +539,7 @@ int lbmep_get_pdfs(lbmep_lattice *L, double *f, int on_device) {
                                L->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     }
-    hipFree(tmp);
+    dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     return LBMEP_OK;
 }
@@ -550,7 +553,6 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     const ParticleArgs pa = particle_args(L);
     for (int32_t it = 0; it < nsteps; ++it) {
         if (L->np > 0) HIP_TRY(launch_fill_f64(L->FM, 0.0, 12 * (size_t)L->np, s));
-        L->ft_buf = L->cur_owner;
         const SweepArgs a = sweep_args(L);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {
@@ -571,21 +573,18 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
         // bounce-back slots and momentum exchange next to solid cells
         HIP_TRY(launch_near(L->precision, a, L->near_list, L->near_count, s));
-        L->cur = 1 - L->cur;
-        L->pmode = true;
         if (L->np > 0 && L->cfg.move_particles) {
             // kinematics, re-mapping and classification of the next level
             const int b = 1 - L->cur_owner;
-            HIP_TRY(launch_map_clear(pa, L->Xheld[b], L->owner[b], s));
-            HIP_TRY(launch_positions(pa, L->level + 1, L->Xheld[b], s));
+            // clear the map buffer b held two levels back, move to level + 1
+            HIP_TRY(launch_advance(pa, L->level + 1, L->Xheld[b], L->owner[b], s));
             HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
             HIP_TRY(launch_classify_boxes(pa, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
                                           L->nearmask, L->owner[b], L->owner[L->cur_owner], s));
-            L->cur_owner = b;
             int rc2 = rebuild_near_list(L);
             if (rc2) return rc2;
         }
-        L->level += 1;
+        advance_state(L);
     }
     return LBMEP_OK;
 }
@@ -607,9 +606,9 @@ int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device) {
     const size_t N = L->g.N;
     double *drho = rho, *du = u;
     if (!on_device) {
-        if (hipMalloc(&drho, N * sizeof(double)) != hipSuccess) return fail(LBMEP_ENOMEM, "temp");
-        if (hipMalloc(&du, 3 * N * sizeof(double)) != hipSuccess) {
-            hipFree(drho);
+        if (dev_alloc(L, (void **)&drho, N * sizeof(double)) != hipSuccess) return fail(LBMEP_ENOMEM, "temp");
+        if (dev_alloc(L, (void **)&du, 3 * N * sizeof(double)) != hipSuccess) {
+            dev_free(L, drho);
             return fail(LBMEP_ENOMEM, "temp");
         }
     }
@@ -624,8 +623,8 @@ int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device) {
     }
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (!on_device) {
-        hipFree(drho);
-        hipFree(du);
+        dev_free(L, drho);
+        dev_free(L, du);
     }
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     return LBMEP_OK;
@@ -658,11 +657,11 @@ int lbmep_get_map(lbmep_lattice *L, uint8_t *flags, int32_t *owner) {
     const size_t N = L->g.N;
     if (flags) {
         uint8_t *tmp = nullptr;
-        HIP_TRY(hipMalloc(&tmp, N));
+        HIP_TRY(dev_alloc(L, (void **)&tmp, N));
         hipError_t e = launch_export_flags(L->g, L->flag, tmp, L->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(flags, tmp, N, hipMemcpyDeviceToHost, L->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-        hipFree(tmp);
+        dev_free(L, tmp);
         if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
     }
     if (owner) {
@@ -845,10 +844,10 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
     if (nc > 0) {
         const size_t need = nc * Ns * compute_bytes(L->precision);
         if (L->force_bytes < need) {
-            hipFree(L->force);
+            dev_free(L, L->force);
             L->force = nullptr;
             L->force_bytes = 0;
-            if (hipMalloc(&L->force, need) != hipSuccess) return fail(LBMEP_ENOMEM, "force");
+            if (dev_alloc(L, (void **)&L->force, need) != hipSuccess) return fail(LBMEP_ENOMEM, "force");
             L->force_bytes = need;
         }
         const size_t cb = N * compute_bytes(L->precision);

@@ -74,6 +74,61 @@ struct SweepArgs {
 // sweep modes: gather + collide, collide in place, gather only (read-out)
 enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2 };
 
+// particle table of one lattice (device pointers)
+struct ParticleArgs {
+    Grid g;
+    int np;
+    int moving;
+    const double *X0, *R, *U, *W;
+};
+
+// ---------------------------------------------------------------------------
+// Packed launches: one dispatch runs a kernel of the step for several
+// resident lattices.  Each lattice has a descriptor in device memory; the
+// kernel arguments carry a table of entries with the first block of each, and
+// every workgroup finds its entry by a binary search over the block starts.
+// ---------------------------------------------------------------------------
+constexpr int kMaxPack = 64;
+
+struct LatticeDev {
+    // sweep arguments by state = cur | cur_owner << 1 (which population grid
+    // is the source, which owner map / positions are the current level's)
+    SweepArgs sweep[4];
+    ParticleArgs pa;
+    uint8_t *flag;
+    uint32_t *nearmask, *near_list, *near_count, *near_bcount;
+    uint32_t *owner[2];
+    double *Xheld[2];
+    int nacc;         // FP64 accumulators (12 per particle) the sweep clears
+    int near_blocks;  // workgroups of the bounce-back / exchange kernel
+    int list_blocks;  // workgroups of the NEAR-list scan
+};
+
+struct PackTable {
+    int n;
+    int xcd_swizzle;
+    uint32_t start[kMaxPack + 1];  // first workgroup of each entry; start[n] = total
+    const LatticeDev *d[kMaxPack];
+    uint32_t state[kMaxPack];      // cur | cur_owner << 1 before the step
+    int64_t level[kMaxPack];       // kinematic level being advanced to (particle kernels)
+};
+
+// entry of the workgroup b (the last entry whose first block is <= b)
+__device__ __forceinline__ int pack_find(const PackTable &t, uint32_t b) {
+    int lo = 0, hi = t.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// launch shape of the packed sweep (x-segments of 128 cells, one cell per thread)
+constexpr int kPackBlockX = 128;
+
 // kernels (host-side launchers); each returns hipError_t of the launch
 hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs &a, int block_x,
                         int cpt, hipStream_t s);
@@ -114,12 +169,6 @@ hipError_t launch_invariants(int precision, const Grid &g, const void *f, const 
 int invariants_blocks(const Grid &g);
 
 // particles
-struct ParticleArgs {
-    Grid g;
-    int np;
-    int moving;
-    const double *X0, *R, *U, *W;
-};
 hipError_t launch_positions(const ParticleArgs &pa, int64_t level, double *X, hipStream_t s);
 hipError_t launch_map_clear(const ParticleArgs &pa, const double *X, uint32_t *owner,
                             hipStream_t s);
@@ -141,5 +190,24 @@ hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double
 hipError_t launch_export_flags(const Grid &g, const uint8_t *flag, uint8_t *out, hipStream_t s);
 // user flags -> internal wall bits (clears OBST/NEAR)
 hipError_t launch_import_flags(const Grid &g, const uint8_t *in, uint8_t *flag, hipStream_t s);
+
+
+// packed launches (tables filled by the host; entries with no work omitted)
+hipError_t launch_sweep_packed(int precision, int force_mode, const PackTable &t, hipStream_t s);
+hipError_t launch_near_packed(int precision, const PackTable &t, hipStream_t s);
+// clear each particle's cells of the map held two levels back, then move it
+// to t.level (one workgroup per particle)
+hipError_t launch_advance_packed(const PackTable &t, hipStream_t s);
+hipError_t launch_map_set_packed(const PackTable &t, hipStream_t s);
+hipError_t launch_classify_packed(const PackTable &t, hipStream_t s);
+// NEAR-list scan: t_cells for the count / write kernels (list_blocks per
+// entry), t_one with one workgroup per entry for the offsets
+hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_one,
+                                   hipStream_t s);
+// workgroups of the bounce-back / exchange kernel for a grid
+int near_blocks(const Grid &g);
+// single-lattice form of the advance kernel
+hipError_t launch_advance(const ParticleArgs &pa, int64_t level, double *X, uint32_t *owner,
+                          hipStream_t s);
 
 }  // namespace lbmep

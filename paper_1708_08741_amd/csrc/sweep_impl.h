@@ -1,4 +1,4 @@
-// sweep_impl.h -- fused collide + push-stream sweep of the D3Q19 TRT lattice
+// sweep_impl.h -- fused gather-stream + collide sweep of the D3Q19 TRT lattice
 // Boltzmann method with a body force and moving-obstacle bounce-back
 // (arXiv:1708.08741, Sec. 3.1 Eq. LBMcollideStep / Eq. LBMstreamStep with
 // Eq. LBE_forcetermLuo and Eq. modified_velocity; Sec. 3.2 Eq. LBMMovWall and
@@ -495,22 +495,22 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
     }
 }
 
-// CPT cells per thread, on consecutive rows y (their loads are all issued
-// before the first collision, for more memory-level parallelism per wave)
+// workgroups are dealt to the 8 XCDs round-robin; this remaps them so that
+// consecutive x-segments (which share cache lines through the +-1 gathers
+// along x) run on the same XCD and its L2.  A permutation of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t lb, uint32_t nblk) {
+    const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
+    return (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
+}
+
+// one workgroup's x-segment of a 1-D grid of segments: CPT cells per
+// thread, on consecutive rows y (their loads are all issued before the first
+// collision, for more memory-level parallelism per wave)
 template <typename ST, int FMODE, typename OFF, int MODE, int CPT>
-__global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_segment(const SweepArgs &a, uint32_t lb) {
     using T = Storage<ST>;
     using CT = typename T::CT;
     const int nx = a.g.nx, ny = a.g.ny;
-    // 1-D grid of x-segments; workgroups are dealt to the 8 XCDs round-robin,
-    // so consecutive segments (which share cache lines through the +-1
-    // gathers along x) are remapped onto the same XCD and its L2
-    const uint32_t nblk = gridDim.x;
-    uint32_t lb = blockIdx.x;
-    if (a.xcd_swizzle) {
-        const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
-        lb = (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
-    }
     const uint32_t nyb = (uint32_t)((ny + CPT - 1) / CPT);
     const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
     const int y0 = (int)(row % nyb) * CPT, z = (int)(row / nyb);
@@ -524,6 +524,31 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
     for (int r = 0; r < CPT; ++r) finish_cell<ST, FMODE, OFF, MODE>(a, x, y0 + r, z, c[r]);
 }
 
+template <typename ST, int FMODE, typename OFF, int MODE, int CPT>
+__global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
+    const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    sweep_segment<ST, FMODE, OFF, MODE, CPT>(a, lb);
+}
+
+// the gather sweep of several lattices in one dispatch; each workgroup also
+// clears its share of the lattice's per-particle accumulators, which the
+// exchange kernel that follows sums into
+template <typename ST, int FMODE>
+__global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
+    const uint32_t gb = t.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int e = pack_find(t, gb);
+    const LatticeDev *d = t.d[e];
+    const SweepArgs a = d->sweep[t.state[e]];
+    const uint32_t lb = gb - t.start[e];
+    if (a.FM) {
+        const uint32_t nb = t.start[e + 1] - t.start[e];
+        for (uint32_t i = lb * blockDim.x + threadIdx.x; i < (uint32_t)d->nacc;
+             i += nb * blockDim.x)
+            a.FM[i] = 0.0;
+    }
+    sweep_segment<ST, FMODE, uint32_t, kPull, 1>(a, lb);
+}
+
 // Bounce-back slots and momentum exchange of the cells next to a solid cell
 // (the list built after every re-mapping), run after the sweep on the
 // post-collision state it wrote.  Each wavefront takes 64 consecutive list
@@ -532,15 +557,15 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
 // FP64 atomic per particle and component.  The count is read on the device,
 // so the launch needs no host synchronisation.
 template <typename ST, typename OFF>
-__global__ void __launch_bounds__(256) k_near(SweepArgs a, const uint32_t *list,
-                                              const uint32_t *count) {
+__device__ __forceinline__ void near_range(const SweepArgs &a, const uint32_t *list,
+                                           const uint32_t *count, uint32_t blk, uint32_t nblk) {
     using T = Storage<ST>;
     using CT = typename T::CT;
     const uint32_t n = *count;
     const int nx = a.g.nx, ny = a.g.ny;
     const OFF pst = (OFF)a.g.Ns * (OFF)sizeof(ST);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
         uint32_t pp = kNone;
         double acc[kAcc];
 #pragma unroll
@@ -624,13 +649,55 @@ __global__ void __launch_bounds__(256) k_near(SweepArgs a, const uint32_t *list,
     }
 }
 
+template <typename ST, typename OFF>
+__global__ void __launch_bounds__(256) k_near(SweepArgs a, const uint32_t *list,
+                                              const uint32_t *count) {
+    near_range<ST, OFF>(a, list, count, blockIdx.x, gridDim.x);
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) k_near_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    const SweepArgs a = d->sweep[t.state[e]];
+    near_range<ST, uint32_t>(a, d->near_list, d->near_count, blockIdx.x - t.start[e],
+                             t.start[e + 1] - t.start[e]);
+}
+
+// workgroups of the exchange kernel for a grid of N cells: enough wavefronts
+// for a list of a few per cent of the cells in one pass
+inline int near_blocks_for(size_t N) {
+    size_t blocks = (N / 32 + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    if (blocks < 1) blocks = 1;
+    return (int)blocks;
+}
+
+template <typename ST>
+hipError_t launch_sweep_packed_typed(int force_mode, const PackTable &t, hipStream_t s) {
+    const uint32_t total = t.start[t.n];
+    if (t.n == 0 || total == 0) return hipSuccess;
+    if (force_mode == kForceNone)
+        hipLaunchKernelGGL((k_sweep_packed<ST, kForceNone>), dim3(total), dim3(kPackBlockX), 0, s, t);
+    else if (force_mode == kForceDense)
+        hipLaunchKernelGGL((k_sweep_packed<ST, kForceDense>), dim3(total), dim3(kPackBlockX), 0, s, t);
+    else
+        hipLaunchKernelGGL((k_sweep_packed<ST, kForceCharge>), dim3(total), dim3(kPackBlockX), 0, s, t);
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t launch_near_packed_typed(const PackTable &t, hipStream_t s) {
+    const uint32_t total = t.start[t.n];
+    if (t.n == 0 || total == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_near_packed<ST>), dim3(total), dim3(256), 0, s, t);
+    return hipGetLastError();
+}
+
 template <typename ST>
 hipError_t launch_near_typed(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
                              hipStream_t s) {
-    // enough wavefronts for a list of a few per cent of the cells in one pass
-    size_t blocks = (a.g.N / 32 + 255) / 256;
-    if (blocks > 65535) blocks = 65535;
-    if (blocks < 1) blocks = 1;
+    const size_t blocks = (size_t)near_blocks_for(a.g.N);
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
     if (small)
         hipLaunchKernelGGL((k_near<ST, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, s, a,

@@ -42,6 +42,43 @@ class Config(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+        ("chunk_steps", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_size_t),
+    ]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("cfg", Config),
+        ("flags", ctypes.c_void_p),
+        ("n", ctypes.c_int32), ("steps", ctypes.c_int32),
+        ("X", ctypes.c_void_p), ("R", ctypes.c_void_p), ("U", ctypes.c_void_p),
+        ("W", ctypes.c_void_p),
+        ("rho_e", ctypes.c_void_p),
+        ("rho_e_dtype", ctypes.c_int32), ("keep_fields", ctypes.c_int32),
+        ("E", ctypes.c_double * 3),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+        ("queued", ctypes.c_int32), ("resident", ctypes.c_int32),
+        ("chunks", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+        ("packed_launches", ctypes.c_uint64),
+        ("cell_updates", ctypes.c_double),
+        ("bytes_reserved", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t),
+        ("budget", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 # exported symbols and their ctypes signatures
@@ -71,6 +108,20 @@ _SIGS = {
     "lbmep_load_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmep_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig),
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "lbmep_server_destroy": (ctypes.c_int, [_P]),
+    "lbmep_server_request_footprint": (ctypes.c_int, [ctypes.POINTER(Request),
+                                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmep_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "lbmep_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "lbmep_server_result": (ctypes.c_int, [_P, ctypes.c_uint64, _P, _P, _D, _D]),
+    "lbmep_server_fields": (ctypes.c_int, [_P, ctypes.c_uint64, _P, _P]),
+    "lbmep_server_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "lbmep_server_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
+    "lbmep_server_now": (ctypes.c_int, [_P, _D]),
 }
 
 
@@ -303,3 +354,142 @@ def from_workload(wl, precision=None, device=0, stream=None, force_dtype=None):
     L.init_equilibrium(1.0, (0.0, 0.0, 0.0))
     L.set_particles(wl.X, wl.R, wl.U, wl.W)
     return L
+
+
+class Server:
+    """Request server of the library (lbmep_server_*): continuous batching of
+    independent simulations with packed launches.  Request inputs are numpy
+    arrays; they are copied by submit."""
+
+    def __init__(self, hbm_budget, max_slots=32, chunk_steps=20, max_queue=100000, device=0):
+        c = ServerConfig()
+        c.device = int(device)
+        c.max_slots = int(max_slots)
+        c.chunk_steps = int(chunk_steps)
+        c.max_queue = int(max_queue)
+        c.hbm_budget = int(hbm_budget)
+        h = ctypes.c_void_p()
+        _check(lib().lbmep_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self.meta = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbmep_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _request(shape, X=None, R=None, U=None, W=None, steps=1, rho_e=None, E=(0, 0, 0),
+                 flags=None, periodic=(True, True, True), nu=1.0 / 6.0, magic=3.0 / 16.0,
+                 precision=FP32DEV, moving=True, keep_fields=False):
+        q = Request()
+        q.cfg = make_config(shape, periodic, nu, magic, precision, moving, 0, None)
+        keep = []
+        X = np.zeros((0, 3)) if X is None else X
+        R = np.zeros(0) if R is None else R
+        U = np.zeros((0, 3)) if U is None else U
+        arrs = {}
+        for k, a in (("X", X), ("R", R), ("U", U), ("W", W)):
+            if a is None:
+                continue
+            a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+            keep.append(a)
+            arrs[k] = a.ctypes.data
+        q.n = len(np.asarray(R).reshape(-1))
+        q.steps = int(steps)
+        q.X, q.R, q.U = arrs["X"], arrs["R"], arrs["U"]
+        q.W = arrs.get("W")
+        if flags is not None:
+            fl = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1)
+            keep.append(fl)
+            q.flags = fl.ctypes.data
+        if rho_e is not None:
+            re = np.ascontiguousarray(rho_e)
+            if re.dtype not in (np.float32, np.float64):
+                re = re.astype(np.float64)
+            re = re.reshape(-1)
+            keep.append(re)
+            q.rho_e = re.ctypes.data
+            q.rho_e_dtype = DTYPE_F32 if re.dtype == np.float32 else DTYPE_F64
+            for k in range(3):
+                q.E[k] = float(E[k])
+        q.keep_fields = 1 if keep_fields else 0
+        return q, keep
+
+    @staticmethod
+    def request_footprint(shape, **kw):
+        q, keep = Server._request(shape, **kw)
+        out = ctypes.c_size_t(0)
+        _check(lib().lbmep_server_request_footprint(ctypes.byref(q), ctypes.byref(out)))
+        return out.value
+
+    def submit(self, shape, **kw):
+        """Queue one simulation; returns its id."""
+        q, keep = self._request(shape, **kw)
+        rid = ctypes.c_uint64(0)
+        _check(lib().lbmep_server_submit(self._h, ctypes.byref(q), ctypes.byref(rid)))
+        R = kw.get("R")
+        self.meta[rid.value] = dict(shape=tuple(shape), n=q.n, steps=q.steps)
+        return rid.value
+
+    def poll(self, cap=1024):
+        ids = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_int32(0)
+        _check(lib().lbmep_server_poll(self._h, ids, cap, ctypes.byref(n)))
+        return [ids[i] for i in range(n.value)]
+
+    def result(self, rid):
+        """(F, M, invariants, (t_submit, t_admit, t_done)) of a finished request."""
+        n = self.meta[rid]["n"]
+        F = np.zeros((n, 3))
+        M = np.zeros((n, 3))
+        inv = np.zeros(4)
+        t = np.zeros(3)
+        _check(lib().lbmep_server_result(self._h, rid, F.ctypes.data, M.ctypes.data, _dp(inv),
+                                         _dp(t)))
+        return F, M, inv, tuple(t)
+
+    def fields(self, rid):
+        nx, ny, nz = self.meta[rid]["shape"]
+        rho = np.zeros((nz, ny, nx))
+        u = np.zeros((3, nz, ny, nx))
+        _check(lib().lbmep_server_fields(self._h, rid, rho.ctypes.data, u.ctypes.data))
+        return rho, u
+
+    def release(self, rid):
+        _check(lib().lbmep_server_release(self._h, rid))
+        self.meta.pop(rid, None)
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().lbmep_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def now(self):
+        t = np.zeros(1)
+        _check(lib().lbmep_server_now(self._h, _dp(t)))
+        return float(t[0])
+
+    def wait_all(self, ids, timeout=600.0, sleep=5e-4):
+        """Poll until every id in `ids` has finished; returns them in
+        completion order."""
+        import time
+        pending = set(ids)
+        order = []
+        t0 = time.monotonic()
+        while pending:
+            for i in self.poll():
+                if i in pending:
+                    pending.discard(i)
+                    order.append(i)
+            if pending:
+                if time.monotonic() - t0 > timeout:
+                    raise TimeoutError(f"{len(pending)} requests still pending")
+                time.sleep(sleep)
+        return order

@@ -37,6 +37,49 @@ def test_config_struct_layout():
     assert lb.Config.nu.offset == 24 and lb.Config.stream.offset == 56
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and offsets a C
+    compiler gives the header's structures."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "lbmep.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu\\n", sizeof(lbmep_config), sizeof(lbmep_server_config),'
+        " sizeof(lbmep_request), sizeof(lbmep_server_stats));\n"
+        '  printf("%zu %zu %zu %zu %zu\\n", offsetof(lbmep_request, flags),'
+        " offsetof(lbmep_request, X), offsetof(lbmep_request, rho_e),"
+        " offsetof(lbmep_request, E), offsetof(lbmep_server_stats, cell_updates));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split()
+    sizes = [int(v) for v in out[:4]]
+    offs = [int(v) for v in out[4:]]
+    assert sizes == [ctypes.sizeof(lb.Config), ctypes.sizeof(lb.ServerConfig),
+                     ctypes.sizeof(lb.Request), ctypes.sizeof(lb.ServerStats)]
+    assert offs == [lb.Request.flags.offset, lb.Request.X.offset, lb.Request.rho_e.offset,
+                    lb.Request.E.offset, lb.ServerStats.cell_updates.offset]
+
+
+def test_server_request_footprint_host_only():
+    """Admission footprint of a request: the lattice's footprint plus the
+    arena alignment, descriptor and set-up staging; checked on the host."""
+    import numpy as np
+    shape = (64, 96, 128)
+    N = 64 * 96 * 128
+    kw = dict(X=np.array([[10.0, 10.0, 10.0]]), R=[4.0], U=np.zeros((1, 3)), steps=100,
+              rho_e=np.zeros(N, dtype=np.float32), E=(1e-3, 0, 0), precision=lb.FP32DEV)
+    fp = lb.Server.request_footprint(shape, **kw)
+    base = lb.footprint(shape, lb.FP32DEV, 1, True)
+    assert base < fp < base + 8 * N + 64 * 4096
+    fp_keep = lb.Server.request_footprint(shape, keep_fields=True, **kw)
+    assert fp_keep - fp >= 32 * N
+    with pytest.raises(lb.LbmepError) as e:
+        lb.Server.request_footprint((0, 4, 4), steps=1)
+    assert e.value.code == lb.EINVAL
+
+
 def test_library_is_gfx950_only():
     """The shared object carries gfx950 device code and no other target."""
     data = open(lb.LIB_PATH, "rb").read()
