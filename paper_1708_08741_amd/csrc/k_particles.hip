@@ -291,8 +291,9 @@ __global__ void __launch_bounds__(kBoxThreads)
 }
 
 // compact list of the fluid cells with a blocked direction, in cell order,
-// by a three-kernel scan (no contended atomics): per-block counts, one block
-// scanning the counts, then each block writing its cells from its offset.  A
+// by a three-kernel scan (no contended atomics): per-block counts, a scan of
+// the counts in tiles of 1024, then each block writing its cells from its
+// offset.  A
 // thread reads the flags of 16 consecutive cells at once (the flag array is
 // padded to a multiple of kListChunk).
 constexpr int kListCells = 16;
@@ -341,15 +342,16 @@ __global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag,
     near_count_block(g, flag, bcount, blockIdx.x);
 }
 
-// exclusive scan of the block counts in place (one block of 1024 threads,
-// each owning a contiguous run of counts); count = total
-__device__ __forceinline__ void near_offsets_block(uint32_t *bcount, int nb, uint32_t *count) {
-    __shared__ uint32_t wsum[16];
+// second level of the scan: workgroup t turns the counts of list blocks
+// [1024 t, 1024 t + 1024) into exclusive prefixes within that tile (one
+// coalesced load per thread) and stores the tile total after the counts
+constexpr int kTile = 1024;
+
+__device__ __forceinline__ void near_tile_block(uint32_t *bcount, int nb, uint32_t tile) {
+    __shared__ uint32_t wsum[kTile / 64];
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
-    const int per = (nb + 1023) / 1024;
-    const int i0 = tid * per, i1 = min(nb, i0 + per);
-    uint32_t mine = 0;
-    for (int i = i0; i < i1; ++i) mine += bcount[i];
+    const size_t i = (size_t)tile * kTile + tid;
+    const uint32_t mine = i < (size_t)nb ? bcount[i] : 0u;
     uint32_t incl = mine;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -358,36 +360,44 @@ __device__ __forceinline__ void near_offsets_block(uint32_t *bcount, int nb, uin
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    uint32_t run = incl - mine;
-    for (int w = 0; w < wave; ++w) run += wsum[w];
-    for (int i = i0; i < i1; ++i) {
-        const uint32_t v = bcount[i];
-        bcount[i] = run;
-        run += v;
+    uint32_t pre = incl - mine;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    if (i < (size_t)nb) bcount[i] = pre;
+    if (tid == kTile - 1) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kTile / 64; ++w) tot += wsum[w];
+        bcount[nb + tile] = tot;
     }
-    if (tid == 1023) *count = run;
 }
 
-__global__ void __launch_bounds__(1024) k_near_offsets(uint32_t *bcount, int nb, uint32_t *count) {
-    near_offsets_block(bcount, nb, count);
+__global__ void __launch_bounds__(kTile) k_near_tiles(uint32_t *bcount, int nb) {
+    near_tile_block(bcount, nb, blockIdx.x);
 }
 
+// list block blk writes its cells from its offset: the exclusive prefix
+// within its tile plus the totals of the earlier tiles; the last block also
+// stores the list length
 __device__ __forceinline__ void near_write_block(const Grid &g, const uint8_t *flag,
-                                                 const uint32_t *boff, uint32_t *list,
-                                                 uint32_t blk) {
+                                                 const uint32_t *bcount, int nb, uint32_t *list,
+                                                 uint32_t *count, uint32_t blk) {
     __shared__ uint32_t wsum[4];
     const size_t c0 = (size_t)blk * kListChunk + (size_t)threadIdx.x * kListCells;
     const uint32_t take = near_bits(g, flag, c0);
+    uint32_t off = bcount[blk];
+    const uint32_t *tsum = bcount + nb;
+    for (uint32_t t = 0; t < blk / kTile; ++t) off += tsum[t];
     uint32_t total;
-    uint32_t pos = boff[blk] + block_scan((uint32_t)__popc(take), wsum, &total);
+    uint32_t pos = off + block_scan((uint32_t)__popc(take), wsum, &total);
 #pragma unroll
     for (int k = 0; k < kListCells; ++k)
         if (take & (1u << k)) list[pos++] = (uint32_t)(c0 + k);
+    if (blk == (uint32_t)nb - 1 && threadIdx.x == 0) *count = off + total;
 }
 
 __global__ void __launch_bounds__(256) k_near_write(Grid g, const uint8_t *flag,
-                                                    const uint32_t *boff, uint32_t *list) {
-    near_write_block(g, flag, boff, list, blockIdx.x);
+                                                    const uint32_t *bcount, int nb,
+                                                    uint32_t *list, uint32_t *count) {
+    near_write_block(g, flag, bcount, nb, list, count, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,15 +438,17 @@ __global__ void __launch_bounds__(256) k_near_count_packed(PackTable t) {
     near_count_block(d->pa.g, d->flag, d->near_bcount, blockIdx.x - t.start[e]);
 }
 
-__global__ void __launch_bounds__(1024) k_near_offsets_packed(PackTable t) {
-    const LatticeDev *d = t.d[blockIdx.x];
-    near_offsets_block(d->near_bcount, d->list_blocks, d->near_count);
+__global__ void __launch_bounds__(kTile) k_near_tiles_packed(PackTable t) {
+    const int e = pack_find(t, blockIdx.x);
+    const LatticeDev *d = t.d[e];
+    near_tile_block(d->near_bcount, d->list_blocks, blockIdx.x - t.start[e]);
 }
 
 __global__ void __launch_bounds__(256) k_near_write_packed(PackTable t) {
     const int e = pack_find(t, blockIdx.x);
     const LatticeDev *d = t.d[e];
-    near_write_block(d->pa.g, d->flag, d->near_bcount, d->near_list, blockIdx.x - t.start[e]);
+    near_write_block(d->pa.g, d->flag, d->near_bcount, d->list_blocks, d->near_list,
+                     d->near_count, blockIdx.x - t.start[e]);
 }
 
 // F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
@@ -457,13 +469,18 @@ __global__ void k_finalize_ft(int np, const double *acc, const double *X, double
 }  // namespace
 
 int near_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kListChunk); }
+int near_list_tiles(const Grid &g) { return (near_list_blocks(g) + kTile - 1) / kTile; }
+size_t near_list_scratch(const Grid &g) {
+    return (size_t)near_list_blocks(g) + (size_t)near_list_tiles(g) + 64;
+}
 
 hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
                             uint32_t *bcount, hipStream_t s) {
     const int nb = near_list_blocks(g);
     hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(256), 0, s, g, flag, bcount);
-    hipLaunchKernelGGL(k_near_offsets, dim3(1), dim3(1024), 0, s, bcount, nb, count);
-    hipLaunchKernelGGL(k_near_write, dim3(nb), dim3(256), 0, s, g, flag, bcount, list);
+    hipLaunchKernelGGL(k_near_tiles, dim3(near_list_tiles(g)), dim3(kTile), 0, s, bcount, nb);
+    hipLaunchKernelGGL(k_near_write, dim3(nb), dim3(256), 0, s, g, flag, bcount, nb, list,
+                       count);
     return hipGetLastError();
 }
 
@@ -503,10 +520,10 @@ hipError_t launch_classify_packed(const PackTable &t, hipStream_t s) {
     return launch_packed(k_classify_packed, t, kBoxThreads, s);
 }
 
-hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_one,
+hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_tiles,
                                    hipStream_t s) {
     hipError_t e = launch_packed(k_near_count_packed, t_cells, 256, s);
-    if (e == hipSuccess) e = launch_packed(k_near_offsets_packed, t_one, 1024, s);
+    if (e == hipSuccess) e = launch_packed(k_near_tiles_packed, t_tiles, kTile, s);
     if (e == hipSuccess) e = launch_packed(k_near_write_packed, t_cells, 256, s);
     return e;
 }

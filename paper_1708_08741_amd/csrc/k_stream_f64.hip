@@ -2,7 +2,7 @@
 // Built without floating-point contraction: the collision, forcing and
 // bounce-back evaluate the same operation sequence as a plain FP64 CPU
 // implementation of Sec. 3.1-3.2 of arXiv:1708.08741.
-#include "sweep_impl.h"
+#include "near_impl.h"
 
 namespace lbmep {
 

@@ -1,7 +1,7 @@
 // k_stream_lp.hip -- FP32 and FP16 deviation-storage instantiations of the
 // fused sweep (sweep_impl.h), FP32 arithmetic, and the precision dispatch of
 // the sweep launch.
-#include "sweep_impl.h"
+#include "near_impl.h"
 
 namespace lbmep {
 

@@ -169,11 +169,18 @@ size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mod
     const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
     const size_t Ns = round_up(N, 128);
     size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
-    b += N + 4 * N + 4 * N;                                    // flags, near masks, near list
+    b += round_up(N, 4096) + 4 * N + 4 * N;                    // flags, near masks, near list
     if (n_particles > 0) b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;
     if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
     if (force_mode == kForceCharge) b += Ns * compute_bytes(cfg->precision);
-    b += 4096 * 5 * 8 + 64;
+    Grid g{};
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    g.N = N;
+    g.Ns = Ns;
+    b += 4 * near_list_scratch(g) + 256;                          // list scan, list length
+    b += (5 * (size_t)invariants_blocks(g) + 4) * sizeof(double);  // reductions
     return b;
 }
 
@@ -297,7 +304,7 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     ok = ok && dev_alloc(L, (void **)&L->nearmask, 4 * g.N) == hipSuccess;
     ok = ok && dev_alloc(L, (void **)&L->near_list, 4 * g.N) == hipSuccess;
     ok = ok && dev_alloc(L, (void **)&L->near_count, 256) == hipSuccess;
-    ok = ok && dev_alloc(L, (void **)&L->near_bcount, 4 * (size_t)near_list_blocks(g) + 256) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->near_bcount, 4 * near_list_scratch(g)) == hipSuccess;
     L->red_blocks = invariants_blocks(g);
     ok = ok && dev_alloc(L, (void **)&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
     if (!ok) {

@@ -138,8 +138,10 @@ hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs
 hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
                        const uint32_t *count, hipStream_t s);
 // compact list of the fluid NEAR cells in cell order; bcount is scratch of
-// near_list_blocks(g) entries
+// near_list_scratch(g) entries
 int near_list_blocks(const Grid &g);
+int near_list_tiles(const Grid &g);
+size_t near_list_scratch(const Grid &g);
 hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
                             uint32_t *bcount, hipStream_t s);
 
@@ -201,8 +203,8 @@ hipError_t launch_advance_packed(const PackTable &t, hipStream_t s);
 hipError_t launch_map_set_packed(const PackTable &t, hipStream_t s);
 hipError_t launch_classify_packed(const PackTable &t, hipStream_t s);
 // NEAR-list scan: t_cells for the count / write kernels (list_blocks per
-// entry), t_one with one workgroup per entry for the offsets
-hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_one,
+// entry), t_tiles for the tile scan (near_list_tiles per entry)
+hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_tiles,
                                    hipStream_t s);
 // workgroups of the bounce-back / exchange kernel for a grid
 int near_blocks(const Grid &g);

@@ -402,7 +402,7 @@ int enqueue_steps(lbmep_server *S, const std::vector<Slot *> &act, int k) {
             }
             tp.start[tp.n + 1] = tp.start[tp.n] + (uint32_t)L->np;
             tc.start[tc.n + 1] = tc.start[tc.n] + (uint32_t)near_list_blocks(L->g);
-            to.start[to.n + 1] = to.start[to.n] + 1u;
+            to.start[to.n + 1] = to.start[to.n] + (uint32_t)near_list_tiles(L->g);
             tp.n++;
             tc.n++;
             to.n++;

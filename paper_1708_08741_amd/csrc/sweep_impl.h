@@ -11,14 +11,11 @@
 // x - e_q (reads shifted by at most one element along x; this completes the
 // stream of Eq. LBMstreamStep), refills the cell if it has just been
 // uncovered, collides, and writes its 19 new values aligned to its own cell.
-// Bounce-back needs no look-up at gather time: after the sweep, a second
-// kernel visits the fluid cells next to a solid cell s (a compact list, ~1%
-// of the cells) and writes the bounced value f*_q - 2 w_q rho0 c_q.u_s/c_s^2
-// (Eq. LBMMovWall) into the slot of s that the fluid cell gathers from at the
-// next step, with the momentum-exchange terms (Eq. LBMhydrodynForce) summed
-// per particle in FP64 (per lane, across the wavefront by shuffles, then one
-// FP64 atomic per particle and wavefront).  Only the edge of a non-periodic
-// axis is resolved at gather time, from the cell coordinates.
+// Bounce-back needs no look-up at gather time: after the sweep, the kernel
+// of near_impl.h writes the bounced value of every blocked link into a slot
+// of the solid neighbour that the fluid cell gathers from at the next step.
+// Only the edge of a non-periodic axis is resolved at gather time, from the
+// cell coordinates.
 //
 // The template is instantiated in two translation units, k_stream_f64.hip
 // (FP64) and k_stream_lp.hip (FP32 / FP16 deviation storage), both compiled
@@ -120,14 +117,6 @@ __device__ __forceinline__ double image_coord(double c, double X, int len, int p
     return c;
 }
 
-// per-particle accumulators: F_dev[3], M_dev[3], K[3], T[3]
-constexpr int kAcc = 12;
-
-__device__ __forceinline__ void flush_particle(double *FM, uint32_t p, const double acc[kAcc]) {
-#pragma unroll
-    for (int k = 0; k < kAcc; ++k) unsafeAtomicAdd(&FM[kAcc * (size_t)p + k], acc[k]);
-}
-
 // address of element `off` (bytes) of the array starting at the uniform
 // `base`; with OFF = uint32_t this becomes a global access with a scalar base
 // register and a 32-bit vector offset
@@ -145,96 +134,6 @@ enum { kPull = 0,     // gather f* of the previous level, refill, collide
        kLocal = 1,    // collide the post-stream state held in the grid
        kReadout = 2   // gather and refill only: write the post-stream state
 };
-
-// neighbour s = x + e_q of a cell: its coordinates (wrapped on periodic
-// axes) and false if it lies beyond the edge of a non-periodic axis
-template <int q>
-__device__ __forceinline__ bool neighbour(const Grid &g, int x, int y, int z, int &sx, int &sy,
-                                          int &sz) {
-    sx = x + kCx[q];
-    sy = y + kCy[q];
-    sz = z + kCz[q];
-    bool inside = true;
-    if (sx < 0 || sx >= g.nx) {
-        if (g.per[0]) sx = sx < 0 ? sx + g.nx : sx - g.nx; else inside = false;
-    }
-    if (sy < 0 || sy >= g.ny) {
-        if (g.per[1]) sy = sy < 0 ? sy + g.ny : sy - g.ny; else inside = false;
-    }
-    if (sz < 0 || sz >= g.nz) {
-        if (g.per[2]) sz = sz < 0 ? sz + g.nz : sz - g.nz; else inside = false;
-    }
-    return inside;
-}
-
-// Bounce-back of population q of a fluid cell whose neighbour s = x + e_q is
-// solid: the value that comes back to the cell as population opp(q) at the
-// next gather is written into slot opp(q) of s; for an obstacle cell of
-// particle p (p != kNone; its centre, velocity and angular velocity given)
-// the momentum exchange is added to the lane's accumulators.
-template <int q, typename ST, typename OFF>
-__device__ __forceinline__ void bounce_apply(const SweepArgs &a, int sx, int sy, int sz,
-                                             typename Storage<ST>::CT fq, uint32_t p,
-                                             const double *X, const double *U, const double *W,
-                                             uint32_t &pp, double acc[kAcc]) {
-    using T = Storage<ST>;
-    using CT = typename T::CT;
-    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
-    const Grid &g = a.g;
-    const OFF s = (OFF)sx + (OFF)g.nx * ((OFF)sy + (OFF)g.ny * (OFF)sz);
-    double mw = 0.0;
-    if (p != kNone) {
-        // lever arm r = x_s - x_C (minimum image) and u_s = U + W x r
-        const double r0 = min_image(((double)sx + 0.5) - X[0], g.nx, g.per[0]);
-        const double r1 = min_image(((double)sy + 0.5) - X[1], g.ny, g.per[1]);
-        const double r2 = min_image(((double)sz + 0.5) - X[2], g.nz, g.per[2]);
-        const double us0 = U[0] + (W[1] * r2 - W[2] * r1);
-        const double us1 = U[1] + (W[2] * r0 - W[0] * r2);
-        const double us2 = U[2] + (W[0] * r1 - W[1] * r0);
-        const double cus = cdot<q>(us0, us1, us2);
-        // 2 (w_q / c_s^2) rho0 c_q . u_s (Eq. LBMMovWall)
-        mw = 2.0 * wq(q) * 3.0 * cus;
-        // [2 f*_q - 2 (w_q/c_s^2) rho0 c_q . u_s] c_q (Eq. LBMhydrodynForce),
-        // summed as [2 (f*_q - w_q) - ...] c_q plus the rest-weight part
-        // 2 w_q c_q = (k/18) c_q (k = 2 axis, 1 diagonal), whose sum cancels
-        // over a closed body and is accumulated exactly as integers:
-        // K = sum k c_q, T = sum k x_s x c_q (x_s the exact half-integer
-        // image of the cell centre)
-        const double gm = 2.0 * T::devval(fq, q) - mw;
-        const double g0 = cx == 0 ? 0.0 : (cx > 0 ? gm : -gm);
-        const double g1 = cy == 0 ? 0.0 : (cy > 0 ? gm : -gm);
-        const double g2 = cz == 0 ? 0.0 : (cz > 0 ? gm : -gm);
-        constexpr double k = q <= 6 ? 2.0 : 1.0;
-        const double xs0 = image_coord((double)sx + 0.5, X[0], g.nx, g.per[0]);
-        const double xs1 = image_coord((double)sy + 0.5, X[1], g.ny, g.per[1]);
-        const double xs2 = image_coord((double)sz + 0.5, X[2], g.nz, g.per[2]);
-        if (pp != p) {
-            if (pp != kNone) flush_particle(a.FM, pp, acc);
-            pp = p;
-#pragma unroll
-            for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-        }
-        acc[0] += g0;
-        acc[1] += g1;
-        acc[2] += g2;
-        acc[3] += r1 * g2 - r2 * g1;
-        acc[4] += r2 * g0 - r0 * g2;
-        acc[5] += r0 * g1 - r1 * g0;
-        acc[6] += k * (double)cx;
-        acc[7] += k * (double)cy;
-        acc[8] += k * (double)cz;
-        acc[9] += k * (xs1 * (double)cz - xs2 * (double)cy);
-        acc[10] += k * (xs2 * (double)cx - xs0 * (double)cz);
-        acc[11] += k * (xs0 * (double)cy - xs1 * (double)cx);
-    }
-    constexpr int qb = opp(q);
-    void *slot = static_cast<char *>(a.dst) + (size_t)qb * a.g.Ns * sizeof(ST);
-    if constexpr (sizeof(CT) == 8) {
-        T::store(at<ST>(slot, s * (OFF)sizeof(ST)), fq - mw);
-    } else {
-        T::store(at<ST>(slot, s * (OFF)sizeof(ST)), (CT)((double)fq - mw));
-    }
-}
 
 // the TRT collision of one opposite pair (q, q+1) with the forcing term
 template <int q, typename CT>
@@ -549,130 +448,6 @@ __global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
     sweep_segment<ST, FMODE, uint32_t, kPull, 1>(a, lb);
 }
 
-// Bounce-back slots and momentum exchange of the cells next to a solid cell
-// (the list built after every re-mapping), run after the sweep on the
-// post-collision state it wrote.  Each wavefront takes 64 consecutive list
-// entries (neighbouring cells, mostly of one particle) at a time and sums
-// their momentum exchange per particle across the wavefront before one
-// FP64 atomic per particle and component.  The count is read on the device,
-// so the launch needs no host synchronisation.
-template <typename ST, typename OFF>
-__device__ __forceinline__ void near_range(const SweepArgs &a, const uint32_t *list,
-                                           const uint32_t *count, uint32_t blk, uint32_t nblk) {
-    using T = Storage<ST>;
-    using CT = typename T::CT;
-    const uint32_t n = *count;
-    const int nx = a.g.nx, ny = a.g.ny;
-    const OFF pst = (OFF)a.g.Ns * (OFF)sizeof(ST);
-    const uint32_t stride = nblk * blockDim.x;
-    for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
-        uint32_t pp = kNone;
-        double acc[kAcc];
-#pragma unroll
-        for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-        const uint32_t i = base + threadIdx.x;
-        if (i < n) {
-            const uint32_t c = list[i];
-            const int x = (int)(c % (uint32_t)nx);
-            const int y = (int)((c / (uint32_t)nx) % (uint32_t)ny);
-            const int z = (int)(c / ((uint32_t)nx * (uint32_t)ny));
-            const uint32_t mask = a.nearmask[c];
-            const OFF cb = (OFF)c * (OFF)sizeof(ST);
-            // phase 1: every load of the blocked links at once (the cell's
-            // post-collision value and the owner of the solid neighbour)
-            CT fq[Q];
-            uint32_t own[Q];
-#define LBMEP_NEAR_LOAD(q)                                                                     \
-    fq[q] = CT(0);                                                                             \
-    own[q] = kNone;                                                                            \
-    if (mask & (1u << ((q)-1))) {                                                              \
-        int sx, sy, sz;                                                                        \
-        const bool in = neighbour<q>(a.g, x, y, z, sx, sy, sz);                                \
-        fq[q] = T::load(at<ST>(static_cast<const char *>(a.dst) + (size_t)(q) * pst, cb));     \
-        if (in && a.owner)                                                                     \
-            own[q] = a.owner[(size_t)sx + (size_t)nx * ((size_t)sy + (size_t)ny * (size_t)sz)]; \
-    }
-            LBMEP_FOR_Q18(LBMEP_NEAR_LOAD)
-#undef LBMEP_NEAR_LOAD
-            // phase 2: the particle of the cell's first particle link (most
-            // cells touch one particle)
-            uint32_t p0 = kNone;
-#pragma unroll
-            for (int q = Q - 1; q >= 1; --q)
-                if (own[q] != kNone) p0 = own[q];
-            double X0[3] = {0, 0, 0}, U0[3] = {0, 0, 0}, W0[3] = {0, 0, 0};
-            if (p0 != kNone) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    X0[k] = a.Xc[3 * (size_t)p0 + k];
-                    U0[k] = a.U[3 * (size_t)p0 + k];
-                    W0[k] = a.W[3 * (size_t)p0 + k];
-                }
-            }
-            // phase 3: bounce-back slots and momentum exchange
-#define LBMEP_NEAR_APPLY(q)                                                                     \
-    if (mask & (1u << ((q)-1))) {                                                               \
-        int sx, sy, sz;                                                                         \
-        if (neighbour<q>(a.g, x, y, z, sx, sy, sz)) {                                           \
-            const uint32_t p = own[q];                                                          \
-            if (p == p0 || p == kNone) {                                                        \
-                bounce_apply<q, ST, OFF>(a, sx, sy, sz, fq[q], p, X0, U0, W0, pp, acc);         \
-            } else {                                                                            \
-                bounce_apply<q, ST, OFF>(a, sx, sy, sz, fq[q], p, a.Xc + 3 * (size_t)p,         \
-                                         a.U + 3 * (size_t)p, a.W + 3 * (size_t)p, pp, acc);    \
-            }                                                                                   \
-        }                                                                                       \
-    }
-            LBMEP_FOR_Q18(LBMEP_NEAR_APPLY)
-#undef LBMEP_NEAR_APPLY
-        }
-        // per-particle sums across the wavefront (every lane takes part)
-        if (a.FM) {
-            unsigned long long pend = __ballot(pp != kNone);
-            while (pend) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const uint32_t lp = (uint32_t)__shfl((int)pp, leader);
-                const bool mine = pp == lp;
-                double t[kAcc];
-#pragma unroll
-                for (int k = 0; k < kAcc; ++k) t[k] = mine ? acc[k] : 0.0;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-                    for (int k = 0; k < kAcc; ++k) t[k] += __shfl_xor(t[k], off);
-                }
-                if ((int)__lane_id() == leader) flush_particle(a.FM, lp, t);
-                if (mine) pp = kNone;
-                pend = __ballot(pp != kNone);
-            }
-        }
-    }
-}
-
-template <typename ST, typename OFF>
-__global__ void __launch_bounds__(256) k_near(SweepArgs a, const uint32_t *list,
-                                              const uint32_t *count) {
-    near_range<ST, OFF>(a, list, count, blockIdx.x, gridDim.x);
-}
-
-template <typename ST>
-__global__ void __launch_bounds__(256) k_near_packed(PackTable t) {
-    const int e = pack_find(t, blockIdx.x);
-    const LatticeDev *d = t.d[e];
-    const SweepArgs a = d->sweep[t.state[e]];
-    near_range<ST, uint32_t>(a, d->near_list, d->near_count, blockIdx.x - t.start[e],
-                             t.start[e + 1] - t.start[e]);
-}
-
-// workgroups of the exchange kernel for a grid of N cells: enough wavefronts
-// for a list of a few per cent of the cells in one pass
-inline int near_blocks_for(size_t N) {
-    size_t blocks = (N / 32 + 255) / 256;
-    if (blocks > 65535) blocks = 65535;
-    if (blocks < 1) blocks = 1;
-    return (int)blocks;
-}
-
 template <typename ST>
 hipError_t launch_sweep_packed_typed(int force_mode, const PackTable &t, hipStream_t s) {
     const uint32_t total = t.start[t.n];
@@ -683,28 +458,6 @@ hipError_t launch_sweep_packed_typed(int force_mode, const PackTable &t, hipStre
         hipLaunchKernelGGL((k_sweep_packed<ST, kForceDense>), dim3(total), dim3(kPackBlockX), 0, s, t);
     else
         hipLaunchKernelGGL((k_sweep_packed<ST, kForceCharge>), dim3(total), dim3(kPackBlockX), 0, s, t);
-    return hipGetLastError();
-}
-
-template <typename ST>
-hipError_t launch_near_packed_typed(const PackTable &t, hipStream_t s) {
-    const uint32_t total = t.start[t.n];
-    if (t.n == 0 || total == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_near_packed<ST>), dim3(total), dim3(256), 0, s, t);
-    return hipGetLastError();
-}
-
-template <typename ST>
-hipError_t launch_near_typed(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
-                             hipStream_t s) {
-    const size_t blocks = (size_t)near_blocks_for(a.g.N);
-    const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
-    if (small)
-        hipLaunchKernelGGL((k_near<ST, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, s, a,
-                           list, count);
-    else
-        hipLaunchKernelGGL((k_near<ST, uint64_t>), dim3((unsigned)blocks), dim3(256), 0, s, a,
-                           list, count);
     return hipGetLastError();
 }
 
