@@ -190,9 +190,10 @@ int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches);
 int lbmep_save_state(lbmep_lattice *L, const char *path);
 int lbmep_load_state(lbmep_lattice *L, const char *path);
 
-/* Device bytes held by a lattice of this configuration with n particles
- * (used for admission by footprint). */
-int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charge, size_t *bytes);
+/* Device bytes held by a lattice of this configuration with n particles of
+ * radius at most r_max (used for admission by footprint).  Errors: EINVAL. */
+int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
+                    size_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of independent simulations on one GPU.

@@ -8,6 +8,8 @@
 // sequence as a plain CPU evaluation (no contraction), so maps are
 // bit-identical to it; shared cells go to the lowest particle index via an
 // atomic minimum.
+#include <cmath>
+
 #include "lbmep_internal.h"
 
 namespace lbmep {
@@ -154,15 +156,36 @@ __global__ void __launch_bounds__(kBoxThreads)
     map_set_particle(pa, blockIdx.x, X, flag, owner);
 }
 
-// flag and blocked-direction mask of one cell from the wall bits and the map;
+// exclusive prefix of `mine` over the workgroup (256 threads); returns the
+// workgroup total in *total
+__device__ __forceinline__ uint32_t block_scan(uint32_t mine, uint32_t *wsum, uint32_t *total) {
+    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t pre = incl - mine;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    return pre;
+}
+
+// one cell's classification from the wall bits and the map (global reads):
+// its flag; *wmask = directions whose neighbour is a wall cell; *pmask =
+// directions whose neighbour is an obstacle cell of particle p (p != kNone);
 // with owner_old, a fluid cell that was an obstacle cell is marked uncovered
-__device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z, uint8_t *flag,
-                                              uint32_t *nearmask, const uint32_t *owner,
-                                              const uint32_t *owner_old) {
+__device__ __forceinline__ uint8_t classify_cell(const Grid &g, int x, int y, int z,
+                                                 const uint8_t *flag, const uint32_t *owner,
+                                                 const uint32_t *owner_old, uint32_t p,
+                                                 uint32_t *wmask, uint32_t *pmask) {
     const size_t c = cell_of(g, x, y, z);
     const uint8_t wall = flag[c] & kWall;
     uint8_t f = wall;
-    uint32_t mask = 0;
+    uint32_t mask = 0, wm = 0, pm = 0;
     if (!wall) {
         if (owner && owner[c] != kNone) {
             f = kObst;
@@ -182,7 +205,11 @@ __device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z
                 }
                 if (!solid) {
                     const size_t s = cell_of(g, sx, sy, sz);
-                    solid = (flag[s] & kWall) || (owner && owner[s] != kNone);
+                    const bool w = flag[s] & kWall;
+                    const uint32_t o = owner ? owner[s] : kNone;
+                    solid = w || o != kNone;
+                    if (w) wm |= 1u << (q - 1);
+                    if (!w && o != kNone && o == p) pm |= 1u << (q - 1);
                 }
                 if (solid) mask |= 1u << (q - 1);
             }
@@ -190,26 +217,39 @@ __device__ __forceinline__ void classify_cell(const Grid &g, int x, int y, int z
             if (owner_old && owner_old[c] != kNone) f |= kUncov;
         }
     }
-    flag[c] = f | wall;
-    nearmask[c] = mask;
+    *wmask = wm;
+    *pmask = pm;
+    return f | wall;
 }
 
-__global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *nearmask, const uint32_t *owner) {
+// the whole grid (after the flags or the particle table changed): flags and
+// the wall-link masks of every cell
+__global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *wallmask, const uint32_t *owner) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= g.nx) return;
-    classify_cell(g, x, blockIdx.y, blockIdx.z, flag, nearmask, owner, nullptr);
+    const int y = blockIdx.y, z = blockIdx.z;
+    uint32_t wm, pm;
+    const uint8_t f = classify_cell(g, x, y, z, flag, owner, nullptr, kNone, &wm, &pm);
+    const size_t c = cell_of(g, x, y, z);
+    flag[c] = f;
+    wallmask[c] = wm;
 }
 
 // solid bits of a box plus a one-cell halo, staged in LDS for the
 // classification (boxes up to kHaloCells cells; larger ones use the global
-// path)
+// path).  Bit 0: solid (wall, obstacle of the new map, beyond a non-periodic
+// edge); bit 1: obstacle cell of this particle.
 constexpr int kHaloCells = 32768;
 
+// Classification around one particle p (union of its boxes at the old and
+// new positions, grown by one cell): flags of the new level and the list of
+// p's links, (cell, directions whose neighbour is an obstacle cell of p), for
+// the bounce-back / exchange kernel.  The list is compacted in box order.
 __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
                                                   const double *Xold, const double *Xnew,
-                                                  uint8_t *flag, uint32_t *nearmask,
-                                                  const uint32_t *owner_new,
+                                                  uint8_t *flag, const uint32_t *owner_new,
                                                   const uint32_t *owner_old, uint8_t *solid) {
+    __shared__ uint32_t wsum[4];
     const Grid &g = pa.g;
     const double R = pa.R[p];
     Box b;
@@ -229,117 +269,117 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
         }
     }
     const int n = box_size(b);
-    if (n == 0) return;
+    uint2 *plist = pa.plist + (size_t)p * pa.pcap;
+    uint32_t base = 0;
     const int hx = b.cnt[0] + 2, hy = b.cnt[1] + 2, hz = b.cnt[2] + 2;
     const int hn = hx * hy * hz;
-    if (hn > kHaloCells) {
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const bool staged = n > 0 && hn <= kHaloCells;
+    if (staged) {
+        const int len[3] = {g.nx, g.ny, g.nz};
+        for (int i = threadIdx.x; i < hn; i += blockDim.x) {
+            int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy,
+                        b.lo[2] - 1 + i / (hx * hy)};
+            bool out = false;
+            for (int k = 0; k < 3; ++k) {
+                if (v[k] < 0 || v[k] >= len[k]) {
+                    if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
+                }
+            }
+            uint8_t sv = 1;
+            if (!out) {
+                const size_t c = cell_of(g, v[0], v[1], v[2]);
+                const bool w = flag[c] & kWall;
+                const uint32_t o = owner_new[c];
+                sv = (w || o != kNone) ? 1 : 0;
+                if (!w && o == (uint32_t)p) sv |= 2;
+            }
+            solid[i] = sv;
+        }
+        __syncthreads();
+    }
+    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        uint32_t cell = 0, pm = 0;
+        if (i < n) {
             int x, y, z;
             box_cell(g, b, i, x, y, z);
-            classify_cell(g, x, y, z, flag, nearmask, owner_new, owner_old);
-        }
-        return;
-    }
-    // stage: solid = wall, obstacle of the new map, or beyond a non-periodic edge
-    const int len[3] = {g.nx, g.ny, g.nz};
-    for (int i = threadIdx.x; i < hn; i += blockDim.x) {
-        int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy, b.lo[2] - 1 + i / (hx * hy)};
-        bool out = false;
-        for (int k = 0; k < 3; ++k) {
-            if (v[k] < 0 || v[k] >= len[k]) {
-                if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
-            }
-        }
-        uint8_t sv = 1;
-        if (!out) {
-            const size_t c = cell_of(g, v[0], v[1], v[2]);
-            sv = (flag[c] & kWall) || owner_new[c] != kNone;
-        }
-        solid[i] = sv;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int ix = i % b.cnt[0], iy = (i / b.cnt[0]) % b.cnt[1], iz = i / (b.cnt[0] * b.cnt[1]);
-        int x, y, z;
-        box_cell(g, b, i, x, y, z);
-        const size_t c = cell_of(g, x, y, z);
-        const uint8_t wall = flag[c] & kWall;
-        uint8_t f = wall;
-        uint32_t mask = 0;
-        if (!wall) {
-            if (owner_new[c] != kNone) {
-                f = kObst;
-            } else {
-                const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
+            const size_t c = cell_of(g, x, y, z);
+            cell = (uint32_t)c;
+            uint8_t f;
+            if (staged) {
+                const int ix = i % b.cnt[0], iy = (i / b.cnt[0]) % b.cnt[1],
+                          iz = i / (b.cnt[0] * b.cnt[1]);
+                const uint8_t wall = flag[c] & kWall;
+                f = wall;
+                if (!wall) {
+                    if (owner_new[c] != kNone) {
+                        f = kObst;
+                    } else {
+                        const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
+                        uint32_t mask = 0;
 #pragma unroll
-                for (int q = 1; q < Q; ++q)
-                    if (solid[h + kCx[q] + hx * (kCy[q] + hy * kCz[q])]) mask |= 1u << (q - 1);
-                f = mask ? kNear : 0;
-                if (owner_old[c] != kNone) f |= kUncov;
+                        for (int q = 1; q < Q; ++q) {
+                            const uint8_t sv = solid[h + kCx[q] + hx * (kCy[q] + hy * kCz[q])];
+                            if (sv & 1) mask |= 1u << (q - 1);
+                            if (sv & 2) pm |= 1u << (q - 1);
+                        }
+                        f = mask ? kNear : 0;
+                        if (owner_old[c] != kNone) f |= kUncov;
+                    }
+                }
+            } else {
+                uint32_t wm;
+                f = classify_cell(g, x, y, z, flag, owner_new, owner_old, (uint32_t)p, &wm, &pm);
             }
+            flag[c] = f;
         }
-        flag[c] = f | wall;
-        nearmask[c] = mask;
+        // append (cell, mask) of this round's cells with links into p
+        uint32_t total;
+        const uint32_t pos = base + block_scan(pm ? 1u : 0u, wsum, &total);
+        if (pm && pos < pa.pcap) plist[pos] = make_uint2(cell, pm);
+        base += total;
+        __syncthreads();  // wsum is reused by the next round
     }
+    if (threadIdx.x == 0) pa.pcount[p] = base < pa.pcap ? base : pa.pcap;
 }
 
 __global__ void __launch_bounds__(kBoxThreads)
     k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
-                     uint32_t *nearmask, const uint32_t *owner_new, const uint32_t *owner_old) {
+                     const uint32_t *owner_new, const uint32_t *owner_old) {
     __shared__ uint8_t solid[kHaloCells];
-    classify_particle(pa, blockIdx.x, Xold, Xnew, flag, nearmask, owner_new, owner_old, solid);
+    classify_particle(pa, blockIdx.x, Xold, Xnew, flag, owner_new, owner_old, solid);
 }
 
-// compact list of the fluid cells with a blocked direction, in cell order,
-// by a three-kernel scan (no contended atomics): per-block counts, a scan of
-// the counts in tiles of 1024, then each block writing its cells from its
-// offset.  A
-// thread reads the flags of 16 consecutive cells at once (the flag array is
-// padded to a multiple of kListChunk).
+// compact list, in cell order, of the cells with a wall link (wall-link mask
+// != 0), by a three-kernel scan (no contended atomics): per-block counts, a
+// scan of the counts in tiles of 1024, then each block writing its cells
+// from its offset.  A thread reads the masks of 16 consecutive cells as four
+// 16-byte loads (the mask array is padded to a multiple of kListChunk).
+// Built when the walls or the particle table are set, not per step.
 constexpr int kListCells = 16;
 constexpr int kListChunk = 256 * kListCells;
 
-__device__ __forceinline__ uint32_t near_bits(const Grid &g, const uint8_t *flag, size_t c0) {
-    const uint4 raw = *reinterpret_cast<const uint4 *>(flag + c0);
-    const uint32_t words[4] = {raw.x, raw.y, raw.z, raw.w};
-    uint32_t take = 0;  // bit k: cell c0 + k is a fluid NEAR cell
+__device__ __forceinline__ uint32_t wall_bits(const Grid &g, const uint32_t *wallmask, size_t c0) {
+    const uint4 *v = reinterpret_cast<const uint4 *>(wallmask + c0);
+    uint32_t take = 0;  // bit k: cell c0 + k has a wall link
 #pragma unroll
-    for (int k = 0; k < kListCells; ++k) {
-        const uint8_t f = (uint8_t)(words[k / 4] >> (8 * (k % 4)));
-        if ((f & kNear) && !(f & (kWall | kObst)) && c0 + k < g.N) take |= 1u << k;
+    for (int j = 0; j < kListCells / 4; ++j) {
+        const uint4 m = v[j];
+        const uint32_t w[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (w[i] && c0 + 4 * j + i < g.N) take |= 1u << (4 * j + i);
     }
     return take;
 }
 
-// exclusive prefix of `mine` over the block (256 threads); returns the
-// block total in *total
-__device__ __forceinline__ uint32_t block_scan(uint32_t mine, uint32_t *wsum, uint32_t *total) {
-    const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
-    uint32_t incl = mine;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
-        if (lane >= off) incl += t;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t pre = incl - mine;
-    for (int w = 0; w < wave; ++w) pre += wsum[w];
-    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    return pre;
-}
-
-__device__ __forceinline__ void near_count_block(const Grid &g, const uint8_t *flag,
-                                                 uint32_t *bcount, uint32_t blk) {
+__global__ void __launch_bounds__(256) k_wall_count(Grid g, const uint32_t *wallmask,
+                                                    uint32_t *bcount) {
     __shared__ uint32_t wsum[4];
-    const size_t c0 = (size_t)blk * kListChunk + (size_t)threadIdx.x * kListCells;
+    const size_t c0 = (size_t)blockIdx.x * kListChunk + (size_t)threadIdx.x * kListCells;
     uint32_t total;
-    block_scan((uint32_t)__popc(near_bits(g, flag, c0)), wsum, &total);
-    if (threadIdx.x == 0) bcount[blk] = total;
-}
-
-__global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag, uint32_t *bcount) {
-    near_count_block(g, flag, bcount, blockIdx.x);
+    block_scan((uint32_t)__popc(wall_bits(g, wallmask, c0)), wsum, &total);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = total;
 }
 
 // second level of the scan: workgroup t turns the counts of list blocks
@@ -347,7 +387,8 @@ __global__ void __launch_bounds__(256) k_near_count(Grid g, const uint8_t *flag,
 // coalesced load per thread) and stores the tile total after the counts
 constexpr int kTile = 1024;
 
-__device__ __forceinline__ void near_tile_block(uint32_t *bcount, int nb, uint32_t tile) {
+__global__ void __launch_bounds__(kTile) k_wall_tiles(uint32_t *bcount, int nb) {
+    const uint32_t tile = blockIdx.x;
     __shared__ uint32_t wsum[kTile / 64];
     const int tid = threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
     const size_t i = (size_t)tile * kTile + tid;
@@ -370,19 +411,16 @@ __device__ __forceinline__ void near_tile_block(uint32_t *bcount, int nb, uint32
     }
 }
 
-__global__ void __launch_bounds__(kTile) k_near_tiles(uint32_t *bcount, int nb) {
-    near_tile_block(bcount, nb, blockIdx.x);
-}
-
 // list block blk writes its cells from its offset: the exclusive prefix
 // within its tile plus the totals of the earlier tiles; the last block also
 // stores the list length
-__device__ __forceinline__ void near_write_block(const Grid &g, const uint8_t *flag,
-                                                 const uint32_t *bcount, int nb, uint32_t *list,
-                                                 uint32_t *count, uint32_t blk) {
+__global__ void __launch_bounds__(256) k_wall_write(Grid g, const uint32_t *wallmask,
+                                                    const uint32_t *bcount, int nb,
+                                                    uint32_t *list, uint32_t *count) {
     __shared__ uint32_t wsum[4];
+    const uint32_t blk = blockIdx.x;
     const size_t c0 = (size_t)blk * kListChunk + (size_t)threadIdx.x * kListCells;
-    const uint32_t take = near_bits(g, flag, c0);
+    const uint32_t take = wall_bits(g, wallmask, c0);
     uint32_t off = bcount[blk];
     const uint32_t *tsum = bcount + nb;
     for (uint32_t t = 0; t < blk / kTile; ++t) off += tsum[t];
@@ -392,12 +430,6 @@ __device__ __forceinline__ void near_write_block(const Grid &g, const uint8_t *f
     for (int k = 0; k < kListCells; ++k)
         if (take & (1u << k)) list[pos++] = (uint32_t)(c0 + k);
     if (blk == (uint32_t)nb - 1 && threadIdx.x == 0) *count = off + total;
-}
-
-__global__ void __launch_bounds__(256) k_near_write(Grid g, const uint8_t *flag,
-                                                    const uint32_t *bcount, int nb,
-                                                    uint32_t *list, uint32_t *count) {
-    near_write_block(g, flag, bcount, nb, list, count, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -429,26 +461,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_classify_packed(PackTable t) {
     const ParticleArgs pa = d->pa;
     const int co = (int)(t.state[e] >> 1), b = 1 - co;
     classify_particle(pa, (int)(blockIdx.x - t.start[e]), d->Xheld[co], d->Xheld[b], d->flag,
-                      d->nearmask, d->owner[b], d->owner[co], solid);
-}
-
-__global__ void __launch_bounds__(256) k_near_count_packed(PackTable t) {
-    const int e = pack_find(t, blockIdx.x);
-    const LatticeDev *d = t.d[e];
-    near_count_block(d->pa.g, d->flag, d->near_bcount, blockIdx.x - t.start[e]);
-}
-
-__global__ void __launch_bounds__(kTile) k_near_tiles_packed(PackTable t) {
-    const int e = pack_find(t, blockIdx.x);
-    const LatticeDev *d = t.d[e];
-    near_tile_block(d->near_bcount, d->list_blocks, blockIdx.x - t.start[e]);
-}
-
-__global__ void __launch_bounds__(256) k_near_write_packed(PackTable t) {
-    const int e = pack_find(t, blockIdx.x);
-    const LatticeDev *d = t.d[e];
-    near_write_block(d->pa.g, d->flag, d->near_bcount, d->list_blocks, d->near_list,
-                     d->near_count, blockIdx.x - t.start[e]);
+                      d->owner[b], d->owner[co], solid);
 }
 
 // F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
@@ -468,18 +481,23 @@ __global__ void k_finalize_ft(int np, const double *acc, const double *X, double
 
 }  // namespace
 
-int near_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kListChunk); }
-int near_list_tiles(const Grid &g) { return (near_list_blocks(g) + kTile - 1) / kTile; }
-size_t near_list_scratch(const Grid &g) {
-    return (size_t)near_list_blocks(g) + (size_t)near_list_tiles(g) + 64;
+int wall_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kListChunk); }
+int wall_list_tiles(const Grid &g) { return (wall_list_blocks(g) + kTile - 1) / kTile; }
+size_t wall_list_scratch(const Grid &g) {
+    return (size_t)wall_list_blocks(g) + (size_t)wall_list_tiles(g) + 64;
 }
 
-hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
-                            uint32_t *bcount, hipStream_t s) {
-    const int nb = near_list_blocks(g);
-    hipLaunchKernelGGL(k_near_count, dim3(nb), dim3(256), 0, s, g, flag, bcount);
-    hipLaunchKernelGGL(k_near_tiles, dim3(near_list_tiles(g)), dim3(kTile), 0, s, bcount, nb);
-    hipLaunchKernelGGL(k_near_write, dim3(nb), dim3(256), 0, s, g, flag, bcount, nb, list,
+uint32_t link_capacity(double r_max) {
+    const double e = 2.0 * std::ceil(r_max) + 3.0;
+    return (uint32_t)(e * e * e);
+}
+
+hipError_t launch_wall_list(const Grid &g, const uint32_t *wallmask, uint32_t *list,
+                            uint32_t *count, uint32_t *scratch, hipStream_t s) {
+    const int nb = wall_list_blocks(g);
+    hipLaunchKernelGGL(k_wall_count, dim3(nb), dim3(256), 0, s, g, wallmask, scratch);
+    hipLaunchKernelGGL(k_wall_tiles, dim3(wall_list_tiles(g)), dim3(kTile), 0, s, scratch, nb);
+    hipLaunchKernelGGL(k_wall_write, dim3(nb), dim3(256), 0, s, g, wallmask, scratch, nb, list,
                        count);
     return hipGetLastError();
 }
@@ -520,14 +538,6 @@ hipError_t launch_classify_packed(const PackTable &t, hipStream_t s) {
     return launch_packed(k_classify_packed, t, kBoxThreads, s);
 }
 
-hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_tiles,
-                                   hipStream_t s) {
-    hipError_t e = launch_packed(k_near_count_packed, t_cells, 256, s);
-    if (e == hipSuccess) e = launch_packed(k_near_tiles_packed, t_tiles, kTile, s);
-    if (e == hipSuccess) e = launch_packed(k_near_write_packed, t_cells, 256, s);
-    return e;
-}
-
 hipError_t launch_positions(const ParticleArgs &pa, int64_t level, double *X, hipStream_t s) {
     if (pa.np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_positions, dim3((pa.np + 127) / 128), dim3(128), 0, s, pa, level, X);
@@ -548,20 +558,20 @@ hipError_t launch_map_set(const ParticleArgs &pa, const double *X, const uint8_t
     return hipGetLastError();
 }
 
-hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
+hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *wallmask,
                                const uint32_t *owner, hipStream_t s) {
     const int bx = 64;
     hipLaunchKernelGGL(k_classify_all, dim3((g.nx + bx - 1) / bx, g.ny, g.nz), dim3(bx), 0, s, g,
-                       flag, nearmask, owner);
+                       flag, wallmask, owner);
     return hipGetLastError();
 }
 
 hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, const double *Xnew,
-                                 uint8_t *flag, uint32_t *nearmask, const uint32_t *owner_new,
+                                 uint8_t *flag, const uint32_t *owner_new,
                                  const uint32_t *owner_old, hipStream_t s) {
     if (pa.np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_classify_boxes, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, Xold, Xnew,
-                       flag, nearmask, owner_new, owner_old);
+                       flag, owner_new, owner_old);
     return hipGetLastError();
 }
 

@@ -11,9 +11,8 @@ hipError_t launch_sweep_f64(int mode, int force_mode, const SweepArgs &a, int bl
     return sweep::launch_typed<double>(mode, force_mode, a, block_x, cpt, s);
 }
 
-hipError_t launch_near_f64(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
-                           hipStream_t s) {
-    return sweep::launch_near_typed<double>(a, list, count, s);
+hipError_t launch_near_f64(const SweepArgs &a, int wall_blocks, hipStream_t s) {
+    return sweep::launch_near_typed<double>(a, wall_blocks, s);
 }
 
 hipError_t launch_sweep_packed_f64(int force_mode, const PackTable &t, hipStream_t s) {
@@ -24,6 +23,6 @@ hipError_t launch_near_packed_f64(const PackTable &t, hipStream_t s) {
     return sweep::launch_near_packed_typed<double>(t, s);
 }
 
-int near_blocks(const Grid &g) { return sweep::near_blocks_for(g.N); }
+int near_wall_blocks(const Grid &g, bool walls) { return sweep::near_wall_blocks(g.N, walls); }
 
 }  // namespace lbmep

@@ -16,14 +16,12 @@ hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs
     return sweep::launch_typed<__half>(mode, force_mode, a, block_x, cpt, s);
 }
 
-hipError_t launch_near_f64(const SweepArgs &a, const uint32_t *list, const uint32_t *count,
-                           hipStream_t s);
+hipError_t launch_near_f64(const SweepArgs &a, int wall_blocks, hipStream_t s);
 
-hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
-                       const uint32_t *count, hipStream_t s) {
-    if (precision == LBMEP_FP64) return launch_near_f64(a, list, count, s);
-    if (precision == LBMEP_FP32DEV) return sweep::launch_near_typed<float>(a, list, count, s);
-    return sweep::launch_near_typed<__half>(a, list, count, s);
+hipError_t launch_near(int precision, const SweepArgs &a, int wall_blocks, hipStream_t s) {
+    if (precision == LBMEP_FP64) return launch_near_f64(a, wall_blocks, s);
+    if (precision == LBMEP_FP32DEV) return sweep::launch_near_typed<float>(a, wall_blocks, s);
+    return sweep::launch_near_typed<__half>(a, wall_blocks, s);
 }
 
 hipError_t launch_sweep_packed_f64(int force_mode, const PackTable &t, hipStream_t s);

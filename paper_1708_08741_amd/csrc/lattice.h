@@ -34,10 +34,15 @@ struct lbmep_lattice {
     // which the sweep (or a read-out) gathers the current state
     bool pmode = false;
     uint8_t *flag = nullptr;
-    uint32_t *nearmask = nullptr;
-    uint32_t *near_list = nullptr;   // fluid cells with a blocked direction
-    uint32_t *near_count = nullptr;  // their number (device)
-    uint32_t *near_bcount = nullptr; // per-block counts of the list scan
+    uint32_t *wallmask = nullptr;     // per cell: directions whose neighbour is a wall
+    uint32_t *wall_list = nullptr;    // cells with a wall link
+    uint32_t *wall_count = nullptr;   // their number (device)
+    uint32_t *wall_scratch = nullptr; // per-block counts of the list scan
+    bool has_walls = false;           // any WALL cell (sizes the wall pass)
+    uint2 *plist = nullptr;           // per particle: link list of the current map
+    uint32_t *pcount = nullptr;       // per particle: list length
+    uint32_t pcap = 0;                // list capacity per particle
+    size_t plist_entries = 0;         // allocated entries
     uint32_t *owner[2] = {nullptr, nullptr};
     double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
     int cur_owner = 0;
@@ -82,7 +87,8 @@ size_t compute_bytes(int precision);
 bool finite_all(const double *p, size_t n);
 int check_config(const lbmep_config *cfg);
 // device bytes of a lattice (what lbmep_footprint reports)
-size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mode);
+size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
+                     int force_mode);
 
 hipError_t dev_alloc(lbmep_lattice *L, void **p, size_t bytes);
 void dev_free(lbmep_lattice *L, void *p);

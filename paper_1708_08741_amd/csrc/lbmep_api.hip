@@ -77,21 +77,18 @@ ParticleArgs particle_args(const lbmep_lattice *L) {
     pa.R = L->R;
     pa.U = L->U;
     pa.W = L->W;
+    pa.plist = L->plist;
+    pa.pcount = L->pcount;
+    pa.pcap = L->pcap;
     return pa;
 }
 
-// rebuild the list of fluid cells next to a solid cell from the flags
-int rebuild_near_list(lbmep_lattice *L) {
-    HIP_TRY(launch_near_list(L->g, L->flag, L->near_list, L->near_count, L->near_bcount,
-                             L->stream));
-    return LBMEP_OK;
-}
-
-// map the particles at `level` into both owner buffers and classify the grid
+// map the particles at `level` into both owner buffers, classify the grid,
+// list the cells with wall links, and write the particles' link lists
 int remap_all(lbmep_lattice *L) {
     hipStream_t s = L->stream;
+    const ParticleArgs pa = particle_args(L);
     if (L->np > 0) {
-        const ParticleArgs pa = particle_args(L);
         for (int b = 0; b < 2; ++b) {
             HIP_TRY(launch_fill_u32(L->owner[b], kNone, L->g.N, s));
             HIP_TRY(launch_positions(pa, L->level, L->Xheld[b], s));
@@ -101,8 +98,12 @@ int remap_all(lbmep_lattice *L) {
         L->ft_buf = 0;
         HIP_TRY(launch_fill_f64(L->FM, 0.0, 18 * (size_t)L->np, s));
     }
-    HIP_TRY(launch_classify_all(L->g, L->flag, L->nearmask, L->np > 0 ? L->owner[0] : nullptr, s));
-    return rebuild_near_list(L);
+    HIP_TRY(launch_classify_all(L->g, L->flag, L->wallmask, L->np > 0 ? L->owner[0] : nullptr, s));
+    HIP_TRY(launch_wall_list(L->g, L->wallmask, L->wall_list, L->wall_count, L->wall_scratch, s));
+    if (L->np > 0)
+        HIP_TRY(launch_classify_boxes(pa, L->Xheld[0], L->Xheld[0], L->flag, L->owner[0],
+                                      L->owner[0], s));
+    return LBMEP_OK;
 }
 
 SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
@@ -111,7 +112,7 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.src = L->f[cur];
     a.dst = L->f[1 - cur];
     a.flag = L->flag;
-    a.nearmask = L->nearmask;
+    a.nearmask = L->wallmask;
     const bool parts = L->np > 0;
     a.owner = parts ? L->owner[co] : nullptr;
     a.owner_old = parts ? L->owner[1 - co] : nullptr;
@@ -128,6 +129,12 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.ao = L->ao;
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
+    a.np = L->np;
+    a.pcap = L->pcap;
+    a.plist = L->plist;
+    a.pcount = L->pcount;
+    a.wlist = L->wall_list;
+    a.wcount = L->wall_count;
     return a;
 }
 
@@ -161,16 +168,22 @@ void free_particles(lbmep_lattice *L) {
     dev_free(L, L->FM);
     dev_free(L, L->Xheld[0]);
     dev_free(L, L->Xheld[1]);
+    dev_free(L, L->pcount);
     L->X0 = L->R = L->U = L->W = L->FM = L->Xheld[0] = L->Xheld[1] = nullptr;
+    L->pcount = nullptr;
     L->np_cap = 0;
 }
 
-size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mode) {
+size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
+                     int force_mode) {
     const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
     const size_t Ns = round_up(N, 128);
     size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
-    b += round_up(N, 4096) + 4 * N + 4 * N;                    // flags, near masks, near list
-    if (n_particles > 0) b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;
+    b += round_up(N, 4096) + 4 * round_up(N, 4096) + 4 * N;      // flags, wall masks, wall list
+    if (n_particles > 0) {
+        b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;  // maps, particle table
+        b += (size_t)n_particles * (8 * (size_t)link_capacity(r_max) + 4);  // link lists
+    }
     if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
     if (force_mode == kForceCharge) b += Ns * compute_bytes(cfg->precision);
     Grid g{};
@@ -179,7 +192,7 @@ size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, int force_mod
     g.nz = cfg->nz;
     g.N = N;
     g.Ns = Ns;
-    b += 4 * near_list_scratch(g) + 256;                          // list scan, list length
+    b += 4 * wall_list_scratch(g) + 256;                          // list scan, list length
     b += (5 * (size_t)invariants_blocks(g) + 4) * sizeof(double);  // reductions
     return b;
 }
@@ -208,11 +221,13 @@ extern "C" {
 
 const char *lbmep_last_error(void) { return g_err.c_str(); }
 
-int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, int with_charge, size_t *bytes) {
+int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
+                    size_t *bytes) {
     int rc = check_config(cfg);
     if (rc) return rc;
-    if (!bytes || n_particles < 0) return fail(LBMEP_EINVAL, "bad footprint arguments");
-    *bytes = lattice_bytes(cfg, n_particles, with_charge ? kForceCharge : kForceNone);
+    if (!bytes || n_particles < 0 || !(r_max >= 0.0) || !std::isfinite(r_max))
+        return fail(LBMEP_EINVAL, "bad footprint arguments");
+    *bytes = lattice_bytes(cfg, n_particles, r_max, with_charge ? kForceCharge : kForceNone);
     return LBMEP_OK;
 }
 
@@ -234,10 +249,11 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->f[0]);
     dev_free(L, L->f[1]);
     dev_free(L, L->flag);
-    dev_free(L, L->nearmask);
-    dev_free(L, L->near_list);
-    dev_free(L, L->near_count);
-    dev_free(L, L->near_bcount);
+    dev_free(L, L->wallmask);
+    dev_free(L, L->wall_list);
+    dev_free(L, L->wall_count);
+    dev_free(L, L->wall_scratch);
+    dev_free(L, L->plist);
     dev_free(L, L->owner[0]);
     dev_free(L, L->owner[1]);
     dev_free(L, L->force);
@@ -301,10 +317,11 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     ok = ok && dev_alloc(L, (void **)&L->f[1], Q * g.Ns * es) == hipSuccess;
     // flags padded for the 16-byte reads of the NEAR-list compaction
     ok = ok && dev_alloc(L, (void **)&L->flag, round_up(g.N, 4096)) == hipSuccess;
-    ok = ok && dev_alloc(L, (void **)&L->nearmask, 4 * g.N) == hipSuccess;
-    ok = ok && dev_alloc(L, (void **)&L->near_list, 4 * g.N) == hipSuccess;
-    ok = ok && dev_alloc(L, (void **)&L->near_count, 256) == hipSuccess;
-    ok = ok && dev_alloc(L, (void **)&L->near_bcount, 4 * near_list_scratch(g)) == hipSuccess;
+    // wall masks padded for the 16-byte reads of the list compaction
+    ok = ok && dev_alloc(L, (void **)&L->wallmask, 4 * round_up(g.N, 4096)) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->wall_list, 4 * g.N) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->wall_count, 256) == hipSuccess;
+    ok = ok && dev_alloc(L, (void **)&L->wall_scratch, 4 * wall_list_scratch(g)) == hipSuccess;
     L->red_blocks = invariants_blocks(g);
     ok = ok && dev_alloc(L, (void **)&L->red, (5 * (size_t)L->red_blocks + 4) * sizeof(double)) == hipSuccess;
     if (!ok) {
@@ -313,9 +330,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     }
     hipStream_t s = L->stream;
     hipError_t e = hipMemsetAsync(L->flag, 0, round_up(g.N, 4096), s);
-    if (e == hipSuccess) e = launch_classify_all(g, L->flag, L->nearmask, nullptr, s);
+    if (e == hipSuccess) e = hipMemsetAsync(L->wallmask, 0, 4 * round_up(g.N, 4096), s);
+    if (e == hipSuccess) e = launch_classify_all(g, L->flag, L->wallmask, nullptr, s);
     if (e == hipSuccess)
-        e = launch_near_list(g, L->flag, L->near_list, L->near_count, L->near_bcount, s);
+        e = launch_wall_list(g, L->wallmask, L->wall_list, L->wall_count, L->wall_scratch, s);
     const double u0[3] = {0, 0, 0};
     if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[0], 1.0, u0, s);
     if (e == hipSuccess) e = launch_init_equilibrium(L->precision, g, L->f[1], 1.0, u0, s);
@@ -360,6 +378,13 @@ int lbmep_set_flags(lbmep_lattice *L, const uint8_t *flags, int on_device) {
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    // the wall pass of the exchange kernel is launched only with wall cells
+    // (device flags are not inspected on the host: assume some)
+    L->has_walls = true;
+    if (!on_device) {
+        L->has_walls = false;
+        for (size_t i = 0; i < N && !L->has_walls; ++i) L->has_walls = flags[i] == LBMEP_WALL;
+    }
     return remap_all(L);
 }
 
@@ -397,7 +422,8 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
         bool ok = dev_alloc(L, (void **)&L->X0, b) == hipSuccess && dev_alloc(L, (void **)&L->U, b) == hipSuccess &&
                   dev_alloc(L, (void **)&L->W, b) == hipSuccess && dev_alloc(L, (void **)&L->R, b / 3) == hipSuccess &&
                   dev_alloc(L, (void **)&L->FM, 6 * b) == hipSuccess && dev_alloc(L, (void **)&L->Xheld[0], b) == hipSuccess &&
-                  dev_alloc(L, (void **)&L->Xheld[1], b) == hipSuccess;
+                  dev_alloc(L, (void **)&L->Xheld[1], b) == hipSuccess &&
+                  dev_alloc(L, (void **)&L->pcount, 4 * (size_t)n) == hipSuccess;
         if (!ok) {
             free_particles(L);
             L->np = 0;
@@ -405,6 +431,21 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
         }
         L->np_cap = n;
     }
+    // link lists: capacity per particle from the largest radius
+    double rmax = 0.0;
+    for (int i = 0; i < n; ++i) rmax = R[i] > rmax ? R[i] : rmax;
+    const uint32_t pcap = n > 0 ? link_capacity(rmax) : 0;
+    if ((size_t)n * pcap > L->plist_entries) {
+        dev_free(L, L->plist);
+        L->plist = nullptr;
+        L->plist_entries = 0;
+        if (dev_alloc(L, (void **)&L->plist, (size_t)n * pcap * sizeof(uint2)) != hipSuccess) {
+            L->np = 0;
+            return fail(LBMEP_ENOMEM, "link list allocation failed");
+        }
+        L->plist_entries = (size_t)n * pcap;
+    }
+    L->pcap = pcap;
     L->np = n;
     L->hX0.assign(X, X + 3 * (size_t)n);
     L->hR.assign(R, R + n);
@@ -559,7 +600,6 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     hipStream_t s = L->stream;
     const ParticleArgs pa = particle_args(L);
     for (int32_t it = 0; it < nsteps; ++it) {
-        if (L->np > 0) HIP_TRY(launch_fill_f64(L->FM, 0.0, 12 * (size_t)L->np, s));
         const SweepArgs a = sweep_args(L);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {
@@ -579,7 +619,7 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
                              L->block_x, L->cpt, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
         // bounce-back slots and momentum exchange next to solid cells
-        HIP_TRY(launch_near(L->precision, a, L->near_list, L->near_count, s));
+        HIP_TRY(launch_near(L->precision, a, near_wall_blocks(L->g, L->has_walls), s));
         if (L->np > 0 && L->cfg.move_particles) {
             // kinematics, re-mapping and classification of the next level
             const int b = 1 - L->cur_owner;
@@ -587,9 +627,7 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
             HIP_TRY(launch_advance(pa, L->level + 1, L->Xheld[b], L->owner[b], s));
             HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
             HIP_TRY(launch_classify_boxes(pa, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
-                                          L->nearmask, L->owner[b], L->owner[L->cur_owner], s));
-            int rc2 = rebuild_near_list(L);
-            if (rc2) return rc2;
+                                          L->owner[b], L->owner[L->cur_owner], s));
         }
         advance_state(L);
     }

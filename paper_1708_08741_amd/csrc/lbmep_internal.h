@@ -56,7 +56,7 @@ struct SweepArgs {
     const void *src;
     void *dst;
     const uint8_t *flag;
-    const uint32_t *nearmask;
+    const uint32_t *nearmask;   // per cell: directions whose neighbour is a wall cell
     const uint32_t *owner;      // map of the current time level
     const uint32_t *owner_old;  // map of the previous time level (refill)
     const double *Xc;  // particle centres of the current time level (3n)
@@ -69,6 +69,12 @@ struct SweepArgs {
     double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
     int nxb;                // x-segments per row (set by the launcher)
     int xcd_swizzle;        // 1: map consecutive segments onto one XCD
+    int np;                 // particles
+    uint32_t pcap;          // link-list capacity per particle
+    const uint2 *plist;     // per particle: (cell, directions into the particle)
+    const uint32_t *pcount; // per particle: list length
+    const uint32_t *wlist;  // cells with a wall link (fixed while the walls are)
+    const uint32_t *wcount; // their number (device)
 };
 
 // sweep modes: gather + collide, collide in place, gather only (read-out)
@@ -80,7 +86,14 @@ struct ParticleArgs {
     int np;
     int moving;
     const double *X0, *R, *U, *W;
+    uint2 *plist;      // link lists written by the classification
+    uint32_t *pcount;
+    uint32_t pcap;
 };
+
+// link-list capacity per particle for radii up to r_max: the cells whose
+// centre lies within one cell (per axis) of the ball, (2 ceil(R) + 3)^3
+uint32_t link_capacity(double r_max);
 
 // ---------------------------------------------------------------------------
 // Packed launches: one dispatch runs a kernel of the step for several
@@ -96,12 +109,9 @@ struct LatticeDev {
     SweepArgs sweep[4];
     ParticleArgs pa;
     uint8_t *flag;
-    uint32_t *nearmask, *near_list, *near_count, *near_bcount;
     uint32_t *owner[2];
     double *Xheld[2];
-    int nacc;         // FP64 accumulators (12 per particle) the sweep clears
-    int near_blocks;  // workgroups of the bounce-back / exchange kernel
-    int list_blocks;  // workgroups of the NEAR-list scan
+    int wall_blocks;  // workgroups of the wall links in the exchange kernel
 };
 
 struct PackTable {
@@ -133,17 +143,17 @@ constexpr int kPackBlockX = 128;
 hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs &a, int block_x,
                         int cpt, hipStream_t s);
 
-// bounce-back slots and momentum exchange of the listed NEAR cells, after a
-// sweep (count read on the device)
-hipError_t launch_near(int precision, const SweepArgs &a, const uint32_t *list,
-                       const uint32_t *count, hipStream_t s);
-// compact list of the fluid NEAR cells in cell order; bcount is scratch of
-// near_list_scratch(g) entries
-int near_list_blocks(const Grid &g);
-int near_list_tiles(const Grid &g);
-size_t near_list_scratch(const Grid &g);
-hipError_t launch_near_list(const Grid &g, const uint8_t *flag, uint32_t *list, uint32_t *count,
-                            uint32_t *bcount, hipStream_t s);
+// bounce-back slots and momentum exchange after a sweep: one workgroup per
+// particle over its link list, then wall_blocks workgroups over the wall list
+hipError_t launch_near(int precision, const SweepArgs &a, int wall_blocks, hipStream_t s);
+int near_wall_blocks(const Grid &g, bool walls);
+// compact list, in cell order, of the cells with a wall link (wallmask != 0);
+// scratch of wall_list_scratch(g) entries
+int wall_list_blocks(const Grid &g);
+int wall_list_tiles(const Grid &g);
+size_t wall_list_scratch(const Grid &g);
+hipError_t launch_wall_list(const Grid &g, const uint32_t *wallmask, uint32_t *list,
+                            uint32_t *count, uint32_t *scratch, hipStream_t s);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, size_t n, hipStream_t s);
@@ -176,13 +186,14 @@ hipError_t launch_map_clear(const ParticleArgs &pa, const double *X, uint32_t *o
                             hipStream_t s);
 hipError_t launch_map_set(const ParticleArgs &pa, const double *X, const uint8_t *flag,
                           uint32_t *owner, hipStream_t s);
-// classify cells (flags + near masks) over the whole grid
-hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *nearmask,
+// classify cells (flags + wall-link masks) over the whole grid
+hipError_t launch_classify_all(const Grid &g, uint8_t *flag, uint32_t *wallmask,
                                const uint32_t *owner, hipStream_t s);
 // classify around every particle (union of the boxes at Xold and Xnew,
-// grown by one cell), marking uncovered cells for the refill in the sweep
+// grown by one cell), marking uncovered cells for the refill in the sweep,
+// and write each particle's link list
 hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, const double *Xnew,
-                                 uint8_t *flag, uint32_t *nearmask, const uint32_t *owner_new,
+                                 uint8_t *flag, const uint32_t *owner_new,
                                  const uint32_t *owner_old, hipStream_t s);
 // final force and torque (6n: F then M per particle) from the 12n sweep
 // accumulators and the particle centres of the streamed time level
@@ -202,12 +213,6 @@ hipError_t launch_near_packed(int precision, const PackTable &t, hipStream_t s);
 hipError_t launch_advance_packed(const PackTable &t, hipStream_t s);
 hipError_t launch_map_set_packed(const PackTable &t, hipStream_t s);
 hipError_t launch_classify_packed(const PackTable &t, hipStream_t s);
-// NEAR-list scan: t_cells for the count / write kernels (list_blocks per
-// entry), t_tiles for the tile scan (near_list_tiles per entry)
-hipError_t launch_near_list_packed(const PackTable &t_cells, const PackTable &t_tiles,
-                                   hipStream_t s);
-// workgroups of the bounce-back / exchange kernel for a grid
-int near_blocks(const Grid &g);
 // single-lattice form of the advance kernel
 hipError_t launch_advance(const ParticleArgs &pa, int64_t level, double *X, uint32_t *owner,
                           hipStream_t s);

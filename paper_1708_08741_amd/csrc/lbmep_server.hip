@@ -25,6 +25,7 @@
 // per-particle sums use FP64 atomics, whose order may differ.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -174,10 +175,10 @@ hipEvent_t get_event(lbmep_server *S) {
     return e;
 }
 
-size_t request_footprint(const lbmep_config &c, int32_t n, bool charge, bool flags,
+size_t request_footprint(const lbmep_config &c, int32_t n, double r_max, bool charge, bool flags,
                          bool keep_fields) {
     const size_t N = (size_t)c.nx * c.ny * c.nz;
-    size_t b = lattice_bytes(&c, n, charge ? kForceCharge : kForceNone);
+    size_t b = lattice_bytes(&c, n, r_max, charge ? kForceCharge : kForceNone);
     b += 32 * Arena::kAlign;                 // alignment of the lattice's arrays
     b += round_up(sizeof(LatticeDev), Arena::kAlign);
     // staging of the inputs during set-up
@@ -232,17 +233,11 @@ int admit(lbmep_server *S, Slot &slot, Request *r) {
         }
     h.pa = particle_args(L);
     h.flag = L->flag;
-    h.nearmask = L->nearmask;
-    h.near_list = L->near_list;
-    h.near_count = L->near_count;
-    h.near_bcount = L->near_bcount;
     for (int b = 0; b < 2; ++b) {
         h.owner[b] = L->owner[b];
         h.Xheld[b] = L->Xheld[b];
     }
-    h.nacc = L->np > 0 ? 12 * L->np : 0;
-    h.near_blocks = near_blocks(L->g);
-    h.list_blocks = near_list_blocks(L->g);
+    h.wall_blocks = near_wall_blocks(L->g, L->has_walls);
     LatticeDev *d = static_cast<LatticeDev *>(S->arena.alloc(sizeof(LatticeDev)));
     if (!d) return undo(fail(LBMEP_ENOMEM, "arena exhausted (descriptor)"));
     double *fields = nullptr;
@@ -368,7 +363,8 @@ int enqueue_steps(lbmep_server *S, const std::vector<Slot *> &act, int k) {
                     ts.state[ts.n] = tn.state[tn.n] = state;
                     ts.level[ts.n] = tn.level[tn.n] = L->level;
                     ts.start[ts.n + 1] = ts.start[ts.n] + sb;
-                    tn.start[tn.n + 1] = tn.start[tn.n] + (uint32_t)near_blocks(L->g);
+                    tn.start[tn.n + 1] =
+                        tn.start[tn.n] + (uint32_t)(L->np + near_wall_blocks(L->g, L->has_walls));
                     ts.n++;
                     tn.n++;
                     if (ts.n == kMaxPack) {
@@ -379,33 +375,26 @@ int enqueue_steps(lbmep_server *S, const std::vector<Slot *> &act, int k) {
                 int rc = flush();
                 if (rc) return rc;
             }
-        // kinematics and re-mapping of every moving lattice
-        PackTable tp{}, tc{}, to{};
+        // kinematics, re-mapping and classification (with the link lists)
+        // of every moving lattice
+        PackTable tp{};
         auto flush_p = [&]() -> int {
             if (tp.n == 0) return LBMEP_OK;
             LBMEP_HIP_TRY(launch_advance_packed(tp, s));
             LBMEP_HIP_TRY(launch_map_set_packed(tp, s));
             LBMEP_HIP_TRY(launch_classify_packed(tp, s));
-            LBMEP_HIP_TRY(launch_near_list_packed(tc, to, s));
-            S->st.packed_launches += 6;
-            tp.n = tc.n = to.n = 0;
+            S->st.packed_launches += 3;
+            tp.n = 0;
             return LBMEP_OK;
         };
         for (Slot *sl : act) {
             lbmep_lattice *L = sl->L;
             if (!(L->np > 0 && L->cfg.move_particles)) continue;
-            const uint32_t state = (uint32_t)(L->cur | (L->cur_owner << 1));
-            for (PackTable *t : {&tp, &tc, &to}) {
-                t->d[t->n] = sl->d;
-                t->state[t->n] = state;
-                t->level[t->n] = L->level + 1;
-            }
+            tp.d[tp.n] = sl->d;
+            tp.state[tp.n] = (uint32_t)(L->cur | (L->cur_owner << 1));
+            tp.level[tp.n] = L->level + 1;
             tp.start[tp.n + 1] = tp.start[tp.n] + (uint32_t)L->np;
-            tc.start[tc.n + 1] = tc.start[tc.n] + (uint32_t)near_list_blocks(L->g);
-            to.start[to.n + 1] = to.start[to.n] + (uint32_t)near_list_tiles(L->g);
             tp.n++;
-            tc.n++;
-            to.n++;
             if (tp.n == kMaxPack) {
                 int rc = flush_p();
                 if (rc) return rc;
@@ -556,7 +545,9 @@ int lbmep_server_request_footprint(const lbmep_request *q, size_t *bytes) {
     if (!q || !bytes) return fail(LBMEP_EINVAL, "null argument");
     int rc = check_config(&q->cfg);
     if (rc) return rc;
-    *bytes = request_footprint(q->cfg, q->n, q->rho_e != nullptr, q->flags != nullptr,
+    double rmax = 0.0;
+    for (int i = 0; q->R && i < q->n; ++i) rmax = std::max(rmax, q->R[i]);
+    *bytes = request_footprint(q->cfg, q->n, rmax, q->rho_e != nullptr, q->flags != nullptr,
                                q->keep_fields != 0);
     return LBMEP_OK;
 }
@@ -578,7 +569,10 @@ int lbmep_server_submit(lbmep_server *S, const lbmep_request *q, uint64_t *id) {
         return fail(LBMEP_EINVAL, "grid too large for the packed sweep (two population grids "
                                   "must be below 4 GiB)");
     const size_t N = (size_t)c.nx * c.ny * c.nz;
-    const size_t fp = request_footprint(c, q->n, q->rho_e != nullptr, q->flags != nullptr,
+    double rmax = 0.0;
+    for (int i = 0; i < q->n; ++i)
+        if (std::isfinite(q->R[i])) rmax = std::max(rmax, q->R[i]);
+    const size_t fp = request_footprint(c, q->n, rmax, q->rho_e != nullptr, q->flags != nullptr,
                                         q->keep_fields != 0);
     if (fp > S->arena.size()) return fail(LBMEP_EINVAL, "request footprint exceeds the budget");
     if ((int32_t)S->queue.size() >= S->cfg.max_queue) return fail(LBMEP_EBUSY, "queue full");

@@ -429,23 +429,13 @@ __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
     sweep_segment<ST, FMODE, OFF, MODE, CPT>(a, lb);
 }
 
-// the gather sweep of several lattices in one dispatch; each workgroup also
-// clears its share of the lattice's per-particle accumulators, which the
-// exchange kernel that follows sums into
+// the gather sweep of several lattices in one dispatch
 template <typename ST, int FMODE>
 __global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
     const uint32_t gb = t.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int e = pack_find(t, gb);
-    const LatticeDev *d = t.d[e];
-    const SweepArgs a = d->sweep[t.state[e]];
-    const uint32_t lb = gb - t.start[e];
-    if (a.FM) {
-        const uint32_t nb = t.start[e + 1] - t.start[e];
-        for (uint32_t i = lb * blockDim.x + threadIdx.x; i < (uint32_t)d->nacc;
-             i += nb * blockDim.x)
-            a.FM[i] = 0.0;
-    }
-    sweep_segment<ST, FMODE, uint32_t, kPull, 1>(a, lb);
+    const SweepArgs a = t.d[e]->sweep[t.state[e]];
+    sweep_segment<ST, FMODE, uint32_t, kPull, 1>(a, gb - t.start[e]);
 }
 
 template <typename ST>

@@ -106,8 +106,8 @@ _SIGS = {
     "lbmep_get_timing": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbmep_save_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "lbmep_load_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
-    "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int,
-                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "lbmep_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig),
                                            ctypes.POINTER(ctypes.c_void_p)]),
     "lbmep_server_destroy": (ctypes.c_int, [_P]),
@@ -184,11 +184,11 @@ def make_config(shape, periodic=(True, True, True), nu=1.0 / 6.0, magic=3.0 / 16
     return c
 
 
-def footprint(shape, precision=FP64, n_particles=0, with_charge=False, **kw):
+def footprint(shape, precision=FP64, n_particles=0, with_charge=False, r_max=8.0, **kw):
     cfg = make_config(shape, precision=precision, **kw)
     out = ctypes.c_size_t(0)
-    _check(lib().lbmep_footprint(ctypes.byref(cfg), int(n_particles), 1 if with_charge else 0,
-                                 ctypes.byref(out)))
+    _check(lib().lbmep_footprint(ctypes.byref(cfg), int(n_particles), float(r_max),
+                                 1 if with_charge else 0, ctypes.byref(out)))
     return out.value
 
 

@@ -5,9 +5,8 @@ launches.
   step counts, served with fewer slots than requests (so that requests are
   admitted while others run) and a chunk length that does not divide the step
   counts, gives every request the result it has alone on a plain lattice:
-  fields and FP64 invariants bitwise; forces and torques within 1e-13 of
-  max |F| (only the order of the FP64 atomic additions differs, over a few
-  hundred terms of size <= max |F|).
+  fields, FP64 invariants, forces and torques bitwise (the per-particle sums
+  are formed in one workgroup in a fixed order).
 * An FP64 request served in the mix matches the FP64 CPU oracle (1e-12).
 * Admission respects the HBM budget: with a budget for two requests at a
   time, never more than two are resident.
@@ -99,10 +98,7 @@ def test_mix_equals_alone(lb):
         rho_a, u_a, inv_a, F_a, M_a = _alone(lb, q)
         assert (rho == rho_a).all() and (u == u_a).all(), q["shape"]
         assert (inv == inv_a).all(), (inv, inv_a)
-        if len(q["R"]):
-            sF = max(np.abs(F_a).max(), 1e-300)
-            assert np.abs(F - F_a).max() <= 1e-13 * sF
-            assert np.abs(M - M_a).max() <= 1e-13 * sF * max(q["R"])
+        assert (F == F_a).all() and (M == M_a).all()
         assert t[0] <= t[1] <= t[2]
         srv.release(rid)
     srv.close()

@@ -95,12 +95,16 @@ def test_library_is_gfx950_only():
     ((64, 96, 128), lb.FP32DEV, 200, True),
 ])
 def test_footprint(shape, prec, np_, charge):
-    """Footprint = two population grids + flags/masks (+ maps, force)."""
-    b = lb.footprint(shape, prec, np_, charge)
+    """Footprint = two population grids + flags/masks (+ maps, force, the
+    particles' link lists, which grow with the largest radius)."""
+    b = lb.footprint(shape, prec, np_, charge, r_max=4.0)
     N = shape[0] * shape[1] * shape[2]
     es = {lb.FP64: 8, lb.FP32DEV: 4, lb.FP16DEV: 2}[prec]
     pops = 2 * 19 * N * es
-    assert pops < b < pops + 18 * N + 8 * N + 10_000_000
+    links = np_ * (8 * 11 ** 3 + 4)  # (2 ceil(R) + 3)^3 entries of 8 bytes per particle
+    assert pops + links < b < pops + links + 18 * N + 8 * N + 10_000_000
+    if np_:
+        assert lb.footprint(shape, prec, np_, charge, r_max=8.0) - b == np_ * 8 * (19 ** 3 - 11 ** 3)
     if shape == (512, 512, 512) and prec == lb.FP32DEV:
         assert 20.4e9 < b < 24e9  # fits one MI355X (288 GB) many times over
 
