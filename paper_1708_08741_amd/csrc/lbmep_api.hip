@@ -298,8 +298,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     }
     // launch shape of the sweep: x-segments of block_x threads (whole
     // wavefronts), cpt cells per thread on consecutive rows, dealt onto XCDs
-    // in contiguous runs; LBMEP_BLOCK_X, LBMEP_CPT and LBMEP_XCD_SWIZZLE
-    // override the defaults for launch-shape sweeps
+    // in contiguous runs, streaming (non-temporal) hints on its loads and
+    // stores (every value is read once and written once per step);
+    // LBMEP_BLOCK_X, LBMEP_CPT, LBMEP_XCD_SWIZZLE and LBMEP_SWEEP_NT override
+    // the defaults for launch-shape sweeps
     L->block_x = 128;
     L->cpt = 1;
     if (const char *e = std::getenv("LBMEP_CPT")) {
@@ -311,6 +313,7 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
     }
     if (const char *e = std::getenv("LBMEP_XCD_SWIZZLE")) L->xcd_swizzle = std::atoi(e) != 0;
+    if (const char *e = std::getenv("LBMEP_SWEEP_NT")) L->sweep_nt = std::atoi(e) != 0;
     const size_t es = storage_bytes(L->precision);
     bool ok = true;
     ok = ok && dev_alloc(L, (void **)&L->f[0], Q * g.Ns * es) == hipSuccess;
@@ -615,8 +618,8 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         }
         // gather + refill + collide + bounce-back slots (or, right after the
         // state was set, collide the stored post-stream state in place)
-        HIP_TRY(launch_sweep(L->precision, L->pmode ? kSweepPull : kSweepLocal, L->force_mode, a,
-                             L->block_x, L->cpt, s));
+        const int mode = L->pmode ? (L->sweep_nt ? kSweepPullNT : kSweepPull) : kSweepLocal;
+        HIP_TRY(launch_sweep(L->precision, mode, L->force_mode, a, L->block_x, L->cpt, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
         // bounce-back slots and momentum exchange next to solid cells
         HIP_TRY(launch_near(L->precision, a, near_wall_blocks(L->g, L->has_walls), s));

@@ -78,7 +78,7 @@ struct SweepArgs {
 };
 
 // sweep modes: gather + collide, collide in place, gather only (read-out)
-enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2 };
+enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2, kSweepPullNT = 3 };
 
 // particle table of one lattice (device pointers)
 struct ParticleArgs {

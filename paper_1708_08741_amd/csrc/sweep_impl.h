@@ -39,6 +39,13 @@ struct Storage<double> {
     using CT = double;
     static __device__ __forceinline__ double load(const double *p) { return *p; }
     static __device__ __forceinline__ void store(double *p, double v) { *p = v; }
+    // streaming forms (non-temporal hint: each value is read or written once)
+    static __device__ __forceinline__ double load_nt(const double *p) {
+        return __builtin_nontemporal_load(p);
+    }
+    static __device__ __forceinline__ void store_nt(double *p, double v) {
+        __builtin_nontemporal_store(v, p);
+    }
     // deviation f - w_q of a computed population q, in FP64
     static __device__ __forceinline__ double devval(double v, int q) { return v - wq(q); }
     // f^eq(rho0 = 1, u) of population q (Eq. fequ_Incompr_SRT) as stored
@@ -51,6 +58,12 @@ struct Storage<float> {
     using CT = float;
     static __device__ __forceinline__ float load(const float *p) { return *p; }
     static __device__ __forceinline__ void store(float *p, float v) { *p = v; }
+    static __device__ __forceinline__ float load_nt(const float *p) {
+        return __builtin_nontemporal_load(p);
+    }
+    static __device__ __forceinline__ void store_nt(float *p, float v) {
+        __builtin_nontemporal_store(v, p);
+    }
     static __device__ __forceinline__ double devval(float v, int q) { return (double)v; }
     static __device__ __forceinline__ float feq(int q, double d) { return (float)(wq(q) * d); }
 };
@@ -64,6 +77,14 @@ struct Storage<__half> {
     }
     static __device__ __forceinline__ void store(__half *p, float v) {
         *p = __float2half_rn(v * kHalfScale);
+    }
+    static __device__ __forceinline__ float load_nt(const __half *p) {
+        const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+        return __half2float(__ushort_as_half(b)) * kHalfInvScale;
+    }
+    static __device__ __forceinline__ void store_nt(__half *p, float v) {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * kHalfScale)),
+                                    reinterpret_cast<unsigned short *>(p));
     }
     static __device__ __forceinline__ double devval(float v, int q) { return (double)v; }
     // rounded to the storage format, as a stored and re-loaded value would be
@@ -132,8 +153,25 @@ __device__ __forceinline__ const ST *at(const void *base, OFF off) {
 // sweep modes
 enum { kPull = 0,     // gather f* of the previous level, refill, collide
        kLocal = 1,    // collide the post-stream state held in the grid
-       kReadout = 2   // gather and refill only: write the post-stream state
+       kReadout = 2,  // gather and refill only: write the post-stream state
+       kPullNT = 3    // as kPull, populations loaded / stored with streaming hints
 };
+
+// load / store of one stored population, with the streaming hint in kPullNT
+template <int MODE, typename ST>
+__device__ __forceinline__ typename Storage<ST>::CT pop_load(const ST *p) {
+    if constexpr (MODE == kPullNT)
+        return Storage<ST>::load_nt(p);
+    else
+        return Storage<ST>::load(p);
+}
+template <int MODE, typename ST>
+__device__ __forceinline__ void pop_store(ST *p, typename Storage<ST>::CT v) {
+    if constexpr (MODE == kPullNT)
+        Storage<ST>::store_nt(p, v);
+    else
+        Storage<ST>::store(p, v);
+}
 
 // the TRT collision of one opposite pair (q, q+1) with the forcing term
 template <int q, typename CT>
@@ -170,7 +208,7 @@ __device__ __forceinline__ void collide_pair(CT (&v)[Q], CT rho, CT ux, CT uy, C
 // gather population q of the cell from x - e_q; beyond the edge of a
 // non-periodic axis the population bounces at the (resting) edge: it is the
 // cell's own opposite population
-template <int q, typename ST, typename OFF>
+template <int q, typename ST, typename OFF, int MODE>
 __device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF pst, OFF es,
                                                            OFF cb, const OFF rows[3][3],
                                                            const bool rok[3][3], const OFF xs[3],
@@ -181,7 +219,7 @@ __device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF 
     const bool ok = rok[kCy[q] + 1][kCz[q] + 1] && xok[kCx[q] + 1];
     const OFF nb = (OFF)(q - lo) * pst + xs[kCx[q] + 1] + rows[kCy[q] + 1][kCz[q] + 1];
     const OFF own = (OFF)(qb - lo) * pst + cb;
-    return Storage<ST>::load(at<ST>(base, ok ? nb : own));
+    return pop_load<MODE, ST>(at<ST>(base, ok ? nb : own));
 }
 
 // loaded inputs of one cell
@@ -206,7 +244,12 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
     const int xc = valid ? x : 0, yc = valid ? y : 0;
     const OFF ci = (OFF)xc + (OFF)nx * ((OFF)yc + (OFF)ny * (OFF)z);
     const OFF cb = ci * es;
-    const uint8_t fl = *at<uint8_t>((const void *)a.flag, ci);
+    const uint8_t *flp = at<uint8_t>((const void *)a.flag, ci);
+    uint8_t fl;
+    if constexpr (MODE == kPullNT)
+        fl = __builtin_nontemporal_load(flp);
+    else
+        fl = *flp;
     c.fl = valid ? fl : kWall;
     if constexpr (MODE == kLocal) {
 #pragma unroll
@@ -244,8 +287,8 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
             xs[i] = (OFF)xq * es;
             xok[i] = ok;
         }
-        c.v[0] = T::load(at<ST>(a.src, cb));
-#define LBMEP_GATHER(q) c.v[q] = gather<q, ST, OFF>(a.src, pst, es, cb, rows, rok, xs, xok);
+        c.v[0] = pop_load<MODE, ST>(at<ST>(a.src, cb));
+#define LBMEP_GATHER(q) c.v[q] = gather<q, ST, OFF, MODE>(a.src, pst, es, cb, rows, rok, xs, xok);
         LBMEP_FOR_Q18(LBMEP_GATHER)
 #undef LBMEP_GATHER
     }
@@ -257,7 +300,12 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
             c.fb1 = *at<CT>(a.force, fo + fs);
             c.fb2 = *at<CT>(a.force, fo + 2 * fs);
         } else if constexpr (FMODE == kForceCharge) {
-            const CT re = *at<CT>(a.force, ci * (OFF)sizeof(CT));
+            const CT *rp = at<CT>(a.force, ci * (OFF)sizeof(CT));
+            CT re;
+            if constexpr (MODE == kPullNT)
+                re = __builtin_nontemporal_load(rp);
+            else
+                re = *rp;
             c.fb0 = re * (CT)a.E[0];
             c.fb1 = re * (CT)a.E[1];
             c.fb2 = re * (CT)a.E[2];
@@ -389,7 +437,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
             // aligned store of the post-collision state
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+                pop_store<MODE, ST>(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
         }
     }
 }
@@ -435,7 +483,7 @@ __global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
     const uint32_t gb = t.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int e = pack_find(t, gb);
     const SweepArgs a = t.d[e]->sweep[t.state[e]];
-    sweep_segment<ST, FMODE, uint32_t, kPull, 1>(a, gb - t.start[e]);
+    sweep_segment<ST, FMODE, uint32_t, kPullNT, 1>(a, gb - t.start[e]);
 }
 
 template <typename ST>
@@ -478,10 +526,11 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     } while (0)
     if (small) {
         if (mode == kPull) LBMEP_BY_CPT(kPull);
+        else if (mode == kPullNT) LBMEP_BY_FORCE(kPullNT, uint32_t, 1);
         else if (mode == kLocal) LBMEP_BY_CPT(kLocal);
         else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t, 1);
     } else {
-        if (mode == kPull) LBMEP_BY_FORCE(kPull, uint64_t, 1);
+        if (mode == kPull || mode == kPullNT) LBMEP_BY_FORCE(kPull, uint64_t, 1);
         else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint64_t, 1);
         else LBMEP_LAUNCH(kReadout, kForceNone, uint64_t, 1);
     }

@@ -178,3 +178,25 @@ def test_empty_particle_table_and_zero_steps(lb):
     g.step(5)
     F, M = g.ft()
     assert F.shape == (0, 3)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_sweep_variants_identical(lb, monkeypatch, precision):
+    """Launch-shape variants of the sweep (streaming hints on / off, one or
+    two cells per thread, XCD block order) compute bitwise the same run."""
+    ref = None
+    for env in [dict(), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
+                dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
+        for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g, _ = _moving_case(lb, precision)
+        g.step(17)
+        out = (g.get_pdfs(), g.ft())
+        g.close()
+        if ref is None:
+            ref = out
+        else:
+            assert (out[0] == ref[0]).all(), env
+            assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all(), env
