@@ -36,6 +36,11 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"fp64": 304, "fp32dev": 152, "fp16dev": 76}
 DTYPE = {"fp64": "f64", "fp32dev": "f32", "fp16dev": "f32"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_512.json")
+# the gather / collide sweep instantiation timed per precision (storage type,
+# charge force, 32-bit offsets, streaming-hint mode, one cell per thread)
+SWEEP_KERNEL = {"fp32dev": "k_sweep<float, 2, unsigned int, 4, 1>",
+                "fp64": "k_sweep<double, 2, unsigned int, 4, 1>",
+                "fp16dev": "k_sweep<__half, 2, unsigned int, 3, 1>"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "sweep_impl.h")
 
 
@@ -362,7 +367,8 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_sweep", "kernel_ms": round(res["kernel_ms"], 4),
+            "kernel": SWEEP_KERNEL.get(args.precision, "k_sweep"),
+            "kernel_ms": round(res["kernel_ms"], 4),
             "bytes_per_cell": bpc,
         },
         "cpu_baseline": cpu,

@@ -61,7 +61,7 @@ struct lbmep_lattice {
     int block_x = 128;
     int cpt = 1;  // cells per thread of the sweep (consecutive rows)
     int xcd_swizzle = 1;
-    int sweep_nt = 1;  // 1: streaming hints on the sweep's loads / stores
+    int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     bool timing = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;

@@ -313,7 +313,14 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
     }
     if (const char *e = std::getenv("LBMEP_XCD_SWIZZLE")) L->xcd_swizzle = std::atoi(e) != 0;
-    if (const char *e = std::getenv("LBMEP_SWEEP_NT")) L->sweep_nt = std::atoi(e) != 0;
+    // measured at 512^3: hints on the stores only are fastest for FP32 and
+    // FP64 storage (the loads' one-element overlaps along x then hit L2);
+    // FP16 gains from hints on the loads as well
+    L->sweep_nt = L->precision == LBMEP_FP16DEV ? 1 : 2;
+    if (const char *e = std::getenv("LBMEP_SWEEP_NT")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= 2) L->sweep_nt = v;
+    }
     const size_t es = storage_bytes(L->precision);
     bool ok = true;
     ok = ok && dev_alloc(L, (void **)&L->f[0], Q * g.Ns * es) == hipSuccess;
@@ -618,7 +625,10 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         }
         // gather + refill + collide + bounce-back slots (or, right after the
         // state was set, collide the stored post-stream state in place)
-        const int mode = L->pmode ? (L->sweep_nt ? kSweepPullNT : kSweepPull) : kSweepLocal;
+        const int mode = !L->pmode ? kSweepLocal
+                         : L->sweep_nt == 1 ? kSweepPullNT
+                         : L->sweep_nt == 2 ? kSweepPullNTS
+                                            : kSweepPull;
         HIP_TRY(launch_sweep(L->precision, mode, L->force_mode, a, L->block_x, L->cpt, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
         // bounce-back slots and momentum exchange next to solid cells

@@ -78,7 +78,13 @@ struct SweepArgs {
 };
 
 // sweep modes: gather + collide, collide in place, gather only (read-out)
-enum SweepMode { kSweepPull = 0, kSweepLocal = 1, kSweepReadout = 2, kSweepPullNT = 3 };
+enum SweepMode {
+    kSweepPull = 0,     // gather + collide
+    kSweepLocal = 1,    // collide in place
+    kSweepReadout = 2,  // gather only
+    kSweepPullNT = 3,   // gather + collide, streaming hints on loads and stores
+    kSweepPullNTS = 4   // gather + collide, streaming hints on stores
+};
 
 // particle table of one lattice (device pointers)
 struct ParticleArgs {

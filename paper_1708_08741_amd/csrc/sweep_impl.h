@@ -154,7 +154,8 @@ __device__ __forceinline__ const ST *at(const void *base, OFF off) {
 enum { kPull = 0,     // gather f* of the previous level, refill, collide
        kLocal = 1,    // collide the post-stream state held in the grid
        kReadout = 2,  // gather and refill only: write the post-stream state
-       kPullNT = 3    // as kPull, populations loaded / stored with streaming hints
+       kPullNT = 3,   // as kPull, loads and stores with streaming hints
+       kPullNTS = 4   // as kPull, stores with streaming hints
 };
 
 // load / store of one stored population, with the streaming hint in kPullNT
@@ -167,7 +168,7 @@ __device__ __forceinline__ typename Storage<ST>::CT pop_load(const ST *p) {
 }
 template <int MODE, typename ST>
 __device__ __forceinline__ void pop_store(ST *p, typename Storage<ST>::CT v) {
-    if constexpr (MODE == kPullNT)
+    if constexpr (MODE == kPullNT || MODE == kPullNTS)
         Storage<ST>::store_nt(p, v);
     else
         Storage<ST>::store(p, v);
@@ -483,7 +484,10 @@ __global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
     const uint32_t gb = t.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int e = pack_find(t, gb);
     const SweepArgs a = t.d[e]->sweep[t.state[e]];
-    sweep_segment<ST, FMODE, uint32_t, kPullNT, 1>(a, gb - t.start[e]);
+    // streaming hints as in the single-lattice default: stores only, and
+    // loads too for FP16 storage
+    constexpr int MODE = sizeof(ST) == 2 ? kPullNT : kPullNTS;
+    sweep_segment<ST, FMODE, uint32_t, MODE, 1>(a, gb - t.start[e]);
 }
 
 template <typename ST>
@@ -527,10 +531,11 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     if (small) {
         if (mode == kPull) LBMEP_BY_CPT(kPull);
         else if (mode == kPullNT) LBMEP_BY_FORCE(kPullNT, uint32_t, 1);
+        else if (mode == kPullNTS) LBMEP_BY_FORCE(kPullNTS, uint32_t, 1);
         else if (mode == kLocal) LBMEP_BY_CPT(kLocal);
         else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t, 1);
     } else {
-        if (mode == kPull || mode == kPullNT) LBMEP_BY_FORCE(kPull, uint64_t, 1);
+        if (mode == kPull || mode == kPullNT || mode == kPullNTS) LBMEP_BY_FORCE(kPull, uint64_t, 1);
         else if (mode == kLocal) LBMEP_BY_FORCE(kLocal, uint64_t, 1);
         else LBMEP_LAUNCH(kReadout, kForceNone, uint64_t, 1);
     }

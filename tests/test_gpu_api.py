@@ -185,7 +185,8 @@ def test_sweep_variants_identical(lb, monkeypatch, precision):
     """Launch-shape variants of the sweep (streaming hints on / off, one or
     two cells per thread, XCD block order) compute bitwise the same run."""
     ref = None
-    for env in [dict(), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
+    for env in [dict(), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1"),
+                dict(LBMEP_SWEEP_NT="2"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
                 dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
         for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X"):
             monkeypatch.delenv(k, raising=False)
