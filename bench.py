@@ -160,21 +160,46 @@ def _serving_inputs(r):
     return q
 
 
+class _RequestStream:
+    """Requests of the serving mix generated by a pool of host processes, at
+    most `ahead` of them in flight or buffered (bounded host memory)."""
+
+    def __init__(self, first, count, ahead=32):
+        import multiprocessing as mp
+        self.pool = mp.get_context("fork").Pool(min(16, os.cpu_count() or 1))
+        self.next_submit = first
+        self.end = first + count
+        self.pending = {}
+        self.ahead = ahead
+        self.next_take = first
+        self._fill()
+
+    def _fill(self):
+        while self.next_submit < self.end and len(self.pending) < self.ahead:
+            r = self.next_submit
+            self.pending[r] = self.pool.apply_async(_serving_inputs, (r,))
+            self.next_submit += 1
+
+    def take(self):
+        r = self.next_take
+        q = self.pending.pop(r).get()
+        self.next_take += 1
+        self._fill()
+        return q
+
+    def close(self):
+        self.pool.terminate()
+        self.pool.join()
+
+
 def serving_bench(n_load, n_sat, load, budget_gib, slots, chunk):
     """Continuous batching of the serving mix (FP32-dev, moving spheres,
-    charge force): saturated throughput with a full queue of n_sat requests,
-    then n_load requests arriving as a Poisson process at `load` times that
-    throughput; latency = completion - arrival (server clock)."""
-    import multiprocessing as mp
-
+    charge force).  Saturated throughput: n_sat requests queued at once (more
+    than the slots), cell updates completed per second while the queue is not
+    empty.  Then n_load requests arriving as a Poisson process (seed 5) at
+    `load` times that throughput; latency = completion - arrival (server
+    clock)."""
     from paper_1708_08741_amd import lbmep as lb
-
-    total = n_sat + n_load
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        reqs = pool.map(_serving_inputs, range(total))
-    log(f"[serve] {total} requests generated in {time.perf_counter() - t0:.1f} s")
-    dropped = sum(q["requested"] - len(q["R"]) for q in reqs)
 
     def work(q):
         nx, ny, nz = q["shape"]
@@ -186,39 +211,60 @@ def serving_bench(n_load, n_sat, load, budget_gib, slots, chunk):
                           precision=lb.FP32DEV, moving=True)
 
     srv = lb.Server(hbm_budget=int(budget_gib * 2 ** 30), max_slots=slots, chunk_steps=chunk)
-    # saturation: everything queued at once
-    sat = reqs[:n_sat]
-    t_a = srv.now()
+    t0 = time.perf_counter()
+    stream = _RequestStream(0, n_sat, ahead=n_sat)
+    sat = [stream.take() for _ in range(n_sat)]
+    stream.close()
+    log(f"[serve] {n_sat} saturation requests generated in {time.perf_counter() - t0:.1f} s")
+    dropped = sum(q["requested"] - len(q["R"]) for q in sat)
     ids = [submit(srv, q) for q in sat]
-    srv.wait_all(ids, timeout=900)
-    t_sat = srv.now() - t_a
+    del sat
+    # rate over the window in which requests wait (every slot or the budget busy)
+    w0 = w1 = None
+    done = set()
+    while len(done) < len(ids):
+        done.update(srv.poll())
+        st = srv.stats()
+        now = srv.now()
+        if st["cell_updates_done"] > 0 and w0 is None:
+            w0 = (now, st["cell_updates_done"])
+        if w0 is not None and (st["queued"] > 0 or w1 is None):
+            w1 = (now, st["cell_updates_done"])
+        time.sleep(2e-4)
     for i in ids:
         srv.release(i)
-    sat_rate = sum(work(q) for q in sat) / t_sat
-    log(f"[serve] saturated: {n_sat} requests in {t_sat:.2f} s = {sat_rate / 1e6:.0f} MLUPS")
+    sat_rate = (w1[1] - w0[1]) / max(w1[0] - w0[0], 1e-9)
+    log(f"[serve] saturated: {sat_rate / 1e6:.0f} MLUPS over {w1[0] - w0[0]:.2f} s "
+        f"with a full queue")
 
-    # Poisson arrivals at `load` of the saturated rate
-    mix = reqs[n_sat:]
-    mean_work = float(np.mean([work(q) for q in reqs]))
+    # Poisson arrivals at `load` of the saturated rate; inputs generated ahead
+    stream = _RequestStream(n_sat, n_load)
+    mean_work = 147.2 ** 3 * 2750.0   # expected cell updates per request of the mix
     lam = load * sat_rate / mean_work
     rng = np.random.default_rng(5)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(mix)))
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_load))
     start = srv.now()
-    ids = []
-    k = 0
+    ids, works = [], []
     done = set()
     max_res = 0
-    while len(done) < len(mix):
+    nxt = stream.take()
+    last_log = time.perf_counter()
+    while len(done) < n_load:
         now = srv.now() - start
-        while k < len(mix) and arrivals[k] <= now:
-            ids.append(submit(srv, mix[k]))
-            k += 1
-        for i in srv.poll():
-            done.add(i)
+        while nxt is not None and arrivals[len(ids)] <= now:
+            ids.append(submit(srv, nxt))
+            works.append(work(nxt))
+            dropped += nxt["requested"] - len(nxt["R"])
+            nxt = stream.take() if len(ids) < n_load else None
+        done.update(srv.poll())
         max_res = max(max_res, srv.stats()["resident"])
-        if srv.now() - start > 1800:
+        if time.perf_counter() - last_log > 30:
+            log(f"[serve] t={now:.0f} s: {len(ids)} arrived, {len(done)} done")
+            last_log = time.perf_counter()
+        if now > 36000:
             raise TimeoutError("serving run did not finish")
         time.sleep(2e-4)
+    stream.close()
     lat, t_end = [], 0.0
     for i in ids:
         _, _, _, t = srv.result(i)
@@ -228,18 +274,17 @@ def serving_bench(n_load, n_sat, load, budget_gib, slots, chunk):
     st = srv.stats()
     srv.close()
     lat = np.array(lat)
-    cells_work = sum(work(q) for q in mix)
     return {
-        "requests": len(mix), "saturation_requests": n_sat,
-        "throughput_req_per_s": round(len(mix) / span, 3),
-        "aggregate_MLUPS": round(cells_work / span / 1e6, 1),
-        "saturated_MLUPS": round(sat_rate / 1e6, 1),
-        "offered_load": load, "arrival_rate_per_s": round(lam, 4),
+        "requests": n_load, "saturation_requests": n_sat,
+        "throughput_req_per_s": round(float(n_load / span), 3),
+        "aggregate_MLUPS": round(float(sum(works) / span / 1e6), 1),
+        "saturated_MLUPS": round(float(sat_rate / 1e6), 1),
+        "offered_load": load, "arrival_rate_per_s": round(float(lam), 4),
         "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
         "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
         "latency_max_s": round(float(lat.max()), 3),
         "max_resident": max_res, "slots": slots, "chunk_steps": chunk,
-        "hbm_budget_GiB": budget_gib, "packed_launches": st["packed_launches"],
+        "hbm_budget_GiB": budget_gib, "packed_launches": int(st["packed_launches"]),
         "spheres_dropped_by_rsa": int(dropped),
         "mix": "edges {64,96,128,192,256}^3, 1-200 spheres R 3-8, 500-5000 steps, FP32-dev",
     }
@@ -258,8 +303,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the Poisson-arrival serving run (0 = no serving leg)")
-    ap.add_argument("--serve-sat-requests", type=int, default=24,
-                    help="requests of the saturated-throughput serving run")
+    ap.add_argument("--serve-sat-requests", type=int, default=48,
+                    help="requests of the saturated-throughput serving run (more than the "
+                         "slots: the rate is taken while requests wait)")
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=32)

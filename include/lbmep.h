@@ -245,7 +245,8 @@ typedef struct {
     uint64_t submitted, admitted, completed, failed;
     int32_t queued, resident;
     uint64_t chunks, steps, packed_launches;
-    double cell_updates;     /* lattice cells advanced (all cells of every step) */
+    double cell_updates;     /* lattice cells advanced (all cells of every step), enqueued */
+    double cell_updates_done;/* of those, in chunks the GPU has completed */
     size_t bytes_reserved;   /* footprints of the resident requests */
     size_t bytes_in_use;     /* arena bytes allocated */
     size_t budget;           /* arena size */

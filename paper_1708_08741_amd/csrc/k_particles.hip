@@ -88,14 +88,30 @@ __global__ void k_positions(ParticleArgs pa, int64_t level, double *X) {
     for (int k = 0; k < 3; ++k) X[3 * p + k] = position(pa, p, k, level);
 }
 
+// inside test of Sec. 3.2 (closed ball, minimum image), FP64 without
+// contraction, as a plain CPU evaluation orders it
+__device__ __forceinline__ bool inside_ball(const Grid &g, int x, int y, int z, const double *Xp,
+                                            double R) {
+    const double r0 = min_image(((double)x + 0.5) - Xp[0], g.nx, g.per[0]);
+    const double r1 = min_image(((double)y + 0.5) - Xp[1], g.ny, g.per[1]);
+    const double r2 = min_image(((double)z + 0.5) - Xp[2], g.nz, g.per[2]);
+    const double d2 = (r0 * r0 + r1 * r1) + r2 * r2;
+    return d2 <= R * R;
+}
+
+// clear the cells particle p covered at position X (every cell of the map
+// lies in the ball of some particle, so clearing each particle's ball
+// empties the map; the following set re-claims shared cells)
 __device__ __forceinline__ void map_clear_particle(const ParticleArgs &pa, int p,
                                                    const double *X, uint32_t *owner) {
-    const Box b = ball_box(pa.g, X + 3 * p, pa.R[p]);
+    const double *Xp = X + 3 * p;
+    const double R = pa.R[p];
+    const Box b = ball_box(pa.g, Xp, R);
     const int n = box_size(b);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         int x, y, z;
         box_cell(pa.g, b, i, x, y, z);
-        owner[cell_of(pa.g, x, y, z)] = kNone;
+        if (inside_ball(pa.g, x, y, z, Xp, R)) owner[cell_of(pa.g, x, y, z)] = kNone;
     }
 }
 
@@ -141,13 +157,9 @@ __device__ __forceinline__ void map_set_particle(const ParticleArgs &pa, int p, 
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         int x, y, z;
         box_cell(pa.g, b, i, x, y, z);
+        if (!inside_ball(pa.g, x, y, z, Xp, R)) continue;
         const size_t c = cell_of(pa.g, x, y, z);
-        if (flag[c] & kWall) continue;
-        const double r0 = min_image(((double)x + 0.5) - Xp[0], pa.g.nx, pa.g.per[0]);
-        const double r1 = min_image(((double)y + 0.5) - Xp[1], pa.g.ny, pa.g.per[1]);
-        const double r2 = min_image(((double)z + 0.5) - Xp[2], pa.g.nz, pa.g.per[2]);
-        const double d2 = (r0 * r0 + r1 * r1) + r2 * r2;
-        if (d2 <= R * R) atomicMin(&owner[c], (uint32_t)p);
+        if (!(flag[c] & kWall)) atomicMin(&owner[c], (uint32_t)p);
     }
 }
 
@@ -235,11 +247,12 @@ __global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *wallmask, const 
     wallmask[c] = wm;
 }
 
-// solid bits of a box plus a one-cell halo, staged in LDS for the
+// state bits of a box plus a one-cell halo, staged in LDS for the
 // classification (boxes up to kHaloCells cells; larger ones use the global
-// path).  Bit 0: solid (wall, obstacle of the new map, beyond a non-periodic
-// edge); bit 1: obstacle cell of this particle.
+// path): solid (wall, obstacle of the new map, or beyond a non-periodic
+// edge), obstacle cell of this particle, obstacle cell, wall cell
 constexpr int kHaloCells = 32768;
+constexpr uint8_t kHSolid = 1, kHMine = 2, kHObst = 4, kHWall = 8;
 
 // Classification around one particle p (union of its boxes at the old and
 // new positions, grown by one cell): flags of the new level and the list of
@@ -249,7 +262,7 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
                                                   const double *Xold, const double *Xnew,
                                                   uint8_t *flag, const uint32_t *owner_new,
                                                   const uint32_t *owner_old, uint8_t *solid) {
-    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t wcnt[kBoxThreads / 64][8];
     const Grid &g = pa.g;
     const double R = pa.R[p];
     Box b;
@@ -276,69 +289,137 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
     const bool staged = n > 0 && hn <= kHaloCells;
     if (staged) {
         const int len[3] = {g.nx, g.ny, g.nz};
-        for (int i = threadIdx.x; i < hn; i += blockDim.x) {
-            int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy,
-                        b.lo[2] - 1 + i / (hx * hy)};
-            bool out = false;
-            for (int k = 0; k < 3; ++k) {
-                if (v[k] < 0 || v[k] >= len[k]) {
-                    if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
+        // four halo cells per thread and pass, their loads issued together
+        constexpr int kU = 4;
+        for (int i0 = 0; i0 < hn; i0 += kU * (int)blockDim.x) {
+            uint8_t fw[kU];
+            uint32_t ow[kU];
+            bool in[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy,
+                            b.lo[2] - 1 + i / (hx * hy)};
+                bool out = i >= hn;
+                for (int k = 0; k < 3; ++k) {
+                    if (v[k] < 0 || v[k] >= len[k]) {
+                        if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
+                    }
+                }
+                in[u] = !out;
+                fw[u] = 0;
+                ow[u] = kNone;
+                if (!out) {
+                    const size_t c = cell_of(g, v[0], v[1], v[2]);
+                    fw[u] = flag[c];
+                    ow[u] = owner_new[c];
                 }
             }
-            uint8_t sv = 1;
-            if (!out) {
-                const size_t c = cell_of(g, v[0], v[1], v[2]);
-                const bool w = flag[c] & kWall;
-                const uint32_t o = owner_new[c];
-                sv = (w || o != kNone) ? 1 : 0;
-                if (!w && o == (uint32_t)p) sv |= 2;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+                if (i >= hn) continue;
+                uint8_t sv = kHSolid;
+                if (in[u]) {
+                    sv = 0;
+                    if (fw[u] & kWall) sv = kHSolid | kHWall;
+                    else if (ow[u] != kNone)
+                        sv = kHSolid | kHObst | (ow[u] == (uint32_t)p ? kHMine : 0);
+                }
+                solid[i] = sv;
             }
-            solid[i] = sv;
         }
         __syncthreads();
     }
-    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
-        const int i = i0 + threadIdx.x;
-        uint32_t cell = 0, pm = 0;
-        if (i < n) {
+    // box cells: kPer cells per thread and pass, consecutive lanes on
+    // consecutive cells (conflict-free LDS reads), their loads issued
+    // together, one barrier per pass for the link-list positions
+    constexpr int kPer = 8;
+    for (int base0 = 0; base0 < n; base0 += kPer * (int)blockDim.x) {
+        uint32_t cells[kPer], pms[kPer];
+        uint8_t fl[kPer];
+        bool fluid[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = base0 + j * (int)blockDim.x + (int)threadIdx.x;
+            cells[j] = 0;
+            pms[j] = 0;
+            fl[j] = 0;
+            fluid[j] = false;
+            if (i >= n) continue;
             int x, y, z;
             box_cell(g, b, i, x, y, z);
             const size_t c = cell_of(g, x, y, z);
-            cell = (uint32_t)c;
-            uint8_t f;
+            cells[j] = (uint32_t)c;
             if (staged) {
+                // the cell itself is in the staged box: no global re-reads
                 const int ix = i % b.cnt[0], iy = (i / b.cnt[0]) % b.cnt[1],
                           iz = i / (b.cnt[0] * b.cnt[1]);
-                const uint8_t wall = flag[c] & kWall;
-                f = wall;
-                if (!wall) {
-                    if (owner_new[c] != kNone) {
-                        f = kObst;
-                    } else {
-                        const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
-                        uint32_t mask = 0;
+                const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
+                const uint8_t me = solid[h];
+                if (me & kHWall) {
+                    fl[j] = kWall;
+                } else if (me & kHObst) {
+                    fl[j] = kObst;
+                } else {
+                    uint32_t mask = 0, pm = 0;
 #pragma unroll
-                        for (int q = 1; q < Q; ++q) {
-                            const uint8_t sv = solid[h + kCx[q] + hx * (kCy[q] + hy * kCz[q])];
-                            if (sv & 1) mask |= 1u << (q - 1);
-                            if (sv & 2) pm |= 1u << (q - 1);
-                        }
-                        f = mask ? kNear : 0;
-                        if (owner_old[c] != kNone) f |= kUncov;
+                    for (int q = 1; q < Q; ++q) {
+                        const uint8_t sv = solid[h + kCx[q] + hx * (kCy[q] + hy * kCz[q])];
+                        if (sv & kHSolid) mask |= 1u << (q - 1);
+                        if (sv & kHMine) pm |= 1u << (q - 1);
                     }
+                    fl[j] = mask ? kNear : 0;
+                    pms[j] = pm;
+                    fluid[j] = true;
                 }
             } else {
                 uint32_t wm;
-                f = classify_cell(g, x, y, z, flag, owner_new, owner_old, (uint32_t)p, &wm, &pm);
+                fl[j] = classify_cell(g, x, y, z, flag, owner_new, nullptr, (uint32_t)p, &wm,
+                                      &pms[j]);
+                fluid[j] = !(fl[j] & (kWall | kObst));
             }
-            flag[c] = f;
         }
-        // append (cell, mask) of this round's cells with links into p
-        uint32_t total;
-        const uint32_t pos = base + block_scan(pm ? 1u : 0u, wsum, &total);
-        if (pm && pos < pa.pcap) plist[pos] = make_uint2(cell, pm);
-        base += total;
-        __syncthreads();  // wsum is reused by the next round
+        // uncovered marks: the previous map, loads issued together
+        uint32_t old[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) old[j] = fluid[j] ? owner_old[cells[j]] : kNone;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int i = base0 + j * (int)blockDim.x + (int)threadIdx.x;
+            if (i >= n) continue;
+            flag[cells[j]] = fl[j] | (old[j] != kNone ? kUncov : 0);
+        }
+        // append (cell, mask) of this pass's cells with links into p, in box
+        // order (j-major, then wavefront, then lane): per-row ballots give
+        // each lane's rank in its wavefront, one LDS exchange of the
+        // wavefronts' counts gives the offsets
+        const int lane = (int)__lane_id(), wave = (int)threadIdx.x / 64;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        uint32_t rank[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const unsigned long long bj = __ballot(pms[j] != 0);
+            rank[j] = (uint32_t)__popcll(bj & below);
+            if (lane == 0) wcnt[wave][j] = (uint32_t)__popcll(bj);
+        }
+        __syncthreads();
+        uint32_t run = base;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            uint32_t pre = 0, row = 0;
+            for (int w = 0; w < kBoxThreads / 64; ++w) {
+                row += wcnt[w][j];
+                if (w < wave) pre += wcnt[w][j];
+            }
+            if (pms[j]) {
+                const uint32_t pos = run + pre + rank[j];
+                if (pos < pa.pcap) plist[pos] = make_uint2(cells[j], pms[j]);
+            }
+            run += row;
+        }
+        base = run;
+        __syncthreads();  // wcnt is reused by the next pass
     }
     if (threadIdx.x == 0) pa.pcount[p] = base < pa.pcap ? base : pa.pcap;
 }

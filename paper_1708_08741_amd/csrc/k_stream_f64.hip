@@ -24,5 +24,8 @@ hipError_t launch_near_packed_f64(const PackTable &t, hipStream_t s) {
 }
 
 int near_wall_blocks(const Grid &g, bool walls) { return sweep::near_wall_blocks(g.N, walls); }
+int near_blocks(int np, const Grid &g, bool walls) {
+    return (int)sweep::near_particle_blocks(np) + sweep::near_wall_blocks(g.N, walls);
+}
 
 }  // namespace lbmep

@@ -153,6 +153,8 @@ hipError_t launch_sweep(int precision, int mode, int force_mode, const SweepArgs
 // particle over its link list, then wall_blocks workgroups over the wall list
 hipError_t launch_near(int precision, const SweepArgs &a, int wall_blocks, hipStream_t s);
 int near_wall_blocks(const Grid &g, bool walls);
+// all workgroups of the exchange kernel (particles, then wall links)
+int near_blocks(int np, const Grid &g, bool walls);
 // compact list, in cell order, of the cells with a wall link (wallmask != 0);
 // scratch of wall_list_scratch(g) entries
 int wall_list_blocks(const Grid &g);

@@ -156,6 +156,7 @@ struct lbmep_server {
     std::deque<uint64_t> unreported;  // finished ids not yet returned by poll
     std::vector<Slot> slots;
     std::deque<hipEvent_t> chunk_ev;  // completion events of enqueued chunks
+    std::deque<double> chunk_work;    // their cell updates
     std::vector<hipEvent_t> ev_pool;
     uint64_t next_id = 1;
     size_t reserved = 0;  // footprints of the resident requests
@@ -364,7 +365,7 @@ int enqueue_steps(lbmep_server *S, const std::vector<Slot *> &act, int k) {
                     ts.level[ts.n] = tn.level[tn.n] = L->level;
                     ts.start[ts.n + 1] = ts.start[ts.n] + sb;
                     tn.start[tn.n + 1] =
-                        tn.start[tn.n] + (uint32_t)(L->np + near_wall_blocks(L->g, L->has_walls));
+                        tn.start[tn.n] + (uint32_t)near_blocks(L->np, L->g, L->has_walls);
                     ts.n++;
                     tn.n++;
                     if (ts.n == kMaxPack) {
@@ -428,6 +429,8 @@ int progress(lbmep_server *S) {
         if (q != hipSuccess) return fail(LBMEP_EDEVICE, std::string("event: ") + hipGetErrorString(q));
         S->ev_pool.push_back(S->chunk_ev.front());
         S->chunk_ev.pop_front();
+        S->st.cell_updates_done += S->chunk_work.front();
+        S->chunk_work.pop_front();
     }
     // 3. admit queued requests (FIFO) while a slot is free and the budget holds
     while (!S->queue.empty()) {
@@ -475,6 +478,7 @@ int progress(lbmep_server *S) {
                 k = std::min(k, sl.to_enqueue);
             }
         if (act.empty()) break;
+        const double before = S->st.cell_updates;
         int rc = enqueue_steps(S, act, k);
         if (rc) return rc;
         for (Slot *sl : act)
@@ -486,6 +490,7 @@ int progress(lbmep_server *S) {
         if (!e) return fail(LBMEP_EDEVICE, "event creation failed");
         LBMEP_HIP_TRY(hipEventRecord(e, S->main));
         S->chunk_ev.push_back(e);
+        S->chunk_work.push_back(S->st.cell_updates - before);
         S->st.chunks += 1;
     }
     return LBMEP_OK;

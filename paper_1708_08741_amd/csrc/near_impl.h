@@ -10,12 +10,12 @@
 // slots are free); a link to an obstacle cell of particle p adds
 // [2 f*_q - 2 w_q rho0 c_q.u_s / c_s^2] c_q to F_p and r x (that) to M_p.
 //
-// Work distribution: one workgroup per particle walks the particle's link
-// list (written by the classification: the fluid cells next to the
-// particle with the directions that hit it), so the particle's position and
-// velocities are uniform, no owner look-up is needed, and force and torque
-// are summed in the workgroup in a fixed order (DPP row butterflies, then
-// across the wavefronts) and stored without atomics.  Links to wall cells
+// Work distribution: one wavefront per particle (four per workgroup) walks
+// 64 entries at a time of the particle's link list, direction by direction (written by the classification: the fluid cells
+// next to the particle with the directions that hit it), so the particle's
+// position and velocities are uniform, no owner look-up is needed, and
+// force and torque are summed over the wavefront in a fixed order (DPP row
+// butterflies) and stored without atomics or barriers.  Links to wall cells
 // come from a list built when the walls are set.
 #pragma once
 #include "sweep_impl.h"
@@ -68,21 +68,6 @@ __device__ __forceinline__ int dir_comp(uint64_t packed, int q) {
     return (int)((packed >> (2 * q)) & 3u) - 1;
 }
 
-// c . a with the zero terms of ((c_x a_x + c_y a_y) + c_z a_z) dropped, in
-// the same order and rounding as cdot<q>
-__device__ __forceinline__ double cdot_rt(int cx, int cy, int cz, double ax, double ay,
-                                          double az) {
-    double r = 0.0;
-    if (cx != 0 && cy != 0)
-        r = (cx > 0 ? ax : -ax) + (cy > 0 ? ay : -ay);
-    else if (cx != 0)
-        r = cx > 0 ? ax : -ax;
-    else if (cy != 0)
-        r = cy > 0 ? ay : -ay;
-    if (cz != 0) r = (cx != 0 || cy != 0) ? r + (cz > 0 ? az : -az) : (cz > 0 ? az : -az);
-    return r;
-}
-
 // wrap one coordinate of a neighbour on a periodic axis; false beyond the
 // edge of a non-periodic axis
 __device__ __forceinline__ bool wrap_axis(int &v, int len, int periodic) {
@@ -117,103 +102,98 @@ __device__ __forceinline__ typename Storage<ST>::CT load_fstar(const SweepArgs &
     return Storage<ST>::load(at<ST>(base, (OFF)c * (OFF)sizeof(ST)));
 }
 
-// sum of v over the workgroup (256 threads); the result is valid in thread 0
-__device__ __forceinline__ double block_sum_f64(double v, double *red) {
-    v = wave_sum_f64(v);
-    const int wave = threadIdx.x / 64;
-    if (__lane_id() == 0) red[wave] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return t;
+// One link of particle p at compile-time direction q: the bounce-back slot
+// and the momentum exchange into the lane's sums.
+template <int q, typename ST, typename OFF>
+__device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, int x, int y, int z,
+                                              const double Xp[3], const double Up[3],
+                                              const double Wp[3], double acc[kAcc]) {
+    using T = Storage<ST>;
+    using CT = typename T::CT;
+    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
+    const Grid &g = a.g;
+    int sx = x + cx, sy = y + cy, sz = z + cz;
+    wrap_axis(sx, g.nx, g.per[0]);  // an obstacle cell: always inside
+    wrap_axis(sy, g.ny, g.per[1]);
+    wrap_axis(sz, g.nz, g.per[2]);
+    const CT fq = load_fstar<ST, OFF>(a, q, c);
+    // lever arm r = x_s - x_C (minimum image) and u_s = U + W x r
+    const double r0 = min_image(((double)sx + 0.5) - Xp[0], g.nx, g.per[0]);
+    const double r1 = min_image(((double)sy + 0.5) - Xp[1], g.ny, g.per[1]);
+    const double r2 = min_image(((double)sz + 0.5) - Xp[2], g.nz, g.per[2]);
+    const double us0 = Up[0] + (Wp[1] * r2 - Wp[2] * r1);
+    const double us1 = Up[1] + (Wp[2] * r0 - Wp[0] * r2);
+    const double us2 = Up[2] + (Wp[0] * r1 - Wp[1] * r0);
+    const double cus = cdot<q>(us0, us1, us2);
+    // 2 (w_q / c_s^2) rho0 c_q . u_s (Eq. LBMMovWall)
+    const double mw = 2.0 * wq(q) * 3.0 * cus;
+    // [2 f*_q - 2 (w_q/c_s^2) rho0 c_q . u_s] c_q (Eq. LBMhydrodynForce),
+    // summed as [2 (f*_q - w_q) - ...] c_q plus the rest-weight part
+    // 2 w_q c_q = (k/18) c_q (k = 2 axis, 1 diagonal), whose sum cancels
+    // over a closed body and is accumulated exactly as integers:
+    // K = sum k c_q, T = sum k x_s x c_q (x_s the exact half-integer image
+    // of the cell centre)
+    const double gm = 2.0 * T::devval(fq, q) - mw;
+    const double g0 = cx == 0 ? 0.0 : (cx > 0 ? gm : -gm);
+    const double g1 = cy == 0 ? 0.0 : (cy > 0 ? gm : -gm);
+    const double g2 = cz == 0 ? 0.0 : (cz > 0 ? gm : -gm);
+    constexpr double k = q <= 6 ? 2.0 : 1.0;
+    const double xs0 = image_coord((double)sx + 0.5, Xp[0], g.nx, g.per[0]);
+    const double xs1 = image_coord((double)sy + 0.5, Xp[1], g.ny, g.per[1]);
+    const double xs2 = image_coord((double)sz + 0.5, Xp[2], g.nz, g.per[2]);
+    acc[0] += g0;
+    acc[1] += g1;
+    acc[2] += g2;
+    acc[3] += r1 * g2 - r2 * g1;
+    acc[4] += r2 * g0 - r0 * g2;
+    acc[5] += r0 * g1 - r1 * g0;
+    acc[6] += k * (double)cx;
+    acc[7] += k * (double)cy;
+    acc[8] += k * (double)cz;
+    acc[9] += k * (xs1 * (double)cz - xs2 * (double)cy);
+    acc[10] += k * (xs2 * (double)cx - xs0 * (double)cz);
+    acc[11] += k * (xs0 * (double)cy - xs1 * (double)cx);
+    const OFF s = (OFF)sx + (OFF)g.nx * ((OFF)sy + (OFF)g.ny * (OFF)sz);
+    store_slot<ST, OFF>(a, q, s, fq, mw);
 }
 
 // All links of particle p (its list from the classification: cells with the
-// directions whose neighbour is an obstacle cell of p), one workgroup: the
-// bounce-back slots and the momentum exchange, summed in the workgroup in a
-// fixed order and stored (no atomics: the result does not depend on
-// scheduling).
+// directions whose neighbour is an obstacle cell of p), one wavefront: the
+// bounce-back slots and the momentum exchange, summed over the wavefront in
+// a fixed order and stored (no atomics: the result does not depend on
+// scheduling).  The lanes take 64 consecutive list entries (neighbouring
+// cells along x) and walk the directions in the same order, so each load
+// and store instruction touches consecutive addresses of one population.
 template <typename ST, typename OFF>
 __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
-    using T = Storage<ST>;
-    using CT = typename T::CT;
-    __shared__ double red[4];
+    const int lane = (int)__lane_id();
     const Grid &g = a.g;
     const int nx = g.nx, ny = g.ny;
     const uint2 *list = a.plist + (size_t)p * a.pcap;
     const uint32_t n = a.pcount[p];
-    const double X0 = a.Xc[3 * (size_t)p], X1 = a.Xc[3 * (size_t)p + 1],
-                 X2 = a.Xc[3 * (size_t)p + 2];
-    const double U0 = a.U[3 * (size_t)p], U1 = a.U[3 * (size_t)p + 1],
-                 U2 = a.U[3 * (size_t)p + 2];
-    const double W0 = a.W[3 * (size_t)p], W1 = a.W[3 * (size_t)p + 1],
-                 W2 = a.W[3 * (size_t)p + 2];
+    const double Xp[3] = {a.Xc[3 * (size_t)p], a.Xc[3 * (size_t)p + 1], a.Xc[3 * (size_t)p + 2]};
+    const double Up[3] = {a.U[3 * (size_t)p], a.U[3 * (size_t)p + 1], a.U[3 * (size_t)p + 2]};
+    const double Wp[3] = {a.W[3 * (size_t)p], a.W[3 * (size_t)p + 1], a.W[3 * (size_t)p + 2]};
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint2 e = list[i];
-        const uint32_t c = e.x;
-        uint32_t mask = e.y;
+    for (uint32_t i0 = 0; i0 < n; i0 += 64u) {
+        const uint32_t i = i0 + (uint32_t)lane;
+        uint2 e = make_uint2(0u, 0u);
+        if (i < n) e = list[i];
+        const uint32_t c = e.x, mask = e.y;
         const int x = (int)(c % (uint32_t)nx);
         const int y = (int)((c / (uint32_t)nx) % (uint32_t)ny);
         const int z = (int)(c / ((uint32_t)nx * (uint32_t)ny));
-        while (mask) {
-            const int q = __ffs((int)mask);  // bit q-1 <-> direction q
-            mask &= mask - 1u;
-            const int cx = dir_comp(kPackCx, q), cy = dir_comp(kPackCy, q),
-                      cz = dir_comp(kPackCz, q);
-            int sx = x + cx, sy = y + cy, sz = z + cz;
-            wrap_axis(sx, nx, g.per[0]);  // an obstacle cell: always inside
-            wrap_axis(sy, ny, g.per[1]);
-            wrap_axis(sz, g.nz, g.per[2]);
-            const CT fq = load_fstar<ST, OFF>(a, q, c);
-            // lever arm r = x_s - x_C (minimum image) and u_s = U + W x r
-            const double r0 = min_image(((double)sx + 0.5) - X0, g.nx, g.per[0]);
-            const double r1 = min_image(((double)sy + 0.5) - X1, g.ny, g.per[1]);
-            const double r2 = min_image(((double)sz + 0.5) - X2, g.nz, g.per[2]);
-            const double us0 = U0 + (W1 * r2 - W2 * r1);
-            const double us1 = U1 + (W2 * r0 - W0 * r2);
-            const double us2 = U2 + (W0 * r1 - W1 * r0);
-            const double cus = cdot_rt(cx, cy, cz, us0, us1, us2);
-            const double w = q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0;
-            // 2 (w_q / c_s^2) rho0 c_q . u_s (Eq. LBMMovWall)
-            const double mw = 2.0 * w * 3.0 * cus;
-            // [2 f*_q - 2 (w_q/c_s^2) rho0 c_q . u_s] c_q (Eq.
-            // LBMhydrodynForce), summed as [2 (f*_q - w_q) - ...] c_q plus the
-            // rest-weight part 2 w_q c_q = (k/18) c_q (k = 2 axis, 1
-            // diagonal), whose sum cancels over a closed body and is
-            // accumulated exactly as integers: K = sum k c_q, T = sum k x_s x
-            // c_q (x_s the exact half-integer image of the cell centre)
-            const double gm = 2.0 * T::devval(fq, q) - mw;
-            const double g0 = cx == 0 ? 0.0 : (cx > 0 ? gm : -gm);
-            const double g1 = cy == 0 ? 0.0 : (cy > 0 ? gm : -gm);
-            const double g2 = cz == 0 ? 0.0 : (cz > 0 ? gm : -gm);
-            const double k = q <= 6 ? 2.0 : 1.0;
-            const double xs0 = image_coord((double)sx + 0.5, X0, g.nx, g.per[0]);
-            const double xs1 = image_coord((double)sy + 0.5, X1, g.ny, g.per[1]);
-            const double xs2 = image_coord((double)sz + 0.5, X2, g.nz, g.per[2]);
-            acc[0] += g0;
-            acc[1] += g1;
-            acc[2] += g2;
-            acc[3] += r1 * g2 - r2 * g1;
-            acc[4] += r2 * g0 - r0 * g2;
-            acc[5] += r0 * g1 - r1 * g0;
-            acc[6] += k * (double)cx;
-            acc[7] += k * (double)cy;
-            acc[8] += k * (double)cz;
-            acc[9] += k * (xs1 * (double)cz - xs2 * (double)cy);
-            acc[10] += k * (xs2 * (double)cx - xs0 * (double)cz);
-            acc[11] += k * (xs0 * (double)cy - xs1 * (double)cx);
-            const OFF s = (OFF)sx + (OFF)nx * ((OFF)sy + (OFF)ny * (OFF)sz);
-            store_slot<ST, OFF>(a, q, s, fq, mw);
-        }
+#define LBMEP_PLINK(q) \
+    if (mask & (1u << ((q)-1))) particle_link<q, ST, OFF>(a, c, x, y, z, Xp, Up, Wp, acc);
+        LBMEP_FOR_Q18(LBMEP_PLINK)
+#undef LBMEP_PLINK
     }
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) {
-        const double t = block_sum_f64(acc[k], red);
-        if (threadIdx.x == 0 && a.FM) a.FM[kAcc * (size_t)p + k] = t;
+        const double t = wave_sum_f64(acc[k]);
+        if (lane == 0 && a.FM) a.FM[kAcc * (size_t)p + k] = t;
     }
 }
 
@@ -247,13 +227,23 @@ __device__ __forceinline__ void near_walls(const SweepArgs &a, uint32_t blk, uin
     }
 }
 
-// workgroups [0, np): one particle each; the rest: the wall links
+// particles per workgroup of the exchange kernel (one per wavefront)
+constexpr int kNearPerBlock = 4;
+
+__host__ __device__ inline uint32_t near_particle_blocks(int np) {
+    return (uint32_t)((np + kNearPerBlock - 1) / kNearPerBlock);
+}
+
+// workgroups [0, pb): kNearPerBlock particles each; the rest: the wall links
 template <typename ST, typename OFF>
 __device__ __forceinline__ void near_block(const SweepArgs &a, uint32_t blk, uint32_t nblk) {
-    if (blk < (uint32_t)a.np)
-        near_particle<ST, OFF>(a, blk);
-    else
-        near_walls<ST, OFF>(a, blk - (uint32_t)a.np, nblk - (uint32_t)a.np);
+    const uint32_t pb = near_particle_blocks(a.np);
+    if (blk < pb) {
+        const uint32_t p = blk * kNearPerBlock + threadIdx.x / 64;
+        if (p < (uint32_t)a.np) near_particle<ST, OFF>(a, p);
+    } else {
+        near_walls<ST, OFF>(a, blk - pb, nblk - pb);
+    }
 }
 
 template <typename ST, typename OFF>
@@ -288,7 +278,7 @@ hipError_t launch_near_packed_typed(const PackTable &t, hipStream_t s) {
 
 template <typename ST>
 hipError_t launch_near_typed(const SweepArgs &a, int wall_blocks, hipStream_t s) {
-    const unsigned blocks = (unsigned)(a.np + wall_blocks);
+    const unsigned blocks = near_particle_blocks(a.np) + (unsigned)wall_blocks;
     if (blocks == 0) return hipSuccess;
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
     if (small)

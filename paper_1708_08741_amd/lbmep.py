@@ -70,7 +70,7 @@ class ServerStats(ctypes.Structure):
         ("queued", ctypes.c_int32), ("resident", ctypes.c_int32),
         ("chunks", ctypes.c_uint64), ("steps", ctypes.c_uint64),
         ("packed_launches", ctypes.c_uint64),
-        ("cell_updates", ctypes.c_double),
+        ("cell_updates", ctypes.c_double), ("cell_updates_done", ctypes.c_double),
         ("bytes_reserved", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t),
         ("budget", ctypes.c_size_t),
     ]

@@ -49,7 +49,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         " sizeof(lbmep_request), sizeof(lbmep_server_stats));\n"
         '  printf("%zu %zu %zu %zu %zu\\n", offsetof(lbmep_request, flags),'
         " offsetof(lbmep_request, X), offsetof(lbmep_request, rho_e),"
-        " offsetof(lbmep_request, E), offsetof(lbmep_server_stats, cell_updates));\n"
+        " offsetof(lbmep_request, E), offsetof(lbmep_server_stats, cell_updates_done));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
@@ -59,7 +59,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert sizes == [ctypes.sizeof(lb.Config), ctypes.sizeof(lb.ServerConfig),
                      ctypes.sizeof(lb.Request), ctypes.sizeof(lb.ServerStats)]
     assert offs == [lb.Request.flags.offset, lb.Request.X.offset, lb.Request.rho_e.offset,
-                    lb.Request.E.offset, lb.ServerStats.cell_updates.offset]
+                    lb.Request.E.offset, lb.ServerStats.cell_updates_done.offset]
 
 
 def test_server_request_footprint_host_only():
