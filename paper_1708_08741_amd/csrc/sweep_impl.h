@@ -530,8 +530,8 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     } while (0)
     if (small) {
         if (mode == kPull) LBMEP_BY_CPT(kPull);
-        else if (mode == kPullNT) LBMEP_BY_FORCE(kPullNT, uint32_t, 1);
-        else if (mode == kPullNTS) LBMEP_BY_FORCE(kPullNTS, uint32_t, 1);
+        else if (mode == kPullNT) LBMEP_BY_CPT(kPullNT);
+        else if (mode == kPullNTS) LBMEP_BY_CPT(kPullNTS);
         else if (mode == kLocal) LBMEP_BY_CPT(kLocal);
         else LBMEP_LAUNCH(kReadout, kForceNone, uint32_t, 1);
     } else {

@@ -187,6 +187,7 @@ def test_sweep_variants_identical(lb, monkeypatch, precision):
     ref = None
     for env in [dict(), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1"),
                 dict(LBMEP_SWEEP_NT="2"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
+                dict(LBMEP_SWEEP_NT="1", LBMEP_CPT="2"), dict(LBMEP_SWEEP_NT="2", LBMEP_CPT="2"),
                 dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
         for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X"):
             monkeypatch.delenv(k, raising=False)

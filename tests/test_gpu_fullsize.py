@@ -105,3 +105,67 @@ def test_window_of_512_run_matches_oracle(suspension, window_oracle, precision):
     sF = np.abs(Fo).max()
     assert np.abs(Fg - Fo).max() <= tol["F"] * sF
     assert np.abs(Mg - Mo).max() <= tol["M"] * sF * R
+
+
+def test_window_of_large_fp64_grid_64bit_offsets(oracle_mod):
+    """A 660^3 FP64 lattice (two population grids of 87 GB: past 4 GiB, so
+    the sweep and the exchange use 64-bit offsets) with 24 moving spheres
+    and a charge force in a window that wraps across the periodic x
+    boundary: the window's core matches the oracle run on the window's
+    inputs."""
+    import torch
+
+    from paper_1708_08741_amd import lbmep
+
+    n, S, o = 660, 64, np.array([630.0, 300.0, 590.0])
+    rng = np.random.default_rng(17)
+    R = 3.5
+    X, Rs = W.rsa_spheres(rng, 24, R, (S, S, S), (False, False, False), gap=2.0,
+                          lo=[4.0] * 3, hi=[S - 4.0] * 3)
+    X = X + o  # inside the window, which wraps across x = 660
+    X[:, 0] = np.mod(X[:, 0], n)
+    U = rng.uniform(-0.02, 0.02, size=(24, 3))
+    Wv = rng.uniform(-1e-3, 1e-3, size=(24, 3))
+    rho_e = W.gaussian_shell_rho_e((n, n, n), (True, True, True), X, Rs)
+    E = (1e-2, -5e-3, 0.0)
+    g = lbmep.Lattice((n, n, n), precision=lbmep.FP64, move_particles=True)
+    g.set_charge_force(rho_e, E)
+    g.init_equilibrium()
+    g.set_particles(X, Rs, U, Wv)
+    steps = 6
+    g.step(steps)
+    rho_t = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    u_t = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+    g.macro_device(rho_t, u_t)
+    oi = o.astype(int)
+    xs = (np.arange(oi[0], oi[0] + S) % n)
+    sl = (slice(oi[2], oi[2] + S), slice(oi[1], oi[1] + S))
+    rho = rho_t[sl].cpu().numpy()[:, :, xs]
+    u = u_t[(slice(None),) + sl].cpu().numpy()[:, :, :, xs]
+    del rho_t, u_t
+    F, M = g.ft()
+    g.close()
+    torch.cuda.empty_cache()
+
+    Xw = X - o
+    Xw[:, 0] = np.where(Xw[:, 0] < -S, Xw[:, 0] + n, Xw[:, 0])
+    rho_w = np.ascontiguousarray(rho_e[sl][:, :, xs])
+    orc = oracle_mod.Oracle((S, S, S), (False, False, False))
+    orc.set_force(np.stack([rho_w * E[0], rho_w * E[1], rho_w * E[2]]))
+    orc.init_equilibrium()
+    orc.set_particles(Xw, Rs, U, Wv, moving=True)
+    orc.step(steps)
+    rho_o, u_o = orc.macro()
+    F_o, M_o = orc.ft()
+    fl_o, _ = orc.map()
+    m = steps + 2
+    core = (slice(m, S - m),) * 3
+    fluid = (fl_o[core] == 0) | (fl_o[core] == 3)
+    du = np.abs(u[(slice(None),) + core] - u_o[(slice(None),) + core])[:, fluid].max()
+    assert du <= 1e-12 * np.abs(u_o[(slice(None),) + core])[:, fluid].max(), du
+    assert np.abs(rho[core] - rho_o[core])[fluid].max() <= 1e-12
+    ok = np.all((Xw > m + R + 1) & (Xw < S - m - R - 1), axis=1)
+    assert ok.sum() >= 5
+    sF = np.abs(F_o[ok]).max()
+    assert np.abs(F[ok] - F_o[ok]).max() <= 1e-12 * sF
+    assert np.abs(M[ok] - M_o[ok]).max() <= 1e-12 * sF * R
