@@ -17,6 +17,9 @@
  *     stream steps (Eq. LBMcollideStep, Eq. LBMstreamStep), Luo forcing
  *     term (Eq. LBE_forcetermLuo), modified momentum density
  *     (Eq. modified_velocity).
+ *   Sec. "Computing Electrostatic Forces on Fluid and Particles": the body
+ *     force rho_e(psi) (E_ext - grad psi) from an EDL potential
+ *     (Eq. ChrgDensDHA, Eq. ElPotGradComp), optional.
  *   Sec. 3.2 (momentum exchange): cells whose centre lies in a particle are
  *     obstacle cells; velocity bounce-back (Eq. LBMMovWall); hydrodynamic
  *     force (Eq. LBMhydrodynForce) and torque; equilibrium refill of
@@ -98,6 +101,9 @@ struct orc_lattice {
     uint8_t *wall;
     int32_t *owner, *owner_old;
     double *fb;
+    /* electrostatic body force from the EDL potential (optional) */
+    int potential;
+    double *psi, *zeta, k_eps, Eext[3];
     int np, moving;
     double *X0, *R, *U, *W;
     double *Xn;   /* positions of the current time level */
@@ -284,7 +290,11 @@ orc_lattice *orc_create(int nx, int ny, int nz, const int periodic[3], double nu
     return L;
 }
 
+static void potential_force(orc_lattice *L);
+
 static void free_particles(orc_lattice *L) {
+    free(L->zeta);
+    L->zeta = NULL;
     free(L->X0); free(L->R); free(L->U); free(L->W); free(L->Xn); free(L->Xold);
     free(L->F); free(L->M);
     L->X0 = L->R = L->U = L->W = L->Xn = L->Xold = L->F = L->M = NULL;
@@ -295,7 +305,8 @@ void orc_destroy(orc_lattice *L) {
     if (!L) return;
     free(L->f); free(L->fstar); free(L->fnew); free(L->wall);
     free(L->owner); free(L->owner_old); free(L->fb);
-    free_particles(L);
+    free(L->psi);
+    free_particles(L); /* also the per-particle zeta */
     free(L);
 }
 
@@ -311,6 +322,7 @@ int orc_set_flags(orc_lattice *L, const uint8_t *flags) {
         map_particles(L, L->Xn, L->owner);
         memcpy(L->owner_old, L->owner, (size_t)L->N * sizeof(int32_t));
     }
+    if (L->potential) potential_force(L);
     return 0;
 }
 
@@ -342,11 +354,99 @@ int orc_set_particles(orc_lattice *L, int n, const double *X, const double *R,
     }
     map_particles(L, L->Xn, L->owner);
     memcpy(L->owner_old, L->owner, (size_t)L->N * sizeof(int32_t));
+    if (L->potential) potential_force(L);
     return 0;
 }
 
 int orc_set_force(orc_lattice *L, const double *fb) {
+    L->potential = 0;
     memcpy(L->fb, fb, sizeof(double) * 3 * (size_t)L->N);
+    return 0;
+}
+
+/* -------------------------------------------------------------------------
+ * Electrostatic body force of the electric double layer (Sec. "Computing
+ * Electrostatic Forces on Fluid and Particles"): at every fluid cell
+ *     f_b = rho_e(psi) (E_ext - grad psi),  rho_e = -kappa^2 eps_e psi
+ * (Eq. ChrgDensDHA).  grad psi is the w_q-weighted difference over the 18
+ * D3Q19 neighbours divided by the rest weight (Eq. ElPotGradComp, dx = 1)
+ * where every neighbour is a fluid cell, and the central D3Q7 difference
+ * where a neighbour is a wall, obstacle or outside a non-periodic edge; the
+ * D3Q7 difference takes the boundary values: psi = zeta_p at obstacle
+ * cells of particle p (the field's value there if no zeta is given), the
+ * field's value at wall cells, and the cell's own value beyond a
+ * non-periodic edge.  Recomputed whenever the map changes.
+ * ---------------------------------------------------------------------- */
+
+/* value of psi at neighbour (x,y,z) + d, the boundary value where it is an
+ * obstacle cell, the centre value c0 beyond a non-periodic edge */
+static double psi_at(const orc_lattice *L, int x, int y, int z, const int d[3], double c0) {
+    long s = neighbour(L, x, y, z, d);
+    if (s < 0) return c0;
+    if (!L->wall[s] && L->owner[s] >= 0 && L->zeta) return L->zeta[L->owner[s]];
+    return L->psi[s];
+}
+
+static void potential_force(orc_lattice *L) {
+    const long N = L->N;
+    long c;
+#pragma omp parallel for schedule(static)
+    for (c = 0; c < N; ++c) {
+        int a, q;
+        int x = (int)(c % L->nx), y = (int)((c / L->nx) % L->ny), z = (int)(c / ((long)L->nx * L->ny));
+        double g[3] = {0.0, 0.0, 0.0}, rho_e;
+        int near = 0;
+        if (!is_fluid(L, c)) {
+            for (a = 0; a < 3; ++a) L->fb[(long)a * N + c] = 0.0;
+            continue;
+        }
+        for (q = 1; q < Q && !near; ++q) {
+            long s = neighbour(L, x, y, z, C[q]);
+            if (s < 0 || !is_fluid(L, s)) near = 1;
+        }
+        if (!near) {
+            /* Eq. ElPotGradComp: (1/w_rest) sum_q w_q psi(x + e_q) e_q */
+            double sum[3] = {0.0, 0.0, 0.0};
+            for (q = 1; q < Q; ++q) {
+                double t = L->w[q] * L->psi[neighbour(L, x, y, z, C[q])];
+                for (a = 0; a < 3; ++a) {
+                    if (C[q][a] > 0) sum[a] = sum[a] + t;
+                    else if (C[q][a] < 0) sum[a] = sum[a] - t;
+                }
+            }
+            for (a = 0; a < 3; ++a) g[a] = sum[a] * 3.0;
+        } else {
+            /* D3Q7 central difference with the boundary values */
+            for (a = 0; a < 3; ++a) {
+                int dp[3] = {0, 0, 0}, dm[3] = {0, 0, 0};
+                dp[a] = 1;
+                dm[a] = -1;
+                g[a] = (psi_at(L, x, y, z, dp, L->psi[c]) - psi_at(L, x, y, z, dm, L->psi[c])) * 0.5;
+            }
+        }
+        rho_e = -(L->k_eps * L->psi[c]);
+        for (a = 0; a < 3; ++a) L->fb[(long)a * N + c] = rho_e * (L->Eext[a] - g[a]);
+    }
+}
+
+int orc_set_potential_force(orc_lattice *L, const double *psi, double kappa2_eps,
+                            const double E[3], const double *zeta) {
+    int a;
+    if (!L->psi) {
+        L->psi = (double *)malloc(sizeof(double) * (size_t)L->N);
+        if (!L->psi) return -1;
+    }
+    memcpy(L->psi, psi, sizeof(double) * (size_t)L->N);
+    free(L->zeta);
+    L->zeta = NULL;
+    if (zeta && L->np > 0) {
+        L->zeta = (double *)malloc(sizeof(double) * (size_t)L->np);
+        memcpy(L->zeta, zeta, sizeof(double) * (size_t)L->np);
+    }
+    L->k_eps = kappa2_eps;
+    for (a = 0; a < 3; ++a) L->Eext[a] = E[a];
+    L->potential = 1;
+    potential_force(L);
     return 0;
 }
 
@@ -575,6 +675,8 @@ static void one_step(orc_lattice *L) {
     } else if (np > 0) {
         memcpy(L->Xold, L->Xn, sizeof(double) * 3 * np);
     }
+    /* the body force of the new level's map */
+    if (L->potential && L->moving && np > 0) potential_force(L);
 }
 
 void orc_step(orc_lattice *L, int nsteps) {
@@ -611,6 +713,10 @@ void orc_get_macro(const orc_lattice *L, double *rho, double *u) {
             }
         }
     }
+}
+
+void orc_get_force(const orc_lattice *L, double *fb) {
+    memcpy(fb, L->fb, sizeof(double) * 3 * (size_t)L->N);
 }
 
 void orc_get_ft(const orc_lattice *L, double *F, double *M) {

@@ -36,6 +36,13 @@ int orc_set_flags(orc_lattice *L, const uint8_t *flags);  /* 0 fluid, 1 wall */
 int orc_set_particles(orc_lattice *L, int n, const double *X, const double *R,
                       const double *U, const double *W, int moving);
 int orc_set_force(orc_lattice *L, const double *fb);      /* 3*N SoA */
+/* body force rho_e(psi) (E - grad psi) from the EDL potential psi[N],
+ * rho_e = -kappa2_eps psi; zeta[np] = potential at each particle's obstacle
+ * cells (NULL: the field's value); recomputed when the map changes */
+int orc_set_potential_force(orc_lattice *L, const double *psi, double kappa2_eps,
+                            const double E[3], const double *zeta);
+/* the body force field currently applied (3*N SoA) */
+void orc_get_force(const orc_lattice *L, double *fb);
 void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]);
 void orc_set_pdfs(orc_lattice *L, const double *f);       /* 19*N */
 void orc_get_pdfs(const orc_lattice *L, double *f);

@@ -58,6 +58,8 @@ def lib():
         L.orc_set_flags.argtypes = [P, ctypes.c_void_p]
         L.orc_set_particles.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
         L.orc_set_force.argtypes = [P, dp]
+        L.orc_set_potential_force.argtypes = [P, dp, ctypes.c_double, dp, ctypes.c_void_p]
+        L.orc_get_force.argtypes = [P, dp]
         L.orc_init_equilibrium.argtypes = [P, ctypes.c_double, dp]
         L.orc_set_pdfs.argtypes = [P, dp]
         L.orc_get_pdfs.argtypes = [P, dp]
@@ -128,6 +130,25 @@ class Oracle:
         f = np.ascontiguousarray(fb, dtype=np.float64).reshape(-1)
         assert f.size == 3 * self.N
         lib().orc_set_force(self._h, _dp(f))
+
+    def set_potential_force(self, psi, kappa2_eps, E, zeta=None):
+        """Body force rho_e(psi) (E - grad psi) from the EDL potential psi
+        (nz, ny, nx), rho_e = -kappa2_eps psi; zeta[np] = potential at each
+        particle's obstacle cells (None: the field's value)."""
+        p = np.ascontiguousarray(psi, dtype=np.float64).reshape(-1)
+        Ea = np.ascontiguousarray(E, dtype=np.float64)
+        zp = None
+        if zeta is not None:
+            z = np.ascontiguousarray(zeta, dtype=np.float64).reshape(-1)
+            self._zeta_keep = z
+            zp = z.ctypes.data
+        lib().orc_set_potential_force(self._h, _dp(p), float(kappa2_eps), _dp(Ea), zp)
+
+    def force(self):
+        nx, ny, nz = self.shape
+        fb = np.zeros((3, nz, ny, nx))
+        lib().orc_get_force(self._h, _dp(fb))
+        return fb
 
     def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
         ua = np.array(u, dtype=np.float64)

@@ -569,3 +569,97 @@ def test_hasimoto_drag_periodic_sphere_array(oracle_mod):
     K = 1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c ** 2
     U_pred = F[0, 0] * K / (6.0 * np.pi * nu * Reff)
     assert abs(U_sup / U_pred - 1.0) < 0.03
+
+
+# ---------------------------------------------------------------------------
+# electrostatic body force from the EDL potential (Sec. "Computing
+# Electrostatic Forces on Fluid and Particles", Eq. ChrgDensDHA,
+# Eq. ElPotGradComp)
+# ---------------------------------------------------------------------------
+
+def _centres(shape):
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5,
+                          indexing="ij")
+    return x, y, z
+
+
+def test_potential_force_linear_and_cubic(oracle_mod):
+    """Away from boundaries the D3Q19 weighted difference of Eq.
+    ElPotGradComp is exact for linear potentials, and for psi = s^3 it gives
+    3 s^2 + 3 sum_q w_q c_qx^4 = 3 s^2 + 1 (its O(dx^2) term, fixed by the
+    weights); the force is rho_e (E - grad psi) with rho_e = -kappa^2 eps psi
+    (Eq. ChrgDensDHA)."""
+    shape = (14, 12, 10)
+    x, y, z = _centres(shape)
+    k, E = 0.7, (2e-3, -1e-3, 5e-4)
+    o = oracle_mod.Oracle(shape, periodic=(False, False, False))
+    inner = (slice(1, -1),) * 3
+    a = (0.3, -0.2, 0.1)
+    psi = 1.5 + a[0] * x + a[1] * y + a[2] * z
+    o.set_potential_force(psi, k, E)
+    fb = o.force()
+    # the stencil sums 18 weighted values: a few ulp of rounding
+    for c in range(3):
+        want = -(k * psi) * (E[c] - a[c])
+        assert np.abs(fb[c][inner] - want[inner]).max() <= 1e-14 * np.abs(want).max()
+    s = x - 6.0
+    psi = s ** 3
+    o.set_potential_force(psi, k, E)
+    fb = o.force()
+    g = (3 * s ** 2 + 1, 0.0, 0.0)
+    for c in range(3):
+        want = -(k * psi) * (E[c] - g[c])
+        assert np.abs(fb[c][inner] - want[inner]).max() <= 1e-12 * np.abs(want).max()
+
+
+def test_potential_force_boundary_values(oracle_mod):
+    """A particle of radius 1.2 centred in cell (8,8,8) covers that cell and
+    its six face neighbours.  Next to it the central D3Q7 difference takes
+    zeta at the obstacle cells: cell (10,8,8) sees psi(9,8,8) = zeta, so
+    grad_x = (psi0 - zeta)/2; cell (10,9,8) touches the particle only along a
+    diagonal, so its D3Q7 stencil sees no boundary and grad = 0; far cells
+    see a uniform field.  Obstacle and wall cells carry no force."""
+    n = 16
+    psi0, zeta, k, E = 0.4, 1.3, 2.0, (1e-3, 2e-3, -3e-3)
+    o = oracle_mod.Oracle((n, n, n))
+    o.set_particles([[8.5, 8.5, 8.5]], [1.2], [[0.0, 0.0, 0.0]])
+    fl, _ = o.map()
+    assert (fl == oracle_mod.OBST).sum() == 7
+    o.set_potential_force(np.full((n, n, n), psi0), k, E, zeta=[zeta])
+    fb = o.force()
+    rho_e = -(k * psi0)
+    f10 = fb[:, 8, 8, 10]
+    assert f10[0] == rho_e * (E[0] - (psi0 - zeta) * 0.5)
+    assert f10[1] == rho_e * E[1] and f10[2] == rho_e * E[2]
+    assert (fb[:, 8, 9, 10] == np.array([rho_e * e for e in E])).all()
+    assert (fb[:, 0, 0, 0] == np.array([rho_e * e for e in E])).all()
+    assert (fb[:, fl == oracle_mod.OBST] == 0).all()
+    # without zeta the obstacle cells' field value (psi0) is the boundary value
+    o.set_potential_force(np.full((n, n, n), psi0), k, E)
+    assert (o.force()[:, 8, 8, 10] == np.array([rho_e * e for e in E])).all()
+
+
+def test_potential_force_enters_the_step(oracle_mod):
+    """The force from the potential is the body force of the step: with a
+    resting sphere the momentum bookkeeping dP = sum_fluid f_b - F holds with
+    the potential's f_b (as for a dense force field)."""
+    n = 20
+    x, y, z = _centres((n, n, n))
+    psi = 1e-3 * np.exp(-((x - 10.3) ** 2 + (y - 9.7) ** 2 + (z - 10.1) ** 2) / 20.0)
+    o = oracle_mod.Oracle((n, n, n))
+    o.init_equilibrium()
+    o.set_particles([[10.3, 9.7, 10.1]], [3.2], [[0.0, 0.0, 0.0]])
+    o.set_potential_force(psi, 1.0, (1e-2, 0.0, 0.0), zeta=[2e-3])
+    fb = o.force()
+    fl, _ = o.map()
+    fluid = (fl == oracle_mod.FLUID) | (fl == oracle_mod.NEAR)
+    sfb = fb[:, fluid].sum(axis=1)
+    assert np.abs(sfb).max() > 0
+    for _ in range(3):
+        i0 = o.invariants()
+        o.step(1)
+        i1 = o.invariants()
+        F, _ = o.ft()
+        # rounding of the stored populations: ~1e-16 per cell and step
+        assert np.allclose(i1[1:] - i0[1:], sfb - F[0], rtol=0, atol=1e-16 * n ** 3)
