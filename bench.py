@@ -67,13 +67,18 @@ def traffic_for(precision):
     return e.get("hbm_bytes_per_launch")
 
 
-def run_gpu(wl, precision, steps, warmup):
+def run_gpu(wl, precision, steps, warmup, potential=None):
     import torch
 
     from paper_1708_08741_amd import lbmep as lb
 
     stream = torch.cuda.current_stream()
     L = lb.from_workload(wl, precision=precision, stream=stream.cuda_stream)
+    if potential is not None:
+        # the body force computed in the sweep from the EDL potential
+        psi, keps, zeta = potential
+        L.set_potential_force(psi.astype(np.float64 if precision == "fp64" else np.float32),
+                              keps, wl.E, zeta)
     fl, _ = L.map()
     nfluid = int(((fl == lb.FLUID) | (fl == lb.NEAR)).sum())
     del fl
@@ -297,8 +302,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="box edge (cells)")
     ap.add_argument("--precision", default="fp32dev", choices=list(BYTES_PER_CELL))
-    ap.add_argument("--variants", default="fp64,fp16dev",
-                    help="other storage precisions timed on the same workload ('' = none)")
+    ap.add_argument("--variants", default="fp64,fp16dev,fp32dev_pot",
+                    help="other storage precisions timed on the same workload ('' = none; "
+                         "a _pot suffix: force from the EDL potential)")
     ap.add_argument("--variant-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64,
@@ -360,15 +366,27 @@ def main():
     for v in [s for s in args.variants.split(",") if s]:
         if v == args.precision:
             continue
-        r = run_gpu(wl, v, args.variant_steps, 5)
+        pot = None
+        base = v
+        if v.endswith("_pot"):
+            # the same suspension with the force from the spheres' Debye-Hueckel
+            # potential (surface potentials in [-0.05, 0.05], kappa = 0.5)
+            base = v[:-4]
+            zeta = np.random.default_rng(4).uniform(-0.05, 0.05, len(wl.R))
+            psi = W.debye_huckel_psi(wl.shape, wl.periodic, wl.X, wl.R, zeta, kappa=0.5,
+                                     cutoff=6.0)
+            pot = (psi, 1e-3, zeta)
+        r = run_gpu(wl, base, args.variant_steps, 5, pot)
+        pot = psi = None
         tv = r["total_ms"] / 1e3
         kv = r["kernel_ms"] / 1e3
+        v_bpc = BYTES_PER_CELL[base]
         variants[v] = {
             "MLUPS": round(cells * args.variant_steps / tv / 1e6, 1),
             "steps": args.variant_steps,
             "sweep_kernel_ms": round(r["kernel_ms"], 4),
-            "sweep_GBps": round(BYTES_PER_CELL[v] * cells / kv / 1e9, 1),
-            "roofline_frac": round(BYTES_PER_CELL[v] * cells / kv / 1e9 / HBM_PEAK_GBS, 4),
+            "sweep_GBps": round(v_bpc * cells / kv / 1e9, 1),
+            "roofline_frac": round(v_bpc * cells / kv / 1e9 / HBM_PEAK_GBS, 4),
         }
         log(f"[bench] {v}: {variants[v]}")
 

@@ -126,6 +126,25 @@ int lbmep_set_force(lbmep_lattice *L, const void *fb, int dtype, int on_device);
 int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const double E[3],
                            int on_device);
 
+/* Set the electric body force of the double layer computed from the EDL
+ * potential psi (N values of dtype, kept in the compute precision) in the
+ * sweep itself (Sec. "Computing Electrostatic Forces on Fluid and
+ * Particles"): at every fluid cell f_b = rho_e (E - grad psi) with the
+ * Debye-Hueckel charge density rho_e = -kappa2_eps * psi (Eq. ChrgDensDHA;
+ * kappa2_eps = kappa^2 eps_e in lattice units).  grad psi is the
+ * w_q-weighted D3Q19 difference divided by the rest weight
+ * (Eq. ElPotGradComp, dx = 1) at cells whose 18 neighbours are all fluid
+ * cells inside the grid, and the central D3Q7 difference elsewhere, where
+ * a neighbour that is an obstacle cell of particle p contributes zeta[p]
+ * (the particle's surface potential; zeta == NULL: psi's own value there),
+ * a wall cell psi's value, and a neighbour beyond a non-periodic edge the
+ * cell's own value.  zeta has L's current particle count of values (host)
+ * and is dropped by the next lbmep_set_particles.  Replaces any other
+ * force.  Errors: EINVAL (null psi or E, bad dtype, non-finite
+ * values), ENOMEM. */
+int lbmep_set_potential_force(lbmep_lattice *L, const void *psi, int dtype, double kappa2_eps,
+                              const double E[3], const double *zeta, int on_device);
+
 /* Set every population to the incompressible equilibrium f^eq(rho, u)
  * (Eq. fequ_Incompr_SRT).  Errors: EINVAL (non-finite). */
 int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]);

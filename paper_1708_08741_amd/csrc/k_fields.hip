@@ -3,7 +3,7 @@
 // storage formats, force conversion, macroscopic read-out (Eq. MacroscopVel
 // with the velocity of Eq. modified_velocity, arXiv:1708.08741 Sec. 3.1) and
 // deterministic FP64 global sums (mass and momentum over fluid cells).
-#include "lbmep_internal.h"
+#include "potential_impl.h"
 
 namespace lbmep {
 namespace {
@@ -120,8 +120,8 @@ __device__ __forceinline__ double min_image(double d, int len, int periodic) {
 template <typename ST, typename CT>
 __global__ void k_macro(Grid g, int force_mode, const ST *f, const uint8_t *flag,
                         const uint32_t *owner, const double *Xc, const double *U, const double *W,
-                        const CT *force, double E0, double E1, double E2, double *rho,
-                        double *u) {
+                        const CT *force, double E0, double E1, double E2, double keps,
+                        const double *zeta, double *rho, double *u) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= g.nx) return;
     const int y = blockIdx.y, z = blockIdx.z;
@@ -155,6 +155,14 @@ __global__ void k_macro(Grid g, int force_mode, const ST *f, const uint8_t *flag
         fb[0] = re * E0;
         fb[1] = re * E1;
         fb[2] = re * E2;
+    } else if (force_mode == kForcePotential) {
+        // the force of the sweep, in its compute precision
+        CT f0, f1, f2;
+        potential_force<CT>(g, x, y, z, fl, force, flag, owner, zeta, (CT)keps, (CT)E0, (CT)E1,
+                            (CT)E2, f0, f1, f2);
+        fb[0] = (double)f0;
+        fb[1] = (double)f1;
+        fb[2] = (double)f2;
     }
     double s = 0.0, j[3] = {0.0, 0.0, 0.0};
     if constexpr (sizeof(ST) == 8) {
@@ -366,21 +374,21 @@ hipError_t launch_convert_force(int precision, const void *in, int in_dtype, voi
 hipError_t launch_macro(int precision, int force_mode, const Grid &g, const void *f,
                         const uint8_t *flag, const uint32_t *owner, const double *Xc,
                         const double *U, const double *W, const void *force, const double E[3],
-                        double *rho, double *u, hipStream_t s) {
+                        double keps, const double *zeta, double *rho, double *u, hipStream_t s) {
     const int bx = 64;
     const dim3 grid((g.nx + bx - 1) / bx, g.ny, g.nz), block(bx);
     if (precision == LBMEP_FP64)
         hipLaunchKernelGGL((k_macro<double, double>), grid, block, 0, s, g, force_mode,
                            (const double *)f, flag, owner, Xc, U, W, (const double *)force, E[0],
-                           E[1], E[2], rho, u);
+                           E[1], E[2], keps, zeta, rho, u);
     else if (precision == LBMEP_FP32DEV)
         hipLaunchKernelGGL((k_macro<float, float>), grid, block, 0, s, g, force_mode,
                            (const float *)f, flag, owner, Xc, U, W, (const float *)force, E[0],
-                           E[1], E[2], rho, u);
+                           E[1], E[2], keps, zeta, rho, u);
     else
         hipLaunchKernelGGL((k_macro<__half, float>), grid, block, 0, s, g, force_mode,
                            (const __half *)f, flag, owner, Xc, U, W, (const float *)force, E[0],
-                           E[1], E[2], rho, u);
+                           E[1], E[2], keps, zeta, rho, u);
     return hipGetLastError();
 }
 

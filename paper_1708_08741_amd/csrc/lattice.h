@@ -56,6 +56,9 @@ struct lbmep_lattice {
     void *force = nullptr;
     size_t force_bytes = 0;
     double E[3] = {0, 0, 0};
+    double keps = 0;           // potential force: kappa^2 eps_e
+    double *zeta = nullptr;    // potential force: per-particle boundary value (device)
+    std::vector<double> hzeta; // host copy (np values, empty: the field's value)
     double *red = nullptr;
     int red_blocks = 0;
     int block_x = 128;

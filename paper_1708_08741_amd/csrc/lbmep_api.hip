@@ -129,6 +129,8 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.ao = L->ao;
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
+    a.keps = L->keps;
+    a.zeta = L->force_mode == kForcePotential ? L->zeta : nullptr;
     a.np = L->np;
     a.pcap = L->pcap;
     a.plist = L->plist;
@@ -185,7 +187,9 @@ size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
         b += (size_t)n_particles * (8 * (size_t)link_capacity(r_max) + 4);  // link lists
     }
     if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
-    if (force_mode == kForceCharge) b += Ns * compute_bytes(cfg->precision);
+    if (force_mode == kForceCharge || force_mode == kForcePotential)
+        b += Ns * compute_bytes(cfg->precision);
+    if (force_mode == kForcePotential) b += 8 * (size_t)n_particles;
     Grid g{};
     g.nx = cfg->nx;
     g.ny = cfg->ny;
@@ -258,6 +262,7 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->owner[1]);
     dev_free(L, L->force);
     dev_free(L, L->red);
+    dev_free(L, L->zeta);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
     delete L;
@@ -456,6 +461,11 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
         L->plist_entries = (size_t)n * pcap;
     }
     L->pcap = pcap;
+    // boundary values of the potential belong to the particle table they
+    // were given with
+    dev_free(L, L->zeta);
+    L->zeta = nullptr;
+    L->hzeta.clear();
     L->np = n;
     L->hX0.assign(X, X + 3 * (size_t)n);
     L->hR.assign(R, R + n);
@@ -542,6 +552,36 @@ int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const
         L->E[2] = E[2];
     }
     return rc;
+}
+
+int lbmep_set_potential_force(lbmep_lattice *L, const void *psi, int dtype, double kappa2_eps,
+                              const double E[3], const double *zeta, int on_device) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (!E || !finite_all(E, 3)) return fail(LBMEP_EINVAL, "bad field E");
+    if (!std::isfinite(kappa2_eps)) return fail(LBMEP_EINVAL, "non-finite kappa^2 eps");
+    if (zeta && !finite_all(zeta, (size_t)L->np)) return fail(LBMEP_EINVAL, "non-finite zeta");
+    int rc = set_device(L);
+    if (rc) return rc;
+    double *dz = nullptr;
+    if (zeta && L->np > 0) {
+        if (dev_alloc(L, (void **)&dz, 8 * (size_t)L->np) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "zeta allocation failed");
+    }
+    rc = set_force_common(L, psi, dtype, on_device, 1, kForcePotential);
+    if (rc) {
+        dev_free(L, dz);
+        return rc;
+    }
+    dev_free(L, L->zeta);
+    L->zeta = dz;
+    L->hzeta.clear();
+    if (dz) {
+        L->hzeta.assign(zeta, zeta + L->np);
+        HIP_TRY(hipMemcpy(dz, zeta, 8 * (size_t)L->np, hipMemcpyHostToDevice));
+    }
+    L->keps = kappa2_eps;
+    for (int k = 0; k < 3; ++k) L->E[k] = E[k];
+    return LBMEP_OK;
 }
 
 int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]) {
@@ -673,7 +713,8 @@ int lbmep_get_macro(lbmep_lattice *L, double *rho, double *u, int on_device) {
     hipError_t e = launch_macro(L->precision, L->force_mode, L->g, L->f[L->cur], L->flag,
                                 L->np > 0 ? L->owner[L->cur_owner] : nullptr,
                                 L->np > 0 ? L->Xheld[L->cur_owner] : nullptr, L->U, L->W, L->force,
-                                L->E, drho, du, L->stream);
+                                L->E, L->keps, L->force_mode == kForcePotential ? L->zeta : nullptr,
+                                drho, du, L->stream);
     if (e == hipSuccess && !on_device) {
         e = hipMemcpyAsync(rho, drho, N * sizeof(double), hipMemcpyDeviceToHost, L->stream);
         if (e == hipSuccess)
@@ -783,7 +824,7 @@ int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches) {
 // ---------------------------------------------------------------------------
 
 namespace {
-const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '1'};
+const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '2'};
 
 struct Header {
     char magic[8];
@@ -792,6 +833,8 @@ struct Header {
     int64_t level;
     int32_t np, force_mode;
     double E[3];
+    double keps;       // potential force: kappa^2 eps_e
+    int32_t nzeta, pad; // potential force: boundary values that follow the particles
 };
 }  // namespace
 
@@ -818,6 +861,8 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
     h.np = L->np;
     h.force_mode = L->force_mode;
     for (int k = 0; k < 3; ++k) h.E[k] = L->E[k];
+    h.keps = L->keps;
+    h.nzeta = (int32_t)L->hzeta.size();
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     const size_t N = L->g.N, Ns = L->g.Ns;
     if (ok && L->np > 0) {
@@ -826,6 +871,7 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
              std::fwrite(L->hU.data(), 8, L->hU.size(), fp) == L->hU.size() &&
              std::fwrite(L->hW.data(), 8, L->hW.size(), fp) == L->hW.size();
     }
+    if (ok && h.nzeta > 0) ok = std::fwrite(L->hzeta.data(), 8, L->hzeta.size(), fp) == L->hzeta.size();
     // user wall flags
     std::vector<uint8_t> fl(N);
     if (ok) {
@@ -869,7 +915,9 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
               h.nx == L->g.nx && h.ny == L->g.ny && h.nz == L->g.nz && h.per[0] == L->g.per[0] &&
               h.per[1] == L->g.per[1] && h.per[2] == L->g.per[2] &&
               h.precision == L->precision && h.move == L->cfg.move_particles &&
-              h.nu == L->cfg.nu && h.magic_param == L->cfg.magic && h.np >= 0 && h.level >= 0;
+              h.nu == L->cfg.nu && h.magic_param == L->cfg.magic && h.np >= 0 && h.level >= 0 &&
+              (h.nzeta == 0 || h.nzeta == h.np) && h.force_mode >= kForceNone &&
+              h.force_mode <= kForcePotential;
     if (!ok) {
         std::fclose(fp);
         return fail(LBMEP_EINVAL, "checkpoint does not match this lattice");
@@ -881,9 +929,11 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
              std::fread(R.data(), 8, R.size(), fp) == R.size() &&
              std::fread(U.data(), 8, U.size(), fp) == U.size() &&
              std::fread(W.data(), 8, W.size(), fp) == W.size();
+    std::vector<double> zeta(h.nzeta);
+    if (h.nzeta > 0) ok = ok && std::fread(zeta.data(), 8, zeta.size(), fp) == zeta.size();
     std::vector<uint8_t> fl(N);
     ok = ok && std::fread(fl.data(), 1, N, fp) == N;
-    const int nc = h.force_mode == kForceDense ? 3 : (h.force_mode == kForceCharge ? 1 : 0);
+    const int nc = h.force_mode == kForceDense ? 3 : (h.force_mode == kForceNone ? 0 : 1);
     std::vector<char> force(nc * N * compute_bytes(L->precision));
     ok = ok && std::fread(force.data(), 1, force.size(), fp) == force.size();
     const size_t es = storage_bytes(L->precision);
@@ -915,6 +965,16 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
     }
     L->force_mode = h.force_mode;
     for (int k = 0; k < 3; ++k) L->E[k] = h.E[k];
+    L->keps = h.keps;
+    dev_free(L, L->zeta);
+    L->zeta = nullptr;
+    L->hzeta.clear();
+    if (h.nzeta > 0) {
+        if (dev_alloc(L, (void **)&L->zeta, 8 * (size_t)h.nzeta) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "zeta");
+        L->hzeta = zeta;
+        HIP_TRY(hipMemcpy(L->zeta, zeta.data(), 8 * (size_t)h.nzeta, hipMemcpyHostToDevice));
+    }
     for (int q = 0; q < Q; ++q)
         HIP_TRY(hipMemcpy((char *)L->f[L->cur] + q * Ns * es, pdf.data() + q * N * es, N * es,
                           hipMemcpyHostToDevice));

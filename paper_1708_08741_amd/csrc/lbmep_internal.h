@@ -41,7 +41,9 @@ constexpr float kHalfScale = 4194304.0f;
 constexpr float kHalfInvScale = 1.0f / 4194304.0f;
 
 // force modes of the sweep
-enum ForceMode { kForceNone = 0, kForceDense = 1, kForceCharge = 2 };
+// (dense f_b field; rho_e field times a uniform E; EDL potential psi, with
+// f_b = rho_e(psi) (E_ext - grad psi) computed in the sweep)
+enum ForceMode { kForceNone = 0, kForceDense = 1, kForceCharge = 2, kForcePotential = 3 };
 
 struct Grid {
     int nx, ny, nz;
@@ -64,8 +66,10 @@ struct SweepArgs {
     const double *U;   // 3n
     const double *W;   // 3n
     double *FM;        // 12n accumulators per particle: F_dev, M_dev, K, T; or null
-    const void *force; // dense: 3*Ns compute type; charge: Ns compute type
-    double E[3];
+    const void *force; // dense: 3*Ns compute type; charge, potential: Ns compute type
+    double E[3];       // charge: the uniform field; potential: E_ext
+    double keps;       // potential: kappa^2 eps_e (rho_e = -keps psi)
+    const double *zeta; // potential: per-particle boundary value, or null
     double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
     int nxb;                // x-segments per row (set by the launcher)
     int xcd_swizzle;        // 1: map consecutive segments onto one XCD
@@ -182,7 +186,8 @@ hipError_t launch_convert_force(int precision, const void *in, int in_dtype, voi
 hipError_t launch_macro(int precision, int force_mode, const Grid &g, const void *f,
                         const uint8_t *flag, const uint32_t *owner, const double *Xc,
                         const double *U, const double *W, const void *force,
-                        const double E[3], double *rho, double *u, hipStream_t s);
+                        const double E[3], double keps, const double *zeta, double *rho,
+                        double *u, hipStream_t s);
 // deterministic FP64 invariants: partial sums per block, then one block
 hipError_t launch_invariants(int precision, const Grid &g, const void *f, const uint8_t *flag,
                              double *partials, int nblocks, double *out, hipStream_t s);

@@ -285,7 +285,8 @@ int enqueue_readout(lbmep_server *S, Slot &slot) {
         LBMEP_HIP_TRY(launch_macro(L->precision, L->force_mode, L->g, L->f[L->cur], L->flag,
                                    L->np > 0 ? L->owner[L->cur_owner] : nullptr,
                                    L->np > 0 ? L->Xheld[L->cur_owner] : nullptr, L->U, L->W,
-                                   L->force, L->E, slot.fields, slot.fields + N, s));
+                                   L->force, L->E, L->keps, nullptr, slot.fields,
+                                   slot.fields + N, s));
     }
     slot.ev = get_event(S);
     if (!slot.ev) return fail(LBMEP_EDEVICE, "event creation failed");

@@ -1,0 +1,88 @@
+// potential_impl.h -- electrostatic body force of the electric double layer
+// from the EDL potential psi (arXiv:1708.08741, Sec. "Computing Electrostatic
+// Forces on Fluid and Particles"): at a fluid cell
+//     f_b = rho_e(psi) (E_ext - grad psi),   rho_e = -kappa^2 eps_e psi
+// (Eq. ChrgDensDHA).  grad psi is the w_q-weighted difference over the 18
+// D3Q19 neighbours divided by the rest weight (Eq. ElPotGradComp, dx = 1)
+// where no neighbour is a wall, obstacle or outside a non-periodic edge (the
+// cell is not NEAR), and the central D3Q7 difference with boundary values
+// otherwise: zeta_p at an obstacle cell of particle p (the field's value
+// there when no zeta is given), the field's value at a wall cell, the cell's
+// own value beyond a non-periodic edge.  Shared by the sweep and the
+// macroscopic read-out; the operation order is fixed (no contraction), so the
+// FP64 form rounds like a plain CPU evaluation.
+#pragma once
+#include "lbmep_internal.h"
+
+namespace lbmep {
+
+// psi at the neighbour (x, y, z) + (dx, dy, dz) for the D3Q7 difference
+template <typename CT>
+__device__ __forceinline__ CT psi_bc(const Grid &g, int x, int y, int z, int dx, int dy, int dz,
+                                     const CT *psi, const uint8_t *flag, const uint32_t *owner,
+                                     const double *zeta, CT centre) {
+    int v[3] = {x + dx, y + dy, z + dz};
+    const int len[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (v[k] < 0 || v[k] >= len[k]) {
+            if (!g.per[k]) return centre;
+            v[k] = v[k] < 0 ? v[k] + len[k] : v[k] - len[k];
+        }
+    }
+    const size_t s = (size_t)v[0] + (size_t)g.nx * ((size_t)v[1] + (size_t)g.ny * (size_t)v[2]);
+    if (zeta && owner && !(flag[s] & kWall)) {
+        const uint32_t p = owner[s];
+        if (p != kNone) return (CT)zeta[p];
+    }
+    return psi[s];
+}
+
+// the body force at fluid cell (x, y, z) with flag fl
+template <typename CT>
+__device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int z, uint8_t fl,
+                                                const CT *psi, const uint8_t *flag,
+                                                const uint32_t *owner, const double *zeta,
+                                                CT keps, CT E0, CT E1, CT E2, CT &f0, CT &f1,
+                                                CT &f2) {
+    const size_t c = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    const CT pc = psi[c];
+    CT g0, g1, g2;
+    if (!(fl & kNear)) {
+        // every neighbour is a fluid cell inside the grid (periodic wrap)
+        const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+        const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+        const int xs[3] = {xm, x, xp}, ys[3] = {ym, y, yp}, zs[3] = {zm, z, zp};
+        CT s0 = CT(0), s1 = CT(0), s2 = CT(0);
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const size_t n = (size_t)xs[kCx[q] + 1] +
+                             (size_t)g.nx * ((size_t)ys[kCy[q] + 1] + (size_t)g.ny * (size_t)zs[kCz[q] + 1]);
+            const CT t = (CT)wq(q) * psi[n];
+            if (kCx[q] > 0) s0 = s0 + t;
+            if (kCx[q] < 0) s0 = s0 - t;
+            if (kCy[q] > 0) s1 = s1 + t;
+            if (kCy[q] < 0) s1 = s1 - t;
+            if (kCz[q] > 0) s2 = s2 + t;
+            if (kCz[q] < 0) s2 = s2 - t;
+        }
+        // divided by the rest weight 1/3
+        g0 = s0 * CT(3.0);
+        g1 = s1 * CT(3.0);
+        g2 = s2 * CT(3.0);
+    } else {
+        g0 = (psi_bc(g, x, y, z, 1, 0, 0, psi, flag, owner, zeta, pc) -
+              psi_bc(g, x, y, z, -1, 0, 0, psi, flag, owner, zeta, pc)) * CT(0.5);
+        g1 = (psi_bc(g, x, y, z, 0, 1, 0, psi, flag, owner, zeta, pc) -
+              psi_bc(g, x, y, z, 0, -1, 0, psi, flag, owner, zeta, pc)) * CT(0.5);
+        g2 = (psi_bc(g, x, y, z, 0, 0, 1, psi, flag, owner, zeta, pc) -
+              psi_bc(g, x, y, z, 0, 0, -1, psi, flag, owner, zeta, pc)) * CT(0.5);
+    }
+    const CT rho_e = -(keps * pc);
+    f0 = rho_e * (E0 - g0);
+    f1 = rho_e * (E1 - g1);
+    f2 = rho_e * (E2 - g2);
+}
+
+}  // namespace lbmep

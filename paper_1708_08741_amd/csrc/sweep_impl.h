@@ -25,7 +25,7 @@
 // Byte offsets are 32-bit (global loads/stores with a scalar base) whenever a
 // population array is smaller than 4 GiB.
 #pragma once
-#include "lbmep_internal.h"
+#include "potential_impl.h"
 
 namespace lbmep {
 namespace sweep {
@@ -300,6 +300,11 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
             c.fb0 = *at<CT>(a.force, fo);
             c.fb1 = *at<CT>(a.force, fo + fs);
             c.fb2 = *at<CT>(a.force, fo + 2 * fs);
+        } else if constexpr (FMODE == kForcePotential) {
+            if (valid && !(fl & (kWall | kObst)))
+                potential_force<CT>(a.g, x, y, z, fl, static_cast<const CT *>(a.force), a.flag,
+                                    a.owner, a.zeta, (CT)a.keps, (CT)a.E[0], (CT)a.E[1],
+                                    (CT)a.E[2], c.fb0, c.fb1, c.fb2);
         } else if constexpr (FMODE == kForceCharge) {
             const CT *rp = at<CT>(a.force, ci * (OFF)sizeof(CT));
             CT re;
@@ -498,8 +503,10 @@ hipError_t launch_sweep_packed_typed(int force_mode, const PackTable &t, hipStre
         hipLaunchKernelGGL((k_sweep_packed<ST, kForceNone>), dim3(total), dim3(kPackBlockX), 0, s, t);
     else if (force_mode == kForceDense)
         hipLaunchKernelGGL((k_sweep_packed<ST, kForceDense>), dim3(total), dim3(kPackBlockX), 0, s, t);
-    else
+    else if (force_mode == kForceCharge)
         hipLaunchKernelGGL((k_sweep_packed<ST, kForceCharge>), dim3(total), dim3(kPackBlockX), 0, s, t);
+    else
+        return hipErrorInvalidValue;  // served requests carry no potential force
     return hipGetLastError();
 }
 
@@ -521,7 +528,8 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     do {                                                                     \
         if (force_mode == kForceNone) LBMEP_LAUNCH(MD, kForceNone, OFF, C);      \
         else if (force_mode == kForceDense) LBMEP_LAUNCH(MD, kForceDense, OFF, C); \
-        else LBMEP_LAUNCH(MD, kForceCharge, OFF, C);                           \
+        else if (force_mode == kForceCharge) LBMEP_LAUNCH(MD, kForceCharge, OFF, C); \
+        else LBMEP_LAUNCH(MD, kForcePotential, OFF, C);                        \
     } while (0)
 #define LBMEP_BY_CPT(MD)                                    \
     do {                                                    \

@@ -92,6 +92,8 @@ _SIGS = {
     "lbmep_set_particles": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P]),
     "lbmep_set_force": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int]),
     "lbmep_set_charge_force": (ctypes.c_int, [_P, _P, ctypes.c_int, _D, ctypes.c_int]),
+    "lbmep_set_potential_force": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, _D, _D,
+                                                 ctypes.c_int]),
     "lbmep_init_equilibrium": (ctypes.c_int, [_P, ctypes.c_double, _D]),
     "lbmep_set_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_get_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -263,6 +265,27 @@ class Lattice:
         Ea = np.array(E, dtype=np.float64)
         p, dev = _ptr(rho_e)
         _check(lib().lbmep_set_charge_force(self._h, p, dt, _dp(Ea), dev))
+
+    def set_potential_force(self, psi, kappa2_eps, E, zeta=None):
+        """Body force rho_e(psi) (E - grad psi) computed in the sweep from the
+        EDL potential psi (nz, ny, nx) with rho_e = -kappa2_eps psi; zeta =
+        per-particle surface potential (None: psi's value at obstacle cells)."""
+        if isinstance(psi, np.ndarray):
+            psi = np.ascontiguousarray(psi)
+            dt = DTYPE_F32 if psi.dtype == np.float32 else DTYPE_F64
+            psi = psi.astype(np.float32 if dt == DTYPE_F32 else np.float64,
+                             copy=False).reshape(-1)
+        else:
+            import torch
+            dt = DTYPE_F32 if psi.dtype == torch.float32 else DTYPE_F64
+        Ea = np.array(E, dtype=np.float64)
+        zp = None
+        if zeta is not None:
+            za = np.ascontiguousarray(zeta, dtype=np.float64).reshape(-1)
+            zp = _dp(za)
+        p, dev = _ptr(psi)
+        _check(lib().lbmep_set_potential_force(self._h, p, dt, float(kappa2_eps), _dp(Ea), zp,
+                                               dev))
 
     def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
         ua = np.array(u, dtype=np.float64)

@@ -185,6 +185,43 @@ def gaussian_shell_rho_e(shape, periodic, X, R, lambda_d=2.0, amp=1e-5, cutoff=6
     return rho
 
 
+def debye_huckel_psi(shape, periodic, X, R, zeta, kappa=0.5, cutoff=12.0):
+    """EDL potential around every sphere: the Debye-Hueckel solution for a
+    sphere of surface potential zeta_p (Sec. "Electrophoresis"),
+
+        psi(x) = sum_p zeta_p (R_p / d_p) exp(-kappa (d_p - R_p)),
+
+    for d_p = |x - X_p| (minimum image) with R_p <= d_p <= R_p + cutoff / kappa;
+    zeta_p inside sphere p; zero beyond the cutoff.  Returned as float64
+    (nz, ny, nx), cell centres at i + 1/2.  The same field is the input of
+    both the CPU oracle and the library.
+    """
+    nx, ny, nz = shape
+    L = (nx, ny, nz)
+    psi = np.zeros((nz, ny, nx), dtype=np.float64)
+    for p in range(len(R)):
+        reach = R[p] + cutoff / kappa
+        idx = []
+        for a in range(3):
+            lo = int(np.floor(X[p, a] - reach)) - 1
+            hi = int(np.floor(X[p, a] + reach)) + 1
+            ii = np.arange(lo, hi + 1)
+            if periodic[a]:
+                ii = np.arange(L[a]) if len(ii) >= L[a] else ii % L[a]
+            else:
+                ii = ii[(ii >= 0) & (ii < L[a])]
+            idx.append(ii)
+        d = [_min_image(idx[a] + 0.5 - X[p, a], L[a], periodic[a]) for a in range(3)]
+        dist = np.sqrt(d[2][:, None, None] ** 2 + d[1][None, :, None] ** 2
+                       + d[0][None, None, :] ** 2)
+        val = np.where(dist < R[p], zeta[p],
+                       np.where(dist <= reach,
+                                zeta[p] * (R[p] / np.maximum(dist, R[p]))
+                                * np.exp(-kappa * (np.maximum(dist, R[p]) - R[p])), 0.0))
+        psi[np.ix_(idx[2], idx[1], idx[0])] += val
+    return psi
+
+
 def channel_flags(shape, wall_axis=1):
     """WALL cells on the first and last layer along wall_axis (0=x,1=y,2=z)."""
     nx, ny, nz = shape

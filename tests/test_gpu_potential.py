@@ -1,0 +1,243 @@
+"""GPU parity of the electrostatic body force computed inside the sweep from
+the EDL potential psi (Sec. "Computing Electrostatic Forces on Fluid and
+Particles"): f_b = rho_e(psi) (E - grad psi) with rho_e = -kappa^2 eps psi
+(Eq. ChrgDensDHA) and grad psi from Eq. ElPotGradComp away from boundaries,
+the D3Q7 difference with boundary values next to them.
+
+The oracle evaluates the same formula on the CPU in FP64.  Bars: FP64 fields,
+forces and torques within 1e-12 relative; FP32 / FP16 deviation storage
+(psi kept in FP32) within the tolerances of the charge-force runs of the same
+storage (the potential adds an FP32 difference of neighbouring psi values,
+a relative error of a few 1e-7 on the gradient).
+"""
+import numpy as np
+import pytest
+
+from paper_1708_08741_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOLS = {  # rho: absolute, or relative to max |u| where that is larger
+    "fp64": dict(u=1e-12, rho=1e-12, rho_u=0.0, F=1e-12, M=1e-12),
+    "fp32dev": dict(u=5e-6, rho=1e-8, rho_u=0.0, F=1e-5, M=1e-6),
+    # FP16 rounds the stored deviations (which grow with |u|, here up to
+    # 0.03) to 2^-11 relative, so the density bound scales with max |u|
+    "fp16dev": dict(u=3e-3, rho=5e-6, rho_u=1e-3, F=5e-3, M=1e-3),
+}
+KEPS = 1e-3       # kappa^2 eps_e in lattice units
+KAPPA = 0.5       # inverse Debye length (cells^-1)
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1708_08741_amd import lbmep
+    lbmep.lib()
+    return lbmep
+
+
+def _fluid(o):
+    from oracle import oracle as O
+    fl, _ = o.map()
+    return (fl == O.FLUID) | (fl == O.NEAR)
+
+
+@pytest.mark.parametrize("shape,periodic,walls,with_zeta,seed", [
+    ((13, 11, 9), (True, True, True), False, True, 0),
+    ((12, 10, 14), (False, True, False), True, True, 1),
+    ((131, 7, 6), (True, False, True), True, False, 2),
+    ((9, 8, 7), (False, False, False), False, False, 3),
+    ((1, 1, 1), (True, True, True), False, False, 4),
+])
+def test_force_at_rest(lb, oracle_mod, shape, periodic, walls, with_zeta, seed):
+    """At rest (rho = 1, u = 0) the read-out velocity is f_b / 2 at fluid
+    cells: a direct comparison of the force stencil on random potentials,
+    random walls, spheres (with and without a surface potential) and
+    non-periodic edges; FP64 within 1e-12, FP32 within 1e-6 of max |f_b|."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    psi = 0.05 * rng.standard_normal((nz, ny, nx))
+    fl = (rng.random((nz, ny, nx)) < (0.12 if walls else 0.0)).astype(np.uint8)
+    n = 2 if min(shape) >= 6 else 0
+    X = np.column_stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0, nz, n)])
+    R = rng.uniform(1.2, 2.5, n)
+    zeta = rng.uniform(-0.1, 0.1, n) if with_zeta and n else None
+    E = (1e-2, -2e-2, 5e-3)
+    o = oracle_mod.Oracle(shape, periodic)
+    o.set_flags(fl)
+    o.set_particles(X, R, np.zeros((n, 3)), moving=False)
+    o.set_potential_force(psi, KEPS, E, zeta)
+    o.init_equilibrium()
+    fb = o.force()
+    rho_o, u_o = o.macro()
+    fluid = _fluid(o)
+    assert np.abs(fb[:, fluid]).max() > 0
+    for prec, tol in ((lb.FP64, 1e-12), (lb.FP32DEV, 1e-6)):
+        g = lb.Lattice(shape, periodic, precision=prec)
+        g.set_flags(fl)
+        g.set_particles(X, R, np.zeros((n, 3)))
+        g.set_potential_force(psi, KEPS, E, zeta)
+        g.init_equilibrium()
+        rho_g, u_g = g.macro()
+        fo, oo = o.map()
+        fg, og = g.map()
+        assert (fg == fo).all() and (og == oo).all()
+        s = np.abs(u_o[:, fluid]).max()
+        assert np.abs(u_g - u_o)[:, fluid].max() <= tol * s, prec
+        assert np.abs(2.0 * u_o[:, fluid] - fb[:, fluid]).max() <= 1e-15 * s
+        g.close()
+
+
+SHAPE, PER = (70, 44, 38), (True, False, True)
+
+
+def _edl_inputs():
+    """Channel (walls at y = 0, ny-1; periodic x, z) with moving charged
+    spheres, their Debye-Hueckel potential held fixed as the input."""
+    rng = np.random.default_rng(11)
+    R0 = 4.0
+    X, R = W.rsa_spheres(rng, 5, R0, SHAPE, PER, gap=3.0, lo=[0.0, 1.0 + R0 + 2.0, 0.0],
+                         hi=[70.0, 44 - 2.0 - R0 - 2.0, 38.0])
+    U = rng.uniform(-0.02, 0.02, size=(len(R), 3))
+    Wv = rng.uniform(-2e-3, 2e-3, size=(len(R), 3))
+    zeta = rng.uniform(-0.08, 0.08, len(R))
+    psi = W.debye_huckel_psi(SHAPE, PER, X, R, zeta, kappa=KAPPA)
+    return dict(X=X, R=R, U=U, W=Wv, zeta=zeta, psi=psi, E=(5e-3, 0.0, -2e-3),
+                flags=W.channel_flags(SHAPE), R0=R0)
+
+
+def _edl_lattice(lbm, precision, q):
+    g = lbm.Lattice(SHAPE, PER, precision=precision, move_particles=True)
+    g.set_flags(q["flags"])
+    g.set_particles(q["X"], q["R"], q["U"], q["W"])
+    g.set_potential_force(q["psi"].astype(np.float64 if precision == lbm.FP64 else np.float32),
+                          KEPS, q["E"], q["zeta"])
+    g.init_equilibrium()
+    return g
+
+
+def _edl_case(precision, lbm, oracle_mod, steps):
+    q = _edl_inputs()
+    o = oracle_mod.Oracle(SHAPE, PER)
+    o.set_flags(q["flags"])
+    o.set_particles(q["X"], q["R"], q["U"], q["W"], moving=True)
+    o.set_potential_force(q["psi"], KEPS, q["E"], q["zeta"])
+    o.init_equilibrium()
+    o.step(steps)
+    g = _edl_lattice(lbm, precision, q)
+    g.step(steps)
+    return o, g, q["R0"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev", "fp16dev"])
+def test_moving_charged_spheres(lb, oracle_mod, precision):
+    """30 steps of moving spheres in a walled channel driven by the EDL
+    force: maps bit-exact, fields / forces / torques within the precision's
+    tolerance of the FP64 oracle."""
+    prec = {"fp64": lb.FP64, "fp32dev": lb.FP32DEV, "fp16dev": lb.FP16DEV}[precision]
+    o, g, R0 = _edl_case(prec, lb, oracle_mod, 30)
+    fo, oo = o.map()
+    fg, og = g.map()
+    assert (fg == fo).all() and (og == oo).all()
+    fluid = _fluid(o)
+    rho_o, u_o = o.macro()
+    rho_g, u_g = g.macro()
+    F_o, M_o = o.ft()
+    F_g, M_g = g.ft()
+    g.close()
+    tol = TOLS[precision]
+    umax = np.abs(u_o[:, fluid]).max()
+    sF = np.linalg.norm(F_o, axis=1).max()
+    err = dict(u=np.abs(u_g - u_o)[:, fluid].max() / umax,
+               rho=np.abs(rho_g - rho_o)[fluid].max(),
+               F=np.linalg.norm(F_g - F_o, axis=1).max() / sF,
+               M=np.linalg.norm(M_g - M_o, axis=1).max() / (sF * R0))
+    print(precision, "umax", umax, err)
+    assert err["u"] <= tol["u"]
+    assert err["rho"] <= max(tol["rho"], tol["rho_u"] * umax)
+    assert err["F"] <= tol["F"]
+    assert err["M"] <= tol["M"]
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_sweep_variants_identical(lb, monkeypatch, precision):
+    """Launch-shape variants of the sweep in the potential mode (streaming
+    hints, one or two cells per thread, block order) give bitwise the same
+    run."""
+    q = _edl_inputs()
+    ref = None
+    for env in [dict(), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1", LBMEP_CPT="2"),
+                dict(LBMEP_SWEEP_NT="2", LBMEP_CPT="2"),
+                dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
+        for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        g = _edl_lattice(lb, precision, q)
+        g.step(13)
+        out = (g.get_pdfs(), g.ft())
+        g.close()
+        if ref is None:
+            ref = out
+        else:
+            assert (out[0] == ref[0]).all(), env
+            assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all(), env
+
+
+def test_checkpoint_keeps_the_potential(lb, tmp_path):
+    """save / load in the potential mode (psi, kappa^2 eps, E, zeta) and
+    continue: bitwise the uninterrupted run."""
+    g = _edl_lattice(lb, lb.FP32DEV, _edl_inputs())
+    g.step(7)
+    path = str(tmp_path / "pot.ck")
+    g.save(path)
+    g.step(9)
+    ref = (g.get_pdfs(), g.ft())
+    g.close()
+    h = lb.Lattice(SHAPE, PER, precision=lb.FP32DEV, move_particles=True)
+    h.load(path)
+    h.step(9)
+    out = (h.get_pdfs(), h.ft())
+    h.close()
+    assert (out[0] == ref[0]).all()
+    assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all()
+
+
+def test_set_particles_drops_zeta(lb):
+    """The surface potentials belong to the particle table they came with:
+    after set_particles the obstacle cells give psi's own value."""
+    shape = (20, 18, 16)
+    rng = np.random.default_rng(5)
+    psi = 0.05 * rng.standard_normal(shape[::-1])
+    X = np.array([[10.0, 9.0, 8.0]])
+    R = np.array([3.0])
+    out = []
+    for zeta in ([0.3], None):
+        g = lb.Lattice(shape, precision=lb.FP64)
+        g.set_particles(X, R, np.zeros((1, 3)))
+        g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+        if zeta is not None:
+            g.set_particles(X, R, np.zeros((1, 3)))
+        g.init_equilibrium()
+        out.append(g.macro()[1])
+        g.close()
+    assert (out[0] == out[1]).all()
+
+
+def test_bad_arguments(lb):
+    g = lb.Lattice((8, 8, 8), precision=lb.FP64)
+    g.set_particles([[4.0, 4.0, 4.0]], [2.0], [[0.0, 0.0, 0.0]])
+    psi = np.zeros((8, 8, 8))
+    for kw in (dict(kappa2_eps=float("nan")), dict(E=(0.0, float("inf"), 0.0)),
+               dict(zeta=[float("nan")])):
+        args = dict(psi=psi, kappa2_eps=1e-3, E=(0.0, 0.0, 0.0), zeta=None)
+        args.update(kw)
+        with pytest.raises(lb.LbmepError) as e:
+            g.set_potential_force(**args)
+        assert e.value.code == lb.EINVAL
+    bad = psi.copy()
+    bad[1, 2, 3] = np.nan
+    with pytest.raises(lb.LbmepError):
+        g.set_potential_force(bad, 1e-3, (0.0, 0.0, 0.0))
+    g.close()
