@@ -209,6 +209,10 @@ int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches);
 int lbmep_save_state(lbmep_lattice *L, const char *path);
 int lbmep_load_state(lbmep_lattice *L, const char *path);
 
+/* The number of particles of L's current particle table (set by
+ * lbmep_set_particles or a load).  Errors: EINVAL (null). */
+int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n);
+
 /* Device bytes held by a lattice of this configuration with n particles of
  * radius at most r_max (used for admission by footprint).  Errors: EINVAL. */
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,

@@ -584,6 +584,12 @@ int lbmep_set_potential_force(lbmep_lattice *L, const void *psi, int dtype, doub
     return LBMEP_OK;
 }
 
+int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n) {
+    if (!L || !n) return fail(LBMEP_EINVAL, "null argument");
+    *n = L->np;
+    return LBMEP_OK;
+}
+
 int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]) {
     if (!L || !u) return fail(LBMEP_EINVAL, "null argument");
     if (!std::isfinite(rho) || !finite_all(u, 3)) return fail(LBMEP_EINVAL, "non-finite state");

@@ -108,6 +108,7 @@ _SIGS = {
     "lbmep_get_timing": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "lbmep_save_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "lbmep_load_state": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "lbmep_get_particle_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "lbmep_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig),
@@ -361,6 +362,9 @@ class Lattice:
 
     def load(self, path):
         _check(lib().lbmep_load_state(self._h, str(path).encode()))
+        n = ctypes.c_int32(0)
+        _check(lib().lbmep_get_particle_count(self._h, ctypes.byref(n)))
+        self.np = n.value
 
 
 def from_workload(wl, precision=None, device=0, stream=None, force_dtype=None):
