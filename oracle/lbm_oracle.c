@@ -20,6 +20,12 @@
  *   Sec. "Computing Electrostatic Forces on Fluid and Particles": the body
  *     force rho_e(psi) (E_ext - grad psi) from an EDL potential
  *     (Eq. ChrgDensDHA, Eq. ElPotGradComp), optional.
+ *   Sec. "Finite Volume Discretization for Electric Potential Equations",
+ *     Sec. "Solver for Linear Elliptic PDEs with Moving Boundaries",
+ *     Sec. "Boundary Condition Handling for Solver Module": the seven-point
+ *     finite-volume Debye-Hueckel equation solved by red-black SOR with the
+ *     particles' surface potentials as Dirichlet values, optional, once per
+ *     time step before the collision (Alg. "Electrophoresis Algorithm").
  *   Sec. 3.2 (momentum exchange): cells whose centre lies in a particle are
  *     obstacle cells; velocity bounce-back (Eq. LBMMovWall); hydrodynamic
  *     force (Eq. LBMhydrodynForce) and torque; equilibrium refill of
@@ -104,6 +110,11 @@ struct orc_lattice {
     /* electrostatic body force from the EDL potential (optional) */
     int potential;
     double *psi, *zeta, k_eps, Eext[3];
+    /* red-black SOR for the Debye-Hueckel equation (optional) */
+    int sor_iters, sor_check;
+    double kappa2, sor_omega, sor_rf;
+    int last_iters;
+    double last_res0, last_res;
     int np, moving;
     double *X0, *R, *U, *W;
     double *Xn;   /* positions of the current time level */
@@ -371,19 +382,26 @@ int orc_set_force(orc_lattice *L, const double *fb) {
  * (Eq. ChrgDensDHA).  grad psi is the w_q-weighted difference over the 18
  * D3Q19 neighbours divided by the rest weight (Eq. ElPotGradComp, dx = 1)
  * where every neighbour is a fluid cell, and the central D3Q7 difference
- * where a neighbour is a wall, obstacle or outside a non-periodic edge; the
- * D3Q7 difference takes the boundary values: psi = zeta_p at obstacle
- * cells of particle p (the field's value there if no zeta is given), the
- * field's value at wall cells, and the cell's own value beyond a
- * non-periodic edge.  Recomputed whenever the map changes.
+ * where a neighbour is a wall, obstacle or outside a non-periodic edge
+ * (Sec. "Boundary Condition Handling for Solver Module": the value at a
+ * boundary cell is extrapolated from the boundary value and the cell's
+ * own value).  Particles carry a Dirichlet value b_p on the face shared
+ * with the obstacle cell: zeta_p, or, without zeta, the field's value at
+ * that obstacle cell; linear extrapolation gives 2 b_p - psi_c there.
+ * Walls and non-periodic edges are homogeneous Neumann boundaries of the
+ * potential (the value there is psi_c).  Recomputed whenever the map or
+ * psi changes.
  * ---------------------------------------------------------------------- */
 
-/* value of psi at neighbour (x,y,z) + d, the boundary value where it is an
- * obstacle cell, the centre value c0 beyond a non-periodic edge */
+/* value of psi at neighbour (x,y,z) + d seen from a cell of value c0: the
+ * boundary-extrapolated value at obstacle, wall and beyond-edge cells */
 static double psi_at(const orc_lattice *L, int x, int y, int z, const int d[3], double c0) {
     long s = neighbour(L, x, y, z, d);
-    if (s < 0) return c0;
-    if (!L->wall[s] && L->owner[s] >= 0 && L->zeta) return L->zeta[L->owner[s]];
+    if (s < 0 || L->wall[s]) return c0;
+    if (L->owner[s] >= 0) {
+        double b = L->zeta ? L->zeta[L->owner[s]] : L->psi[s];
+        return 2.0 * b - c0;
+    }
     return L->psi[s];
 }
 
@@ -448,6 +466,136 @@ int orc_set_potential_force(orc_lattice *L, const double *psi, double kappa2_eps
     L->potential = 1;
     potential_force(L);
     return 0;
+}
+
+/* -------------------------------------------------------------------------
+ * Debye-Hueckel equation for the EDL potential (Sec. "Finite Volume
+ * Discretization for Electric Potential Equations"): at every cell i that
+ * is neither a wall nor an obstacle cell (an unknown), the seven-point
+ * finite-volume form with dx = 1,
+ *     (6 + kappa^2) psi_i - sum_{q=1..6} psi(x_i + e_q) = 0,
+ * where a neighbour that is no unknown takes its boundary-extrapolated
+ * value (psi_at above: 2 b_p - psi_i at obstacle cells of particle p,
+ * psi_i at walls and beyond non-periodic edges).  Moved into the stencil
+ * and the right-hand side (Sec. "Boundary Condition Handling for Solver
+ * Module"), this is
+ *     diag_i psi_i - sum_{unknown q} psi(x_i + e_q) = rhs_i,
+ *     diag_i = 6 + kappa^2 + n_D - n_N,  rhs_i = 2 sum_{obstacle q} b_p.
+ * Solved by SOR in red-black order (Sec. "Solver for Linear Elliptic PDEs
+ * with Moving Boundaries"): first all cells with x + y + z even, then all
+ * with x + y + z odd, each relaxed as
+ *     psi_i <- (1 - omega) psi_i + omega (rhs_i + sum_unknown) / diag_i,
+ * until the L2 norm of the residual falls below rf times its initial value
+ * (or a fixed count).  The L2 norm is the root mean square over the
+ * unknowns (the reading under which the paper's initial residual is the
+ * same at every problem size of its weak scaling).
+ * ---------------------------------------------------------------------- */
+
+/* diag_i, rhs_i and the sum over unknown neighbours at unknown cell c */
+static void dha_row(const orc_lattice *L, long c, double *diag, double *rhs, double *sum) {
+    int x = (int)(c % L->nx), y = (int)((c / L->nx) % L->ny), z = (int)(c / ((long)L->nx * L->ny));
+    int a, sgn;
+    *diag = 6.0 + L->kappa2;
+    *rhs = 0.0;
+    *sum = 0.0;
+    for (a = 0; a < 3; ++a)
+        for (sgn = -1; sgn <= 1; sgn += 2) {
+            int d[3] = {0, 0, 0};
+            long s;
+            d[a] = sgn;
+            s = neighbour(L, x, y, z, d);
+            if (s < 0 || L->wall[s]) {
+                *diag -= 1.0; /* homogeneous Neumann */
+            } else if (L->owner[s] >= 0) {
+                double b = L->zeta ? L->zeta[L->owner[s]] : L->psi[s];
+                *diag += 1.0; /* Dirichlet on the shared face */
+                *rhs += 2.0 * b;
+            } else {
+                *sum += L->psi[s];
+            }
+        }
+}
+
+static int dha_unknown(const orc_lattice *L, long c) { return !L->wall[c] && L->owner[c] < 0; }
+
+double orc_dha_residual(const orc_lattice *L) {
+    double ss = 0.0;
+    long c, n = 0;
+    for (c = 0; c < L->N; ++c) {
+        double diag, rhs, sum, r;
+        if (!dha_unknown(L, c)) continue;
+        dha_row(L, c, &diag, &rhs, &sum);
+        r = rhs + sum - diag * L->psi[c];
+        ss += r * r;
+        ++n;
+    }
+    return n > 0 ? sqrt(ss / (double)n) : 0.0;
+}
+
+/* one half-sweep over the cells of one colour; cells of a colour have no
+ * neighbour of the same colour (even extents on periodic axes), so their
+ * order does not matter */
+static void sor_colour(orc_lattice *L, int colour) {
+    long c;
+    for (c = 0; c < L->N; ++c) {
+        int x = (int)(c % L->nx), y = (int)((c / L->nx) % L->ny), z = (int)(c / ((long)L->nx * L->ny));
+        double diag, rhs, sum;
+        if (((x + y + z) & 1) != colour || !dha_unknown(L, c)) continue;
+        dha_row(L, c, &diag, &rhs, &sum);
+        L->psi[c] = (1.0 - L->sor_omega) * L->psi[c] + L->sor_omega * ((rhs + sum) / diag);
+    }
+}
+
+int orc_set_potential_solver(orc_lattice *L, double kappa2, double omega, int max_iter,
+                             double rf, int check_every) {
+    int a;
+    for (a = 0; a < 3; ++a)
+        if (L->per[a] && ((a == 0 ? L->nx : a == 1 ? L->ny : L->nz) & 1)) return -1;
+    if (!L->psi || !(kappa2 > 0.0) || !(omega > 0.0 && omega < 2.0) || max_iter < 0 ||
+        check_every < 1)
+        return -1;
+    L->kappa2 = kappa2;
+    L->sor_omega = omega;
+    L->sor_iters = max_iter;
+    L->sor_rf = rf;
+    L->sor_check = check_every;
+    return 0;
+}
+
+/* one solve on the current map: iterations until res < rf res0 (rf > 0,
+ * checked every sor_check iterations) or sor_iters iterations */
+int orc_solve_potential(orc_lattice *L, int *iters, double *res0, double *res) {
+    int it = 0;
+    double r0 = L->sor_rf > 0.0 ? orc_dha_residual(L) : -1.0, r = r0;
+    if (!(L->sor_rf > 0.0 && r0 == 0.0)) {
+        while (it < L->sor_iters) {
+            sor_colour(L, 0);
+            sor_colour(L, 1);
+            ++it;
+            if (L->sor_rf > 0.0 && (it % L->sor_check == 0 || it == L->sor_iters)) {
+                r = orc_dha_residual(L);
+                if (r < L->sor_rf * r0) break;
+            }
+        }
+    }
+    L->last_iters = it;
+    L->last_res0 = r0;
+    L->last_res = r;
+    if (iters) *iters = it;
+    if (res0) *res0 = r0;
+    if (res) *res = r;
+    if (L->potential) potential_force(L);
+    return 0;
+}
+
+void orc_get_solver_stats(const orc_lattice *L, int *iters, double *res0, double *res) {
+    *iters = L->last_iters;
+    *res0 = L->last_res0;
+    *res = L->last_res;
+}
+
+void orc_get_potential(const orc_lattice *L, double *psi) {
+    memcpy(psi, L->psi, sizeof(double) * (size_t)L->N);
 }
 
 void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]) {
@@ -526,6 +674,9 @@ static void one_step(orc_lattice *L) {
     double *Sz = NULL;
     int z;
     if (np > 0) Sz = (double *)calloc((size_t)nz * np * 12, sizeof(double));
+
+    /* 0. the EDL potential of this level's map and its body force */
+    if (L->potential && L->sor_iters > 0) orc_solve_potential(L, NULL, NULL, NULL);
 
     /* 1. collide every fluid cell */
 #pragma omp parallel for schedule(static)

@@ -43,6 +43,15 @@ int orc_set_potential_force(orc_lattice *L, const double *psi, double kappa2_eps
                             const double E[3], const double *zeta);
 /* the body force field currently applied (3*N SoA) */
 void orc_get_force(const orc_lattice *L, double *fb);
+/* red-black SOR for the Debye-Hueckel equation of psi (after
+ * orc_set_potential_force); max_iter > 0 also solves at every step.
+ * Returns -1 for odd periodic extents or bad parameters. */
+int orc_set_potential_solver(orc_lattice *L, double kappa2, double omega, int max_iter,
+                             double rf, int check_every);
+int orc_solve_potential(orc_lattice *L, int *iters, double *res0, double *res);
+void orc_get_solver_stats(const orc_lattice *L, int *iters, double *res0, double *res);
+double orc_dha_residual(const orc_lattice *L);
+void orc_get_potential(const orc_lattice *L, double *psi);
 void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]);
 void orc_set_pdfs(orc_lattice *L, const double *f);       /* 19*N */
 void orc_get_pdfs(const orc_lattice *L, double *f);

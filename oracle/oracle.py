@@ -60,6 +60,13 @@ def lib():
         L.orc_set_force.argtypes = [P, dp]
         L.orc_set_potential_force.argtypes = [P, dp, ctypes.c_double, dp, ctypes.c_void_p]
         L.orc_get_force.argtypes = [P, dp]
+        L.orc_set_potential_solver.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                               ctypes.c_double, ctypes.c_int]
+        L.orc_solve_potential.argtypes = [P, ip, dp, dp]
+        L.orc_get_solver_stats.argtypes = [P, ip, dp, dp]
+        L.orc_dha_residual.argtypes = [P]
+        L.orc_dha_residual.restype = ctypes.c_double
+        L.orc_get_potential.argtypes = [P, dp]
         L.orc_init_equilibrium.argtypes = [P, ctypes.c_double, dp]
         L.orc_set_pdfs.argtypes = [P, dp]
         L.orc_get_pdfs.argtypes = [P, dp]
@@ -133,8 +140,8 @@ class Oracle:
 
     def set_potential_force(self, psi, kappa2_eps, E, zeta=None):
         """Body force rho_e(psi) (E - grad psi) from the EDL potential psi
-        (nz, ny, nx), rho_e = -kappa2_eps psi; zeta[np] = potential at each
-        particle's obstacle cells (None: the field's value)."""
+        (nz, ny, nx), rho_e = -kappa2_eps psi; zeta[np] = surface potential
+        of each particle (None: the field's value at its obstacle cells)."""
         p = np.ascontiguousarray(psi, dtype=np.float64).reshape(-1)
         Ea = np.ascontiguousarray(E, dtype=np.float64)
         zp = None
@@ -143,6 +150,38 @@ class Oracle:
             self._zeta_keep = z
             zp = z.ctypes.data
         lib().orc_set_potential_force(self._h, _dp(p), float(kappa2_eps), _dp(Ea), zp)
+
+    def set_potential_solver(self, kappa2, omega=1.7, max_iter=0, rf=0.0, check_every=1):
+        """Red-black SOR for the Debye-Hueckel equation of the potential set
+        by set_potential_force; max_iter > 0 also solves before every step."""
+        rc = lib().orc_set_potential_solver(self._h, float(kappa2), float(omega), int(max_iter),
+                                            float(rf), int(check_every))
+        if rc:
+            raise ValueError("oracle: bad solver parameters (odd periodic extent?)")
+
+    def solve_potential(self):
+        """One solve on the current map: (iterations, res0, res)."""
+        it = ctypes.c_int(0)
+        r0 = ctypes.c_double(0)
+        r = ctypes.c_double(0)
+        lib().orc_solve_potential(self._h, ctypes.byref(it), ctypes.byref(r0), ctypes.byref(r))
+        return it.value, r0.value, r.value
+
+    def solver_stats(self):
+        it = ctypes.c_int(0)
+        r0 = ctypes.c_double(0)
+        r = ctypes.c_double(0)
+        lib().orc_get_solver_stats(self._h, ctypes.byref(it), ctypes.byref(r0), ctypes.byref(r))
+        return it.value, r0.value, r.value
+
+    def dha_residual(self):
+        return lib().orc_dha_residual(self._h)
+
+    def potential(self):
+        nx, ny, nz = self.shape
+        out = np.zeros((nz, ny, nx))
+        lib().orc_get_potential(self._h, _dp(out))
+        return out
 
     def force(self):
         nx, ny, nz = self.shape

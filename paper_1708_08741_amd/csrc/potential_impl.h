@@ -5,18 +5,23 @@
 // (Eq. ChrgDensDHA).  grad psi is the w_q-weighted difference over the 18
 // D3Q19 neighbours divided by the rest weight (Eq. ElPotGradComp, dx = 1)
 // where no neighbour is a wall, obstacle or outside a non-periodic edge (the
-// cell is not NEAR), and the central D3Q7 difference with boundary values
-// otherwise: zeta_p at an obstacle cell of particle p (the field's value
-// there when no zeta is given), the field's value at a wall cell, the cell's
-// own value beyond a non-periodic edge.  Shared by the sweep and the
-// macroscopic read-out; the operation order is fixed (no contraction), so the
-// FP64 form rounds like a plain CPU evaluation.
+// cell is not NEAR), and the central D3Q7 difference otherwise, with the
+// value at a boundary cell extrapolated from the boundary value (Sec.
+// "Boundary Condition Handling for Solver Module"): particle p holds the
+// Dirichlet value b_p (zeta_p, or the field's value at the obstacle cell
+// when no zeta is given) on the shared face, so the obstacle cell counts
+// 2 b_p - psi_c; walls and non-periodic edges are homogeneous Neumann
+// boundaries (they count psi_c).  Shared by the sweep and the macroscopic
+// read-out; the operation order is fixed, so the FP64 form rounds like a
+// plain CPU evaluation.
 #pragma once
 #include "lbmep_internal.h"
 
 namespace lbmep {
 
-// psi at the neighbour (x, y, z) + (dx, dy, dz) for the D3Q7 difference
+// psi at the neighbour (x, y, z) + (dx, dy, dz) seen from a cell of value
+// centre: the boundary-extrapolated value at obstacle, wall and beyond-edge
+// cells
 template <typename CT>
 __device__ __forceinline__ CT psi_bc(const Grid &g, int x, int y, int z, int dx, int dy, int dz,
                                      const CT *psi, const uint8_t *flag, const uint32_t *owner,
@@ -31,9 +36,13 @@ __device__ __forceinline__ CT psi_bc(const Grid &g, int x, int y, int z, int dx,
         }
     }
     const size_t s = (size_t)v[0] + (size_t)g.nx * ((size_t)v[1] + (size_t)g.ny * (size_t)v[2]);
-    if (zeta && owner && !(flag[s] & kWall)) {
+    if (flag[s] & kWall) return centre;
+    if (owner) {
         const uint32_t p = owner[s];
-        if (p != kNone) return (CT)zeta[p];
+        if (p != kNone) {
+            const CT b = zeta ? (CT)zeta[p] : psi[s];
+            return CT(2.0) * b - centre;
+        }
     }
     return psi[s];
 }

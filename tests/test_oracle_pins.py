@@ -616,10 +616,11 @@ def test_potential_force_linear_and_cubic(oracle_mod):
 def test_potential_force_boundary_values(oracle_mod):
     """A particle of radius 1.2 centred in cell (8,8,8) covers that cell and
     its six face neighbours.  Next to it the central D3Q7 difference takes
-    zeta at the obstacle cells: cell (10,8,8) sees psi(9,8,8) = zeta, so
-    grad_x = (psi0 - zeta)/2; cell (10,9,8) touches the particle only along a
-    diagonal, so its D3Q7 stencil sees no boundary and grad = 0; far cells
-    see a uniform field.  Obstacle and wall cells carry no force."""
+    the value extrapolated from the Dirichlet value zeta on the shared face:
+    cell (10,8,8) sees 2 zeta - psi0 at (9,8,8), so grad_x = psi0 - zeta;
+    cell (10,9,8) touches the particle only along a diagonal, so its D3Q7
+    stencil sees no boundary and grad = 0; far cells see a uniform field.
+    Obstacle and wall cells carry no force."""
     n = 16
     psi0, zeta, k, E = 0.4, 1.3, 2.0, (1e-3, 2e-3, -3e-3)
     o = oracle_mod.Oracle((n, n, n))
@@ -630,7 +631,8 @@ def test_potential_force_boundary_values(oracle_mod):
     fb = o.force()
     rho_e = -(k * psi0)
     f10 = fb[:, 8, 8, 10]
-    assert f10[0] == rho_e * (E[0] - (psi0 - zeta) * 0.5)
+    assert f10[0] == rho_e * (E[0] - (psi0 - (2.0 * zeta - psi0)) * 0.5)
+    assert abs(f10[0] - rho_e * (E[0] - (psi0 - zeta))) <= 1e-15
     assert f10[1] == rho_e * E[1] and f10[2] == rho_e * E[2]
     assert (fb[:, 8, 9, 10] == np.array([rho_e * e for e in E])).all()
     assert (fb[:, 0, 0, 0] == np.array([rho_e * e for e in E])).all()
@@ -638,6 +640,37 @@ def test_potential_force_boundary_values(oracle_mod):
     # without zeta the obstacle cells' field value (psi0) is the boundary value
     o.set_potential_force(np.full((n, n, n), psi0), k, E)
     assert (o.force()[:, 8, 8, 10] == np.array([rho_e * e for e in E])).all()
+
+
+def test_potential_force_neumann_walls_and_edges(oracle_mod):
+    """Walls and non-periodic edges are homogeneous Neumann boundaries of
+    the potential: for psi = a y + b x in a channel with walls at y = 0 and
+    y = n - 1 (and a non-periodic x axis), the D3Q7 difference next to the
+    wall is one-sided with half weight (a / 2), and next to the x edge b / 2;
+    in the interior the gradient is exact."""
+    nx, ny, nz = 10, 12, 8
+    flags = W.channel_flags((nx, ny, nz))
+    x, y, z = _centres((nx, ny, nz))
+    a, b = 0.03, -0.02
+    psi = a * y + b * x
+    o = oracle_mod.Oracle((nx, ny, nz), periodic=(False, False, True))
+    o.set_flags(flags)
+    k, E = 1.5, (0.0, 0.0, 0.0)
+    o.set_potential_force(psi, k, E)
+    fb = o.force()
+    rho_e = -(k * psi)
+    # next to the wall at y = 0 (cell y = 1), away from the x edges
+    c = (3, 1, 5)
+    assert abs(fb[1][c] - rho_e[c] * (-(a / 2))) <= 1e-15
+    assert abs(fb[0][c] - rho_e[c] * (-b)) <= 1e-15
+    # next to the x edge (x = 0), away from the walls
+    c = (3, 5, 0)
+    assert abs(fb[0][c] - rho_e[c] * (-(b / 2))) <= 1e-15
+    assert abs(fb[1][c] - rho_e[c] * (-a)) <= 1e-15
+    # interior (D3Q19 weighted difference): exact for a linear field
+    c = (3, 5, 5)
+    assert abs(fb[0][c] - rho_e[c] * (-b)) <= 1e-15
+    assert abs(fb[1][c] - rho_e[c] * (-a)) <= 1e-15
 
 
 def test_potential_force_enters_the_step(oracle_mod):
@@ -663,3 +696,212 @@ def test_potential_force_enters_the_step(oracle_mod):
         F, _ = o.ft()
         # rounding of the stored populations: ~1e-16 per cell and step
         assert np.allclose(i1[1:] - i0[1:], sfb - F[0], rtol=0, atol=1e-16 * n ** 3)
+
+
+# ---------------------------------------------------------------------------
+# Debye-Hueckel equation by red-black SOR (Sec. "Finite Volume
+# Discretization for Electric Potential Equations", Sec. "Solver for Linear
+# Elliptic PDEs with Moving Boundaries", Sec. "Boundary Condition Handling
+# for Solver Module")
+# ---------------------------------------------------------------------------
+
+def test_dha_residual_of_a_constant_field(oracle_mod):
+    """For psi = c everywhere (no particles) every row gives r = -kappa^2 c,
+    with periodic axes and with Neumann edges alike: the L2 norm (RMS over
+    the unknowns) is kappa^2 |c|."""
+    for per in ((True, True, True), (False, False, False), (True, False, True)):
+        o = oracle_mod.Oracle((6, 8, 4), per)
+        o.set_potential_force(np.full((4, 8, 6), -0.7), 1.0, (0.0, 0.0, 0.0))
+        o.set_potential_solver(0.3, 1.7, 0)
+        # rows sum values of magnitude 6 |c| to a result of kappa^2 |c|
+        assert abs(o.dha_residual() - 0.3 * 0.7) <= 1e-14
+
+
+def _slab_case(oracle_mod, nx, kappa2, zeta):
+    """A sphere centred on the x = 0 face of a (nx, 2, 2) box, periodic in y
+    and z, of radius sqrt(2.6^2 + 0.5): it covers the cells x = 0, 1, 2
+    across the whole cross-section, a planar Dirichlet boundary."""
+    o = oracle_mod.Oracle((nx, 2, 2), (False, True, True))
+    o.set_particles([[0.0, 1.0, 1.0]], [np.sqrt(2.6 ** 2 + 0.5)], [[0.0, 0.0, 0.0]])
+    fl, _ = o.map()
+    assert (fl[:, :, :3] == oracle_mod.OBST).all() and (fl[:, :, 3:] != oracle_mod.OBST).all()
+    o.set_potential_force(np.zeros((2, 2, nx)), 1.0, (0.0, 0.0, 0.0), zeta=[zeta])
+    o.set_potential_solver(kappa2, 1.7, 20000, 1e-14)
+    return o
+
+
+def test_dha_planar_closed_form(oracle_mod):
+    """Planar Dirichlet wall (value zeta on the face x = 3) and a Neumann
+    edge at x = nx: uniform in y, z, the seven-point equation reduces to
+    (2 + kappa^2) psi_j = psi_{j-1} + psi_{j+1}, whose solutions are
+    A lam^j + B lam^-j with lam + 1/lam = 2 + kappa^2; the boundary rows
+    fix A, B through the ghost values 2 zeta - psi_0 and psi_{m-1}.  The
+    converged SOR solution equals this closed form."""
+    nx, kappa2, zeta = 40, 0.25, 0.8
+    o = _slab_case(oracle_mod, nx, kappa2, zeta)
+    it, r0, r = o.solve_potential()
+    assert 0 < it < 20000 and r < 1e-14 * r0
+    m = nx - 3
+    t = 2.0 + kappa2
+    lam = (t - np.sqrt(t * t - 4.0)) / 2.0
+    # ghost rows: psi_{-1} = 2 zeta - psi_0 and psi_m = psi_{m-1}
+    M = np.array([[lam ** -1 + 1.0, lam + 1.0],
+                  [lam ** m - lam ** (m - 1), lam ** -m - lam ** (-(m - 1))]])
+    A, B = np.linalg.solve(M, [2.0 * zeta, 0.0])
+    j = np.arange(m)
+    want = A * lam ** j + B * lam ** (-j)
+    psi = o.potential()
+    for yz in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        assert np.abs(psi[yz[0], yz[1], 3:] - want).max() <= 1e-12 * zeta
+    # the face value: the mean of psi_0 and its ghost is zeta
+    assert abs(0.5 * (psi[0, 0, 3] + (2 * zeta - psi[0, 0, 3])) - zeta) <= 1e-15
+
+
+def test_dha_one_sor_iteration_is_the_splitting_form(oracle_mod):
+    """One SOR iteration in red-black order is the textbook matrix form
+    x1 = (D - omega L)^-1 ((1 - omega) D + omega U) x0 + omega (D - omega
+    L)^-1 b, with A = D - L - U ordered red (x + y + z even) first, on a
+    small box with a particle, a wall and Neumann edges (A and b assembled
+    from the seven-point rows)."""
+    from scipy.linalg import solve_triangular
+    nx, ny, nz = 5, 4, 4
+    per = (False, True, True)
+    rng = np.random.default_rng(3)
+    flags = np.zeros((nz, ny, nx), np.uint8)
+    flags[0, 0, 4] = W.WALL
+    kappa2, omega, zeta = 0.4, 1.7, 0.6
+    o = oracle_mod.Oracle((nx, ny, nz), per)
+    o.set_flags(flags)
+    o.set_particles([[1.5, 1.5, 1.5]], [1.0], [[0.0, 0.0, 0.0]])
+    psi0 = rng.uniform(-1, 1, (nz, ny, nx))
+    o.set_potential_force(psi0, 1.0, (0.0, 0.0, 0.0), zeta=[zeta])
+    o.set_potential_solver(kappa2, omega, 1)
+    fl, _ = o.map()
+    cells = [(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)
+             if fl[z, y, x] not in (oracle_mod.OBST, oracle_mod.WALL)]
+    order = sorted(cells, key=lambda c: ((c[0] + c[1] + c[2]) & 1, c[2], c[1], c[0]))
+    idx = {c: i for i, c in enumerate(order)}
+    n = len(order)
+    A = np.zeros((n, n))
+    b = np.zeros(n)
+    for (x, y, z), i in idx.items():
+        A[i, i] = 6.0 + kappa2
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            v = [x + d[0], y + d[1], z + d[2]]
+            out = False
+            for a, ln in enumerate((nx, ny, nz)):
+                if v[a] < 0 or v[a] >= ln:
+                    if per[a]:
+                        v[a] %= ln
+                    else:
+                        out = True
+            if out or fl[v[2], v[1], v[0]] == oracle_mod.WALL:
+                A[i, i] -= 1.0
+            elif fl[v[2], v[1], v[0]] == oracle_mod.OBST:
+                A[i, i] += 1.0
+                b[i] += 2.0 * zeta
+            else:
+                A[i, idx[tuple(v)]] -= 1.0
+    D = np.diag(np.diag(A))
+    Lm = -np.tril(A, -1)
+    Um = -np.triu(A, 1)
+    x0 = np.array([psi0[z, y, x] for (x, y, z) in order])
+    x1 = solve_triangular(D - omega * Lm, ((1 - omega) * D + omega * Um) @ x0 + omega * b,
+                          lower=True)
+    o.solve_potential()
+    psi = o.potential()
+    got = np.array([psi[z, y, x] for (x, y, z) in order])
+    assert np.abs(got - x1).max() <= 1e-14
+    # cells that are no unknowns keep their values
+    keep = (fl == oracle_mod.OBST) | (fl == oracle_mod.WALL)
+    assert (psi[keep] == psi0[keep]).all()
+
+
+def test_dha_paper_initial_residual(oracle_mod):
+    """Sec. 'Parallel Performance and Scaling': on the per-process block of
+    the weak-scaling runs (144^3 cells, 4^3 spheres R = 6, periodic in y,
+    Neumann elsewhere) with zeta = 10 mV, the L2 norm of the initial residual
+    of the Debye-Hueckel equation is 3.37e-3 (tests/golden/paper_block.json).
+    With psi = 0 in the fluid the residual is the Dirichlet right-hand side
+    2 zeta per particle face: the value fixes both the extrapolation and the
+    norm (root mean square over the unknowns)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_block.json")))
+    d = g["dha"]
+    n = g["block_cells"]
+    k = g["spheres_per_axis"]
+    ax = g["first_centre"] + g["spacing"] * np.arange(k)
+    X = np.array([[x, y, z] for z in ax for y in ax for x in ax])
+    o = oracle_mod.Oracle((n, n, n), periodic=tuple(d["periodic"]))
+    o.set_particles(X, np.full(len(X), g["radius"]), np.zeros((len(X), 3)))
+    kl = d["kappa_per_metre"] * d["dx_metre"]
+    o.set_potential_force(np.zeros((n, n, n)), 1.0, (0.0, 0.0, 0.0),
+                          zeta=np.full(len(X), d["zeta_volt"]))
+    o.set_potential_solver(kl * kl, 1.7, 0)
+    r0 = o.dha_residual()
+    assert float(f"{r0:.2e}") == d["printed_initial_residual"], r0
+
+
+def test_dha_sphere_approaches_the_analytic_edl(oracle_mod):
+    """Sec. 'Electric Potential in an EDL around a Sphere': around a sphere
+    of surface potential zeta the converged discrete potential follows
+    zeta R / r exp(-kappa (r - R)) (the Debye-Hueckel solution) away from
+    the staircase surface: along the axes, from 2 to 8 cells outside,
+    within 2 % of zeta (observed 1 %)."""
+    n, R, kappa, zeta = 48, 6.0, 0.25, 1.0
+    o = oracle_mod.Oracle((n, n, n), (False, False, False))
+    c = n / 2.0
+    o.set_particles([[c, c, c]], [R], [[0.0, 0.0, 0.0]])
+    o.set_potential_force(np.zeros((n, n, n)), 1.0, (0.0, 0.0, 0.0), zeta=[zeta])
+    o.set_potential_solver(kappa * kappa, 1.7, 4000, 1e-10)
+    it, r0, r = o.solve_potential()
+    assert r < 1e-10 * r0
+    psi = o.potential()
+    i = np.arange(int(c + R + 2), int(c + R + 9))
+    rr = i + 0.5 - c
+    want = zeta * R / rr * np.exp(-kappa * (rr - R))
+    line = psi[n // 2, n // 2, i]
+    assert np.abs(line - want).max() <= 0.02 * zeta, np.abs(line - want).max()
+
+
+def test_dha_solved_before_each_step(oracle_mod):
+    """With a per-step solve, step n first solves on the map of level n and
+    then collides with the force of that potential: after one step the
+    potential equals a standalone solve on the initial map, and the
+    potential stays untouched between steps without a solver."""
+    shape = (16, 12, 10)
+    rng = np.random.default_rng(8)
+    X = np.array([[8.0, 6.0, 5.0]])
+    R = np.array([2.5])
+    U = np.array([[0.05, 0.0, 0.0]])
+    psi0 = 0.01 * rng.standard_normal(shape[::-1])
+    a = oracle_mod.Oracle(shape)
+    b = oracle_mod.Oracle(shape)
+    for o in (a, b):
+        o.set_particles(X, R, U, moving=True)
+        o.set_potential_force(psi0, 1e-3, (1e-3, 0.0, 0.0), zeta=[0.05])
+        o.set_potential_solver(0.2, 1.7, 7)
+        o.init_equilibrium()
+    a.step(1)
+    b.solve_potential()
+    assert (a.potential() == b.potential()).all()
+    assert a.solver_stats()[0] == 7
+    c = oracle_mod.Oracle(shape)
+    c.set_particles(X, R, U, moving=True)
+    c.set_potential_force(psi0, 1e-3, (1e-3, 0.0, 0.0), zeta=[0.05])
+    c.init_equilibrium()
+    c.step(2)
+    assert (c.potential() == psi0).all()
+
+
+def test_dha_solver_rejects_odd_periodic_extents(oracle_mod):
+    """Red-black ordering needs even extents along periodic axes (cells of
+    one colour must not be neighbours across the periodic boundary)."""
+    o = oracle_mod.Oracle((5, 4, 4), (True, True, True))
+    o.set_potential_force(np.zeros((4, 4, 5)), 1.0, (0.0, 0.0, 0.0))
+    with pytest.raises(ValueError):
+        o.set_potential_solver(0.2, 1.7, 3)
+    o = oracle_mod.Oracle((5, 4, 4), (False, True, True))
+    o.set_potential_force(np.zeros((4, 4, 5)), 1.0, (0.0, 0.0, 0.0))
+    o.set_potential_solver(0.2, 1.7, 3)
