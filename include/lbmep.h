@@ -145,6 +145,43 @@ int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const
 int lbmep_set_potential_force(lbmep_lattice *L, const void *psi, int dtype, double kappa2_eps,
                               const double E[3], const double *zeta, int on_device);
 
+/* Configure the solver of the Debye-Hueckel equation for the potential psi
+ * held by lbmep_set_potential_force (Sec. "Finite Volume Discretization for
+ * Electric Potential Equations": the seven-point finite-volume form
+ * (6 + kappa2) psi_i - sum_q psi(x_i + e_q) = 0 with dx = 1 at every cell
+ * that is neither a wall nor an obstacle cell).  Obstacle cells of particle
+ * p are Dirichlet boundaries with the value b_p (zeta_p, or psi's value
+ * there without zeta) on the shared face, walls and non-periodic edges
+ * homogeneous Neumann boundaries (Sec. "Boundary Condition Handling for
+ * Solver Module").  SOR in red-black order ((x+y+z) even first) with
+ * relaxation omega (Sec. "Solver for Linear Elliptic PDEs with Moving
+ * Boundaries"): at most max_iter iterations; with rf > 0 the L2 norm of the
+ * residual (root mean square over the unknowns) is taken before the first
+ * and after every check_every-th and the last iteration, and the solve stops
+ * once it is below rf times the first.  With max_iter > 0, lbmep_step solves
+ * on the current map before every collision (Alg. "Electrophoresis
+ * Algorithm"), starting from the previous solution.  psi is updated in place
+ * (compute precision); obstacle and wall cells keep their values.  Errors:
+ * EINVAL (no potential set, kappa2 <= 0, omega outside (0, 2), max_iter < 0,
+ * check_every < 1, an odd extent along a periodic axis). */
+int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, int32_t max_iter,
+                               double rf, int32_t check_every);
+
+/* One solve now, on the current map, as configured.  iters (may be NULL):
+ * iterations done; res (may be NULL): L2 norm of the initial and of the last
+ * computed residual (-1 where not computed, i.e. rf <= 0).  Synchronises
+ * when iters or res is given, and every 64 iterations when rf > 0.
+ * Errors: EINVAL (no solver configured), EDEVICE. */
+int lbmep_solve_potential(lbmep_lattice *L, int32_t *iters, double res[2]);
+
+/* Iterations and residual norms of the last solve (as above); synchronises.
+ * Errors: EINVAL (null, no solver configured). */
+int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]);
+
+/* Copy psi (N values, FP64) to host or device memory.  Errors: EINVAL (null,
+ * no potential set), ENOMEM, EDEVICE. */
+int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device);
+
 /* Set every population to the incompressible equilibrium f^eq(rho, u)
  * (Eq. fequ_Incompr_SRT).  Errors: EINVAL (non-finite). */
 int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]);

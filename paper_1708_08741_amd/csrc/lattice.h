@@ -59,6 +59,13 @@ struct lbmep_lattice {
     double keps = 0;           // potential force: kappa^2 eps_e
     double *zeta = nullptr;    // potential force: per-particle boundary value (device)
     std::vector<double> hzeta; // host copy (np values, empty: the field's value)
+    // red-black SOR for the Debye-Hueckel equation of psi (per-step solve
+    // when sor_iters > 0)
+    int32_t sor_iters = 0, sor_check = 1;
+    double sor_kappa2 = 0, sor_omega = 1.7, sor_rf = 0;
+    bool sor_set = false;
+    lbmep::SorCtl *sor_ctl = nullptr;
+    double *sor_partial = nullptr;
     double *red = nullptr;
     int red_blocks = 0;
     int block_x = 128;

@@ -263,6 +263,8 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->force);
     dev_free(L, L->red);
     dev_free(L, L->zeta);
+    dev_free(L, L->sor_ctl);
+    dev_free(L, L->sor_partial);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
     delete L;
@@ -584,6 +586,107 @@ int lbmep_set_potential_force(lbmep_lattice *L, const void *psi, int dtype, doub
     return LBMEP_OK;
 }
 
+static SorArgs sor_args(const lbmep_lattice *L) {
+    SorArgs a;
+    a.g = L->g;
+    a.psi = L->force;
+    a.flag = L->flag;
+    a.owner = L->np > 0 ? L->owner[L->cur_owner] : nullptr;
+    a.zeta = L->zeta;
+    a.kappa2 = L->sor_kappa2;
+    a.omega = L->sor_omega;
+    a.rf = L->sor_rf;
+    a.ctl = L->sor_ctl;
+    a.partial = L->sor_partial;
+    a.xcd_swizzle = L->xcd_swizzle;
+    return a;
+}
+
+int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, int32_t max_iter,
+                               double rf, int32_t check_every) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (L->force_mode != kForcePotential) return fail(LBMEP_EINVAL, "no potential set");
+    if (!(std::isfinite(kappa2) && kappa2 > 0.0)) return fail(LBMEP_EINVAL, "kappa^2 must be > 0");
+    if (!(omega > 0.0 && omega < 2.0)) return fail(LBMEP_EINVAL, "omega outside (0, 2)");
+    if (max_iter < 0 || check_every < 1 || !std::isfinite(rf))
+        return fail(LBMEP_EINVAL, "bad iteration parameters");
+    const int len[3] = {L->g.nx, L->g.ny, L->g.nz};
+    for (int k = 0; k < 3; ++k)
+        if (L->g.per[k] && (len[k] & 1))
+            return fail(LBMEP_EINVAL, "red-black ordering needs even periodic extents");
+    int rc = set_device(L);
+    if (rc) return rc;
+    if (!L->sor_ctl) {
+        if (dev_alloc(L, (void **)&L->sor_ctl, sizeof(SorCtl)) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "solver control block");
+        if (dev_alloc(L, (void **)&L->sor_partial, sizeof(double) * kSorPartials) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "solver partial sums");
+        SorCtl c{};
+        c.res0 = c.res = -1.0;
+        HIP_TRY(hipMemcpy(L->sor_ctl, &c, sizeof c, hipMemcpyHostToDevice));
+    }
+    L->sor_kappa2 = kappa2;
+    L->sor_omega = omega;
+    L->sor_iters = max_iter;
+    L->sor_rf = rf;
+    L->sor_check = check_every;
+    L->sor_set = true;
+    return LBMEP_OK;
+}
+
+int lbmep_solve_potential(lbmep_lattice *L, int32_t *iters, double res[2]) {
+    if (!L) return fail(LBMEP_EINVAL, "null lattice");
+    if (L->force_mode != kForcePotential || !L->sor_set)
+        return fail(LBMEP_EINVAL, "no potential solver configured");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(launch_sor_solve(L->precision, sor_args(L), L->sor_iters, L->sor_check, true,
+                             L->stream));
+    if (iters || res) {
+        SorCtl c;
+        HIP_TRY(hipMemcpyAsync(&c, L->sor_ctl, sizeof c, hipMemcpyDeviceToHost, L->stream));
+        HIP_TRY(hipStreamSynchronize(L->stream));
+        if (iters) *iters = c.iters;
+        if (res) {
+            res[0] = c.res0;
+            res[1] = c.res;
+        }
+    }
+    return LBMEP_OK;
+}
+
+int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]) {
+    if (!L || !iters || !res) return fail(LBMEP_EINVAL, "null argument");
+    if (!L->sor_ctl) return fail(LBMEP_EINVAL, "no potential solver configured");
+    int rc = set_device(L);
+    if (rc) return rc;
+    SorCtl c;
+    HIP_TRY(hipMemcpyAsync(&c, L->sor_ctl, sizeof c, hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    *iters = c.iters;
+    res[0] = c.res0;
+    res[1] = c.res;
+    return LBMEP_OK;
+}
+
+int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device) {
+    if (!L || !psi) return fail(LBMEP_EINVAL, "null argument");
+    if (L->force_mode != kForcePotential) return fail(LBMEP_EINVAL, "no potential set");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = L->g.N;
+    double *d = psi;
+    if (!on_device && dev_alloc(L, (void **)&d, N * sizeof(double)) != hipSuccess)
+        return fail(LBMEP_ENOMEM, "temp");
+    hipError_t e = launch_potential_to_f64(L->precision, L->g, L->force, d, L->stream);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(psi, d, N * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (!on_device) dev_free(L, d);
+    if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+    return LBMEP_OK;
+}
+
 int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n) {
     if (!L || !n) return fail(LBMEP_EINVAL, "null argument");
     *n = L->np;
@@ -655,7 +758,13 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     if (rc) return rc;
     hipStream_t s = L->stream;
     const ParticleArgs pa = particle_args(L);
+    const bool solve = L->force_mode == kForcePotential && L->sor_set && L->sor_iters > 0;
     for (int32_t it = 0; it < nsteps; ++it) {
+        // the EDL potential of this level's map, before the collision that
+        // uses its force
+        if (solve)
+            HIP_TRY(launch_sor_solve(L->precision, sor_args(L), L->sor_iters, L->sor_check, true,
+                                     s));
         const SweepArgs a = sweep_args(L);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {
@@ -841,6 +950,9 @@ struct Header {
     double E[3];
     double keps;       // potential force: kappa^2 eps_e
     int32_t nzeta, pad; // potential force: boundary values that follow the particles
+    // red-black SOR of the potential (sor_set = 0: not configured)
+    double sor_kappa2, sor_omega, sor_rf;
+    int32_t sor_iters, sor_check, sor_set, pad2;
 };
 }  // namespace
 
@@ -869,6 +981,12 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
     for (int k = 0; k < 3; ++k) h.E[k] = L->E[k];
     h.keps = L->keps;
     h.nzeta = (int32_t)L->hzeta.size();
+    h.sor_kappa2 = L->sor_kappa2;
+    h.sor_omega = L->sor_omega;
+    h.sor_rf = L->sor_rf;
+    h.sor_iters = L->sor_iters;
+    h.sor_check = L->sor_check;
+    h.sor_set = L->sor_set ? 1 : 0;
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     const size_t N = L->g.N, Ns = L->g.Ns;
     if (ok && L->np > 0) {
@@ -985,6 +1103,12 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
         HIP_TRY(hipMemcpy((char *)L->f[L->cur] + q * Ns * es, pdf.data() + q * N * es, N * es,
                           hipMemcpyHostToDevice));
     HIP_TRY(hipStreamSynchronize(L->stream));
+    L->sor_set = false;
+    if (h.sor_set) {
+        rc = lbmep_set_potential_solver(L, h.sor_kappa2, h.sor_omega, h.sor_iters, h.sor_rf,
+                                        h.sor_check);
+        if (rc) return rc;
+    }
     L->pmode = false;
     return LBMEP_OK;
 }

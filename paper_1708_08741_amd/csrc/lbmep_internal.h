@@ -52,6 +52,15 @@ struct Grid {
     size_t Ns;  // population stride (N rounded up to a multiple of 128)
 };
 
+// workgroups are dealt to the 8 XCDs round-robin; this remaps them so that
+// consecutive segments of a grid (which share cache lines through their
+// neighbour reads) run on the same XCD and its L2.  A permutation of
+// [0, nblk).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t lb, uint32_t nblk) {
+    const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
+    return (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
+}
+
 // arguments of the fused stream-collide sweep
 struct SweepArgs {
     Grid g;
@@ -188,6 +197,36 @@ hipError_t launch_macro(int precision, int force_mode, const Grid &g, const void
                         const double *U, const double *W, const void *force,
                         const double E[3], double keps, const double *zeta, double *rho,
                         double *u, hipStream_t s);
+// Debye-Hueckel equation of the EDL potential by red-black SOR: control
+// block in device memory (the kernels of a solve stop once done is set)
+struct SorCtl {
+    int32_t done;
+    int32_t iters;   // iterations of the current / last solve
+    int32_t pad[2];
+    double res0;     // L2 norm of the initial residual (-1: not computed)
+    double res;      // L2 norm of the last computed residual (-1: none)
+};
+struct SorArgs {
+    Grid g;
+    void *psi;                 // Ns values of the compute type
+    const uint8_t *flag;       // map of the current time level
+    const uint32_t *owner;     // null without particles
+    const double *zeta;        // per-particle Dirichlet value, or null
+    double kappa2, omega, rf;
+    SorCtl *ctl;
+    double *partial;           // kSorPartials FP64 partial sums
+    uint32_t xcd_swizzle;
+};
+constexpr int kSorPartials = 8192;
+// one solve on the current map: max_iter iterations of (red, black), with
+// rf > 0 a residual before the first and after every check_every-th (and the
+// last) iteration, stopping at res < rf res0; with poll, the host reads the
+// control block every 64 iterations and stops launching once it is done
+hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int check_every,
+                            bool poll, hipStream_t s);
+hipError_t launch_potential_to_f64(int precision, const Grid &g, const void *psi, double *out,
+                                   hipStream_t s);
+
 // deterministic FP64 invariants: partial sums per block, then one block
 hipError_t launch_invariants(int precision, const Grid &g, const void *f, const uint8_t *flag,
                              double *partials, int nblocks, double *out, hipStream_t s);

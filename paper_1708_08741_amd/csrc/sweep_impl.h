@@ -448,13 +448,6 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
     }
 }
 
-// workgroups are dealt to the 8 XCDs round-robin; this remaps them so that
-// consecutive x-segments (which share cache lines through the +-1 gathers
-// along x) run on the same XCD and its L2.  A permutation of [0, nblk).
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t lb, uint32_t nblk) {
-    const uint32_t xcd = lb % 8u, slot = lb / 8u, per = nblk / 8u, rem = nblk % 8u;
-    return (xcd < rem ? xcd * (per + 1u) : rem * (per + 1u) + (xcd - rem) * per) + slot;
-}
 
 // one workgroup's x-segment of a 1-D grid of segments: CPT cells per
 // thread, on consecutive rows y (their loads are all issued before the first

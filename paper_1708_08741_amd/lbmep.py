@@ -94,6 +94,12 @@ _SIGS = {
     "lbmep_set_charge_force": (ctypes.c_int, [_P, _P, ctypes.c_int, _D, ctypes.c_int]),
     "lbmep_set_potential_force": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_double, _D, _D,
                                                  ctypes.c_int]),
+    "lbmep_set_potential_solver": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_int32, ctypes.c_double,
+                                                  ctypes.c_int32]),
+    "lbmep_solve_potential": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
+    "lbmep_get_solver_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
+    "lbmep_get_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_init_equilibrium": (ctypes.c_int, [_P, ctypes.c_double, _D]),
     "lbmep_set_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_get_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -287,6 +293,33 @@ class Lattice:
         p, dev = _ptr(psi)
         _check(lib().lbmep_set_potential_force(self._h, p, dt, float(kappa2_eps), _dp(Ea), zp,
                                                dev))
+
+    def set_potential_solver(self, kappa2, omega=1.7, max_iter=0, rf=0.0, check_every=1):
+        """Red-black SOR for the Debye-Hueckel equation of the potential;
+        max_iter > 0 also solves before every step."""
+        _check(lib().lbmep_set_potential_solver(self._h, float(kappa2), float(omega),
+                                                int(max_iter), float(rf), int(check_every)))
+
+    def solve_potential(self):
+        """One solve on the current map: (iterations, res0, res)."""
+        it = ctypes.c_int32(0)
+        res = np.zeros(2)
+        _check(lib().lbmep_solve_potential(self._h, ctypes.byref(it), _dp(res)))
+        return it.value, float(res[0]), float(res[1])
+
+    def solver_stats(self):
+        it = ctypes.c_int32(0)
+        res = np.zeros(2)
+        _check(lib().lbmep_get_solver_stats(self._h, ctypes.byref(it), _dp(res)))
+        return it.value, float(res[0]), float(res[1])
+
+    def potential(self, out=None):
+        nx, ny, nz = self.shape
+        if out is None:
+            out = np.zeros((nz, ny, nx))
+        p, dev = _ptr(out)
+        _check(lib().lbmep_get_potential(self._h, p, dev))
+        return out
 
     def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
         ua = np.array(u, dtype=np.float64)

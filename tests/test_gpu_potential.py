@@ -241,3 +241,186 @@ def test_bad_arguments(lb):
     with pytest.raises(lb.LbmepError):
         g.set_potential_force(bad, 1e-3, (0.0, 0.0, 0.0))
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# red-black SOR for the Debye-Hueckel equation of psi
+# ---------------------------------------------------------------------------
+
+def _sor_case(shape, periodic, walls, n, with_zeta, seed):
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    psi = 0.05 * rng.standard_normal((nz, ny, nx))
+    fl = (rng.random((nz, ny, nx)) < (0.08 if walls else 0.0)).astype(np.uint8)
+    X = np.column_stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0, nz, n)])
+    R = rng.uniform(1.5, 3.0, n)
+    zeta = rng.uniform(-0.1, 0.1, n) if with_zeta and n else None
+    return psi, fl, X, R, zeta
+
+
+@pytest.mark.parametrize("shape,periodic,walls,n,with_zeta,rf,seed", [
+    ((16, 12, 10), (True, True, True), False, 3, True, 0.0, 0),
+    ((13, 12, 9), (False, True, False), True, 2, True, 0.0, 1),
+    ((131, 6, 8), (False, True, True), True, 2, False, 0.0, 2),
+    ((20, 18, 16), (True, False, True), False, 4, True, 1e-6, 3),
+    ((9, 7, 5), (False, False, False), True, 1, True, 1e-9, 4),
+    ((2, 2, 2), (True, True, True), False, 0, False, 0.0, 5),
+])
+def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, with_zeta, rf,
+                                  seed):
+    """One solve (fixed count, or to a residual reduction checked every 3
+    iterations): FP64 psi, iteration count and residual norms equal to the
+    oracle's (1e-12); FP32 psi within 1e-5 of max |psi|.  Ragged x extents,
+    walls, particles with and without surface potentials, Neumann edges."""
+    psi, fl, X, R, zeta = _sor_case(shape, periodic, walls, n, with_zeta, seed)
+    kappa2, omega, iters = 0.3, 1.7, 40
+    o = oracle_mod.Oracle(shape, periodic)
+    o.set_flags(fl)
+    o.set_particles(X, R, np.zeros((n, 3)), moving=False)
+    o.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+    o.set_potential_solver(kappa2, omega, iters, rf, 3)
+    it_o, r0_o, r_o = o.solve_potential()
+    psi_o = o.potential()
+    s = np.abs(psi_o).max()
+    for prec, tol in ((lb.FP64, 1e-12), (lb.FP32DEV, 1e-5)):
+        g = lb.Lattice(shape, periodic, precision=prec)
+        g.set_flags(fl)
+        g.set_particles(X, R, np.zeros((n, 3)))
+        g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+        g.set_potential_solver(kappa2, omega, iters, rf, 3)
+        it_g, r0_g, r_g = g.solve_potential()
+        psi_g = g.potential()
+        g.close()
+        err = np.abs(psi_g - psi_o).max()
+        print(prec, it_g, it_o, r0_g, r0_o, r_g, r_o, err / s)
+        assert err <= tol * s, (prec, err / s)
+        if prec == lb.FP64:
+            assert it_g == it_o
+            if rf > 0:
+                assert abs(r0_g - r0_o) <= 1e-12 * r0_o and abs(r_g - r_o) <= 1e-12 * r0_o
+            else:
+                assert r0_g == -1.0 and r_g == -1.0
+
+
+def _coupled_inputs():
+    shape = (48, 36, 32)
+    per = (True, False, True)
+    rng = np.random.default_rng(21)
+    R0 = 4.0
+    X, R = W.rsa_spheres(rng, 4, R0, shape, per, gap=3.0, lo=[0.0, 1.0 + R0 + 2.0, 0.0],
+                         hi=[48.0, 36 - 2.0 - R0 - 2.0, 32.0])
+    U = rng.uniform(-0.03, 0.03, size=(len(R), 3))
+    Wv = rng.uniform(-2e-3, 2e-3, size=(len(R), 3))
+    zeta = rng.uniform(-0.08, 0.08, len(R))
+    return dict(shape=shape, per=per, X=X, R=R, U=U, W=Wv, zeta=zeta, R0=R0,
+                flags=W.channel_flags(shape), E=(5e-3, 0.0, -2e-3))
+
+
+@pytest.mark.parametrize("precision,rf", [("fp64", 0.0), ("fp64", 1e-4), ("fp32dev", 0.0)])
+def test_coupled_steps_with_per_step_solve(lb, oracle_mod, precision, rf):
+    """Electrophoresis loop (Alg. 'Electrophoresis Algorithm'): before every
+    collision the Debye-Hueckel equation is solved on the current map of
+    the moving spheres (starting from the previous solution), and the
+    collision uses the force of that potential.  25 steps from psi = 0:
+    maps bit-exact; FP64 fields, forces, torques and potential within 1e-12
+    of the oracle, FP32 within the charge-force tolerances."""
+    q = _coupled_inputs()
+    shape, per = q["shape"], q["per"]
+    psi0 = np.zeros(shape[::-1])
+    kappa2, iters, steps = 0.05, 12, 25
+    o = oracle_mod.Oracle(shape, per)
+    o.set_flags(q["flags"])
+    o.set_particles(q["X"], q["R"], q["U"], q["W"], moving=True)
+    o.set_potential_force(psi0, KEPS, q["E"], q["zeta"])
+    o.set_potential_solver(kappa2, 1.7, iters, rf, 2)
+    o.init_equilibrium()
+    o.step(steps)
+    prec = {"fp64": lb.FP64, "fp32dev": lb.FP32DEV}[precision]
+    g = lb.Lattice(shape, per, precision=prec, move_particles=True)
+    g.set_flags(q["flags"])
+    g.set_particles(q["X"], q["R"], q["U"], q["W"])
+    g.set_potential_force(psi0.astype(np.float64 if prec == lb.FP64 else np.float32), KEPS,
+                          q["E"], q["zeta"])
+    g.set_potential_solver(kappa2, 1.7, iters, rf, 2)
+    g.init_equilibrium()
+    g.step(steps)
+    fo, oo = o.map()
+    fg, og = g.map()
+    assert (fg == fo).all() and (og == oo).all()
+    fluid = _fluid(o)
+    rho_o, u_o = o.macro()
+    rho_g, u_g = g.macro()
+    F_o, M_o = o.ft()
+    F_g, M_g = g.ft()
+    psi_o, psi_g = o.potential(), g.potential()
+    st_o, st_g = o.solver_stats(), g.solver_stats()
+    g.close()
+    tol = TOLS[precision]
+    umax = np.abs(u_o[:, fluid]).max()
+    sF = np.linalg.norm(F_o, axis=1).max()
+    err = dict(u=np.abs(u_g - u_o)[:, fluid].max() / umax,
+               rho=np.abs(rho_g - rho_o)[fluid].max(),
+               F=np.linalg.norm(F_g - F_o, axis=1).max() / sF,
+               M=np.linalg.norm(M_g - M_o, axis=1).max() / (sF * q["R0"]),
+               psi=np.abs(psi_g - psi_o).max() / np.abs(psi_o).max())
+    print(precision, rf, st_g, st_o, err)
+    assert err["u"] <= tol["u"]
+    assert err["rho"] <= max(tol["rho"], tol["rho_u"] * umax)
+    assert err["F"] <= tol["F"]
+    assert err["M"] <= tol["M"]
+    assert err["psi"] <= (1e-12 if precision == "fp64" else 1e-5)
+    if precision == "fp64":
+        assert st_g[0] == st_o[0]
+
+
+def test_sor_bad_arguments(lb):
+    g = lb.Lattice((6, 4, 4), precision=lb.FP64)
+    with pytest.raises(lb.LbmepError) as e:
+        g.set_potential_solver(0.2, 1.7, 3)  # no potential yet
+    assert e.value.code == lb.EINVAL
+    g.set_potential_force(np.zeros((4, 4, 6)), 1e-3, (0.0, 0.0, 0.0))
+    for args in ((0.0, 1.7, 3), (0.2, 2.0, 3), (0.2, 1.7, -1), (float("nan"), 1.7, 3)):
+        with pytest.raises(lb.LbmepError) as e:
+            g.set_potential_solver(*args)
+        assert e.value.code == lb.EINVAL
+    with pytest.raises(lb.LbmepError):
+        g.set_potential_solver(0.2, 1.7, 3, 0.0, 0)
+    g.close()
+    h = lb.Lattice((5, 4, 4), precision=lb.FP64)  # odd periodic extent
+    h.set_potential_force(np.zeros((4, 4, 5)), 1e-3, (0.0, 0.0, 0.0))
+    with pytest.raises(lb.LbmepError) as e:
+        h.set_potential_solver(0.2, 1.7, 3)
+    assert e.value.code == lb.EINVAL
+    h.close()
+    k = lb.Lattice((5, 4, 4), (False, True, True), precision=lb.FP64)
+    k.set_potential_force(np.zeros((4, 4, 5)), 1e-3, (0.0, 0.0, 0.0))
+    k.set_potential_solver(0.2, 1.7, 3)
+    assert k.solve_potential()[0] == 3
+    k.close()
+
+
+def test_checkpoint_keeps_the_solver(lb, tmp_path):
+    """save / load with a configured per-step solve: bitwise continuation."""
+    q = _coupled_inputs()
+    def make():
+        g = lb.Lattice(q["shape"], q["per"], precision=lb.FP32DEV, move_particles=True)
+        g.set_flags(q["flags"])
+        g.set_particles(q["X"], q["R"], q["U"], q["W"])
+        g.set_potential_force(np.zeros(q["shape"][::-1], np.float32), KEPS, q["E"], q["zeta"])
+        g.set_potential_solver(0.05, 1.7, 6)
+        g.init_equilibrium()
+        return g
+    g = make()
+    g.step(5)
+    path = str(tmp_path / "sor.ck")
+    g.save(path)
+    g.step(6)
+    ref = (g.get_pdfs(), g.potential(), g.ft())
+    g.close()
+    h = lb.Lattice(q["shape"], q["per"], precision=lb.FP32DEV, move_particles=True)
+    h.load(path)
+    h.step(6)
+    out = (h.get_pdfs(), h.potential(), h.ft())
+    h.close()
+    assert (out[0] == ref[0]).all() and (out[1] == ref[1]).all()
+    assert (out[2][0] == ref[2][0]).all() and (out[2][1] == ref[2][1]).all()
