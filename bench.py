@@ -103,6 +103,49 @@ def run_gpu(wl, precision, steps, warmup, potential=None):
                 nfluid=nfluid, invariants=inv.tolist())
 
 
+def run_coupled(wl, precision, steps, warmup, sor_iters, kappa=0.5):
+    """The electrophoresis step (Alg. "Electrophoresis Algorithm"): a fixed
+    number of red-black SOR iterations of the Debye-Hueckel equation on the
+    current map, then the stream-collide step with the force from the
+    potential.  The spheres' Debye-Hueckel fields (surface potentials in
+    [-0.05, 0.05]) are the initial potential.  Also times one standalone
+    solve of sor_iters iterations (HIP events on the lattice's stream)."""
+    import torch
+
+    from paper_1708_08741_amd import lbmep as lb
+    from paper_1708_08741_amd import workloads as W
+
+    zeta = np.random.default_rng(4).uniform(-0.05, 0.05, len(wl.R))
+    psi = W.debye_huckel_psi(wl.shape, wl.periodic, wl.X, wl.R, zeta, kappa=kappa, cutoff=6.0)
+    stream = torch.cuda.current_stream()
+    L = lb.from_workload(wl, precision=precision, stream=stream.cuda_stream)
+    L.set_potential_force(psi.astype(np.float64 if precision == "fp64" else np.float32),
+                          1e-3, wl.E, zeta)
+    del psi
+    L.set_potential_solver(kappa * kappa, 1.7, sor_iters, 0.0)
+    L.step(warmup)
+    L.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    L.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    # one standalone solve: 2 sor_iters half-sweep launches back to back
+    solves = 3
+    e0.record(stream)
+    for _ in range(solves):
+        L.solve_potential()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1) / solves
+    L.close()
+    torch.cuda.empty_cache()
+    return dict(step_ms=step_ms, solve_ms=solve_ms)
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on a bounded sample: the 128^3 sub-run of the same
     workload shape (64 moving R=4 spheres, same force construction).
@@ -306,6 +349,9 @@ def main():
                     help="other storage precisions timed on the same workload ('' = none; "
                          "a _pot suffix: force from the EDL potential)")
     ap.add_argument("--variant-steps", type=int, default=100)
+    ap.add_argument("--sor-iters", type=int, default=29,
+                    help="SOR iterations per step of the coupled electrophoresis leg (0 = none)")
+    ap.add_argument("--coupled-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the Poisson-arrival serving run (0 = no serving leg)")
@@ -390,6 +436,26 @@ def main():
         }
         log(f"[bench] {v}: {variants[v]}")
 
+    coupled = None
+    if args.sor_iters > 0:
+        # the electrophoresis step: SOR iterations + stream-collide with the
+        # force from the potential (the paper's scaling runs use 29 per step)
+        r = run_coupled(wl, args.precision, args.coupled_steps, 3, args.sor_iters)
+        es = 4 if args.precision != "fp64" else 8
+        sor_bytes = (2 * es + 1) * cells  # psi read and written once, one flag byte
+        it_ms = r["solve_ms"] / args.sor_iters
+        coupled = {
+            "MLUPS": round(cells / (r["step_ms"] / 1e3) / 1e6, 1),
+            "ms_per_step": round(r["step_ms"], 4),
+            "sor_iterations_per_step": args.sor_iters,
+            "sor_ms_per_iteration": round(it_ms, 4),
+            "sor_GBps": round(sor_bytes / (it_ms / 1e3) / 1e9, 1),
+            "sor_roofline_frac": round(sor_bytes / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "sor_bytes_per_cell_iteration": 2 * es + 1,
+            "steps": args.coupled_steps,
+        }
+        log(f"[bench] coupled step: {coupled}")
+
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
@@ -437,6 +503,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "variants": variants,
+        "coupled_electrophoresis_step": coupled,
         "errors_vs_fp64_oracle": errors,
         "serving": serving,
     }

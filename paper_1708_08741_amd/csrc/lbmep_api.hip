@@ -265,6 +265,7 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->zeta);
     dev_free(L, L->sor_ctl);
     dev_free(L, L->sor_partial);
+    dev_free(L, L->psi2);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
     delete L;
@@ -590,6 +591,7 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     SorArgs a;
     a.g = L->g;
     a.psi = L->force;
+    a.psi2 = L->psi2;
     a.flag = L->flag;
     a.owner = L->np > 0 ? L->owner[L->cur_owner] : nullptr;
     a.zeta = L->zeta;
@@ -600,6 +602,19 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.partial = L->sor_partial;
     a.xcd_swizzle = L->xcd_swizzle;
     return a;
+}
+
+// one solve as configured; the fused iteration may leave the result in the
+// second buffer, which then becomes psi
+static int run_solve(lbmep_lattice *L, hipStream_t s) {
+    int swapped = 0;
+    HIP_TRY(launch_sor_solve(L->precision, sor_args(L), L->sor_iters, L->sor_check,
+                             L->sor_fused, s, &swapped));
+    if (swapped) {
+        std::swap(L->force, L->psi2);
+        std::swap(L->force_bytes, L->psi2_bytes);
+    }
+    return LBMEP_OK;
 }
 
 int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, int32_t max_iter,
@@ -625,6 +640,17 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
         c.res0 = c.res = -1.0;
         HIP_TRY(hipMemcpy(L->sor_ctl, &c, sizeof c, hipMemcpyHostToDevice));
     }
+    const char *fz = std::getenv("LBMEP_SOR_FUSED");
+    L->sor_fused = !(fz && fz[0] == '0');
+    const size_t need = L->g.Ns * compute_bytes(L->precision);
+    if (L->sor_fused && L->psi2_bytes < need) {
+        dev_free(L, L->psi2);
+        L->psi2 = nullptr;
+        L->psi2_bytes = 0;
+        if (dev_alloc(L, &L->psi2, need) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "second potential buffer");
+        L->psi2_bytes = need;
+    }
     L->sor_kappa2 = kappa2;
     L->sor_omega = omega;
     L->sor_iters = max_iter;
@@ -640,8 +666,8 @@ int lbmep_solve_potential(lbmep_lattice *L, int32_t *iters, double res[2]) {
         return fail(LBMEP_EINVAL, "no potential solver configured");
     int rc = set_device(L);
     if (rc) return rc;
-    HIP_TRY(launch_sor_solve(L->precision, sor_args(L), L->sor_iters, L->sor_check, true,
-                             L->stream));
+    rc = run_solve(L, L->stream);
+    if (rc) return rc;
     if (iters || res) {
         SorCtl c;
         HIP_TRY(hipMemcpyAsync(&c, L->sor_ctl, sizeof c, hipMemcpyDeviceToHost, L->stream));
@@ -762,9 +788,10 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     for (int32_t it = 0; it < nsteps; ++it) {
         // the EDL potential of this level's map, before the collision that
         // uses its force
-        if (solve)
-            HIP_TRY(launch_sor_solve(L->precision, sor_args(L), L->sor_iters, L->sor_check, true,
-                                     s));
+        if (solve) {
+            rc = run_solve(L, s);
+            if (rc) return rc;
+        }
         const SweepArgs a = sweep_args(L);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {

@@ -208,7 +208,8 @@ struct SorCtl {
 };
 struct SorArgs {
     Grid g;
-    void *psi;                 // Ns values of the compute type
+    void *psi;                 // Ns values of the compute type (current iterate)
+    void *psi2;                // second buffer of the fused iteration
     const uint8_t *flag;       // map of the current time level
     const uint32_t *owner;     // null without particles
     const double *zeta;        // per-particle Dirichlet value, or null
@@ -220,10 +221,13 @@ struct SorArgs {
 constexpr int kSorPartials = 8192;
 // one solve on the current map: max_iter iterations of (red, black), with
 // rf > 0 a residual before the first and after every check_every-th (and the
-// last) iteration, stopping at res < rf res0; with poll, the host reads the
-// control block every 64 iterations and stops launching once it is done
+// last) iteration, stopping at res < rf res0 (the host reads the control
+// block every 64 iterations and stops launching once it is done).  fused:
+// one launch per iteration from psi into psi2 and back; *swapped = 1 when
+// the result ends in psi2 (the caller swaps the buffers).  Otherwise one
+// launch per colour in place.
 hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int check_every,
-                            bool poll, hipStream_t s);
+                            bool fused, hipStream_t s, int *swapped);
 hipError_t launch_potential_to_f64(int precision, const Grid &g, const void *psi, double *out,
                                    hipStream_t s);
 

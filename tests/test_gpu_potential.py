@@ -302,6 +302,41 @@ def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, wit
                 assert r0_g == -1.0 and r_g == -1.0
 
 
+@pytest.mark.parametrize("shape,periodic,n,rf", [
+    ((130, 34, 70), (False, True, True), 6, 0.0),
+    ((64, 16, 32), (True, True, True), 3, 0.0),
+    ((66, 18, 34), (True, True, True), 4, 1e-3),
+    ((7, 5, 3), (False, False, False), 1, 0.0),
+    ((2, 2, 2), (True, True, True), 0, 0.0),
+    ((1, 1, 1), (False, False, False), 0, 0.0),
+])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sor_fused_equals_two_pass(lb, monkeypatch, shape, periodic, n, rf, precision):
+    """The fused iteration (one launch, tiles of 64 x 16 with plane rings,
+    chunks of 32 planes, two buffers) gives bitwise the psi of the in-place
+    one-launch-per-colour form: several tiles and chunks with ragged tails,
+    periodic wrap of the halos, walls, particles, tiny grids; odd and even
+    iteration counts, with and without a residual stop."""
+    psi, fl, X, R, zeta = _sor_case(shape, periodic, True, n, True, 9)
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("LBMEP_SOR_FUSED", fused)
+        res = []
+        for iters in (7, 8):
+            g = lb.Lattice(shape, periodic, precision=precision)
+            g.set_flags(fl)
+            g.set_particles(X, R, np.zeros((n, 3)))
+            g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+            g.set_potential_solver(0.3, 1.7, iters, rf, 2)
+            st = g.solve_potential()
+            res.append((st, g.potential()))
+            g.close()
+        out[fused] = res
+    for (st_f, p_f), (st_t, p_t) in zip(out["1"], out["0"]):
+        assert st_f[0] == st_t[0]
+        assert (p_f == p_t).all(), np.abs(p_f - p_t).max()
+
+
 def _coupled_inputs():
     shape = (48, 36, 32)
     per = (True, False, True)
