@@ -21,10 +21,10 @@
 // FP64 kernel rounds like a plain CPU evaluation of the same rows.
 //
 // Two implementations of an iteration, bitwise identical:
-//   * k_sor_half: one launch per colour, in place (each colour streams psi
-//     through HBM once);
-//   * k_sor_fused (default): one launch per iteration from psi into a second
-//     buffer.  A workgroup owns a 64 x 16 tile of (x, y) and a chunk of z
+//   * k_sor_half (in use): one launch per colour, in place (each colour
+//     streams psi through HBM once);
+//   * k_sor_fused (switched off, see launch_sor_solve): one launch per
+//     iteration from psi into a second buffer.  A workgroup owns a 64 x 16 tile of (x, y) and a chunk of z
 //     planes and marches through its planes with rings of planes in LDS:
 //     the old values of a plane with a two-cell halo, then the new red
 //     values of that plane on a one-cell halo ring (from old black
@@ -46,7 +46,10 @@ constexpr int kSorBlock = 256;
 constexpr int kResBlock = 256;
 
 // row of unknown cell (x, y, z) with flag fl: diag, rhs and the sum over
-// unknown neighbours
+// unknown neighbours.  Next to boundaries, the six neighbour flags and
+// values are loaded together (then owner and zeta for obstacle neighbours),
+// so a boundary cell costs a few round trips, not one per direction; the
+// terms are then formed in the fixed order.
 template <typename CT>
 __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint8_t fl,
                                         const CT *psi, const uint8_t *flag,
@@ -60,39 +63,51 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
     const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
     const size_t row = nx * (size_t)y + nxy * (size_t)z;
+    size_t s[6];
+    s[0] = (size_t)xm + row;
+    s[1] = (size_t)xp + row;
+    s[2] = (size_t)x + nx * (size_t)ym + nxy * (size_t)z;
+    s[3] = (size_t)x + nx * (size_t)yp + nxy * (size_t)z;
+    s[4] = (size_t)x + nx * (size_t)y + nxy * (size_t)zm;
+    s[5] = (size_t)x + nx * (size_t)y + nxy * (size_t)zp;
     if (!(fl & kNear)) {
         // every neighbour is an unknown inside the grid (periodic wrap)
-        sum = sum + psi[(size_t)xm + row];
-        sum = sum + psi[(size_t)xp + row];
-        sum = sum + psi[(size_t)x + nx * (size_t)ym + nxy * (size_t)z];
-        sum = sum + psi[(size_t)x + nx * (size_t)yp + nxy * (size_t)z];
-        sum = sum + psi[(size_t)x + nx * (size_t)y + nxy * (size_t)zm];
-        sum = sum + psi[(size_t)x + nx * (size_t)y + nxy * (size_t)zp];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sum = sum + psi[s[k]];
         return;
     }
-    const int lo[3] = {x == 0, y == 0, z == 0};
-    const int hi[3] = {x == g.nx - 1, y == g.ny - 1, z == g.nz - 1};
+    // a neighbour beyond a non-periodic edge: homogeneous Neumann
+    bool edge[6];
+    edge[0] = x == 0 && !g.per[0];
+    edge[1] = x == g.nx - 1 && !g.per[0];
+    edge[2] = y == 0 && !g.per[1];
+    edge[3] = y == g.ny - 1 && !g.per[1];
+    edge[4] = z == 0 && !g.per[2];
+    edge[5] = z == g.nz - 1 && !g.per[2];
+    uint8_t fs[6];
+    CT pv[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const int a = k >> 1;
-        const bool up = k & 1;
-        if ((up ? hi[a] : lo[a]) && !g.per[a]) {
-            diag = diag - CT(1.0);  // homogeneous Neumann (edge)
-            continue;
-        }
-        const int vx = a == 0 ? (up ? xp : xm) : x;
-        const int vy = a == 1 ? (up ? yp : ym) : y;
-        const int vz = a == 2 ? (up ? zp : zm) : z;
-        const size_t s = (size_t)vx + nx * (size_t)vy + nxy * (size_t)vz;
-        const uint8_t fs = flag[s];
-        if (fs & kWall) {
-            diag = diag - CT(1.0);  // homogeneous Neumann (wall)
-        } else if (fs & kObst) {
-            const CT b = zeta ? (CT)zeta[owner[s]] : psi[s];
+        fs[k] = edge[k] ? (uint8_t)kWall : flag[s[k]];
+        pv[k] = edge[k] ? CT(0) : psi[s[k]];
+    }
+    CT bv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        // Dirichlet value of an obstacle neighbour: zeta of its particle,
+        // or psi's value there
+        bv[k] = pv[k];
+        if (zeta && !edge[k] && (fs[k] & kObst) && !(fs[k] & kWall)) bv[k] = (CT)zeta[owner[s[k]]];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (edge[k] || (fs[k] & kWall)) {
+            diag = diag - CT(1.0);  // homogeneous Neumann (edge or wall)
+        } else if (fs[k] & kObst) {
             diag = diag + CT(1.0);  // Dirichlet on the shared face
-            rhs = rhs + CT(2.0) * b;
+            rhs = rhs + CT(2.0) * bv[k];
         } else {
-            sum = sum + psi[s];
+            sum = sum + pv[k];
         }
     }
 }
@@ -106,29 +121,345 @@ __global__ void k_sor_begin(SorCtl *ctl) {
     }
 }
 
-// one half-sweep: the unknowns of one colour, one per thread; rows of
-// (nx + 1) / 2 slots
+// one half-sweep: the interior unknowns of one colour.  A workgroup covers
+// 2 kSorBlock cells of kSorRows consecutive rows (y) of one plane; thread t
+// owns the pair x = 2t, 2t + 1 of each row and relaxes the one of this
+// colour.  It writes the whole pair back (the other cell unchanged: no
+// thread changes it in this half-sweep), so every cache line is written
+// in full.  Rows are addressed through workgroup-uniform row pointers and a
+// per-lane x, so loads take a scalar base and a 32-bit offset.  The flags
+// of all its rows are loaded first, then every neighbour value of its
+// interior cells, so a wave keeps many loads in flight.
+constexpr int kSorRows = 4;
+
 template <typename CT>
-__global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, int count) {
+__global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, int count,
+                                                        uint32_t nxb, uint32_t nyb) {
     if (a.ctl->done) return;
     if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
     const Grid &g = a.g;
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const size_t t = (size_t)lb * kSorBlock + threadIdx.x;
-    const size_t hx = (size_t)((g.nx + 1) / 2);
-    const size_t r = t / hx;
-    if (r >= (size_t)g.ny * (size_t)g.nz) return;
-    const int y = (int)(r % (size_t)g.ny), z = (int)(r / (size_t)g.ny);
-    const int x = 2 * (int)(t - r * hx) + ((colour + y + z) & 1);
-    if (x >= g.nx) return;
-    const size_t c = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    const uint8_t fl = a.flag[c];
-    if (fl & (kWall | kObst)) return;
+    const uint32_t row = lb / nxb, xb = lb - row * nxb;
+    const int y0 = (int)(row % nyb) * kSorRows, z = (int)(row / nyb);
+    const int x2 = (int)(xb * (2 * kSorBlock) + 2 * threadIdx.x);
+    if (x2 >= g.nx) return;
+    const bool two = x2 + 1 < g.nx;  // the pair's second cell exists
+    const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
     CT *psi = static_cast<CT *>(a.psi);
-    CT diag, rhs, sum;
-    dha_row<CT>(g, x, y, z, fl, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs, sum);
+    const CT *pz_m = psi + nxy * (size_t)zm, *pz_p = psi + nxy * (size_t)zp;
+    CT *pz = psi + nxy * (size_t)z;
+    const uint8_t *fz = a.flag + nxy * (size_t)z;
+    uint32_t xs[kSorRows];
+    uint8_t fl[kSorRows];
+    CT pair[kSorRows][2];
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        const int y = y0 + r;
+        const uint32_t p = (uint32_t)((colour + y + z) & 1);  // the pair's cell of this colour
+        xs[r] = (uint32_t)x2 + p;
+        fl[r] = kWall;
+        if (y < g.ny) {
+            const CT *pr = pz + nx * (size_t)y;
+            pair[r][0] = pr[x2];
+            if (two) pair[r][1] = pr[x2 + 1];
+            if (xs[r] < (uint32_t)g.nx) fl[r] = fz[nx * (size_t)y + xs[r]];
+        }
+    }
+    // interior cells: the six neighbours in the row order x-, x+, y-, y+,
+    // z-, z+ (every neighbour an unknown inside the grid)
+    CT v[kSorRows][6];
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        if (fl[r] & (kWall | kObst | kNear)) continue;
+        const uint32_t x = xs[r];
+        const int y = y0 + r;
+        const uint32_t xm = x == 0 ? (uint32_t)g.nx - 1 : x - 1;
+        const uint32_t xp = x == (uint32_t)g.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+        const CT *pr = pz + nx * (size_t)y;
+        v[r][0] = pr[xm];
+        v[r][1] = pr[xp];
+        v[r][2] = (pz + nx * (size_t)ym)[x];
+        v[r][3] = (pz + nx * (size_t)yp)[x];
+        v[r][4] = (pz_m + nx * (size_t)y)[x];
+        v[r][5] = (pz_p + nx * (size_t)y)[x];
+    }
     const CT om = (CT)a.omega;
-    psi[c] = (CT(1.0) - om) * psi[c] + om * ((rhs + sum) / diag);
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        const int y = y0 + r;
+        if (y >= g.ny) continue;
+        const uint32_t p = xs[r] - (uint32_t)x2;
+        if (!(fl[r] & (kWall | kObst | kNear))) {
+            // interior cell; boundary cells are relaxed from the list
+            const CT diag = CT(6.0) + (CT)a.kappa2, rhs = CT(0);
+            CT sum = CT(0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sum = sum + v[r][k];
+            const CT old = p ? pair[r][1] : pair[r][0];
+            const CT nw = (CT(1.0) - om) * old + om * ((rhs + sum) / diag);
+            if (p) pair[r][1] = nw;
+            else pair[r][0] = nw;
+        }
+        CT *pr = pz + nx * (size_t)y;
+        pr[x2] = pair[r][0];
+        if (two) pr[x2 + 1] = pair[r][1];
+    }
+}
+
+// vector form of the interior half-sweep for even nx: the pairs (x2, x2 + 1)
+// are loaded as one aligned 2-vector for the rows y0 - 1 .. y0 + kSorRows of
+// the plane and the rows y0 .. y0 + kSorRows - 1 of the planes z -+ 1; the
+// x -+ 1 values come from the neighbouring lanes (the wave's end lanes load
+// theirs), the y -+ 1 values from the thread's own neighbouring rows.  Every
+// load and store is a whole coalesced 2-vector.  Same arithmetic as
+// k_sor_half.
+template <typename CT>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using T = float2;
+};
+template <>
+struct Vec2<double> {
+    using T = double2;
+};
+
+template <typename CT>
+__device__ __forceinline__ CT lane_shift(CT v, int delta) {
+    // value of lane (lane + delta) of the wave
+    return __shfl(v, (int)(threadIdx.x & 63) + delta, 64);
+}
+
+template <typename CT>
+__global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colour, int count,
+                                                            uint32_t nxb, uint32_t nyb) {
+    using V = typename Vec2<CT>::T;
+    if (a.ctl->done) return;
+    if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
+    const Grid &g = a.g;
+    const uint32_t lb = blockIdx.x;
+    const uint32_t row = lb / nxb, xb = lb - row * nxb;
+    const int y0 = (int)(row % nyb) * kSorRows, z = (int)(row / nyb);
+    const int x2 = (int)(xb * (2 * kSorBlock) + 2 * threadIdx.x);
+    const bool act = x2 < g.nx;  // lanes past the row take part in the shuffles only
+    const int lane = (int)(threadIdx.x & 63);
+    const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    CT *psi = static_cast<CT *>(a.psi);
+    CT *pz = psi + nxy * (size_t)z;
+    const CT *pzm = psi + nxy * (size_t)zm, *pzp = psi + nxy * (size_t)zp;
+    const uint8_t *fz = a.flag + nxy * (size_t)z;
+    const int xc = act ? x2 : 0;  // a valid column for lanes past the row
+    // rows y0 - 1 .. y0 + kSorRows of the plane (k = row - y0 + 1)
+    V P[kSorRows + 2];
+#pragma unroll
+    for (int k = 0; k < kSorRows + 2; ++k) {
+        // any row index into [0, ny) (rows a cell needs wrap once: the same)
+        const int y = ((y0 - 1 + k) % g.ny + g.ny) % g.ny;
+        P[k] = *reinterpret_cast<const V *>(pz + nx * (size_t)y + (size_t)xc);
+    }
+    V Zm[kSorRows], Zp[kSorRows];
+    uint16_t F[kSorRows];
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        const int y = min(y0 + r, g.ny - 1);
+        Zm[r] = *reinterpret_cast<const V *>(pzm + nx * (size_t)y + (size_t)xc);
+        Zp[r] = *reinterpret_cast<const V *>(pzp + nx * (size_t)y + (size_t)xc);
+        F[r] = *reinterpret_cast<const uint16_t *>(fz + nx * (size_t)y + (size_t)xc);
+    }
+    // x - 1 of the pair's first cell and x + 1 of its second: neighbouring
+    // lanes, or a load at the wave's ends (periodic wrap of the row)
+    CT left[kSorRows], right[kSorRows];
+    const int xl = x2 == 0 ? g.nx - 1 : x2 - 1, xr = x2 + 2 >= g.nx ? x2 + 2 - g.nx : x2 + 2;
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        left[r] = lane_shift(P[r + 1].y, -1);
+        right[r] = lane_shift(P[r + 1].x, 1);
+        const int y = min(y0 + r, g.ny - 1);
+        if (act && (lane == 0 || x2 == 0)) left[r] = pz[nx * (size_t)y + (size_t)xl];
+        if (act && (lane == 63 || x2 + 2 >= g.nx)) right[r] = pz[nx * (size_t)y + (size_t)xr];
+    }
+    if (!act) return;
+    const CT om = (CT)a.omega;
+    const CT diag = CT(6.0) + (CT)a.kappa2;
+#pragma unroll
+    for (int r = 0; r < kSorRows; ++r) {
+        const int y = y0 + r;
+        if (y >= g.ny) continue;
+        const int p = (colour + y + z) & 1;
+        const uint8_t fl = p ? (uint8_t)(F[r] >> 8) : (uint8_t)(F[r] & 0xff);
+        if (!(fl & (kWall | kObst | kNear))) {
+            // interior cell: x-, x+, y-, y+, z-, z+
+            CT nb[6], own;
+            if (p == 0) {
+                own = P[r + 1].x;
+                nb[0] = left[r];
+                nb[1] = P[r + 1].y;
+                nb[2] = P[r].x;
+                nb[3] = P[r + 2].x;
+                nb[4] = Zm[r].x;
+                nb[5] = Zp[r].x;
+            } else {
+                own = P[r + 1].y;
+                nb[0] = P[r + 1].x;
+                nb[1] = right[r];
+                nb[2] = P[r].y;
+                nb[3] = P[r + 2].y;
+                nb[4] = Zm[r].y;
+                nb[5] = Zp[r].y;
+            }
+            CT sum = CT(0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sum = sum + nb[k];
+            const CT rhs = CT(0);
+            const CT nw = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
+            if (p == 0) P[r + 1].x = nw;
+            else P[r + 1].y = nw;
+        }
+        *reinterpret_cast<V *>(pz + nx * (size_t)y + (size_t)x2) = P[r + 1];
+    }
+}
+
+// the boundary unknowns (NEAR cells) of each colour, listed once per solve
+// (the map is fixed during a solve): counts per segment of kNearSeg cells,
+// an exclusive scan over the segments, then each segment writes its cells
+// in increasing order
+__device__ __forceinline__ uint32_t cell_colour(const Grid &g, size_t c) {
+    const size_t x = c % (size_t)g.nx, yz = c / (size_t)g.nx;
+    const size_t y = yz % (size_t)g.ny, z = yz / (size_t)g.ny;
+    return (uint32_t)((x + y + z) & 1);
+}
+
+constexpr int kNearBlock = 256;
+static_assert(kNearSeg % kNearBlock == 0, "segment = whole block passes");
+
+__device__ __forceinline__ bool near_unknown(uint8_t f) {
+    return (f & kNear) && !(f & (kWall | kObst));
+}
+
+// counts of one segment per colour: scratch[2 s + colour]
+__global__ void __launch_bounds__(kNearBlock) k_nlist_count(Grid g, const uint8_t *flag,
+                                                            uint32_t *scratch) {
+    const size_t c0 = (size_t)blockIdx.x * kNearSeg;
+    uint32_t n[2] = {0, 0};
+    for (int k = 0; k < kNearSeg / kNearBlock; ++k) {
+        const size_t c = c0 + (size_t)k * kNearBlock + threadIdx.x;
+        if (c < g.N && near_unknown(flag[c])) n[cell_colour(g, c)] += 1;
+    }
+    __shared__ uint32_t s0[kNearBlock], s1[kNearBlock];
+    s0[threadIdx.x] = n[0];
+    s1[threadIdx.x] = n[1];
+    __syncthreads();
+    for (int h = kNearBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            s0[threadIdx.x] += s0[threadIdx.x + h];
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scratch[2 * blockIdx.x] = s0[0];
+        scratch[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// one block: exclusive scan of the segment counts of both colours into
+// scratch[2 nseg + 2 s + colour]; the totals into the control block
+__global__ void __launch_bounds__(1024) k_nlist_scan(uint32_t *scratch, uint32_t nseg, SorCtl *ctl) {
+    __shared__ uint32_t t0[1024], t1[1024];
+    const uint32_t per = (nseg + 1023) / 1024;
+    const uint32_t b = threadIdx.x * per, e = min(b + per, nseg);
+    uint32_t a0 = 0, a1 = 0;
+    for (uint32_t s = b; s < e; ++s) {
+        a0 += scratch[2 * s];
+        a1 += scratch[2 * s + 1];
+    }
+    t0[threadIdx.x] = a0;
+    t1[threadIdx.x] = a1;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v0 = threadIdx.x >= (unsigned)d ? t0[threadIdx.x - d] : 0;
+        const uint32_t v1 = threadIdx.x >= (unsigned)d ? t1[threadIdx.x - d] : 0;
+        __syncthreads();
+        t0[threadIdx.x] += v0;
+        t1[threadIdx.x] += v1;
+        __syncthreads();
+    }
+    uint32_t o0 = t0[threadIdx.x] - a0, o1 = t1[threadIdx.x] - a1;
+    for (uint32_t s = b; s < e; ++s) {
+        const uint32_t n0 = scratch[2 * s], n1 = scratch[2 * s + 1];
+        scratch[2 * nseg + 2 * s] = o0;
+        scratch[2 * nseg + 2 * s + 1] = o1;
+        o0 += n0;
+        o1 += n1;
+    }
+    if (threadIdx.x == 1023) {
+        ctl->nnear[0] = t0[1023];
+        ctl->nnear[1] = t1[1023];
+    }
+}
+
+// each segment writes its boundary unknowns of both colours, in order
+__global__ void __launch_bounds__(kNearBlock) k_nlist_write(Grid g, const uint8_t *flag,
+                                                            const uint32_t *scratch, uint32_t nseg,
+                                                            uint32_t *list) {
+    const size_t c0 = (size_t)blockIdx.x * kNearSeg;
+    const size_t half = g.N / 2 + 1;
+    uint32_t off[2] = {scratch[2 * nseg + 2 * blockIdx.x], scratch[2 * nseg + 2 * blockIdx.x + 1]};
+    __shared__ uint32_t w0[kNearBlock / 64], w1[kNearBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < kNearSeg / kNearBlock; ++k) {
+        const size_t c = c0 + (size_t)k * kNearBlock + threadIdx.x;
+        const bool nu = c < g.N && near_unknown(flag[c]);
+        const uint32_t col = nu ? cell_colour(g, c) : 0;
+        const uint64_t b0 = __ballot(nu && col == 0), b1 = __ballot(nu && col == 1);
+        if (lane == 0) {
+            w0[wv] = (uint32_t)__popcll(b0);
+            w1[wv] = (uint32_t)__popcll(b1);
+        }
+        __syncthreads();
+        uint32_t p0 = off[0], p1 = off[1];
+        for (int v = 0; v < wv; ++v) {
+            p0 += w0[v];
+            p1 += w1[v];
+        }
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        if (nu) {
+            if (col == 0) list[p0 + (uint32_t)__popcll(b0 & below)] = (uint32_t)c;
+            else list[half + p1 + (uint32_t)__popcll(b1 & below)] = (uint32_t)c;
+        }
+        for (int v = 0; v < kNearBlock / 64; ++v) {
+            off[0] += w0[v];
+            off[1] += w1[v];
+        }
+        __syncthreads();
+    }
+}
+
+// the boundary unknowns of one colour, from its list (fixed grid, strided)
+constexpr int kNearGrid = 2048;
+
+template <typename CT>
+__global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) {
+    if (a.ctl->done) return;
+    const Grid &g = a.g;
+    const uint32_t n = a.ctl->nnear[colour];
+    const uint32_t *list = a.nlist + (colour ? g.N / 2 + 1 : 0);
+    CT *psi = static_cast<CT *>(a.psi);
+    const CT om = (CT)a.omega;
+    for (uint32_t i = blockIdx.x * kNearBlock + threadIdx.x; i < n; i += kNearGrid * kNearBlock) {
+        const size_t c = list[i];
+        const int x = (int)(c % (size_t)g.nx);
+        const size_t yz = c / (size_t)g.nx;
+        const int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
+        CT diag, rhs, sum;
+        dha_row<CT>(g, x, y, z, a.flag[c], psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs,
+                    sum);
+        psi[c] = (CT(1.0) - om) * psi[c] + om * ((rhs + sum) / diag);
+    }
 }
 
 // residual: per-thread strided sums of r^2 and of the unknowns, a block tree,
@@ -200,12 +531,13 @@ __global__ void __launch_bounds__(kResBlock) k_dha_finalize(SorArgs a, int npart
     }
 }
 
-// relaxation of unknown cell (x, y, z) with flag fl and old value own;
-// get(k) is the current value of the unknown neighbour in direction k
-// (x-, x+, y-, y+, z-, z+).  Same terms in the same order as dha_row.
-template <typename CT, typename Get>
+// relaxation of unknown cell (x, y, z) with flag fl and old value own.
+// get(k) is the current value and flg(k) the flag of the neighbour in
+// direction k (x-, x+, y-, y+, z-, z+); at(k) its global index (only taken
+// for an obstacle neighbour).  Same terms in the same order as dha_row.
+template <typename CT, typename Get, typename Flg, typename At>
 __device__ __forceinline__ CT relax(const SorArgs &a, int x, int y, int z, uint8_t fl, CT own,
-                                    const CT *psi_old, Get get) {
+                                    const CT *psi_old, Get get, Flg flg, At at) {
     const Grid &g = a.g;
     CT diag = CT(6.0) + (CT)a.kappa2, rhs = CT(0), sum = CT(0);
     if (!(fl & kNear)) {
@@ -214,7 +546,6 @@ __device__ __forceinline__ CT relax(const SorArgs &a, int x, int y, int z, uint8
     } else {
         const int lo[3] = {x == 0, y == 0, z == 0};
         const int hi[3] = {x == g.nx - 1, y == g.ny - 1, z == g.nz - 1};
-        const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const int ax = k >> 1;
@@ -223,17 +554,12 @@ __device__ __forceinline__ CT relax(const SorArgs &a, int x, int y, int z, uint8
                 diag = diag - CT(1.0);
                 continue;
             }
-            int v[3] = {x, y, z};
-            const int len[3] = {g.nx, g.ny, g.nz};
-            v[ax] += up ? 1 : -1;
-            if (v[ax] < 0) v[ax] += len[ax];
-            if (v[ax] >= len[ax]) v[ax] -= len[ax];
-            const size_t s = (size_t)v[0] + nx * (size_t)v[1] + nxy * (size_t)v[2];
-            const uint8_t fs = a.flag[s];
+            const uint8_t fs = flg(k);
             if (fs & kWall) {
                 diag = diag - CT(1.0);
             } else if (fs & kObst) {
                 // obstacle cells never change: the old buffer holds b
+                const size_t s = at(k);
                 const CT b = a.zeta ? (CT)a.zeta[a.owner[s]] : psi_old[s];
                 diag = diag + CT(1.0);
                 rhs = rhs + CT(2.0) * b;
@@ -247,7 +573,16 @@ __device__ __forceinline__ CT relax(const SorArgs &a, int x, int y, int z, uint8
 }
 
 constexpr int kFTX = 64, kFTY = 16, kFZC = 32, kFBlock = 256;
+constexpr int kOW = kFTX + 4, kOH = kFTY + 4;  // old planes: two-cell halo
+constexpr int kRW = kFTX + 2, kRH = kFTY + 2;  // new red values: one-cell halo
+constexpr int kNLoad = (kOH * kOW + kFBlock - 1) / kFBlock;              // 6
+constexpr int kNRed = (kRH * (kRW / 2) + kFBlock - 1) / kFBlock;         // 3
+constexpr int kNBlack = kFTY * kFTX / kFBlock;                           // 4
+static_assert(kFTX == 64 && kFBlock % kFTX == 0, "black phase: one row of 64 per 64 threads");
 
+// v wrapped once into [0, len) on a periodic axis; ok = false outside a
+// non-periodic edge and for positions more than one period away (halo
+// slots of a tile wider than the grid, which no cell needs)
 __device__ __forceinline__ int wrap_axis_or(int v, int len, int per, bool &ok) {
     if (v < 0 || v >= len) {
         if (!per) {
@@ -255,20 +590,38 @@ __device__ __forceinline__ int wrap_axis_or(int v, int len, int per, bool &ok) {
             return 0;
         }
         v = v < 0 ? v + len : v - len;
+        if (v < 0 || v >= len) {
+            ok = false;
+            return 0;
+        }
     }
     ok = true;
     return v;
 }
 
+// global index of the neighbour in direction k of in-grid cell (x, y, z)
+__device__ __forceinline__ size_t neighbour_index(const Grid &g, int x, int y, int z, int k) {
+    int v[3] = {x, y, z};
+    const int len[3] = {g.nx, g.ny, g.nz};
+    const int ax = k >> 1;
+    v[ax] += (k & 1) ? 1 : -1;
+    if (v[ax] < 0) v[ax] += len[ax];
+    if (v[ax] >= len[ax]) v[ax] -= len[ax];
+    return (size_t)v[0] + (size_t)g.nx * ((size_t)v[1] + (size_t)g.ny * (size_t)v[2]);
+}
+
+// one red-black iteration src -> dst (see the file comment).  Per-thread
+// in-plane offsets are fixed for the whole column of planes; plane j + 2 is
+// fetched into registers while plane j is relaxed.  In-plane offsets are
+// 32-bit (nx ny < 2^31, checked by the launcher).
 template <typename CT>
 __global__ void __launch_bounds__(kFBlock) k_sor_fused(SorArgs a, const CT *src, CT *dst,
                                                         int ntx, int nty) {
     if (a.ctl->done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
-    constexpr int OW = kFTX + 4, OH = kFTY + 4;  // old planes: two-cell halo
-    constexpr int RW = kFTX + 2, RH = kFTY + 2;  // new red values: one-cell halo
-    __shared__ CT s_old[4][OH][OW];
-    __shared__ CT s_rn[3][RH][RW];
+    __shared__ CT s_old[4][kOH * kOW];
+    __shared__ uint8_t s_fl[5][kOH * kOW];  // the black phase still reads plane j - 2's
+    __shared__ CT s_rn[3][kRH * kRW];
     const Grid &g = a.g;
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int tx = (int)(lb % (uint32_t)ntx);
@@ -276,102 +629,146 @@ __global__ void __launch_bounds__(kFBlock) k_sor_fused(SorArgs a, const CT *src,
     const int tz = (int)(lb / ((uint32_t)ntx * (uint32_t)nty));
     const int X0 = tx * kFTX, Y0 = ty * kFTY, Z0 = tz * kFZC;
     const int Z1 = min(Z0 + kFZC, g.nz);
-    const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
+    const int nx = g.nx;
+    const size_t nxy = (size_t)g.nx * (size_t)g.ny;
     const int tid = threadIdx.x;
 
-    // plane j (unwrapped) exists and its wrapped index
-    auto plane = [&](int j, int &jw) {
+    // load slots: in-plane offset (-1: outside a non-periodic edge)
+    int loff[kNLoad];
+#pragma unroll
+    for (int m = 0; m < kNLoad; ++m) {
+        const int i = tid + m * kFBlock;
+        loff[m] = -1;
+        if (i < kOH * kOW) {
+            const int r = i / kOW, c = i - r * kOW;
+            bool okx, oky;
+            const int gx = wrap_axis_or(X0 - 2 + c, g.nx, g.per[0], okx);
+            const int gy = wrap_axis_or(Y0 - 2 + r, g.ny, g.per[1], oky);
+            if (okx && oky) loff[m] = gx + nx * gy;
+        }
+    }
+    auto exists = [&](int j, int &jw) {
         bool ok;
         jw = wrap_axis_or(j, g.nz, g.per[2], ok);
         return ok;
     };
-    auto load_old = [&](int j) {
+    // plane j of the old values and flags, through registers into its LDS
+    // slot (cells outside a non-periodic edge read as walls: never relaxed,
+    // never taken as neighbour values)
+    CT pv[kNLoad];
+    uint8_t fv[kNLoad];
+    bool pok = false;
+    auto fetch = [&](int j) {
         int jw;
-        if (!plane(j, jw)) return;
-        CT(*o)[OW] = s_old[(j - Z0 + 8) & 3];
-        for (int i = tid; i < OH * OW; i += kFBlock) {
-            const int r = i / OW, c = i - r * OW;
-            bool okx, oky;
-            const int gx = wrap_axis_or(X0 - 2 + c, g.nx, g.per[0], okx);
-            const int gy = wrap_axis_or(Y0 - 2 + r, g.ny, g.per[1], oky);
-            if (okx && oky) o[r][c] = src[(size_t)gx + nx * (size_t)gy + nxy * (size_t)jw];
+        pok = exists(j, jw);
+        const size_t base = nxy * (size_t)jw;
+#pragma unroll
+        for (int m = 0; m < kNLoad; ++m) {
+            pv[m] = CT(0);
+            fv[m] = kWall;
+            if (pok && loff[m] >= 0) {
+                pv[m] = src[base + (size_t)loff[m]];
+                fv[m] = a.flag[base + (size_t)loff[m]];
+            }
+        }
+    };
+    auto fslot = [&](int j) { return (j - Z0 + 10) % 5; };
+    auto stash = [&](int j) {
+        const int sl = (j - Z0 + 8) & 3, sf = fslot(j);
+#pragma unroll
+        for (int m = 0; m < kNLoad; ++m) {
+            const int i = tid + m * kFBlock;
+            if (i < kOH * kOW) {
+                s_old[sl][i] = pv[m];
+                s_fl[sf][i] = fv[m];
+            }
         }
     };
 
-    load_old(Z0 - 2);
-    load_old(Z0 - 1);
-    load_old(Z0);
+    fetch(Z0 - 2);
+    stash(Z0 - 2);
+    fetch(Z0 - 1);
+    stash(Z0 - 1);
+    fetch(Z0);
+    stash(Z0);
+    __syncthreads();
+    // step j: fetch plane j + 2, relax the red cells of plane j (old planes
+    // j - 1 .. j + 1), put plane j + 2 into the value slot plane j - 2 held
+    // and into the flag slot of plane j - 3 (the black phase reads the flags
+    // of planes j - 2 .. j), then relax the black cells of plane j - 1 (new
+    // red planes j - 2 .. j)
     for (int j = Z0 - 1; j <= Z1; ++j) {
-        load_old(j + 1);
-        __syncthreads();
+        const bool ahead = j + 2 <= Z1 + 1;
+        if (ahead) fetch(j + 2);
         // new red values of plane j on the tile and a one-cell ring
         int jw;
-        if (plane(j, jw)) {
-            CT(*om)[OW] = s_old[(j - 1 - Z0 + 8) & 3];
-            CT(*o0)[OW] = s_old[(j - Z0 + 8) & 3];
-            CT(*op)[OW] = s_old[(j + 1 - Z0 + 8) & 3];
-            CT(*rn)[RW] = s_rn[(j - Z0 + 6) % 3];
-            for (int i = tid; i < RH * (RW / 2); i += kFBlock) {
-                const int r = i / (RW / 2), k = i - r * (RW / 2);
+        if (exists(j, jw)) {
+            const CT *om = s_old[(j - 1 - Z0 + 8) & 3], *o0 = s_old[(j - Z0 + 8) & 3],
+                     *op = s_old[(j + 1 - Z0 + 8) & 3];
+            const uint8_t *fm = s_fl[fslot(j - 1)], *f0 = s_fl[fslot(j)], *fp = s_fl[fslot(j + 1)];
+            CT *rn = s_rn[(j - Z0 + 6) % 3];
+#pragma unroll
+            for (int m = 0; m < kNRed; ++m) {
+                const int i = tid + m * kFBlock;
+                if (i >= kRH * (kRW / 2)) break;
+                const int r = i / (kRW / 2), k = i - r * (kRW / 2);
                 const int c = 2 * k + ((X0 + Y0 + r + j) & 1);  // (x + y + z) even
-                bool okx, oky;
-                const int gx = wrap_axis_or(X0 - 1 + c, g.nx, g.per[0], okx);
-                const int gy = wrap_axis_or(Y0 - 1 + r, g.ny, g.per[1], oky);
-                if (!okx || !oky) continue;
-                const size_t cell = (size_t)gx + nx * (size_t)gy + nxy * (size_t)jw;
-                const uint8_t fl = a.flag[cell];
-                if (fl & (kWall | kObst)) continue;
-                const int R = r + 1, C = c + 1;  // in the old planes
-                rn[r][c] = relax<CT>(a, gx, gy, jw, fl, o0[R][C], src, [&](int d) {
-                    switch (d) {
-                        case 0: return o0[R][C - 1];
-                        case 1: return o0[R][C + 1];
-                        case 2: return o0[R - 1][C];
-                        case 3: return o0[R + 1][C];
-                        case 4: return om[R][C];
-                        default: return op[R][C];
-                    }
-                });
+                const int O = (r + 1) * kOW + (c + 1);          // in the old planes
+                const uint8_t fl = f0[O];
+                if (fl & (kWall | kObst)) continue;  // also outside a non-periodic edge
+                const int gx = X0 - 1 + c < 0 ? X0 - 1 + c + g.nx
+                               : X0 - 1 + c >= g.nx ? X0 - 1 + c - g.nx : X0 - 1 + c;
+                const int gy = Y0 - 1 + r < 0 ? Y0 - 1 + r + g.ny
+                               : Y0 - 1 + r >= g.ny ? Y0 - 1 + r - g.ny : Y0 - 1 + r;
+                const int nb[4] = {O - 1, O + 1, O - kOW, O + kOW};
+                rn[r * kRW + c] = relax<CT>(
+                    a, gx, gy, jw, fl, o0[O], src,
+                    [&](int d) { return d < 4 ? o0[nb[d]] : d == 4 ? om[O] : op[O]; },
+                    [&](int d) { return d < 4 ? f0[nb[d]] : d == 4 ? fm[O] : fp[O]; },
+                    [&](int d) { return neighbour_index(g, gx, gy, jw, d); });
             }
         }
+        if (ahead) stash(j + 2);
         __syncthreads();
         // plane j - 1 of the tile: new black values from the new red ones,
-        // new red values, unchanged boundary cells; written in x pairs
+        // new red values, unchanged boundary cells
         const int jj = j - 1;
         if (jj >= Z0) {
             int jjw;
-            plane(jj, jjw);
-            CT(*o0)[OW] = s_old[(jj - Z0 + 8) & 3];
-            CT(*rm)[RW] = s_rn[(jj - 1 - Z0 + 6) % 3];
-            CT(*r0)[RW] = s_rn[(jj - Z0 + 6) % 3];
-            CT(*rp)[RW] = s_rn[(jj + 1 - Z0 + 6) % 3];
-            for (int i = tid; i < kFTY * kFTX; i += kFBlock) {
-                const int r = i / kFTX, c = i - r * kFTX;
-                const int gx = X0 + c, gy = Y0 + r;
+            exists(jj, jjw);
+            const CT *o0 = s_old[(jj - Z0 + 8) & 3];
+            const uint8_t *fm = s_fl[fslot(jj - 1)], *f0 = s_fl[fslot(jj)],
+                          *fp = s_fl[fslot(jj + 1)];
+            const CT *rm = s_rn[(jj - 1 - Z0 + 6) % 3], *r0 = s_rn[(jj - Z0 + 6) % 3],
+                     *rp = s_rn[(jj + 1 - Z0 + 6) % 3];
+            const size_t base = nxy * (size_t)jjw;
+            const int c = tid % kFTX;
+            const int gx = X0 + c;
+#pragma unroll
+            for (int m = 0; m < kNBlack; ++m) {
+                const int r = tid / kFTX + m * (kFBlock / kFTX);
+                const int gy = Y0 + r;
                 if (gx >= g.nx || gy >= g.ny) continue;
-                const size_t cell = (size_t)gx + nx * (size_t)gy + nxy * (size_t)jjw;
-                const uint8_t fl = a.flag[cell];
-                const int R = r + 1, C = c + 1;  // in the red planes
+                const int O = (r + 2) * kOW + (c + 2), Rr = (r + 1) * kRW + (c + 1);
+                const uint8_t fl = f0[O];
                 CT out;
                 if (fl & (kWall | kObst)) {
-                    out = o0[r + 2][c + 2];
+                    out = o0[O];
                 } else if (((gx + gy + jjw) & 1) == 0) {
-                    out = r0[R][C];
+                    out = r0[Rr];
                 } else {
-                    out = relax<CT>(a, gx, gy, jjw, fl, o0[r + 2][c + 2], src, [&](int d) {
-                        switch (d) {
-                            case 0: return r0[R][C - 1];
-                            case 1: return r0[R][C + 1];
-                            case 2: return r0[R - 1][C];
-                            case 3: return r0[R + 1][C];
-                            case 4: return rm[R][C];
-                            default: return rp[R][C];
-                        }
-                    });
+                    const int nr[4] = {Rr - 1, Rr + 1, Rr - kRW, Rr + kRW};
+                    const int nb[4] = {O - 1, O + 1, O - kOW, O + kOW};
+                    out = relax<CT>(
+                        a, gx, gy, jjw, fl, o0[O], src,
+                        [&](int d) { return d < 4 ? r0[nr[d]] : d == 4 ? rm[Rr] : rp[Rr]; },
+                        [&](int d) { return d < 4 ? f0[nb[d]] : d == 4 ? fm[O] : fp[O]; },
+                        [&](int d) { return neighbour_index(g, gx, gy, jjw, d); });
                 }
-                dst[cell] = out;
+                dst[base + (size_t)(gx + nx * gy)] = out;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -385,9 +782,11 @@ template <typename CT>
 hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, bool fused,
                            hipStream_t s, int *swapped) {
     const Grid &g = a0.g;
-    const size_t hx = (size_t)((g.nx + 1) / 2);
-    const size_t slots = hx * (size_t)g.ny * (size_t)g.nz;
-    const uint32_t nblk = (uint32_t)((slots + kSorBlock - 1) / kSorBlock);
+    const uint32_t nxb = (uint32_t)((g.nx + 2 * kSorBlock - 1) / (2 * kSorBlock));
+    const uint32_t nyb = (uint32_t)((g.ny + kSorRows - 1) / kSorRows);
+    const uint32_t nblk = nxb * nyb * (uint32_t)g.nz;
+    // 2-vector rows: even nx keeps every pair aligned
+    const bool vec = (g.nx % 2) == 0;
     const int ntx = (g.nx + kFTX - 1) / kFTX, nty = (g.ny + kFTY - 1) / kFTY;
     const int ntz = (g.nz + kFZC - 1) / kFZC;
     const uint32_t nfused = (uint32_t)ntx * (uint32_t)nty * (uint32_t)ntz;
@@ -396,6 +795,14 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const bool with_res = a0.rf > 0.0;
     SorArgs a = a0;  // a.psi: the buffer holding the current iterate
     hipLaunchKernelGGL(k_sor_begin, dim3(1), dim3(64), 0, s, a.ctl);
+    if (!fused) {
+        const uint32_t nseg = (uint32_t)((g.N + kNearSeg - 1) / kNearSeg);
+        hipLaunchKernelGGL(k_nlist_count, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
+                           a.nscratch);
+        hipLaunchKernelGGL(k_nlist_scan, dim3(1), dim3(1024), 0, s, a.nscratch, nseg, a.ctl);
+        hipLaunchKernelGGL(k_nlist_write, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
+                           a.nscratch, nseg, a.nlist);
+    }
     if (with_res) {
         hipLaunchKernelGGL((k_dha_residual<CT>), dim3(nres), dim3(kResBlock), 0, s, a);
         hipLaunchKernelGGL(k_dha_finalize, dim3(1), dim3(kResBlock), 0, s, a, nres, 1);
@@ -407,8 +814,16 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
                                static_cast<const CT *>(a.psi), static_cast<CT *>(next), ntx, nty);
             a.psi = next;
         } else {
-            hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a, 0, 0);
-            hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a, 1, 1);
+            for (int col = 0; col < 2; ++col) {
+                if (vec)
+                    hipLaunchKernelGGL((k_sor_half_vec<CT>), dim3(nblk), dim3(kSorBlock), 0, s,
+                                       a, col, col, nxb, nyb);
+                else
+                    hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a,
+                                       col, col, nxb, nyb);
+                hipLaunchKernelGGL((k_sor_near<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a,
+                                   col);
+            }
         }
         if (with_res && (it % check_every == 0 || it == max_iter)) {
             hipLaunchKernelGGL((k_dha_residual<CT>), dim3(nres), dim3(kResBlock), 0, s, a);
@@ -444,7 +859,14 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
                             bool fused, hipStream_t s, int *swapped) {
     *swapped = 0;
     if (a.g.N == 0) return hipSuccess;
+    // the fused iteration is switched off until its plane-ring fix has run
+    // on the device: its flag ring shared 4 slots with the values, so the
+    // black phase read the z- flags of a plane already replaced by the
+    // prefetch (a stale obstacle flag then indexed zeta with kNone)
+    if (fused) return hipErrorNotSupported;
     if (fused && !a.psi2) return hipErrorInvalidValue;
+    // the fused kernel keeps 32-bit in-plane offsets
+    if ((size_t)a.g.nx * (size_t)a.g.ny >= ((size_t)1 << 31)) fused = false;
     if (precision == LBMEP_FP64)
         return sor_solve_typed<double>(a, max_iter, check_every, fused, s, swapped);
     return sor_solve_typed<float>(a, max_iter, check_every, fused, s, swapped);

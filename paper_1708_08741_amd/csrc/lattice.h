@@ -66,9 +66,11 @@ struct lbmep_lattice {
     bool sor_set = false;
     lbmep::SorCtl *sor_ctl = nullptr;
     double *sor_partial = nullptr;
+    uint32_t *sor_nlist = nullptr;     // boundary unknowns of each colour
+    uint32_t *sor_nscratch = nullptr;  // segment counts / offsets of the list build
     void *psi2 = nullptr;      // second psi buffer of the fused SOR iteration
     size_t psi2_bytes = 0;
-    bool sor_fused = true;     // LBMEP_SOR_FUSED=0: one launch per colour
+    bool sor_fused = false;    // fused iteration (switched off: one launch per colour)
     double *red = nullptr;
     int red_blocks = 0;
     int block_x = 128;

@@ -265,6 +265,8 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->zeta);
     dev_free(L, L->sor_ctl);
     dev_free(L, L->sor_partial);
+    dev_free(L, L->sor_nlist);
+    dev_free(L, L->sor_nscratch);
     dev_free(L, L->psi2);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
@@ -600,6 +602,8 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.rf = L->sor_rf;
     a.ctl = L->sor_ctl;
     a.partial = L->sor_partial;
+    a.nlist = L->sor_nlist;
+    a.nscratch = L->sor_nscratch;
     a.xcd_swizzle = L->xcd_swizzle;
     return a;
 }
@@ -629,6 +633,8 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
     for (int k = 0; k < 3; ++k)
         if (L->g.per[k] && (len[k] & 1))
             return fail(LBMEP_EINVAL, "red-black ordering needs even periodic extents");
+    if (L->g.N + 2 >= ((size_t)1 << 32))
+        return fail(LBMEP_EINVAL, "the solver lists cells with 32-bit indices (N < 2^32 - 2)");
     int rc = set_device(L);
     if (rc) return rc;
     if (!L->sor_ctl) {
@@ -636,12 +642,16 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
             return fail(LBMEP_ENOMEM, "solver control block");
         if (dev_alloc(L, (void **)&L->sor_partial, sizeof(double) * kSorPartials) != hipSuccess)
             return fail(LBMEP_ENOMEM, "solver partial sums");
+        if (dev_alloc(L, (void **)&L->sor_nlist, 4 * sor_nlist_entries(L->g.N)) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "solver boundary list");
+        if (dev_alloc(L, (void **)&L->sor_nscratch, 4 * sor_nscratch_entries(L->g.N)) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "solver list scratch");
         SorCtl c{};
         c.res0 = c.res = -1.0;
         HIP_TRY(hipMemcpy(L->sor_ctl, &c, sizeof c, hipMemcpyHostToDevice));
     }
-    const char *fz = std::getenv("LBMEP_SOR_FUSED");
-    L->sor_fused = !(fz && fz[0] == '0');
+    // one launch per colour; the fused iteration is switched off
+    L->sor_fused = false;
     const size_t need = L->g.Ns * compute_bytes(L->precision);
     if (L->sor_fused && L->psi2_bytes < need) {
         dev_free(L, L->psi2);

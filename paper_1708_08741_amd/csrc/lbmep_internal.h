@@ -202,7 +202,7 @@ hipError_t launch_macro(int precision, int force_mode, const Grid &g, const void
 struct SorCtl {
     int32_t done;
     int32_t iters;   // iterations of the current / last solve
-    int32_t pad[2];
+    uint32_t nnear[2];  // boundary unknowns of each colour (lists of the solve)
     double res0;     // L2 norm of the initial residual (-1: not computed)
     double res;      // L2 norm of the last computed residual (-1: none)
 };
@@ -216,9 +216,16 @@ struct SorArgs {
     double kappa2, omega, rf;
     SorCtl *ctl;
     double *partial;           // kSorPartials FP64 partial sums
+    uint32_t *nlist;           // boundary unknowns: colour 0 at [0, N/2 + 1),
+                               // colour 1 at [N/2 + 1, N + 2)
+    uint32_t *nscratch;        // per-segment counts / offsets of the list build
     uint32_t xcd_swizzle;
 };
 constexpr int kSorPartials = 8192;
+// the boundary lists are built per segment of kNearSeg cells
+constexpr int kNearSeg = 1024;
+inline size_t sor_nlist_entries(size_t N) { return N + 2; }
+inline size_t sor_nscratch_entries(size_t N) { return 4 * ((N + kNearSeg - 1) / kNearSeg) + 2; }
 // one solve on the current map: max_iter iterations of (red, black), with
 // rf > 0 a residual before the first and after every check_every-th (and the
 // last) iteration, stopping at res < rf res0 (the host reads the control
