@@ -52,6 +52,23 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+SOR_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "k_potential.hip")
+
+
+def sor_traffic():
+    """HBM bytes per FP32 interior half-sweep from the committed counter
+    summary, if it was taken on the current SOR source; else None."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    sha = hashlib.sha256(open(SOR_SRC, "rb").read()).hexdigest()[:16]
+    if d.get("sor_kernel_sha") != sha:
+        return None
+    e = d.get("other_kernels", {}).get("k_sor_half_vec<float>")
+    return e.get("hbm_bytes_per_launch") if e else None
+
+
 def traffic_for(precision):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current sweep source; else None."""
@@ -452,6 +469,9 @@ def main():
             "sor_GBps": round(sor_bytes / (it_ms / 1e3) / 1e9, 1),
             "sor_roofline_frac": round(sor_bytes / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "sor_bytes_per_cell_iteration": 2 * es + 1,
+            "sor_kernel": "k_sor_half_vec (interior, one colour) + k_sor_near (listed "
+                          "boundary cells), two of each per iteration",
+            "sor_traffic_per_half_sweep": sor_traffic() if es == 4 else None,
             "steps": args.coupled_steps,
         }
         log(f"[bench] coupled step: {coupled}")

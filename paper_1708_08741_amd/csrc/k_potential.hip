@@ -326,10 +326,12 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
 // (the map is fixed during a solve): counts per segment of kNearSeg cells,
 // an exclusive scan over the segments, then each segment writes its cells
 // in increasing order
-__device__ __forceinline__ uint32_t cell_colour(const Grid &g, size_t c) {
-    const size_t x = c % (size_t)g.nx, yz = c / (size_t)g.nx;
-    const size_t y = yz % (size_t)g.ny, z = yz / (size_t)g.ny;
-    return (uint32_t)((x + y + z) & 1);
+// (the solver requires N < 2^32 - 2, so cell indices fit 32 bits)
+__device__ __forceinline__ uint32_t cell_colour(const Grid &g, uint32_t c) {
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+    const uint32_t yz = c / nx, x = c - yz * nx;
+    const uint32_t z = yz / ny, y = yz - z * ny;
+    return (x + y + z) & 1u;
 }
 
 constexpr int kNearBlock = 256;
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_count(Grid g, const uint8_
     uint32_t n[2] = {0, 0};
     for (int k = 0; k < kNearSeg / kNearBlock; ++k) {
         const size_t c = c0 + (size_t)k * kNearBlock + threadIdx.x;
-        if (c < g.N && near_unknown(flag[c])) n[cell_colour(g, c)] += 1;
+        if (c < g.N && near_unknown(flag[c])) n[cell_colour(g, (uint32_t)c)] += 1;
     }
     __shared__ uint32_t s0[kNearBlock], s1[kNearBlock];
     s0[threadIdx.x] = n[0];
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_write(Grid g, const uint8_
     for (int k = 0; k < kNearSeg / kNearBlock; ++k) {
         const size_t c = c0 + (size_t)k * kNearBlock + threadIdx.x;
         const bool nu = c < g.N && near_unknown(flag[c]);
-        const uint32_t col = nu ? cell_colour(g, c) : 0;
+        const uint32_t col = nu ? cell_colour(g, (uint32_t)c) : 0;
         const uint64_t b0 = __ballot(nu && col == 0), b1 = __ballot(nu && col == 1);
         if (lane == 0) {
             w0[wv] = (uint32_t)__popcll(b0);
@@ -451,14 +453,15 @@ __global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) 
     CT *psi = static_cast<CT *>(a.psi);
     const CT om = (CT)a.omega;
     for (uint32_t i = blockIdx.x * kNearBlock + threadIdx.x; i < n; i += kNearGrid * kNearBlock) {
-        const size_t c = list[i];
-        const int x = (int)(c % (size_t)g.nx);
-        const size_t yz = c / (size_t)g.nx;
-        const int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
+        const uint32_t c = list[i];
+        const uint32_t yz = c / (uint32_t)g.nx;
+        const int x = (int)(c - yz * (uint32_t)g.nx);
+        const int z = (int)(yz / (uint32_t)g.ny), y = (int)(yz - (uint32_t)z * (uint32_t)g.ny);
+        // every listed cell is a NEAR unknown: its own flag is not needed
+        const CT own = psi[c];
         CT diag, rhs, sum;
-        dha_row<CT>(g, x, y, z, a.flag[c], psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs,
-                    sum);
-        psi[c] = (CT(1.0) - om) * psi[c] + om * ((rhs + sum) / diag);
+        dha_row<CT>(g, x, y, z, kNear, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs, sum);
+        psi[c] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
     }
 }
 

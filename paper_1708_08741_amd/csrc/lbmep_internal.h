@@ -223,7 +223,7 @@ struct SorArgs {
 };
 constexpr int kSorPartials = 8192;
 // the boundary lists are built per segment of kNearSeg cells
-constexpr int kNearSeg = 1024;
+constexpr int kNearSeg = 8192;
 inline size_t sor_nlist_entries(size_t N) { return N + 2; }
 inline size_t sor_nscratch_entries(size_t N) { return 4 * ((N + kNearSeg - 1) / kNearSeg) + 2; }
 // one solve on the current map: max_iter iterations of (red, black), with
