@@ -26,6 +26,10 @@
  *     finite-volume Debye-Hueckel equation solved by red-black SOR with the
  *     particles' surface potentials as Dirichlet values, optional, once per
  *     time step before the collision (Alg. "Electrophoresis Algorithm").
+ *   Alg. "Electrophoresis Algorithm" (last block) with Sec. "Computing
+ *     Electrostatic Forces on Fluid and Particles": optional Newton-Euler
+ *     dynamics of the spheres under the hydrodynamic force and torque of the
+ *     step plus the force q E of the applied field on their charge.
  *   Sec. 3.2 (momentum exchange): cells whose centre lies in a particle are
  *     obstacle cells; velocity bounce-back (Eq. LBMMovWall); hydrodynamic
  *     force (Eq. LBMhydrodynForce) and torque; equilibrium refill of
@@ -111,6 +115,9 @@ struct orc_lattice {
     int potential;
     double *psi, *zeta, k_eps, Eext[3];
     /* red-black SOR for the Debye-Hueckel equation (optional) */
+    /* Newton-Euler dynamics of the particles (optional) */
+    int dynamic;
+    double rho_p, Edyn[3], *q;
     int sor_iters, sor_check;
     double kappa2, sor_omega, sor_rf;
     int last_iters;
@@ -306,6 +313,9 @@ static void potential_force(orc_lattice *L);
 static void free_particles(orc_lattice *L) {
     free(L->zeta);
     L->zeta = NULL;
+    free(L->q);
+    L->q = NULL;
+    L->dynamic = 0;
     free(L->X0); free(L->R); free(L->U); free(L->W); free(L->Xn); free(L->Xold);
     free(L->F); free(L->M);
     L->X0 = L->R = L->U = L->W = L->Xn = L->Xold = L->F = L->M = NULL;
@@ -667,6 +677,69 @@ static void kahan_add(double *sum, double *comp, double x) {
 /* -------------------------------------------------------------------------
  * One time step n -> n+1.
  * ---------------------------------------------------------------------- */
+/* -------------------------------------------------------------------------
+ * Particle dynamics (Alg. "Electrophoresis Algorithm": after the LBM sweep
+ * the hydrodynamic force and torque of the momentum exchange, together with
+ * the electrostatic force F_C = q E_ext on the particle's charge (Sec.
+ * "Computing Electrostatic Forces on Fluid and Particles"), move the
+ * particles).  Newton-Euler for homogeneous spheres without collisions,
+ * one explicit update per lattice step (dt = 1), velocities first:
+ *     U <- U + (F_h + q E) / m,   W <- W + M_h / I,   X <- X + U (new U),
+ * m = rho_p (4/3) pi R^3, I = (2/5) m R^2.  The velocities of a level are
+ * those of its bounce-back, exchange and refill.
+ * ---------------------------------------------------------------------- */
+static const double PI_D = 3.14159265358979323846;
+
+static void particle_dynamics(orc_lattice *L) {
+    int p, a;
+    for (p = 0; p < L->np; ++p) {
+        const double R = L->R[p];
+        const double m = L->rho_p * (4.0 / 3.0) * PI_D * R * R * R;
+        const double I = 0.4 * m * R * R;
+        const double qp = L->q ? L->q[p] : 0.0;
+        for (a = 0; a < 3; ++a) {
+            L->U[3 * p + a] = L->U[3 * p + a] + (L->F[3 * p + a] + qp * L->Edyn[a]) / m;
+            L->W[3 * p + a] = L->W[3 * p + a] + L->M[3 * p + a] / I;
+        }
+    }
+}
+
+/* the next position of particle p from its current one and its new
+ * velocity, wrapped into [0, L) on periodic axes */
+static void dynamic_position(const orc_lattice *L, int p, double out[3]) {
+    int a;
+    const int len[3] = {L->nx, L->ny, L->nz};
+    for (a = 0; a < 3; ++a) {
+        double x = L->Xold[3 * p + a] + L->U[3 * p + a];
+        if (L->per[a]) {
+            x = x - (double)len[a] * floor(x / (double)len[a]);
+            if (x >= (double)len[a]) x -= (double)len[a];
+        }
+        out[a] = x;
+    }
+}
+
+int orc_set_dynamics(orc_lattice *L, double rho_p, const double *q, const double E[3]) {
+    int a;
+    if (!L->moving || !(rho_p > 0.0)) return -1;
+    free(L->q);
+    L->q = NULL;
+    if (q && L->np > 0) {
+        L->q = (double *)malloc(sizeof(double) * (size_t)L->np);
+        memcpy(L->q, q, sizeof(double) * (size_t)L->np);
+    }
+    L->rho_p = rho_p;
+    for (a = 0; a < 3; ++a) L->Edyn[a] = E[a];
+    L->dynamic = 1;
+    return 0;
+}
+
+void orc_get_particles(const orc_lattice *L, double *X, double *U, double *W) {
+    memcpy(X, L->Xn, sizeof(double) * 3 * (size_t)L->np);
+    memcpy(U, L->U, sizeof(double) * 3 * (size_t)L->np);
+    memcpy(W, L->W, sizeof(double) * 3 * (size_t)L->np);
+}
+
 static void one_step(orc_lattice *L) {
     const long N = L->N;
     const int nx = L->nx, ny = L->ny, nz = L->nz, np = L->np;
@@ -772,6 +845,10 @@ static void one_step(orc_lattice *L) {
     }
     free(Sz);
 
+    /* Newton-Euler update of the particles with this step's force and
+     * torque (see particle_dynamics) */
+    if (L->dynamic) particle_dynamics(L);
+
     /* bookkeeping: total body force on the fluid cells of this step */
     {
         long c;
@@ -797,7 +874,10 @@ static void one_step(orc_lattice *L) {
         long c;
         int32_t *t;
         memcpy(L->Xold, L->Xn, sizeof(double) * 3 * np);
-        for (p = 0; p < np; ++p) particle_position(L, p, L->step, L->Xn + 3 * p);
+        for (p = 0; p < np; ++p) {
+            if (L->dynamic) dynamic_position(L, p, L->Xn + 3 * p);
+            else particle_position(L, p, L->step, L->Xn + 3 * p);
+        }
         t = L->owner_old;
         L->owner_old = L->owner;
         L->owner = t;

@@ -52,6 +52,11 @@ int orc_solve_potential(orc_lattice *L, int *iters, double *res0, double *res);
 void orc_get_solver_stats(const orc_lattice *L, int *iters, double *res0, double *res);
 double orc_dha_residual(const orc_lattice *L);
 void orc_get_potential(const orc_lattice *L, double *psi);
+/* Newton-Euler dynamics of the (moving) particles: density rho_p, charges
+ * q[np] (NULL: 0), applied field E for q E.  Returns -1 unless the particle
+ * table was set with moving = 1 and rho_p > 0.  Dropped by set_particles. */
+int orc_set_dynamics(orc_lattice *L, double rho_p, const double *q, const double E[3]);
+void orc_get_particles(const orc_lattice *L, double *X, double *U, double *W);
 void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]);
 void orc_set_pdfs(orc_lattice *L, const double *f);       /* 19*N */
 void orc_get_pdfs(const orc_lattice *L, double *f);

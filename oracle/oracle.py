@@ -67,6 +67,8 @@ def lib():
         L.orc_dha_residual.argtypes = [P]
         L.orc_dha_residual.restype = ctypes.c_double
         L.orc_get_potential.argtypes = [P, dp]
+        L.orc_set_dynamics.argtypes = [P, ctypes.c_double, ctypes.c_void_p, dp]
+        L.orc_get_particles.argtypes = [P, dp, dp, dp]
         L.orc_init_equilibrium.argtypes = [P, ctypes.c_double, dp]
         L.orc_set_pdfs.argtypes = [P, dp]
         L.orc_get_pdfs.argtypes = [P, dp]
@@ -182,6 +184,26 @@ class Oracle:
         out = np.zeros((nz, ny, nx))
         lib().orc_get_potential(self._h, _dp(out))
         return out
+
+    def set_dynamics(self, rho_p, q=None, E=(0.0, 0.0, 0.0)):
+        """Newton-Euler dynamics of the moving particles: density rho_p,
+        charges q (None: 0), applied field E for the forces q E."""
+        qp = None
+        if q is not None:
+            qa = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+            self._q_keep = qa
+            qp = qa.ctypes.data
+        Ea = np.ascontiguousarray(E, dtype=np.float64)
+        if lib().orc_set_dynamics(self._h, float(rho_p), qp, _dp(Ea)):
+            raise ValueError("oracle: dynamics need moving particles and rho_p > 0")
+
+    def particles(self):
+        """Current positions, velocities and angular velocities (np, 3)."""
+        X = np.zeros((self.np, 3))
+        U = np.zeros((self.np, 3))
+        Wv = np.zeros((self.np, 3))
+        lib().orc_get_particles(self._h, _dp(X), _dp(U), _dp(Wv))
+        return X, U, Wv
 
     def force(self):
         nx, ny, nz = self.shape
