@@ -123,8 +123,9 @@ def run_gpu(wl, precision, steps, warmup, potential=None):
 def run_coupled(wl, precision, steps, warmup, sor_iters, kappa=0.5):
     """The electrophoresis step (Alg. "Electrophoresis Algorithm"): a fixed
     number of red-black SOR iterations of the Debye-Hueckel equation on the
-    current map, then the stream-collide step with the force from the
-    potential.  The spheres' Debye-Hueckel fields (surface potentials in
+    current map, the stream-collide step with the force from the potential,
+    the momentum exchange, and the Newton-Euler update of the charged
+    particles.  The spheres' Debye-Hueckel fields (surface potentials in
     [-0.05, 0.05]) are the initial potential.  Also times one standalone
     solve of sor_iters iterations (HIP events on the lattice's stream)."""
     import torch
@@ -140,6 +141,10 @@ def run_coupled(wl, precision, steps, warmup, sor_iters, kappa=0.5):
                           1e-3, wl.E, zeta)
     del psi
     L.set_potential_solver(kappa * kappa, 1.7, sor_iters, 0.0)
+    # the particles move under their forces: density ratio of the paper's
+    # particles (1195 / 1000), charges q ~ U[-0.1, 0.1] in the applied field
+    qp = np.random.default_rng(5).uniform(-0.1, 0.1, len(wl.R))
+    L.set_dynamics(1.195, qp, wl.E)
     L.step(warmup)
     L.sync()
     e0 = torch.cuda.Event(enable_timing=True)

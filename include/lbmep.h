@@ -182,6 +182,27 @@ int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]);
  * no potential set), ENOMEM, EDEVICE. */
 int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device);
 
+/* Let the particles move under their forces instead of the prescribed
+ * kinematics (Alg. "Electrophoresis Algorithm", last block; the force on a
+ * particle's charge q E of Sec. "Computing Electrostatic Forces on Fluid and
+ * Particles").  After the momentum exchange of every step, each sphere
+ * (density rho_p, fluid density 1) is advanced by one explicit Newton-Euler
+ * step without collisions: U += (F_h + q E)/m, Omega += M_h/I, X += U (the
+ * new U), m = rho_p 4/3 pi R^3, I = 2/5 m R^2; F_h, M_h are the step's
+ * hydrodynamic force and torque.  The new velocities act at the next step
+ * (bounce-back, exchange, refill).  q: L's particle count of charges (host;
+ * NULL: uncharged); E: the applied field for q E.  Needs move_particles = 1;
+ * dropped by the next lbmep_set_particles.  A particle must stay below one
+ * cell per step (lbmep_get_particles reports it).  Errors: EINVAL (null E,
+ * not moving, rho_p <= 0, non-finite values), ENOMEM. */
+int lbmep_set_dynamics(lbmep_lattice *L, double rho_p, const double *q, const double E[3]);
+
+/* Current positions, velocities and angular velocities of the particles
+ * (host arrays of 3 n doubles each; synchronises).  Errors: EINVAL (null
+ * with n > 0; a velocity component reached one cell per step under
+ * dynamics, i.e. the mapping no longer follows the body), EDEVICE. */
+int lbmep_get_particles(lbmep_lattice *L, double *X, double *U, double *W);
+
 /* Set every population to the incompressible equilibrium f^eq(rho, u)
  * (Eq. fequ_Incompr_SRT).  Errors: EINVAL (non-finite). */
 int lbmep_init_equilibrium(lbmep_lattice *L, double rho, const double u[3]);

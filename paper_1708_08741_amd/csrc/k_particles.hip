@@ -125,8 +125,9 @@ __global__ void __launch_bounds__(kBoxThreads)
 __device__ __forceinline__ double position(const ParticleArgs &pa, int p, int k, int64_t level) {
     const int len[3] = {pa.g.nx, pa.g.ny, pa.g.nz};
     double x = pa.X0[3 * p + k];
-    // prescribed kinematics X(n) = X(0) + n U, evaluated in this form
-    if (pa.moving) x = pa.X0[3 * p + k] + (double)level * pa.U[3 * p + k];
+    // prescribed kinematics X(n) = X(0) + n U, evaluated in this form; with
+    // dynamics X0 already holds the level's position
+    if (pa.moving && !pa.dynamic) x = pa.X0[3 * p + k] + (double)level * pa.U[3 * p + k];
     if (pa.g.per[k]) {
         x = x - (double)len[k] * floor(x / (double)len[k]);
         if (x >= (double)len[k]) x -= (double)len[k];
@@ -560,7 +561,52 @@ __global__ void k_finalize_ft(int np, const double *acc, const double *X, double
     out[6 * (size_t)p + 5] = t[5] + (t[11] - (Xp[0] * t[7] - Xp[1] * t[6])) / 18.0;
 }
 
+// Newton-Euler update of particle p (Alg. "Electrophoresis Algorithm": the
+// hydrodynamic force and torque of the step and the force q E of the
+// applied field move the particle), one explicit step, velocities first:
+//     U += (F_h + q E) / m,  W += M_h / I,  X(n+1) = X(n) + U,
+// m = rho_p 4/3 pi R^3, I = 2/5 m R^2; F_h, M_h assembled as k_finalize_ft
+// does, in the same order
+__global__ void k_dynamics(DynArgs d) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d.np) return;
+    const double *t = d.acc + 12 * (size_t)p;
+    const double *Xp = d.X + 3 * (size_t)p;
+    double F[3], M[3];
+    F[0] = t[0] + t[6] / 18.0;
+    F[1] = t[1] + t[7] / 18.0;
+    F[2] = t[2] + t[8] / 18.0;
+    M[0] = t[3] + (t[9] - (Xp[1] * t[8] - Xp[2] * t[7])) / 18.0;
+    M[1] = t[4] + (t[10] - (Xp[2] * t[6] - Xp[0] * t[8])) / 18.0;
+    M[2] = t[5] + (t[11] - (Xp[0] * t[7] - Xp[1] * t[6])) / 18.0;
+    const double R = d.R[p];
+    const double m = d.rho_p * (4.0 / 3.0) * 3.14159265358979323846 * R * R * R;
+    const double I = 0.4 * m * R * R;
+    const double qp = d.q ? d.q[p] : 0.0;
+    const int len[3] = {d.g.nx, d.g.ny, d.g.nz};
+    bool fast = false;
+    for (int a = 0; a < 3; ++a) {
+        const double u = d.U[3 * p + a] + (F[a] + qp * d.E[a]) / m;
+        d.U[3 * p + a] = u;
+        d.W[3 * p + a] = d.W[3 * p + a] + M[a] / I;
+        fast = fast || !(fabs(u) < 1.0);
+        double x = Xp[a] + u;
+        if (d.g.per[a]) {
+            x = x - (double)len[a] * floor(x / (double)len[a]);
+            if (x >= (double)len[a]) x -= (double)len[a];
+        }
+        d.X0[3 * p + a] = x;
+    }
+    if (fast) *d.too_fast = 1;
+}
+
 }  // namespace
+
+hipError_t launch_dynamics(const DynArgs &d, hipStream_t s) {
+    if (d.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dynamics, dim3((d.np + 127) / 128), dim3(128), 0, s, d);
+    return hipGetLastError();
+}
 
 int wall_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kListChunk); }
 int wall_list_tiles(const Grid &g) { return (wall_list_blocks(g) + kTile - 1) / kTile; }

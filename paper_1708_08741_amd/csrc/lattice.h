@@ -56,6 +56,12 @@ struct lbmep_lattice {
     void *force = nullptr;
     size_t force_bytes = 0;
     double E[3] = {0, 0, 0};
+    // Newton-Euler dynamics of the particles (X0, U, W become state)
+    bool dynamic = false;
+    double rho_p = 0, Edyn[3] = {0, 0, 0};
+    double *q = nullptr;           // device charges (np), or null
+    std::vector<double> hq;        // host copy
+    int32_t *too_fast = nullptr;   // device flag: a velocity reached 1
     double keps = 0;           // potential force: kappa^2 eps_e
     double *zeta = nullptr;    // potential force: per-particle boundary value (device)
     std::vector<double> hzeta; // host copy (np values, empty: the field's value)

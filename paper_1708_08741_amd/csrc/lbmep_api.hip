@@ -73,6 +73,7 @@ ParticleArgs particle_args(const lbmep_lattice *L) {
     pa.g = L->g;
     pa.np = L->np;
     pa.moving = L->cfg.move_particles;
+    pa.dynamic = L->dynamic ? 1 : 0;
     pa.X0 = L->X0;
     pa.R = L->R;
     pa.U = L->U;
@@ -263,6 +264,8 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->force);
     dev_free(L, L->red);
     dev_free(L, L->zeta);
+    dev_free(L, L->q);
+    dev_free(L, L->too_fast);
     dev_free(L, L->sor_ctl);
     dev_free(L, L->sor_partial);
     dev_free(L, L->sor_nlist);
@@ -466,11 +469,15 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
         L->plist_entries = (size_t)n * pcap;
     }
     L->pcap = pcap;
-    // boundary values of the potential belong to the particle table they
-    // were given with
+    // boundary values of the potential and the dynamics belong to the
+    // particle table they were given with
     dev_free(L, L->zeta);
     L->zeta = nullptr;
     L->hzeta.clear();
+    dev_free(L, L->q);
+    L->q = nullptr;
+    L->hq.clear();
+    L->dynamic = false;
     L->np = n;
     L->hX0.assign(X, X + 3 * (size_t)n);
     L->hR.assign(R, R + n);
@@ -723,6 +730,57 @@ int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device) {
     return LBMEP_OK;
 }
 
+int lbmep_set_dynamics(lbmep_lattice *L, double rho_p, const double *q, const double E[3]) {
+    if (!L || !E) return fail(LBMEP_EINVAL, "null argument");
+    if (!L->cfg.move_particles) return fail(LBMEP_EINVAL, "dynamics need move_particles = 1");
+    if (!(std::isfinite(rho_p) && rho_p > 0.0)) return fail(LBMEP_EINVAL, "rho_p must be > 0");
+    if (!finite_all(E, 3) || (q && !finite_all(q, (size_t)L->np)))
+        return fail(LBMEP_EINVAL, "non-finite E or charge");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    if (!L->too_fast) {
+        if (dev_alloc(L, (void **)&L->too_fast, 64) != hipSuccess) return fail(LBMEP_ENOMEM, "flag");
+        HIP_TRY(hipMemset(L->too_fast, 0, 64));
+    }
+    dev_free(L, L->q);
+    L->q = nullptr;
+    L->hq.clear();
+    if (q && L->np > 0) {
+        if (dev_alloc(L, (void **)&L->q, 8 * (size_t)L->np) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "charges");
+        L->hq.assign(q, q + L->np);
+        HIP_TRY(hipMemcpy(L->q, q, 8 * (size_t)L->np, hipMemcpyHostToDevice));
+    }
+    if (L->np > 0 && !L->dynamic) {
+        // from now on X0 holds the current level's positions
+        const ParticleArgs pa = particle_args(L);
+        HIP_TRY(launch_positions(pa, L->level, L->X0, L->stream));
+        HIP_TRY(hipStreamSynchronize(L->stream));
+    }
+    L->rho_p = rho_p;
+    for (int k = 0; k < 3; ++k) L->Edyn[k] = E[k];
+    L->dynamic = true;
+    return LBMEP_OK;
+}
+
+int lbmep_get_particles(lbmep_lattice *L, double *X, double *U, double *W) {
+    if (!L || (L->np > 0 && (!X || !U || !W))) return fail(LBMEP_EINVAL, "null argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    if (L->np == 0) return LBMEP_OK;
+    const size_t b = 3 * (size_t)L->np * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(X, L->Xheld[L->cur_owner], b, hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(hipMemcpyAsync(U, L->U, b, hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(hipMemcpyAsync(W, L->W, b, hipMemcpyDeviceToHost, L->stream));
+    int32_t fast = 0;
+    if (L->too_fast)
+        HIP_TRY(hipMemcpyAsync(&fast, L->too_fast, 4, hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    if (fast) return fail(LBMEP_EINVAL, "a particle reached one cell per step: the mapping is not valid");
+    return LBMEP_OK;
+}
+
 int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n) {
     if (!L || !n) return fail(LBMEP_EINVAL, "null argument");
     *n = L->np;
@@ -825,6 +883,23 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
         // bounce-back slots and momentum exchange next to solid cells
         HIP_TRY(launch_near(L->precision, a, near_wall_blocks(L->g, L->has_walls), s));
+        if (L->dynamic && L->np > 0) {
+            // the particles move under this step's force and torque
+            DynArgs d;
+            d.g = L->g;
+            d.np = L->np;
+            d.acc = L->FM;
+            d.X = L->Xheld[L->cur_owner];
+            d.R = L->R;
+            d.q = L->q;
+            d.U = L->U;
+            d.W = L->W;
+            d.X0 = L->X0;
+            d.rho_p = L->rho_p;
+            for (int k = 0; k < 3; ++k) d.E[k] = L->Edyn[k];
+            d.too_fast = L->too_fast;
+            HIP_TRY(launch_dynamics(d, s));
+        }
         if (L->np > 0 && L->cfg.move_particles) {
             // kinematics, re-mapping and classification of the next level
             const int b = 1 - L->cur_owner;
@@ -990,6 +1065,10 @@ struct Header {
     // red-black SOR of the potential (sor_set = 0: not configured)
     double sor_kappa2, sor_omega, sor_rf;
     int32_t sor_iters, sor_check, sor_set, pad2;
+    // particle dynamics (dyn = 0: prescribed); with dynamics the particle
+    // table holds the current positions and velocities
+    double rho_p, Edyn[3];
+    int32_t dyn, nq;
 };
 }  // namespace
 
@@ -1024,15 +1103,31 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
     h.sor_iters = L->sor_iters;
     h.sor_check = L->sor_check;
     h.sor_set = L->sor_set ? 1 : 0;
+    h.dyn = L->dynamic ? 1 : 0;
+    h.rho_p = L->rho_p;
+    for (int k = 0; k < 3; ++k) h.Edyn[k] = L->Edyn[k];
+    h.nq = (int32_t)L->hq.size();
+    // with dynamics the table's positions and velocities are the device state
+    std::vector<double> pX = L->hX0, pU = L->hU, pW = L->hW;
+    if (L->dynamic && L->np > 0) {
+        const size_t b = 3 * (size_t)L->np * sizeof(double);
+        if (hipMemcpy(pX.data(), L->X0, b, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(pU.data(), L->U, b, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(pW.data(), L->W, b, hipMemcpyDeviceToHost) != hipSuccess) {
+            std::fclose(fp);
+            return fail(LBMEP_EDEVICE, "particle state read-back failed");
+        }
+    }
     bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1;
     const size_t N = L->g.N, Ns = L->g.Ns;
     if (ok && L->np > 0) {
-        ok = std::fwrite(L->hX0.data(), 8, L->hX0.size(), fp) == L->hX0.size() &&
+        ok = std::fwrite(pX.data(), 8, pX.size(), fp) == pX.size() &&
              std::fwrite(L->hR.data(), 8, L->hR.size(), fp) == L->hR.size() &&
-             std::fwrite(L->hU.data(), 8, L->hU.size(), fp) == L->hU.size() &&
-             std::fwrite(L->hW.data(), 8, L->hW.size(), fp) == L->hW.size();
+             std::fwrite(pU.data(), 8, pU.size(), fp) == pU.size() &&
+             std::fwrite(pW.data(), 8, pW.size(), fp) == pW.size();
     }
     if (ok && h.nzeta > 0) ok = std::fwrite(L->hzeta.data(), 8, L->hzeta.size(), fp) == L->hzeta.size();
+    if (ok && h.nq > 0) ok = std::fwrite(L->hq.data(), 8, L->hq.size(), fp) == L->hq.size();
     // user wall flags
     std::vector<uint8_t> fl(N);
     if (ok) {
@@ -1077,7 +1172,8 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
               h.per[1] == L->g.per[1] && h.per[2] == L->g.per[2] &&
               h.precision == L->precision && h.move == L->cfg.move_particles &&
               h.nu == L->cfg.nu && h.magic_param == L->cfg.magic && h.np >= 0 && h.level >= 0 &&
-              (h.nzeta == 0 || h.nzeta == h.np) && h.force_mode >= kForceNone &&
+              (h.nzeta == 0 || h.nzeta == h.np) && (h.nq == 0 || h.nq == h.np) &&
+              (h.dyn == 0 || (h.dyn == 1 && h.move)) && h.force_mode >= kForceNone &&
               h.force_mode <= kForcePotential;
     if (!ok) {
         std::fclose(fp);
@@ -1092,6 +1188,8 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
              std::fread(W.data(), 8, W.size(), fp) == W.size();
     std::vector<double> zeta(h.nzeta);
     if (h.nzeta > 0) ok = ok && std::fread(zeta.data(), 8, zeta.size(), fp) == zeta.size();
+    std::vector<double> qv(h.nq);
+    if (h.nq > 0) ok = ok && std::fread(qv.data(), 8, qv.size(), fp) == qv.size();
     std::vector<uint8_t> fl(N);
     ok = ok && std::fread(fl.data(), 1, N, fp) == N;
     const int nc = h.force_mode == kForceDense ? 3 : (h.force_mode == kForceNone ? 0 : 1);
@@ -1107,6 +1205,11 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
     if (rc) return rc;
     rc = lbmep_set_particles(L, h.np, X.data(), R.data(), U.data(), W.data());
     if (rc) return rc;
+    if (h.dyn) {
+        // the table holds the saved level's positions and velocities
+        rc = lbmep_set_dynamics(L, h.rho_p, h.nq > 0 ? qv.data() : nullptr, h.Edyn);
+        if (rc) return rc;
+    }
     L->level = h.level;
     rc = remap_all(L);
     if (rc) return rc;

@@ -104,6 +104,7 @@ struct ParticleArgs {
     Grid g;
     int np;
     int moving;
+    int dynamic;       // Newton-Euler dynamics: X0 holds the current positions
     const double *X0, *R, *U, *W;
     uint2 *plist;      // link lists written by the classification
     uint32_t *pcount;
@@ -260,6 +261,22 @@ hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, con
                                  const uint32_t *owner_old, hipStream_t s);
 // final force and torque (6n: F then M per particle) from the 12n sweep
 // accumulators and the particle centres of the streamed time level
+// Newton-Euler update of every particle from the step's accumulators: U, W
+// in place, X0 = the next level's positions; *too_fast = 1 when a velocity
+// component reaches one cell per step
+struct DynArgs {
+    Grid g;
+    int np;
+    const double *acc;   // 12 per particle (F_dev, M_dev, K, T)
+    const double *X;     // current positions
+    const double *R;
+    const double *q;     // charges or null
+    double *U, *W, *X0;
+    double rho_p;
+    double E[3];
+    int32_t *too_fast;
+};
+hipError_t launch_dynamics(const DynArgs &d, hipStream_t s);
 hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double *out,
                               hipStream_t s);
 // map read-out in the ABI encoding

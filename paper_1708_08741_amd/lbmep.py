@@ -100,6 +100,8 @@ _SIGS = {
     "lbmep_solve_potential": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_solver_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lbmep_set_dynamics": (ctypes.c_int, [_P, ctypes.c_double, _P, _D]),
+    "lbmep_get_particles": (ctypes.c_int, [_P, _D, _D, _D]),
     "lbmep_init_equilibrium": (ctypes.c_int, [_P, ctypes.c_double, _D]),
     "lbmep_set_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_get_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -320,6 +322,24 @@ class Lattice:
         p, dev = _ptr(out)
         _check(lib().lbmep_get_potential(self._h, p, dev))
         return out
+
+    def set_dynamics(self, rho_p, q=None, E=(0.0, 0.0, 0.0)):
+        """Newton-Euler dynamics of the (moving) particles: density rho_p,
+        charges q (None: uncharged), applied field E for the forces q E."""
+        qp = None
+        if q is not None:
+            qa = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+            qp = ctypes.c_void_p(qa.ctypes.data)
+        Ea = np.array(E, dtype=np.float64)
+        _check(lib().lbmep_set_dynamics(self._h, float(rho_p), qp, _dp(Ea)))
+
+    def particles(self):
+        """Current positions, velocities, angular velocities, (n, 3) each."""
+        X = np.zeros((self.np, 3))
+        U = np.zeros((self.np, 3))
+        Wv = np.zeros((self.np, 3))
+        _check(lib().lbmep_get_particles(self._h, _dp(X), _dp(U), _dp(Wv)))
+        return X, U, Wv
 
     def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
         ua = np.array(u, dtype=np.float64)
