@@ -169,3 +169,81 @@ def test_window_of_large_fp64_grid_64bit_offsets(oracle_mod):
     sF = np.abs(F_o[ok]).max()
     assert np.abs(F[ok] - F_o[ok]).max() <= 1e-12 * sF
     assert np.abs(M[ok] - M_o[ok]).max() <= 1e-12 * sF * R
+
+
+def test_window_of_512_electrophoresis_step(oracle_mod):
+    """One full electrophoresis step of the benchmark's coupled leg at 512^3
+    (FP32 storage): 29 red-black SOR iterations of the Debye-Hueckel equation
+    from the spheres' Debye-Hueckel fields, the force from psi, the
+    stream-collide step and the Newton-Euler update of 4096 charged spheres.
+    A red-black iteration reaches two cells, so after the step a cell
+    depends on the inputs within 2 x 29 + 1 cells; the oracle runs the same
+    step on a 192^3 window with closed faces, and the window's core (62
+    cells from every face) must agree: maps bit-exact, psi and fields within
+    the FP32 tolerances, particle velocities within 5e-5 of the largest."""
+    import torch
+
+    from paper_1708_08741_amd import lbmep
+
+    n, S, o = 512, 192, np.array([250.0, 150.0, 300.0])
+    wl = W.periodic_suspension(n=n, count=4096, R=4.0, seed=3, steps=1, precision="fp32dev")
+    zeta = np.random.default_rng(4).uniform(-0.05, 0.05, len(wl.R))
+    psi = W.debye_huckel_psi(wl.shape, wl.periodic, wl.X, wl.R, zeta, kappa=0.5, cutoff=6.0)
+    q = np.random.default_rng(5).uniform(-0.1, 0.1, len(wl.R))
+    kappa2, iters, keps = 0.25, 29, 1e-3
+    g = lbmep.from_workload(wl, precision="fp32dev")
+    g.set_potential_force(psi.astype(np.float32), keps, wl.E, zeta)
+    g.set_potential_solver(kappa2, 1.7, iters, 0.0)
+    g.set_dynamics(1.195, q, wl.E)
+    g.step(1)
+    sl = tuple(slice(int(o[a]), int(o[a]) + S) for a in (2, 1, 0))
+    psi_t = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    g.potential(psi_t)
+    psi_g = psi_t[sl].cpu().numpy()
+    del psi_t
+    rho_t = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    u_t = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+    g.macro_device(rho_t, u_t)
+    rho_g = rho_t[sl].cpu().numpy()
+    u_g = u_t[(slice(None),) + sl].cpu().numpy()
+    del rho_t, u_t
+    fl_g, ow_g = g.map()
+    fl_g, ow_g = fl_g[sl], ow_g[sl]
+    Xg, Ug, Wg = g.particles()
+    g.close()
+    torch.cuda.empty_cache()
+
+    R = wl.R[0]
+    reach = R + 3.0
+    inside = np.all((wl.X > o - reach) & (wl.X < o + S + reach), axis=1)
+    idx = np.nonzero(inside)[0]
+    orc = oracle_mod.Oracle((S, S, S), (False, False, False), wl.nu, wl.magic)
+    orc.init_equilibrium()
+    orc.set_particles(wl.X[idx] - o, wl.R[idx], wl.U[idx], wl.W[idx], moving=True)
+    orc.set_potential_force(np.ascontiguousarray(psi[sl]), keps, wl.E, zeta[idx])
+    orc.set_potential_solver(kappa2, 1.7, iters, 0.0)
+    orc.set_dynamics(1.195, q[idx], wl.E)
+    orc.step(1)
+    psi_o = orc.potential()
+    rho_o, u_o = orc.macro()
+    fl_o, ow_o = orc.map()
+    Xo, Uo, Wo = orc.particles()
+
+    m = 2 * iters + 4
+    core = (slice(m, S - m),) * 3
+    assert (fl_g[core] == fl_o[core]).all()
+    glob = np.where(ow_o[core] >= 0, idx[np.maximum(ow_o[core], 0)], -1)
+    assert (ow_g[core] == glob).all()
+    unk = (fl_o[core] == 0) | (fl_o[core] == 3)
+    s_psi = np.abs(psi_o[core][unk]).max()
+    assert np.abs(psi_g[core] - psi_o[core])[unk].max() <= 1e-5 * s_psi
+    du = np.abs(u_g[(slice(None),) + core] - u_o[(slice(None),) + core])[:, unk].max()
+    assert du <= 5e-6 * np.abs(u_o[(slice(None),) + core])[:, unk].max(), du
+    assert np.abs(rho_g[core] - rho_o[core])[unk].max() <= 1e-8
+    # particles whose neighbourhood lies in the core
+    Xw = wl.X[idx] - o
+    ok = np.all((Xw > m + R + 2) & (Xw < S - m - R - 2), axis=1)
+    assert ok.sum() >= 3
+    dU = np.abs(Ug[idx[ok]] - Uo[ok]).max()
+    assert dU <= 5e-5 * np.abs(Uo[ok] - wl.U[idx[ok]]).max(), dU
+    assert np.abs((Xg[idx[ok]] - o) - Xo[ok]).max() <= 1e-6
