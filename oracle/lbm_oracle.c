@@ -55,7 +55,8 @@
  *   - Cell centres at i + 1/2 (0-based); the inside test is the closed
  *     ball on the minimum-image distance; the lowest particle index owns a
  *     cell claimed by several; WALL cells are never particle cells.
- *   - Outside a non-periodic axis there is an implicit no-slip wall.
+ *   - Outside a non-periodic axis there is an implicit no-slip wall, or a
+ *     free-slip (specular) face where set.
  *   - Newly covered cells lose their populations; newly uncovered cells get
  *     f^eq(rho0, u_s) with u_s of the previous owner at its previous place.
  *   - Prescribed kinematics X_p(n) = X_p(0) + n U_p (evaluated in that form),
@@ -115,6 +116,8 @@ struct orc_lattice {
     int potential;
     double *psi, *zeta, k_eps, Eext[3];
     /* red-black SOR for the Debye-Hueckel equation (optional) */
+    /* free-slip faces x-, x+, y-, y+, z-, z+ (non-periodic axes only) */
+    int slip[6];
     /* Newton-Euler dynamics of the particles (optional) */
     int dynamic;
     double rho_p, Edyn[3], *q;
@@ -740,6 +743,61 @@ void orc_get_particles(const orc_lattice *L, double *X, double *U, double *W) {
     memcpy(W, L->W, sizeof(double) * 3 * (size_t)L->np);
 }
 
+/* -------------------------------------------------------------------------
+ * Free-slip faces (no-slip and free-slip boundaries are the two wall
+ * conditions of the paper's simulations, Sec. "Lattice Boltzmann Method with
+ * Forcing"; the paper defers their form to earlier work).  Reading: a free-slip face of
+ * a non-periodic axis is a plane half a cell beyond the last cell that
+ * reflects populations specularly.  For fluid cell x and direction q whose
+ * source x - e_q lies beyond the grid along the axes O, and every face so
+ * crossed is free-slip: the population left the cell s' = x - e_q with its
+ * O-components set back to x's, in the direction p = e_q mirrored in O, and
+ * the reflection delivers it to x.  If s' is a wall or obstacle cell there
+ * is no such population and the link takes the resting half-way
+ * bounce-back; a face that is not free-slip always does.  Both keep the
+ * streaming a one-to-one map of populations, so mass is conserved.
+ * ---------------------------------------------------------------------- */
+static int mirrored_direction(int q, const int flip[3]) {
+    int k, want[3], a;
+    for (a = 0; a < 3; ++a) want[a] = flip[a] ? -C[q][a] : C[q][a];
+    for (k = 0; k < Q; ++k)
+        if (C[k][0] == want[0] && C[k][1] == want[1] && C[k][2] == want[2]) return k;
+    return -1;
+}
+
+static int free_slip_source(const orc_lattice *L, int x, int y, int z, int q, long *src, int *pdir) {
+    const int len[3] = {L->nx, L->ny, L->nz};
+    const int v[3] = {x, y, z};
+    int flip[3] = {0, 0, 0}, w[3], a, any = 0;
+    for (a = 0; a < 3; ++a) {
+        int u = v[a] - C[q][a];
+        w[a] = u;
+        if (u >= 0 && u < len[a]) continue;
+        if (L->per[a]) {
+            w[a] = u < 0 ? u + len[a] : u - len[a];
+            continue;
+        }
+        /* crosses the low (2a) or high (2a + 1) face of axis a */
+        if (!L->slip[2 * a + (u < 0 ? 0 : 1)]) return 0;
+        flip[a] = 1;
+        w[a] = v[a];
+        any = 1;
+    }
+    if (!any) return 0;
+    *src = cell_index(L, w[0], w[1], w[2]);
+    if (!is_fluid(L, *src)) return 0;
+    *pdir = mirrored_direction(q, flip);
+    return 1;
+}
+
+int orc_set_free_slip(orc_lattice *L, const int faces[6]) {
+    int k;
+    for (k = 0; k < 6; ++k)
+        if (faces[k] && L->per[k / 2]) return -1;
+    for (k = 0; k < 6; ++k) L->slip[k] = faces[k] != 0;
+    return 0;
+}
+
 static void one_step(orc_lattice *L) {
     const long N = L->N;
     const int nx = L->nx, ny = L->ny, nz = L->nz, np = L->np;
@@ -779,8 +837,13 @@ static void one_step(orc_lattice *L) {
                     const int back[3] = {-C[q][0], -C[q][1], -C[q][2]};
                     long s = neighbour(L, x, y, z, back); /* x - e_q */
                     int qb = L->opp[q];
+                    long ss;
+                    int ps;
                     if (s >= 0 && is_fluid(L, s)) {
                         L->fnew[(long)q * N + c] = L->fstar[(long)q * N + s];
+                    } else if (s < 0 && free_slip_source(L, x, y, z, q, &ss, &ps)) {
+                        /* specular reflection at a free-slip face */
+                        L->fnew[(long)q * N + c] = L->fstar[(long)ps * N + ss];
                     } else if (s < 0 || L->wall[s]) {
                         /* resting no-slip wall half-way */
                         L->fnew[(long)q * N + c] = L->fstar[(long)qb * N + c];

@@ -57,6 +57,9 @@ void orc_get_potential(const orc_lattice *L, double *psi);
  * table was set with moving = 1 and rho_p > 0.  Dropped by set_particles. */
 int orc_set_dynamics(orc_lattice *L, double rho_p, const double *q, const double E[3]);
 void orc_get_particles(const orc_lattice *L, double *X, double *U, double *W);
+/* free-slip faces x-, x+, y-, y+, z-, z+ (1 = specular reflection; only on
+ * non-periodic axes, else -1) */
+int orc_set_free_slip(orc_lattice *L, const int faces[6]);
 void orc_init_equilibrium(orc_lattice *L, double rho, const double u[3]);
 void orc_set_pdfs(orc_lattice *L, const double *f);       /* 19*N */
 void orc_get_pdfs(const orc_lattice *L, double *f);

@@ -68,6 +68,7 @@ def lib():
         L.orc_dha_residual.restype = ctypes.c_double
         L.orc_get_potential.argtypes = [P, dp]
         L.orc_set_dynamics.argtypes = [P, ctypes.c_double, ctypes.c_void_p, dp]
+        L.orc_set_free_slip.argtypes = [P, ip]
         L.orc_get_particles.argtypes = [P, dp, dp, dp]
         L.orc_init_equilibrium.argtypes = [P, ctypes.c_double, dp]
         L.orc_set_pdfs.argtypes = [P, dp]
@@ -196,6 +197,12 @@ class Oracle:
         Ea = np.ascontiguousarray(E, dtype=np.float64)
         if lib().orc_set_dynamics(self._h, float(rho_p), qp, _dp(Ea)):
             raise ValueError("oracle: dynamics need moving particles and rho_p > 0")
+
+    def set_free_slip(self, faces):
+        """Free-slip faces (x-, x+, y-, y+, z-, z+), non-periodic axes only."""
+        f = (ctypes.c_int * 6)(*[1 if v else 0 for v in faces])
+        if lib().orc_set_free_slip(self._h, f):
+            raise ValueError("oracle: free-slip only on non-periodic axes")
 
     def particles(self):
         """Current positions, velocities and angular velocities (np, 3)."""

@@ -1002,3 +1002,113 @@ def test_dynamics_need_moving_particles(oracle_mod):
     with pytest.raises(ValueError):
         o.set_dynamics(0.0)
     o.set_dynamics(1.2)
+
+
+# ---------------------------------------------------------------------------
+# free-slip faces (Sec. "Lattice Boltzmann Method with Forcing": no-slip and
+# free-slip walls; specular reflection at the half-way plane)
+# ---------------------------------------------------------------------------
+
+def test_free_slip_channel_plug_flow(oracle_mod):
+    """A channel whose y faces are free-slip, driven by a uniform force along
+    x, accelerates as a plug: every cell carries u_x = (n + 1/2) f_b after n
+    steps, as in a periodic box (no-slip faces would give a parabola)."""
+    shape = (6, 10, 4)
+    fb = 1e-5
+    o = oracle_mod.Oracle(shape, (True, False, True))
+    o.set_free_slip([0, 0, 1, 1, 0, 0])
+    F = np.zeros((3, 4, 10, 6))
+    F[0] = fb
+    o.set_force(F)
+    o.init_equilibrium()
+    o.step(40)
+    rho, u = o.macro()
+    assert np.abs(u[0] - 40.5 * fb).max() <= 1e-15
+    assert np.abs(u[1]).max() <= 1e-18 and np.abs(u[2]).max() <= 1e-18
+    # control: no-slip faces slow the cells next to them
+    c = oracle_mod.Oracle(shape, (True, False, True))
+    c.set_force(F)
+    c.init_equilibrium()
+    c.step(40)
+    _, uc = c.macro()
+    assert uc[0][:, 0, :].max() < 0.9 * 40.5 * fb
+
+
+def _mirror_state(f, axes, W19):
+    """Populations of a box mirrored across its upper faces along `axes`:
+    the image cell holds the population of the mirrored direction."""
+    C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+                  [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+    out = f
+    for ax in axes:  # ax: 0 = x, 1 = y, 2 = z (array axis 3 - 1 - ax after the q axis)
+        flip = C.copy()
+        flip[:, ax] *= -1
+        perm = [int(np.nonzero((C == flip[q]).all(axis=1))[0][0]) for q in range(19)]
+        arr_ax = 3 - ax  # (q, z, y, x)
+        img = np.flip(out[perm], axis=arr_ax)
+        out = np.concatenate([out, img], axis=arr_ax)
+    return out
+
+
+def _mirror_force(fb, axes):
+    out = fb
+    for ax in axes:
+        arr_ax = 3 - ax
+        img = np.flip(out, axis=arr_ax).copy()
+        img[ax] *= -1
+        out = np.concatenate([out, img], axis=arr_ax)
+    return out
+
+
+@pytest.mark.parametrize("axes", [(1,), (1, 2), (0, 1, 2)])
+def test_free_slip_is_the_mirror_image(oracle_mod, axes):
+    """Method of images: a box with free-slip faces on `axes` evolves exactly
+    like the periodic box of twice the size along those axes that holds the
+    box and its mirror image (populations of mirrored directions, mirrored
+    force), restricted to the original half.  Random states and forces, 3
+    steps, corners included (1e-14: the mirrored cells sum their moments in
+    another order)."""
+    shape = [5, 6, 4]
+    rng = np.random.default_rng(len(axes))
+    nx, ny, nz = shape
+    f = W.random_state(rng, tuple(shape), oracle_mod.W, amp=0.05)
+    fb = 1e-3 * rng.standard_normal((3, nz, ny, nx))
+    per = [a not in axes for a in range(3)]
+    o = oracle_mod.Oracle(tuple(shape), tuple(per))
+    o.set_free_slip([1 if (k // 2) in axes else 0 for k in range(6)])
+    o.set_force(fb)
+    o.set_pdfs(f)
+    big = [s * (2 if a in axes else 1) for a, s in enumerate(shape)]
+    p = oracle_mod.Oracle(tuple(big), (True, True, True))
+    p.set_force(_mirror_force(fb, axes))
+    p.set_pdfs(_mirror_state(f, axes, oracle_mod.W))
+    for _ in range(3):
+        o.step(1)
+        p.step(1)
+    fo = o.get_pdfs()
+    fp = p.get_pdfs()[:, :nz, :ny, :nx]
+    assert np.abs(fo - fp).max() <= 1e-14
+
+
+def test_free_slip_conserves_mass_with_a_sphere_at_the_face(oracle_mod):
+    """Specular reflection and the bounce-back fallback (where the mirrored
+    source is a solid cell) keep streaming one-to-one: with a resting sphere
+    cut by a free-slip face, mass is conserved to rounding."""
+    shape = (12, 10, 8)
+    rng = np.random.default_rng(9)
+    o = oracle_mod.Oracle(shape, (True, False, False))
+    o.set_free_slip([0, 0, 1, 1, 1, 0])
+    o.set_particles([[6.0, 1.0, 4.0]], [2.5], [[0.0, 0.0, 0.0]])
+    o.set_pdfs(W.random_state(rng, shape, oracle_mod.W, amp=0.05))
+    m0 = o.invariants()[0]
+    for _ in range(10):
+        o.step(1)
+    assert abs(o.invariants()[0] - m0) <= 1e-13 * m0
+
+
+def test_free_slip_only_on_non_periodic_axes(oracle_mod):
+    o = oracle_mod.Oracle((4, 4, 4), (True, False, True))
+    with pytest.raises(ValueError):
+        o.set_free_slip([1, 0, 0, 0, 0, 0])
+    o.set_free_slip([0, 0, 1, 0, 0, 0])
