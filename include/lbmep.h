@@ -182,6 +182,17 @@ int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]);
  * no potential set), ENOMEM, EDEVICE. */
 int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device);
 
+/* Free-slip faces (Sec. "Lattice Boltzmann Method with Forcing": no-slip
+ * and free-slip walls).  faces[6] for x-, x+, y-, y+, z-, z+: 1 makes the
+ * implicit wall beyond that face of a non-periodic axis a specular
+ * reflector at the half-way plane (a population whose source lies beyond it
+ * comes from the tangential neighbour with the crossed components of its
+ * direction mirrored; if that cell is a wall or obstacle cell the link
+ * bounces back), 0 keeps the no-slip wall.  The potential's boundary
+ * condition at faces stays homogeneous Neumann.  Errors: EINVAL (null, a
+ * value not 0 / 1, a free-slip face on a periodic axis). */
+int lbmep_set_free_slip(lbmep_lattice *L, const int32_t faces[6]);
+
 /* Let the particles move under their forces instead of the prescribed
  * kinematics (Alg. "Electrophoresis Algorithm", last block; the force on a
  * particle's charge q E of Sec. "Computing Electrostatic Forces on Fluid and

@@ -56,6 +56,7 @@ struct lbmep_lattice {
     void *force = nullptr;
     size_t force_bytes = 0;
     double E[3] = {0, 0, 0};
+    int slip = 0;              // free-slip faces (bit 2a + side)
     // Newton-Euler dynamics of the particles (X0, U, W become state)
     bool dynamic = false;
     double rho_p = 0, Edyn[3] = {0, 0, 0};

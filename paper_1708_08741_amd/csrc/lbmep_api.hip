@@ -130,6 +130,7 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.ao = L->ao;
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
+    a.slip = L->slip;
     a.keps = L->keps;
     a.zeta = L->force_mode == kForcePotential ? L->zeta : nullptr;
     a.np = L->np;
@@ -781,6 +782,24 @@ int lbmep_get_particles(lbmep_lattice *L, double *X, double *U, double *W) {
     return LBMEP_OK;
 }
 
+int lbmep_set_free_slip(lbmep_lattice *L, const int32_t faces[6]) {
+    if (!L || !faces) return fail(LBMEP_EINVAL, "null argument");
+    int bits = 0;
+    for (int k = 0; k < 6; ++k) {
+        if (faces[k] != 0 && faces[k] != 1) return fail(LBMEP_EINVAL, "face value not 0 / 1");
+        if (faces[k] && L->g.per[k / 2]) return fail(LBMEP_EINVAL, "free-slip face on a periodic axis");
+        if (faces[k]) bits |= 1 << k;
+    }
+    int rc = set_device(L);
+    if (rc) return rc;
+    // the stored state is the post-stream state of its level under the old
+    // faces; bring it there before the faces change
+    rc = materialize(L);
+    if (rc) return rc;
+    L->slip = bits;
+    return LBMEP_OK;
+}
+
 int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n) {
     if (!L || !n) return fail(LBMEP_EINVAL, "null argument");
     *n = L->np;
@@ -1069,6 +1088,7 @@ struct Header {
     // table holds the current positions and velocities
     double rho_p, Edyn[3];
     int32_t dyn, nq;
+    int32_t slip, pad3;  // free-slip faces
 };
 }  // namespace
 
@@ -1107,6 +1127,7 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
     h.rho_p = L->rho_p;
     for (int k = 0; k < 3; ++k) h.Edyn[k] = L->Edyn[k];
     h.nq = (int32_t)L->hq.size();
+    h.slip = L->slip;
     // with dynamics the table's positions and velocities are the device state
     std::vector<double> pX = L->hX0, pU = L->hU, pW = L->hW;
     if (L->dynamic && L->np > 0) {
@@ -1173,7 +1194,8 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
               h.precision == L->precision && h.move == L->cfg.move_particles &&
               h.nu == L->cfg.nu && h.magic_param == L->cfg.magic && h.np >= 0 && h.level >= 0 &&
               (h.nzeta == 0 || h.nzeta == h.np) && (h.nq == 0 || h.nq == h.np) &&
-              (h.dyn == 0 || (h.dyn == 1 && h.move)) && h.force_mode >= kForceNone &&
+              (h.dyn == 0 || (h.dyn == 1 && h.move)) && (h.slip & ~63) == 0 &&
+              h.force_mode >= kForceNone &&
               h.force_mode <= kForcePotential;
     if (!ok) {
         std::fclose(fp);
@@ -1203,6 +1225,7 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
     // walls, particles (time level 0 map), then the saved time level
     rc = lbmep_set_flags(L, fl.data(), 0);
     if (rc) return rc;
+    L->slip = h.slip;
     rc = lbmep_set_particles(L, h.np, X.data(), R.data(), U.data(), W.data());
     if (rc) return rc;
     if (h.dyn) {

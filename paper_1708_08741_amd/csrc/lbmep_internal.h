@@ -22,6 +22,15 @@ constexpr int kCy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1
 constexpr int kCz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
 __host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+// the direction of q with the components in mask (bit a = axis a) negated
+__host__ __device__ constexpr int mirror_dir(int q, int mask) {
+    const int wx = (mask & 1) ? -kCx[q] : kCx[q];
+    const int wy = (mask & 2) ? -kCy[q] : kCy[q];
+    const int wz = (mask & 4) ? -kCz[q] : kCz[q];
+    for (int k = 0; k < Q; ++k)
+        if (kCx[k] == wx && kCy[k] == wy && kCz[k] == wz) return k;
+    return -1;
+}
 __host__ __device__ constexpr double wq(int q) {
     return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
@@ -82,6 +91,7 @@ struct SweepArgs {
     double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
     int nxb;                // x-segments per row (set by the launcher)
     int xcd_swizzle;        // 1: map consecutive segments onto one XCD
+    int slip;               // free-slip faces: bit 2a + side (a = axis, side 1 = high)
     int np;                 // particles
     uint32_t pcap;          // link-list capacity per particle
     const uint2 *plist;     // per particle: (cell, directions into the particle)

@@ -223,6 +223,47 @@ __device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF 
     return pop_load<MODE, ST>(at<ST>(base, ok ? nb : own));
 }
 
+// free-slip faces: population q of a cell whose source x - c_q lies beyond a
+// free-slip face (along the axes of mask) comes from the tangential
+// neighbour s' (x - c_q with those components set back to x's) in the
+// mirrored direction, unless s' is a wall or obstacle cell or a crossed face
+// is no-slip (then the gather's half-way bounce-back stands).  Rare: only
+// cells on a free-slip face run this.
+template <int q, typename ST>
+__device__ __forceinline__ void slip_fix(const SweepArgs &a, int x, int y, int z,
+                                         typename Storage<ST>::CT &v) {
+    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
+    const int len[3] = {a.g.nx, a.g.ny, a.g.nz};
+    int s[3] = {x - cx, y - cy, z - cz};
+    const int o[3] = {x, y, z};
+    int mask = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (s[k] >= 0 && s[k] < len[k]) continue;
+        if (a.g.per[k]) {
+            s[k] = s[k] < 0 ? s[k] + len[k] : s[k] - len[k];
+            continue;
+        }
+        if (!(a.slip & (1 << (2 * k + (s[k] < 0 ? 0 : 1))))) return;  // no-slip face
+        mask |= 1 << k;
+        s[k] = o[k];
+    }
+    if (!mask) return;
+    const size_t sc = (size_t)s[0] + (size_t)a.g.nx * ((size_t)s[1] + (size_t)a.g.ny * (size_t)s[2]);
+    if (a.flag[sc] & (kWall | kObst)) return;
+    int p = q;
+    switch (mask) {
+        case 1: p = mirror_dir(q, 1); break;
+        case 2: p = mirror_dir(q, 2); break;
+        case 3: p = mirror_dir(q, 3); break;
+        case 4: p = mirror_dir(q, 4); break;
+        case 5: p = mirror_dir(q, 5); break;
+        case 6: p = mirror_dir(q, 6); break;
+        default: p = mirror_dir(q, 7); break;
+    }
+    v = Storage<ST>::load(static_cast<const ST *>(a.src) + (size_t)p * a.g.Ns + sc);
+}
+
 // loaded inputs of one cell
 template <typename CT>
 struct CellIn {
@@ -292,6 +333,14 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
 #define LBMEP_GATHER(q) c.v[q] = gather<q, ST, OFF, MODE>(a.src, pst, es, cb, rows, rok, xs, xok);
         LBMEP_FOR_Q18(LBMEP_GATHER)
 #undef LBMEP_GATHER
+        if (a.slip && valid &&
+            (((a.slip & 1) && x == 0) || ((a.slip & 2) && x == nx - 1) ||
+             ((a.slip & 4) && y == 0) || ((a.slip & 8) && y == ny - 1) ||
+             ((a.slip & 16) && z == 0) || ((a.slip & 32) && z == nz - 1))) {
+#define LBMEP_SLIP(q) slip_fix<q, ST>(a, x, y, z, c.v[q]);
+            LBMEP_FOR_Q18(LBMEP_SLIP)
+#undef LBMEP_SLIP
+        }
     }
     c.fb0 = c.fb1 = c.fb2 = CT(0);
     if constexpr (MODE != kReadout) {

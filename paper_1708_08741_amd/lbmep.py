@@ -101,6 +101,7 @@ _SIGS = {
     "lbmep_get_solver_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_set_dynamics": (ctypes.c_int, [_P, ctypes.c_double, _P, _D]),
+    "lbmep_set_free_slip": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbmep_get_particles": (ctypes.c_int, [_P, _D, _D, _D]),
     "lbmep_init_equilibrium": (ctypes.c_int, [_P, ctypes.c_double, _D]),
     "lbmep_set_pdfs": (ctypes.c_int, [_P, _P, ctypes.c_int]),
@@ -322,6 +323,11 @@ class Lattice:
         p, dev = _ptr(out)
         _check(lib().lbmep_get_potential(self._h, p, dev))
         return out
+
+    def set_free_slip(self, faces):
+        """Free-slip faces (x-, x+, y-, y+, z-, z+), non-periodic axes only."""
+        f = (ctypes.c_int32 * 6)(*[1 if v else 0 for v in faces])
+        _check(lib().lbmep_set_free_slip(self._h, f))
 
     def set_dynamics(self, rho_p, q=None, E=(0.0, 0.0, 0.0)):
         """Newton-Euler dynamics of the (moving) particles: density rho_p,
