@@ -54,7 +54,7 @@ template <typename CT>
 __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint8_t fl,
                                         const CT *psi, const uint8_t *flag,
                                         const uint32_t *owner, const double *zeta, CT kappa2,
-                                        CT &diag, CT &rhs, CT &sum) {
+                                        CT &diag, CT &rhs, CT &sum, uint8_t *unknown = nullptr) {
     diag = CT(6.0) + kappa2;
     rhs = CT(0);
     sum = CT(0);
@@ -74,6 +74,7 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
         // every neighbour is an unknown inside the grid (periodic wrap)
 #pragma unroll
         for (int k = 0; k < 6; ++k) sum = sum + psi[s[k]];
+        if (unknown) *unknown = 63;
         return;
     }
     // a neighbour beyond a non-periodic edge: homogeneous Neumann
@@ -99,6 +100,7 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
         bv[k] = pv[k];
         if (zeta && !edge[k] && (fs[k] & kObst) && !(fs[k] & kWall)) bv[k] = (CT)zeta[owner[s[k]]];
     }
+    uint8_t um = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         if (edge[k] || (fs[k] & kWall)) {
@@ -108,8 +110,10 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
             rhs = rhs + CT(2.0) * bv[k];
         } else {
             sum = sum + pv[k];
+            um |= (uint8_t)(1u << k);
         }
     }
+    if (unknown) *unknown = um;
 }
 
 __global__ void k_sor_begin(SorCtl *ctl) {
@@ -239,6 +243,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     if (a.ctl->done) return;
     if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
     const Grid &g = a.g;
+    // hardware block order (measured: the XCD-contiguous order is slower here)
     const uint32_t lb = blockIdx.x;
     const uint32_t row = lb / nxb, xb = lb - row * nxb;
     const int y0 = (int)(row % nyb) * kSorRows, z = (int)(row / nyb);
@@ -250,7 +255,6 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     CT *psi = static_cast<CT *>(a.psi);
     CT *pz = psi + nxy * (size_t)z;
     const CT *pzm = psi + nxy * (size_t)zm, *pzp = psi + nxy * (size_t)zp;
-    const uint8_t *fz = a.flag + nxy * (size_t)z;
     const int xc = act ? x2 : 0;  // a valid column for lanes past the row
     // rows y0 - 1 .. y0 + kSorRows of the plane (k = row - y0 + 1)
     V P[kSorRows + 2];
@@ -261,13 +265,14 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         P[k] = *reinterpret_cast<const V *>(pz + nx * (size_t)y + (size_t)xc);
     }
     V Zm[kSorRows], Zp[kSorRows];
-    uint16_t F[kSorRows];
+    uint32_t F[kSorRows];  // the pair's two interior bits (bit 0: x2, bit 1: x2 + 1)
 #pragma unroll
     for (int r = 0; r < kSorRows; ++r) {
         const int y = min(y0 + r, g.ny - 1);
         Zm[r] = *reinterpret_cast<const V *>(pzm + nx * (size_t)y + (size_t)xc);
         Zp[r] = *reinterpret_cast<const V *>(pzp + nx * (size_t)y + (size_t)xc);
-        F[r] = *reinterpret_cast<const uint16_t *>(fz + nx * (size_t)y + (size_t)xc);
+        const uint32_t c2 = (uint32_t)(nxy * (size_t)z + nx * (size_t)y) + (uint32_t)xc;
+        F[r] = (a.ibits[c2 >> 5] >> (c2 & 31)) & 3u;  // c2 even: both bits in one word
     }
     // x - 1 of the pair's first cell and x + 1 of its second: neighbouring
     // lanes, or a load at the wave's ends (periodic wrap of the row)
@@ -289,8 +294,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         const int y = y0 + r;
         if (y >= g.ny) continue;
         const int p = (colour + y + z) & 1;
-        const uint8_t fl = p ? (uint8_t)(F[r] >> 8) : (uint8_t)(F[r] & 0xff);
-        if (!(fl & (kWall | kObst | kNear))) {
+        if ((F[r] >> p) & 1u) {
             // interior cell: x-, x+, y-, y+, z-, z+
             CT nb[6], own;
             if (p == 0) {
@@ -320,6 +324,30 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         }
         *reinterpret_cast<V *>(pz + nx * (size_t)y + (size_t)x2) = P[r + 1];
     }
+}
+
+// once per solve: bit c of ibits = cell c is an interior unknown (neither
+// wall, obstacle nor NEAR), 32 cells per word
+__global__ void __launch_bounds__(256) k_interior_bits(Grid g, const uint8_t *flag,
+                                                       uint32_t *ibits) {
+    const size_t w = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t c0 = w * 32;
+    if (c0 >= g.N) return;
+    uint32_t bits = 0;
+    if (c0 + 32 <= g.N) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(flag + c0);
+        const uint4 lo = p[0], hi = p[1];
+        const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const uint32_t f = (v[k >> 2] >> (8 * (k & 3))) & 0xffu;
+            bits |= (f & (kWall | kObst | kNear)) ? 0u : (1u << k);
+        }
+    } else {
+        for (int k = 0; c0 + k < g.N; ++k)
+            bits |= (flag[c0 + k] & (kWall | kObst | kNear)) ? 0u : (1u << k);
+    }
+    ibits[w] = bits;
 }
 
 // the boundary unknowns (NEAR cells) of each colour, listed once per solve
@@ -444,23 +472,73 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_write(Grid g, const uint8_
 // the boundary unknowns of one colour, from its list (fixed grid, strided)
 constexpr int kNearGrid = 2048;
 
+// global indices of the six D3Q7 neighbours (periodic wrap; a neighbour
+// beyond a non-periodic edge gets the cell itself, never used)
+__device__ __forceinline__ void d3q7_neighbours(const Grid &g, uint32_t c, uint32_t s[6]) {
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
+    const uint32_t yz = c / nx, x = c - yz * nx;
+    const uint32_t z = yz / ny, y = yz - z * ny;
+    const uint32_t row = c - x, plane = nx * ny;
+    s[0] = row + (x == 0 ? nx - 1 : x - 1);
+    s[1] = row + (x == nx - 1 ? 0 : x + 1);
+    s[2] = c - (y == 0 ? 0 : nx) + (y == 0 ? (ny - 1) * nx : 0);
+    s[3] = y == ny - 1 ? c - (ny - 1) * nx : c + nx;
+    s[4] = z == 0 ? c + (nz - 1) * plane : c - plane;
+    s[5] = z == nz - 1 ? c - (nz - 1) * plane : c + plane;
+}
+
+// once per solve: the boundary rows of both lists, diag, rhs and the mask of
+// unknown neighbours, formed as dha_row forms them (the map and the
+// obstacle cells' values are fixed during a solve)
+template <typename CT>
+__global__ void __launch_bounds__(kNearBlock) k_nlist_rows(SorArgs a) {
+    const Grid &g = a.g;
+    const size_t half = g.N / 2 + 1;
+    const CT *psi = static_cast<const CT *>(a.psi);
+    CT *rows = static_cast<CT *>(a.nrow);
+    for (int colour = 0; colour < 2; ++colour) {
+        const uint32_t n = a.ctl->nnear[colour];
+        const size_t base = colour ? half : 0;
+        for (uint32_t i = blockIdx.x * kNearBlock + threadIdx.x; i < n;
+             i += kNearGrid * kNearBlock) {
+            const uint32_t c = a.nlist[base + i];
+            const uint32_t yz = c / (uint32_t)g.nx;
+            const int x = (int)(c - yz * (uint32_t)g.nx);
+            const int z = (int)(yz / (uint32_t)g.ny), y = (int)(yz - (uint32_t)z * (uint32_t)g.ny);
+            CT diag, rhs, sum;
+            uint8_t mask;
+            dha_row<CT>(g, x, y, z, kNear, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs,
+                        sum, &mask);
+            rows[2 * (base + i)] = diag;
+            rows[2 * (base + i) + 1] = rhs;
+            a.nmask[base + i] = mask;
+        }
+    }
+}
+
 template <typename CT>
 __global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) {
     if (a.ctl->done) return;
     const Grid &g = a.g;
     const uint32_t n = a.ctl->nnear[colour];
-    const uint32_t *list = a.nlist + (colour ? g.N / 2 + 1 : 0);
+    const size_t base = colour ? g.N / 2 + 1 : 0;
+    const CT *rows = static_cast<const CT *>(a.nrow);
     CT *psi = static_cast<CT *>(a.psi);
     const CT om = (CT)a.omega;
     for (uint32_t i = blockIdx.x * kNearBlock + threadIdx.x; i < n; i += kNearGrid * kNearBlock) {
-        const uint32_t c = list[i];
-        const uint32_t yz = c / (uint32_t)g.nx;
-        const int x = (int)(c - yz * (uint32_t)g.nx);
-        const int z = (int)(yz / (uint32_t)g.ny), y = (int)(yz - (uint32_t)z * (uint32_t)g.ny);
-        // every listed cell is a NEAR unknown: its own flag is not needed
+        const uint32_t c = a.nlist[base + i];
+        const uint8_t mask = a.nmask[base + i];
+        const CT diag = rows[2 * (base + i)], rhs = rows[2 * (base + i) + 1];
+        uint32_t s[6];
+        d3q7_neighbours(g, c, s);
+        CT v[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] = (mask >> k) & 1 ? psi[s[k]] : CT(0);
         const CT own = psi[c];
-        CT diag, rhs, sum;
-        dha_row<CT>(g, x, y, z, kNear, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs, sum);
+        CT sum = CT(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if ((mask >> k) & 1) sum = sum + v[k];
         psi[c] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
     }
 }
@@ -805,6 +883,12 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
         hipLaunchKernelGGL(k_nlist_scan, dim3(1), dim3(1024), 0, s, a.nscratch, nseg, a.ctl);
         hipLaunchKernelGGL(k_nlist_write, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
                            a.nscratch, nseg, a.nlist);
+        hipLaunchKernelGGL((k_nlist_rows<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a);
+        if (vec) {
+            const size_t words = (g.N + 31) / 32;
+            hipLaunchKernelGGL(k_interior_bits, dim3((uint32_t)((words + 255) / 256)), dim3(256),
+                               0, s, g, a.flag, a.ibits);
+        }
     }
     if (with_res) {
         hipLaunchKernelGGL((k_dha_residual<CT>), dim3(nres), dim3(kResBlock), 0, s, a);

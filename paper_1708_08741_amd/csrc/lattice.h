@@ -75,6 +75,9 @@ struct lbmep_lattice {
     double *sor_partial = nullptr;
     uint32_t *sor_nlist = nullptr;     // boundary unknowns of each colour
     uint32_t *sor_nscratch = nullptr;  // segment counts / offsets of the list build
+    void *sor_nrow = nullptr;          // per list entry: diag, rhs (compute precision)
+    uint8_t *sor_nmask = nullptr;      // per list entry: unknown neighbours
+    uint32_t *sor_ibits = nullptr;     // interior unknowns, one bit per cell
     void *psi2 = nullptr;      // second psi buffer of the fused SOR iteration
     size_t psi2_bytes = 0;
     bool sor_fused = false;    // fused iteration (switched off: one launch per colour)

@@ -271,6 +271,9 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->sor_partial);
     dev_free(L, L->sor_nlist);
     dev_free(L, L->sor_nscratch);
+    dev_free(L, L->sor_nrow);
+    dev_free(L, L->sor_nmask);
+    dev_free(L, L->sor_ibits);
     dev_free(L, L->psi2);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
@@ -612,6 +615,9 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.partial = L->sor_partial;
     a.nlist = L->sor_nlist;
     a.nscratch = L->sor_nscratch;
+    a.nrow = L->sor_nrow;
+    a.nmask = L->sor_nmask;
+    a.ibits = L->sor_ibits;
     a.xcd_swizzle = L->xcd_swizzle;
     return a;
 }
@@ -654,6 +660,11 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
             return fail(LBMEP_ENOMEM, "solver boundary list");
         if (dev_alloc(L, (void **)&L->sor_nscratch, 4 * sor_nscratch_entries(L->g.N)) != hipSuccess)
             return fail(LBMEP_ENOMEM, "solver list scratch");
+        if (dev_alloc(L, &L->sor_nrow, 2 * compute_bytes(L->precision) *
+                                           sor_nlist_entries(L->g.N)) != hipSuccess ||
+            dev_alloc(L, (void **)&L->sor_nmask, sor_nlist_entries(L->g.N)) != hipSuccess ||
+            dev_alloc(L, (void **)&L->sor_ibits, 4 * ((L->g.N + 31) / 32)) != hipSuccess)
+            return fail(LBMEP_ENOMEM, "solver boundary rows");
         SorCtl c{};
         c.res0 = c.res = -1.0;
         HIP_TRY(hipMemcpy(L->sor_ctl, &c, sizeof c, hipMemcpyHostToDevice));

@@ -230,6 +230,9 @@ struct SorArgs {
     uint32_t *nlist;           // boundary unknowns: colour 0 at [0, N/2 + 1),
                                // colour 1 at [N/2 + 1, N + 2)
     uint32_t *nscratch;        // per-segment counts / offsets of the list build
+    void *nrow;                // per list entry: diag and rhs of the row (2 compute values)
+    uint8_t *nmask;            // per list entry: bit k = neighbour k is an unknown
+    uint32_t *ibits;           // bit c: cell c is an interior unknown ((N + 31) / 32 words)
     uint32_t xcd_swizzle;
 };
 constexpr int kSorPartials = 8192;
