@@ -283,7 +283,11 @@ int lbmep_load_state(lbmep_lattice *L, const char *path);
 int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n);
 
 /* Device bytes held by a lattice of this configuration with n particles of
- * radius at most r_max (used for admission by footprint).  Errors: EINVAL. */
+ * radius at most r_max and a charge force or none (used for admission by
+ * footprint).  Not counted: a potential solver (lbmep_set_potential_solver
+ * adds 4 N + 9 N (FP32) / 17 N (FP64) + N / 8 bytes for the boundary lists,
+ * their rows and the interior bitmask) and the per-particle charges of the
+ * dynamics (8 n).  Errors: EINVAL. */
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
                     size_t *bytes);
 
