@@ -217,7 +217,8 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, i
 // the plane and the rows y0 .. y0 + kSorRows - 1 of the planes z -+ 1; the
 // x -+ 1 values come from the neighbouring lanes (the wave's end lanes load
 // theirs), the y -+ 1 values from the thread's own neighbouring rows.  Every
-// load and store is a whole coalesced 2-vector.  Same arithmetic as
+// load and store is a whole coalesced 2-vector; a pair is written only when
+// its cell of this colour is an interior unknown.  Same arithmetic as
 // k_sor_half.
 template <typename CT>
 struct Vec2;
@@ -237,14 +238,27 @@ __device__ __forceinline__ CT lane_shift(CT v, int delta) {
 }
 
 template <typename CT>
+__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb);
+
+template <typename CT>
 __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colour, int count,
-                                                            uint32_t nxb, uint32_t nyb) {
+                                                            uint32_t nxb, uint32_t nyb,
+                                                            uint32_t ninterior) {
     using V = typename Vec2<CT>::T;
     if (a.ctl->done) return;
     if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
+    // the grid's first blocks (dispatched first, so they overlap the
+    // streaming) relax the colour's listed boundary cells: the interior
+    // blocks write no boundary cell, and both read only cells of the other
+    // colour
+    const uint32_t nnb = gridDim.x - ninterior;
+    if (blockIdx.x < nnb) {
+        sor_near_part<CT>(a, colour, blockIdx.x, nnb);
+        return;
+    }
     const Grid &g = a.g;
     // hardware block order (measured: the XCD-contiguous order is slower here)
-    const uint32_t lb = blockIdx.x;
+    const uint32_t lb = blockIdx.x - nnb;
     const uint32_t row = lb / nxb, xb = lb - row * nxb;
     const int y0 = (int)(row % nyb) * kSorRows, z = (int)(row / nyb);
     const int x2 = (int)(xb * (2 * kSorBlock) + 2 * threadIdx.x);
@@ -321,8 +335,9 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
             const CT nw = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
             if (p == 0) P[r + 1].x = nw;
             else P[r + 1].y = nw;
+            // the whole pair (its other cell unchanged: of the other colour)
+            *reinterpret_cast<V *>(pz + nx * (size_t)y + (size_t)x2) = P[r + 1];
         }
-        *reinterpret_cast<V *>(pz + nx * (size_t)y + (size_t)x2) = P[r + 1];
     }
 }
 
@@ -471,6 +486,7 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_write(Grid g, const uint8_
 
 // the boundary unknowns of one colour, from its list (fixed grid, strided)
 constexpr int kNearGrid = 2048;
+constexpr int kNearInVec = 1024;  // list blocks appended to a vector half-sweep
 
 // global indices of the six D3Q7 neighbours (periodic wrap; a neighbour
 // beyond a non-periodic edge gets the cell itself, never used)
@@ -516,16 +532,17 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_rows(SorArgs a) {
     }
 }
 
+// the colour's listed boundary cells, entries strided over nb blocks of
+// kNearBlock threads (this block: b0)
 template <typename CT>
-__global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) {
-    if (a.ctl->done) return;
+__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb) {
     const Grid &g = a.g;
     const uint32_t n = a.ctl->nnear[colour];
     const size_t base = colour ? g.N / 2 + 1 : 0;
     const CT *rows = static_cast<const CT *>(a.nrow);
     CT *psi = static_cast<CT *>(a.psi);
     const CT om = (CT)a.omega;
-    for (uint32_t i = blockIdx.x * kNearBlock + threadIdx.x; i < n; i += kNearGrid * kNearBlock) {
+    for (uint32_t i = b0 * kNearBlock + threadIdx.x; i < n; i += nb * kNearBlock) {
         const uint32_t c = a.nlist[base + i];
         const uint8_t mask = a.nmask[base + i];
         const CT diag = rows[2 * (base + i)], rhs = rows[2 * (base + i) + 1];
@@ -541,6 +558,12 @@ __global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) 
             if ((mask >> k) & 1) sum = sum + v[k];
         psi[c] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
     }
+}
+
+template <typename CT>
+__global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) {
+    if (a.ctl->done) return;
+    sor_near_part<CT>(a, colour, blockIdx.x, gridDim.x);
 }
 
 // residual: per-thread strided sums of r^2 and of the unknowns, a block tree,
@@ -902,14 +925,16 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
             a.psi = next;
         } else {
             for (int col = 0; col < 2; ++col) {
-                if (vec)
-                    hipLaunchKernelGGL((k_sor_half_vec<CT>), dim3(nblk), dim3(kSorBlock), 0, s,
-                                       a, col, col, nxb, nyb);
-                else
+                if (vec) {
+                    // kNearInVec blocks for the boundary list, then the interior blocks
+                    hipLaunchKernelGGL((k_sor_half_vec<CT>), dim3(nblk + kNearInVec),
+                                       dim3(kSorBlock), 0, s, a, col, col, nxb, nyb, nblk);
+                } else {
                     hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a,
                                        col, col, nxb, nyb);
-                hipLaunchKernelGGL((k_sor_near<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a,
-                                   col);
+                    hipLaunchKernelGGL((k_sor_near<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s,
+                                       a, col);
+                }
             }
         }
         if (with_res && (it % check_every == 0 || it == max_iter)) {
