@@ -164,9 +164,13 @@ __device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, in
 // scheduling).  The lanes take 64 consecutive list entries (neighbouring
 // cells along x) and walk the directions in the same order, so each load
 // and store instruction touches consecutive addresses of one population.
+// waves per particle in the exchange kernel (a 256-thread workgroup)
+constexpr int kNearWaves = 4;
+
 template <typename ST, typename OFF>
 __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
     const int lane = (int)__lane_id();
+    const int wave = (int)(threadIdx.x / 64);
     const Grid &g = a.g;
     const int nx = g.nx, ny = g.ny;
     const uint2 *list = a.plist + (size_t)p * a.pcap;
@@ -177,7 +181,8 @@ __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-    for (uint32_t i0 = 0; i0 < n; i0 += 64u) {
+    // the waves of the workgroup take every kNearWaves-th chunk of 64 entries
+    for (uint32_t i0 = 64u * (uint32_t)wave; i0 < n; i0 += 64u * kNearWaves) {
         const uint32_t i = i0 + (uint32_t)lane;
         uint2 e = make_uint2(0u, 0u);
         if (i < n) e = list[i];
@@ -190,10 +195,19 @@ __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
         LBMEP_FOR_Q18(LBMEP_PLINK)
 #undef LBMEP_PLINK
     }
+    // wave sums, then the waves' sums in wave order: a fixed order
+    __shared__ double part[kNearWaves][kAcc];
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) {
         const double t = wave_sum_f64(acc[k]);
-        if (lane == 0 && a.FM) a.FM[kAcc * (size_t)p + k] = t;
+        if (lane == 0) part[wave][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kAcc && a.FM) {
+        double t = part[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kNearWaves; ++w) t += part[w][threadIdx.x];
+        a.FM[kAcc * (size_t)p + threadIdx.x] = t;
     }
 }
 
@@ -227,20 +241,15 @@ __device__ __forceinline__ void near_walls(const SweepArgs &a, uint32_t blk, uin
     }
 }
 
-// particles per workgroup of the exchange kernel (one per wavefront)
-constexpr int kNearPerBlock = 4;
+// one particle per workgroup of the exchange kernel
+__host__ __device__ inline uint32_t near_particle_blocks(int np) { return (uint32_t)np; }
 
-__host__ __device__ inline uint32_t near_particle_blocks(int np) {
-    return (uint32_t)((np + kNearPerBlock - 1) / kNearPerBlock);
-}
-
-// workgroups [0, pb): kNearPerBlock particles each; the rest: the wall links
+// workgroups [0, np): one particle each; the rest: the wall links
 template <typename ST, typename OFF>
 __device__ __forceinline__ void near_block(const SweepArgs &a, uint32_t blk, uint32_t nblk) {
     const uint32_t pb = near_particle_blocks(a.np);
     if (blk < pb) {
-        const uint32_t p = blk * kNearPerBlock + threadIdx.x / 64;
-        if (p < (uint32_t)a.np) near_particle<ST, OFF>(a, p);
+        near_particle<ST, OFF>(a, blk);
     } else {
         near_walls<ST, OFF>(a, blk - pb, nblk - pb);
     }
