@@ -21,8 +21,11 @@
 // FP64 kernel rounds like a plain CPU evaluation of the same rows.
 //
 // Two implementations of an iteration, bitwise identical:
-//   * k_sor_half (in use): one launch per colour, in place (each colour
-//     streams psi through HBM once);
+//   * in use: one launch per colour, in place (each colour streams psi
+//     through HBM once): for even nx k_sor_half_vec, whose workgroups march
+//     through chunks of z planes with the three-plane window in registers
+//     and relax the listed boundary cells in the same grid; for odd nx
+//     k_sor_half, then k_sor_near for the listed cells;
 //   * k_sor_fused (switched off, see launch_sor_solve): one launch per
 //     iteration from psi into a second buffer.  A workgroup owns a 64 x 16 tile of (x, y) and a chunk of z
 //     planes and marches through its planes with rings of planes in LDS:
@@ -225,10 +228,12 @@ struct Vec2;
 template <>
 struct Vec2<float> {
     using T = float2;
+    using M = float __attribute__((ext_vector_type(2)));  // memory access type
 };
 template <>
 struct Vec2<double> {
     using T = double2;
+    using M = double __attribute__((ext_vector_type(2)));
 };
 
 template <typename CT>
@@ -240,11 +245,45 @@ __device__ __forceinline__ CT lane_shift(CT v, int delta) {
 template <typename CT>
 __device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb);
 
-template <typename CT>
+// a wave-uniform global pointer, made opaque to the optimiser: loads then
+// take it as a scalar base plus the lane's 32-bit offset, instead of a
+// per-lane 64-bit address kept in vector registers across the plane loop
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ GlobalPtr<T> uniform_ptr(T *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (GlobalPtr<T>)(((uint64_t)hi << 32) | lo);
+}
+
+// the interior half-sweep for even nx, marching along z.  A workgroup is
+// four waves stacked in y; lane l of a wave owns the x-pair (2l, 2l + 1) of
+// a 128-cell segment in kSorRows consecutive rows, and the workgroup walks
+// a.zc consecutive planes.  Per thread the window of three planes stays in
+// registers (rows y0 - 1 .. y0 + kSorRows of the plane, kSorRows rows of
+// each neighbour plane); moving to the next plane loads kSorRows rows of the
+// new plane ahead and the two y-halo rows of the new centre plane (6 row
+// loads per plane instead of 14).  Values a thread reads as neighbours are of
+// the other colour, which nobody writes in this half-sweep, so reading them
+// early changes nothing: every cell gets the same operands, in the same
+// order, as in a plane-at-a-time sweep.
+constexpr int kSorWaves = kSorBlock / 64;
+constexpr int kSorWaveX = 128;  // cells of a wave's row segment
+// workgroup tile: WX waves along x, kSorWaves / WX along y
+template <int WX>
+constexpr int sor_tile_x() { return WX * kSorWaveX; }
+template <int WX>
+constexpr int sor_tile_y() { return (kSorWaves / WX) * kSorRows; }
+
+template <typename CT, int WX>
 __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colour, int count,
                                                             uint32_t nxb, uint32_t nyb,
                                                             uint32_t ninterior) {
+    static_assert(kSorWaves % WX == 0, "whole waves along y");
     using V = typename Vec2<CT>::T;
+    using VM = typename Vec2<CT>::M;
     if (a.ctl->done) return;
     if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
     // the grid's first blocks (dispatched first, so they overlap the
@@ -257,86 +296,146 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         return;
     }
     const Grid &g = a.g;
-    // hardware block order (measured: the XCD-contiguous order is slower here)
-    const uint32_t lb = blockIdx.x - nnb;
-    const uint32_t row = lb / nxb, xb = lb - row * nxb;
-    const int y0 = (int)(row % nyb) * kSorRows, z = (int)(row / nyb);
-    const int x2 = (int)(xb * (2 * kSorBlock) + 2 * threadIdx.x);
-    const bool act = x2 < g.nx;  // lanes past the row take part in the shuffles only
+    // tiles in x, then y, then z-chunk order; with the XCD-contiguous order
+    // neighbouring tiles (whose halo lines a tile reads) share an L2
+    const uint32_t hb = blockIdx.x - nnb;  // nnb % 8 == 0: same XCD as blockIdx.x
+    const uint32_t lb = a.xcd_swizzle ? xcd_remap(hb, ninterior) : hb;
+    const uint32_t t = lb / nxb, xb = lb - t * nxb;
+    const uint32_t zb = t / nyb, yb = t - zb * nyb;
     const int lane = (int)(threadIdx.x & 63);
+    // wave-uniform (scalar): rows and planes are addressed by scalar bases
+    // plus the lane's 32-bit column
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wx = w % WX, wy = w / WX;
+    const int y0 = (int)yb * sor_tile_y<WX>() + wy * kSorRows;
+    const int zs = (int)zb * (int)a.zc;
+    const int ze = min(zs + (int)a.zc, g.nz);
+    const int x2 = (int)xb * sor_tile_x<WX>() + wx * kSorWaveX + 2 * lane;
+    const bool act = x2 < g.nx;  // lanes past the row take part in the shuffles only
+    const uint32_t xc = act ? (uint32_t)x2 : 0u;  // a valid column for lanes past the row
+    const uint32_t xl = x2 == 0 ? (uint32_t)(g.nx - 1) : (uint32_t)(x2 - 1);
+    const uint32_t xr = x2 + 2 >= g.nx ? (uint32_t)(x2 + 2 - g.nx) : (uint32_t)(x2 + 2);
     const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
-    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
     CT *psi = static_cast<CT *>(a.psi);
-    CT *pz = psi + nxy * (size_t)z;
-    const CT *pzm = psi + nxy * (size_t)zm, *pzp = psi + nxy * (size_t)zp;
-    const int xc = act ? x2 : 0;  // a valid column for lanes past the row
-    // rows y0 - 1 .. y0 + kSorRows of the plane (k = row - y0 + 1)
-    V P[kSorRows + 2];
+    // rows y0 .. y0 + kSorRows - 1 and the two halo rows, wrapped into the
+    // grid (rows a cell needs wrap once; the rows past ny of the last
+    // workgroup are the wrapped y + 1 neighbours of its last valid row after
+    // the window slides, so they wrap too)
+    size_t ro[kSorRows];
 #pragma unroll
-    for (int k = 0; k < kSorRows + 2; ++k) {
-        // any row index into [0, ny) (rows a cell needs wrap once: the same)
-        const int y = ((y0 - 1 + k) % g.ny + g.ny) % g.ny;
-        P[k] = *reinterpret_cast<const V *>(pz + nx * (size_t)y + (size_t)xc);
-    }
-    V Zm[kSorRows], Zp[kSorRows];
-    uint32_t F[kSorRows];  // the pair's two interior bits (bit 0: x2, bit 1: x2 + 1)
+    for (int r = 0; r < kSorRows; ++r) ro[r] = nx * (size_t)((y0 + r) % g.ny);
+    const size_t rlo = nx * (size_t)(((y0 - 1) % g.ny + g.ny) % g.ny);
+    const size_t rhi = nx * (size_t)((y0 + kSorRows) % g.ny);
+    auto plane = [&](int z) -> CT * {
+        const int zw = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
+        return psi + nxy * (size_t)zw;
+    };
+    // byte offsets of the lane's columns (32-bit: a row is < 4 GiB)
+    const uint32_t xo = xc * (uint32_t)sizeof(CT), xlo = xl * (uint32_t)sizeof(CT),
+                   xro = xr * (uint32_t)sizeof(CT);
+    auto at = [&](const CT *row, uint32_t off) -> GlobalPtr<const char> {
+        return uniform_ptr(reinterpret_cast<const char *>(row)) + off;
+    };
+    auto ldv = [&](const CT *row) -> V {
+        const VM m = *reinterpret_cast<GlobalPtr<const VM>>(at(row, xo));
+        V v;
+        v.x = m.x;
+        v.y = m.y;
+        return v;
+    };
+    auto bits = [&](int z, int r) -> uint32_t {
+        const uint32_t c2 = (uint32_t)(nxy * (size_t)z + ro[r]) + xc;  // even: one word
+        return (a.ibits[c2 >> 5] >> (c2 & 31)) & 3u;
+    };
+    // window at the first plane
+    V C[kSorRows + 2], M[kSorRows], P[kSorRows];
+    uint32_t F = 0;  // bits 2r, 2r + 1: the interior bits of row r's pair
+    {
+        const CT *pz = plane(zs), *pm = plane(zs - 1), *pp = plane(zs + 1);
+        C[0] = ldv(pz + rlo);
+        C[kSorRows + 1] = ldv(pz + rhi);
 #pragma unroll
-    for (int r = 0; r < kSorRows; ++r) {
-        const int y = min(y0 + r, g.ny - 1);
-        Zm[r] = *reinterpret_cast<const V *>(pzm + nx * (size_t)y + (size_t)xc);
-        Zp[r] = *reinterpret_cast<const V *>(pzp + nx * (size_t)y + (size_t)xc);
-        const uint32_t c2 = (uint32_t)(nxy * (size_t)z + nx * (size_t)y) + (uint32_t)xc;
-        F[r] = (a.ibits[c2 >> 5] >> (c2 & 31)) & 3u;  // c2 even: both bits in one word
+        for (int r = 0; r < kSorRows; ++r) {
+            C[r + 1] = ldv(pz + ro[r]);
+            M[r] = ldv(pm + ro[r]);
+            P[r] = ldv(pp + ro[r]);
+            F |= bits(zs, r) << (2 * r);
+        }
     }
-    // x - 1 of the pair's first cell and x + 1 of its second: neighbouring
-    // lanes, or a load at the wave's ends (periodic wrap of the row)
-    CT left[kSorRows], right[kSorRows];
-    const int xl = x2 == 0 ? g.nx - 1 : x2 - 1, xr = x2 + 2 >= g.nx ? x2 + 2 - g.nx : x2 + 2;
-#pragma unroll
-    for (int r = 0; r < kSorRows; ++r) {
-        left[r] = lane_shift(P[r + 1].y, -1);
-        right[r] = lane_shift(P[r + 1].x, 1);
-        const int y = min(y0 + r, g.ny - 1);
-        if (act && (lane == 0 || x2 == 0)) left[r] = pz[nx * (size_t)y + (size_t)xl];
-        if (act && (lane == 63 || x2 + 2 >= g.nx)) right[r] = pz[nx * (size_t)y + (size_t)xr];
-    }
-    if (!act) return;
     const CT om = (CT)a.omega;
     const CT diag = CT(6.0) + (CT)a.kappa2;
+#pragma unroll 1
+    for (int z = zs; z < ze; ++z) {
+        if (z > zs) {
+            // slide the window one plane up: the plane behind is the old
+            // centre, the centre is the old plane ahead plus its two halo
+            // rows, and the new plane ahead is loaded
+            const CT *pz = plane(z), *pp = plane(z + 1);
+            C[0] = ldv(pz + rlo);
+            C[kSorRows + 1] = ldv(pz + rhi);
+            F = 0;
 #pragma unroll
-    for (int r = 0; r < kSorRows; ++r) {
-        const int y = y0 + r;
-        if (y >= g.ny) continue;
-        const int p = (colour + y + z) & 1;
-        if ((F[r] >> p) & 1u) {
-            // interior cell: x-, x+, y-, y+, z-, z+
-            CT nb[6], own;
-            if (p == 0) {
-                own = P[r + 1].x;
-                nb[0] = left[r];
-                nb[1] = P[r + 1].y;
-                nb[2] = P[r].x;
-                nb[3] = P[r + 2].x;
-                nb[4] = Zm[r].x;
-                nb[5] = Zp[r].x;
-            } else {
-                own = P[r + 1].y;
-                nb[0] = P[r + 1].x;
-                nb[1] = right[r];
-                nb[2] = P[r].y;
-                nb[3] = P[r + 2].y;
-                nb[4] = Zm[r].y;
-                nb[5] = Zp[r].y;
+            for (int r = 0; r < kSorRows; ++r) {
+                M[r] = C[r + 1];
+                C[r + 1] = P[r];
+                P[r] = ldv(pp + ro[r]);
+                F |= bits(z, r) << (2 * r);
             }
-            CT sum = CT(0);
+        }
+        CT *pz = psi + nxy * (size_t)z;
+        // x - 1 of the pair's first cell and x + 1 of its second: neighbouring
+        // lanes, or a load at the wave's ends (periodic wrap of the row)
+        CT left[kSorRows], right[kSorRows];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) sum = sum + nb[k];
-            const CT rhs = CT(0);
-            const CT nw = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
-            if (p == 0) P[r + 1].x = nw;
-            else P[r + 1].y = nw;
-            // the whole pair (its other cell unchanged: of the other colour)
-            *reinterpret_cast<V *>(pz + nx * (size_t)y + (size_t)x2) = P[r + 1];
+        for (int r = 0; r < kSorRows; ++r) {
+            left[r] = lane_shift(C[r + 1].y, -1);
+            right[r] = lane_shift(C[r + 1].x, 1);
+            if (act && (lane == 0 || x2 == 0))
+                left[r] = *reinterpret_cast<GlobalPtr<const CT>>(at(pz + ro[r], xlo));
+            if (act && (lane == 63 || x2 + 2 >= g.nx))
+                right[r] = *reinterpret_cast<GlobalPtr<const CT>>(at(pz + ro[r], xro));
+        }
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < kSorRows; ++r) {
+                const int y = y0 + r;
+                if (y >= g.ny) continue;
+                const int p = (colour + y + z) & 1;
+                if ((F >> (2 * r + p)) & 1u) {
+                    // interior cell: x-, x+, y-, y+, z-, z+
+                    CT nb[6], own;
+                    if (p == 0) {
+                        own = C[r + 1].x;
+                        nb[0] = left[r];
+                        nb[1] = C[r + 1].y;
+                        nb[2] = C[r].x;
+                        nb[3] = C[r + 2].x;
+                        nb[4] = M[r].x;
+                        nb[5] = P[r].x;
+                    } else {
+                        own = C[r + 1].y;
+                        nb[0] = C[r + 1].x;
+                        nb[1] = right[r];
+                        nb[2] = C[r].y;
+                        nb[3] = C[r + 2].y;
+                        nb[4] = M[r].y;
+                        nb[5] = P[r].y;
+                    }
+                    CT sum = CT(0);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) sum = sum + nb[k];
+                    const CT rhs = CT(0);
+                    const CT nw = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
+                    if (p == 0) C[r + 1].x = nw;
+                    else C[r + 1].y = nw;
+                    // the whole pair (its other cell unchanged: of the other colour)
+                    VM m;
+                    m.x = C[r + 1].x;
+                    m.y = C[r + 1].y;
+                    *reinterpret_cast<GlobalPtr<VM>>(
+                        uniform_ptr(reinterpret_cast<char *>(pz + ro[r])) + xo) = m;
+                }
+            }
         }
     }
 }
@@ -889,6 +988,12 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const uint32_t nxb = (uint32_t)((g.nx + 2 * kSorBlock - 1) / (2 * kSorBlock));
     const uint32_t nyb = (uint32_t)((g.ny + kSorRows - 1) / kSorRows);
     const uint32_t nblk = nxb * nyb * (uint32_t)g.nz;
+    // the z-marching interior half-sweep (even nx): tile of wx waves along x
+    const int wx = a0.wx == 2 || a0.wx == 4 ? (int)a0.wx : 1;
+    const uint32_t vxb = (uint32_t)((g.nx + wx * kSorWaveX - 1) / (wx * kSorWaveX));
+    const int tyr = (kSorWaves / wx) * kSorRows;
+    const uint32_t vyb = (uint32_t)((g.ny + tyr - 1) / tyr);
+    const uint32_t vblk = vxb * vyb * (uint32_t)((g.nz + (int)a0.zc - 1) / (int)a0.zc);
     // 2-vector rows: even nx keeps every pair aligned
     const bool vec = (g.nx % 2) == 0;
     const int ntx = (g.nx + kFTX - 1) / kFTX, nty = (g.ny + kFTY - 1) / kFTY;
@@ -927,8 +1032,16 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
             for (int col = 0; col < 2; ++col) {
                 if (vec) {
                     // kNearInVec blocks for the boundary list, then the interior blocks
-                    hipLaunchKernelGGL((k_sor_half_vec<CT>), dim3(nblk + kNearInVec),
-                                       dim3(kSorBlock), 0, s, a, col, col, nxb, nyb, nblk);
+                    const dim3 grid(vblk + kNearInVec), blk(kSorBlock);
+                    if (wx == 4)
+                        hipLaunchKernelGGL((k_sor_half_vec<CT, 4>), grid, blk, 0, s, a, col, col,
+                                           vxb, vyb, vblk);
+                    else if (wx == 2)
+                        hipLaunchKernelGGL((k_sor_half_vec<CT, 2>), grid, blk, 0, s, a, col, col,
+                                           vxb, vyb, vblk);
+                    else
+                        hipLaunchKernelGGL((k_sor_half_vec<CT, 1>), grid, blk, 0, s, a, col, col,
+                                           vxb, vyb, vblk);
                 } else {
                     hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a,
                                        col, col, nxb, nyb);
@@ -976,6 +1089,7 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
     // black phase read the z- flags of a plane already replaced by the
     // prefetch (a stale obstacle flag then indexed zeta with kNone)
     if (fused) return hipErrorNotSupported;
+    if (a.zc < 1) return hipErrorInvalidValue;
     if (fused && !a.psi2) return hipErrorInvalidValue;
     // the fused kernel keeps 32-bit in-plane offsets
     if ((size_t)a.g.nx * (size_t)a.g.ny >= ((size_t)1 << 31)) fused = false;

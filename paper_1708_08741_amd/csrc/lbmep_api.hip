@@ -325,6 +325,15 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         const int c = std::atoi(e);
         if (c == 1 || c == 2) L->cpt = c;
     }
+    if (const char *e = std::getenv("LBMEP_SOR_ZC")) {
+        const int c = std::atoi(e);
+        if (c >= 1 && c <= 1024) L->sor_zc = c;
+    }
+    if (const char *e = std::getenv("LBMEP_SOR_WX")) {
+        const int c = std::atoi(e);
+        if (c == 1 || c == 2 || c == 4) L->sor_wx = c;
+    }
+    if (const char *e = std::getenv("LBMEP_SOR_XCD")) L->sor_xcd = std::atoi(e) != 0;
     if (const char *e = std::getenv("LBMEP_BLOCK_X")) {
         const int b = std::atoi(e);
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
@@ -618,7 +627,9 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.nrow = L->sor_nrow;
     a.nmask = L->sor_nmask;
     a.ibits = L->sor_ibits;
-    a.xcd_swizzle = L->xcd_swizzle;
+    a.xcd_swizzle = (uint32_t)L->sor_xcd;
+    a.zc = (uint32_t)L->sor_zc;
+    a.wx = (uint32_t)L->sor_wx;
     return a;
 }
 

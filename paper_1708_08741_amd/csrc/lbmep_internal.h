@@ -234,6 +234,8 @@ struct SorArgs {
     uint8_t *nmask;            // per list entry: bit k = neighbour k is an unknown
     uint32_t *ibits;           // bit c: cell c is an interior unknown ((N + 31) / 32 words)
     uint32_t xcd_swizzle;
+    uint32_t zc;               // planes per workgroup of the interior half-sweep (>= 1)
+    uint32_t wx;               // waves along x of its workgroup tile (1, 2 or 4)
 };
 constexpr int kSorPartials = 8192;
 // the boundary lists are built per segment of kNearSeg cells

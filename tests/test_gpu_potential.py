@@ -267,6 +267,8 @@ def _sor_case(shape, periodic, walls, n, with_zeta, seed):
     ((2, 2, 2), (True, True, True), False, 0, False, 0.0, 5),
     ((1030, 6, 4), (True, True, True), True, 3, True, 0.0, 6),
     ((516, 6, 5), (False, True, False), False, 2, False, 1e-5, 7),
+    ((130, 37, 19), (True, False, False), True, 5, True, 0.0, 8),
+    ((258, 34, 12), (True, True, True), False, 6, True, 1e-6, 9),
 ])
 def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, with_zeta, rf,
                                   seed):
@@ -341,6 +343,45 @@ def test_sor_fused_equals_two_pass(lb, monkeypatch, shape, periodic, n, rf, prec
     for (st_f, p_f), (st_t, p_t) in zip(out["1"], out["0"]):
         assert st_f[0] == st_t[0]
         assert (p_f == p_t).all(), np.abs(p_f - p_t).max()
+
+
+@pytest.mark.parametrize("shape,periodic,n", [
+    ((130, 37, 19), (True, False, False), 5),
+    ((64, 16, 32), (True, True, True), 3),
+    ((258, 18, 9), (True, True, False), 4),
+    ((1030, 12, 6), (True, True, True), 5),
+    ((2, 2, 2), (True, True, True), 0),
+    ((4, 40, 3), (False, False, False), 1),
+])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sor_plane_chunks_identical(lb, monkeypatch, shape, periodic, n, precision):
+    """The interior half-sweep marches each workgroup through a chunk of z
+    planes (LBMEP_SOR_ZC planes, the window of three planes in registers):
+    every chunk size, workgroup tile (LBMEP_SOR_WX waves along x) and block
+    order (LBMEP_SOR_XCD) gives bitwise the same psi -- one plane per
+    workgroup, chunks with ragged tails, one chunk over the whole grid --
+    with several row segments and tiles with ragged ends, periodic wrap in
+    z and y, walls and particles."""
+    psi, fl, X, R, zeta = _sor_case(shape, periodic, True, n, True, 11)
+    ref = None
+    for zc, wx, xcd in (("1", "1", "0"), ("3", "1", "1"), ("8", "2", "0"), ("1024", "4", "1"),
+                        ("5", "4", "0"), ("8", "1", "1")):
+        monkeypatch.setenv("LBMEP_SOR_ZC", zc)
+        monkeypatch.setenv("LBMEP_SOR_WX", wx)
+        monkeypatch.setenv("LBMEP_SOR_XCD", xcd)
+        g = lb.Lattice(shape, periodic, precision=precision)
+        g.set_flags(fl)
+        g.set_particles(X, R, np.zeros((n, 3)))
+        g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+        g.set_potential_solver(0.3, 1.7, 9, 0.0, 1)
+        st = g.solve_potential()
+        out = (st[0], g.potential())
+        g.close()
+        if ref is None:
+            ref = out
+        else:
+            assert out[0] == ref[0]
+            assert (out[1] == ref[1]).all(), (zc, np.abs(out[1] - ref[1]).max())
 
 
 def _coupled_inputs():
