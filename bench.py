@@ -65,8 +65,10 @@ def sor_traffic():
     sha = hashlib.sha256(open(SOR_SRC, "rb").read()).hexdigest()[:16]
     if d.get("sor_kernel_sha") != sha:
         return None
-    e = d.get("other_kernels", {}).get("k_sor_half_vec<float>")
-    return e.get("hbm_bytes_per_launch") if e else None
+    for k, e in d.get("other_kernels", {}).items():
+        if k.startswith("k_sor_half_vec<float"):
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def traffic_for(precision):
