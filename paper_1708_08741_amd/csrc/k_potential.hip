@@ -73,10 +73,13 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
     s[3] = (size_t)x + nx * (size_t)yp + nxy * (size_t)z;
     s[4] = (size_t)x + nx * (size_t)y + nxy * (size_t)zm;
     s[5] = (size_t)x + nx * (size_t)y + nxy * (size_t)zp;
+    // the six neighbours have the other colour (even extents along periodic
+    // axes; a neighbour beyond a non-periodic edge is never read)
+    const uint32_t oc = (uint32_t)((x + y + z + 1) & 1);
     if (!(fl & kNear)) {
         // every neighbour is an unknown inside the grid (periodic wrap)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) sum = sum + psi[s[k]];
+        for (int k = 0; k < 6; ++k) sum = sum + psi[psi_slot(g, s[k], oc)];
         if (unknown) *unknown = 63;
         return;
     }
@@ -93,7 +96,7 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         fs[k] = edge[k] ? (uint8_t)kWall : flag[s[k]];
-        pv[k] = edge[k] ? CT(0) : psi[s[k]];
+        pv[k] = edge[k] ? CT(0) : psi[psi_slot(g, s[k], oc)];
     }
     CT bv[6];
 #pragma unroll
@@ -258,19 +261,26 @@ __device__ __forceinline__ GlobalPtr<T> uniform_ptr(T *p) {
     return (GlobalPtr<T>)(((uint64_t)hi << 32) | lo);
 }
 
-// the interior half-sweep for even nx, marching along z.  A workgroup is
-// four waves stacked in y; lane l of a wave owns the x-pair (2l, 2l + 1) of
-// a 128-cell segment in kSorRows consecutive rows, and the workgroup walks
-// a.zc consecutive planes.  Per thread the window of three planes stays in
-// registers (rows y0 - 1 .. y0 + kSorRows of the plane, kSorRows rows of
-// each neighbour plane); moving to the next plane loads kSorRows rows of the
-// new plane ahead and the two y-halo rows of the new centre plane (6 row
-// loads per plane instead of 14).  Values a thread reads as neighbours are of
-// the other colour, which nobody writes in this half-sweep, so reading them
-// early changes nothing: every cell gets the same operands, in the same
-// order, as in a plane-at-a-time sweep.
+// the interior half-sweep for even nx, on the colour-split storage of psi,
+// marching along z.  Entry i of the row (y, z) of colour k is the cell
+// x = 2i + p, p = (k + y + z) & 1; its neighbours all have the other colour:
+// x - 1 and x + 1 are entries i - 1 + p and i + p of the other colour's row
+// (y, z), and y -+ 1 and z -+ 1 are entry i of the other colour's rows
+// (y -+ 1, z) and (y, z -+ 1).  A workgroup is four waves, WX along x and
+// 4 / WX along y; lane l of a wave owns entry i of a 64-entry segment (128
+// cells) in kSorRows consecutive rows, and the workgroup walks a.zc
+// consecutive planes.  Per thread the window of three planes of the other
+// colour stays in registers (rows y0 - 1 .. y0 + kSorRows of the plane,
+// kSorRows rows of each neighbour plane); moving to the next plane loads
+// kSorRows rows of the new plane ahead, the two y-halo rows of the new
+// centre plane and the thread's own entries.  The second x-neighbour comes
+// from the neighbouring lane (the wave's end lanes load theirs).  The other
+// colour is not written in this half-sweep, so reading it early changes
+// nothing: every cell gets the same operands, in the same order, as in a
+// plane-at-a-time sweep; a half-sweep reads the other colour once and reads
+// and writes its own once.
 constexpr int kSorWaves = kSorBlock / 64;
-constexpr int kSorWaveX = 128;  // cells of a wave's row segment
+constexpr int kSorWaveX = 64;  // entries (of one colour) of a wave's row segment
 // workgroup tile: WX waves along x, kSorWaves / WX along y
 template <int WX>
 constexpr int sor_tile_x() { return WX * kSorWaveX; }
@@ -282,8 +292,6 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
                                                             uint32_t nxb, uint32_t nyb,
                                                             uint32_t ninterior) {
     static_assert(kSorWaves % WX == 0, "whole waves along y");
-    using V = typename Vec2<CT>::T;
-    using VM = typename Vec2<CT>::M;
     if (a.ctl->done) return;
     if (count && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
     // the grid's first blocks (dispatched first, so they overlap the
@@ -304,164 +312,142 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     const uint32_t zb = t / nyb, yb = t - zb * nyb;
     const int lane = (int)(threadIdx.x & 63);
     // wave-uniform (scalar): rows and planes are addressed by scalar bases
-    // plus the lane's 32-bit column
+    // plus the lane's 32-bit entry offset
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wx = w % WX, wy = w / WX;
     const int y0 = (int)yb * sor_tile_y<WX>() + wy * kSorRows;
     const int zs = (int)zb * (int)a.zc;
     const int ze = min(zs + (int)a.zc, g.nz);
-    const int x2 = (int)xb * sor_tile_x<WX>() + wx * kSorWaveX + 2 * lane;
-    const bool act = x2 < g.nx;  // lanes past the row take part in the shuffles only
-    const uint32_t xc = act ? (uint32_t)x2 : 0u;  // a valid column for lanes past the row
-    const uint32_t xl = x2 == 0 ? (uint32_t)(g.nx - 1) : (uint32_t)(x2 - 1);
-    const uint32_t xr = x2 + 2 >= g.nx ? (uint32_t)(x2 + 2 - g.nx) : (uint32_t)(x2 + 2);
-    const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
+    const int hx = g.nx >> 1;  // entries of one colour per row
+    const int i = (int)xb * sor_tile_x<WX>() + wx * kSorWaveX + lane;
+    const bool act = i < hx;  // lanes past the row take part in the shuffles only
+    const uint32_t ic = act ? (uint32_t)i : 0u;  // a valid entry for lanes past the row
+    const uint32_t il = i == 0 ? (uint32_t)(hx - 1) : (uint32_t)(i - 1);
+    const uint32_t ir = i + 1 >= hx ? (uint32_t)(i + 1 - hx) : (uint32_t)(i + 1);
+    const size_t hxs = (size_t)hx, hxy = (size_t)hx * (size_t)g.ny;
     CT *psi = static_cast<CT *>(a.psi);
-    // rows y0 .. y0 + kSorRows - 1 and the two halo rows, wrapped into the
-    // grid (rows a cell needs wrap once; the rows past ny of the last
-    // workgroup are the wrapped y + 1 neighbours of its last valid row after
-    // the window slides, so they wrap too)
+    CT *own = psi + (size_t)colour * (g.Ns >> 1);
+    const CT *oth = psi + (size_t)(colour ^ 1) * (g.Ns >> 1);
+    const uint32_t *bits_c = a.ibits + (size_t)colour * sor_ibits_words_per_colour(g.N);
+    // rows y0 .. y0 + kSorRows - 1 and the two halo rows (in entries),
+    // wrapped into the grid (rows a cell needs wrap once; the rows past ny of
+    // the last workgroup are the wrapped y + 1 neighbours of its last valid
+    // row after the window slides, so they wrap too)
     size_t ro[kSorRows];
 #pragma unroll
-    for (int r = 0; r < kSorRows; ++r) ro[r] = nx * (size_t)((y0 + r) % g.ny);
-    const size_t rlo = nx * (size_t)(((y0 - 1) % g.ny + g.ny) % g.ny);
-    const size_t rhi = nx * (size_t)((y0 + kSorRows) % g.ny);
-    auto plane = [&](int z) -> CT * {
+    for (int r = 0; r < kSorRows; ++r) ro[r] = hxs * (size_t)((y0 + r) % g.ny);
+    const size_t rlo = hxs * (size_t)(((y0 - 1) % g.ny + g.ny) % g.ny);
+    const size_t rhi = hxs * (size_t)((y0 + kSorRows) % g.ny);
+    auto plane = [&](const CT *base, int z) -> const CT * {
         const int zw = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
-        return psi + nxy * (size_t)zw;
+        return base + hxy * (size_t)zw;
     };
-    // byte offsets of the lane's columns (32-bit: a row is < 4 GiB)
-    const uint32_t xo = xc * (uint32_t)sizeof(CT), xlo = xl * (uint32_t)sizeof(CT),
-                   xro = xr * (uint32_t)sizeof(CT);
-    auto at = [&](const CT *row, uint32_t off) -> GlobalPtr<const char> {
-        return uniform_ptr(reinterpret_cast<const char *>(row)) + off;
+    // byte offsets of the lane's entries (32-bit: a row is < 4 GiB)
+    const uint32_t io = ic * (uint32_t)sizeof(CT), ilo = il * (uint32_t)sizeof(CT),
+                   iro = ir * (uint32_t)sizeof(CT);
+    auto ld = [&](const CT *row, uint32_t off) -> CT {
+        return *reinterpret_cast<GlobalPtr<const CT>>(
+            uniform_ptr(reinterpret_cast<const char *>(row)) + off);
     };
-    auto ldv = [&](const CT *row) -> V {
-        const VM m = *reinterpret_cast<GlobalPtr<const VM>>(at(row, xo));
-        V v;
-        v.x = m.x;
-        v.y = m.y;
-        return v;
-    };
-    auto bits = [&](int z, int r) -> uint32_t {
-        const uint32_t c2 = (uint32_t)(nxy * (size_t)z + ro[r]) + xc;  // even: one word
-        return (a.ibits[c2 >> 5] >> (c2 & 31)) & 3u;
+    // interior bit of the lane's entry in row r of plane z
+    auto bit = [&](int z, int r) -> uint32_t {
+        const uint32_t e = (uint32_t)(hxy * (size_t)z + ro[r]) + ic;
+        return (bits_c[e >> 5] >> (e & 31)) & 1u;
     };
     // window at the first plane
-    V C[kSorRows + 2], M[kSorRows], P[kSorRows];
-    uint32_t F = 0;  // bits 2r, 2r + 1: the interior bits of row r's pair
+    CT C[kSorRows + 2], M[kSorRows], P[kSorRows], O[kSorRows];
+    uint32_t F = 0;  // bit r: row r's entry is an interior unknown
     {
-        const CT *pz = plane(zs), *pm = plane(zs - 1), *pp = plane(zs + 1);
-        C[0] = ldv(pz + rlo);
-        C[kSorRows + 1] = ldv(pz + rhi);
+        const CT *pz = plane(oth, zs), *pm = plane(oth, zs - 1), *pp = plane(oth, zs + 1);
+        const CT *qz = plane(own, zs);
+        C[0] = ld(pz + rlo, io);
+        C[kSorRows + 1] = ld(pz + rhi, io);
 #pragma unroll
         for (int r = 0; r < kSorRows; ++r) {
-            C[r + 1] = ldv(pz + ro[r]);
-            M[r] = ldv(pm + ro[r]);
-            P[r] = ldv(pp + ro[r]);
-            F |= bits(zs, r) << (2 * r);
+            C[r + 1] = ld(pz + ro[r], io);
+            M[r] = ld(pm + ro[r], io);
+            P[r] = ld(pp + ro[r], io);
+            O[r] = ld(qz + ro[r], io);
+            F |= bit(zs, r) << r;
         }
     }
     const CT om = (CT)a.omega;
     const CT diag = CT(6.0) + (CT)a.kappa2;
-#pragma unroll 1
     for (int z = zs; z < ze; ++z) {
         if (z > zs) {
             // slide the window one plane up: the plane behind is the old
             // centre, the centre is the old plane ahead plus its two halo
-            // rows, and the new plane ahead is loaded
-            const CT *pz = plane(z), *pp = plane(z + 1);
-            C[0] = ldv(pz + rlo);
-            C[kSorRows + 1] = ldv(pz + rhi);
+            // rows, and the new plane ahead and the own entries are loaded
+            const CT *pz = plane(oth, z), *pp = plane(oth, z + 1), *qz = plane(own, z);
+            C[0] = ld(pz + rlo, io);
+            C[kSorRows + 1] = ld(pz + rhi, io);
             F = 0;
 #pragma unroll
             for (int r = 0; r < kSorRows; ++r) {
                 M[r] = C[r + 1];
                 C[r + 1] = P[r];
-                P[r] = ldv(pp + ro[r]);
-                F |= bits(z, r) << (2 * r);
+                P[r] = ld(pp + ro[r], io);
+                O[r] = ld(qz + ro[r], io);
+                F |= bit(z, r) << r;
             }
         }
-        CT *pz = psi + nxy * (size_t)z;
-        // x - 1 of the pair's first cell and x + 1 of its second: neighbouring
-        // lanes, or a load at the wave's ends (periodic wrap of the row)
-        CT left[kSorRows], right[kSorRows];
+        const CT *pz = oth + hxy * (size_t)z;
+        CT *qz = own + hxy * (size_t)z;
+        // the two x-neighbours: entries i - 1 + p and i + p of the other
+        // colour's row; one is the lane's own, the other the neighbouring
+        // lane's (p is uniform per row), or a load at the wave's ends
+        CT xm[kSorRows], xp[kSorRows];
 #pragma unroll
         for (int r = 0; r < kSorRows; ++r) {
-            left[r] = lane_shift(C[r + 1].y, -1);
-            right[r] = lane_shift(C[r + 1].x, 1);
-            if (act && (lane == 0 || x2 == 0))
-                left[r] = *reinterpret_cast<GlobalPtr<const CT>>(at(pz + ro[r], xlo));
-            if (act && (lane == 63 || x2 + 2 >= g.nx))
-                right[r] = *reinterpret_cast<GlobalPtr<const CT>>(at(pz + ro[r], xro));
+            const int p = (colour + y0 + r + z) & 1;
+            if (p) {
+                xm[r] = C[r + 1];
+                xp[r] = lane_shift(C[r + 1], 1);
+                if (act && (lane == 63 || i + 1 >= hx)) xp[r] = ld(pz + ro[r], iro);
+            } else {
+                xp[r] = C[r + 1];
+                xm[r] = lane_shift(C[r + 1], -1);
+                if (act && (lane == 0 || i == 0)) xm[r] = ld(pz + ro[r], ilo);
+            }
         }
         if (act) {
 #pragma unroll
             for (int r = 0; r < kSorRows; ++r) {
-                const int y = y0 + r;
-                if (y >= g.ny) continue;
-                const int p = (colour + y + z) & 1;
-                if ((F >> (2 * r + p)) & 1u) {
-                    // interior cell: x-, x+, y-, y+, z-, z+
-                    CT nb[6], own;
-                    if (p == 0) {
-                        own = C[r + 1].x;
-                        nb[0] = left[r];
-                        nb[1] = C[r + 1].y;
-                        nb[2] = C[r].x;
-                        nb[3] = C[r + 2].x;
-                        nb[4] = M[r].x;
-                        nb[5] = P[r].x;
-                    } else {
-                        own = C[r + 1].y;
-                        nb[0] = C[r + 1].x;
-                        nb[1] = right[r];
-                        nb[2] = C[r].y;
-                        nb[3] = C[r + 2].y;
-                        nb[4] = M[r].y;
-                        nb[5] = P[r].y;
-                    }
-                    CT sum = CT(0);
+                if (y0 + r >= g.ny || !((F >> r) & 1u)) continue;
+                // interior cell: x-, x+, y-, y+, z-, z+
+                const CT nb[6] = {xm[r], xp[r], C[r], C[r + 2], M[r], P[r]};
+                CT sum = CT(0);
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) sum = sum + nb[k];
-                    const CT rhs = CT(0);
-                    const CT nw = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
-                    if (p == 0) C[r + 1].x = nw;
-                    else C[r + 1].y = nw;
-                    // the whole pair (its other cell unchanged: of the other colour)
-                    VM m;
-                    m.x = C[r + 1].x;
-                    m.y = C[r + 1].y;
-                    *reinterpret_cast<GlobalPtr<VM>>(
-                        uniform_ptr(reinterpret_cast<char *>(pz + ro[r])) + xo) = m;
-                }
+                for (int k = 0; k < 6; ++k) sum = sum + nb[k];
+                const CT rhs = CT(0);
+                const CT nw = (CT(1.0) - om) * O[r] + om * ((rhs + sum) / diag);
+                *reinterpret_cast<GlobalPtr<CT>>(
+                    uniform_ptr(reinterpret_cast<char *>(qz + ro[r])) + io) = nw;
             }
         }
     }
 }
 
-// once per solve: bit c of ibits = cell c is an interior unknown (neither
-// wall, obstacle nor NEAR), 32 cells per word
-__global__ void __launch_bounds__(256) k_interior_bits(Grid g, const uint8_t *flag,
-                                                       uint32_t *ibits) {
+// once per solve (even nx): bit e of colour k's bitmap = the cell of colour k
+// at entry e is an interior unknown (neither wall, obstacle nor NEAR); a
+// thread covers the 64 cells of 32 entries of each colour
+__global__ void __launch_bounds__(256) k_interior_bits_split(Grid g, const uint8_t *flag,
+                                                             uint32_t *ibits) {
     const size_t w = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const size_t c0 = w * 32;
-    if (c0 >= g.N) return;
-    uint32_t bits = 0;
-    if (c0 + 32 <= g.N) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(flag + c0);
-        const uint4 lo = p[0], hi = p[1];
-        const uint32_t v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            const uint32_t f = (v[k >> 2] >> (8 * (k & 3))) & 0xffu;
-            bits |= (f & (kWall | kObst | kNear)) ? 0u : (1u << k);
-        }
-    } else {
-        for (int k = 0; c0 + k < g.N; ++k)
-            bits |= (flag[c0 + k] & (kWall | kObst | kNear)) ? 0u : (1u << k);
+    const size_t e0 = w * 32, half = g.N / 2;
+    if (e0 >= half) return;
+    uint32_t b[2] = {0, 0};
+    const size_t nx = (size_t)g.nx, ny = (size_t)g.ny;
+    for (int k = 0; k < 32 && e0 + k < half; ++k) {
+        const size_t c = 2 * (e0 + k);  // x even: the pair (c, c + 1) is one row's
+        const size_t yz = c / nx;
+        const uint32_t col = (uint32_t)((yz % ny + yz / ny) & 1);  // colour of c
+        const uint8_t f0 = flag[c], f1 = flag[c + 1];
+        if (!(f0 & (kWall | kObst | kNear))) b[col] |= 1u << k;
+        if (!(f1 & (kWall | kObst | kNear))) b[col ^ 1] |= 1u << k;
     }
-    ibits[w] = bits;
+    ibits[w] = b[0];
+    ibits[sor_ibits_words_per_colour(g.N) + w] = b[1];
 }
 
 // the boundary unknowns (NEAR cells) of each colour, listed once per solve
@@ -647,15 +633,18 @@ __device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_
         const CT diag = rows[2 * (base + i)], rhs = rows[2 * (base + i) + 1];
         uint32_t s[6];
         d3q7_neighbours(g, c, s);
+        // the neighbours have the other colour (even periodic extents)
         CT v[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] = (mask >> k) & 1 ? psi[s[k]] : CT(0);
-        const CT own = psi[c];
+        for (int k = 0; k < 6; ++k)
+            v[k] = (mask >> k) & 1 ? psi[psi_slot(g, s[k], (uint32_t)colour ^ 1u)] : CT(0);
+        const size_t pc = psi_slot(g, c, (uint32_t)colour);
+        const CT own = psi[pc];
         CT sum = CT(0);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             if ((mask >> k) & 1) sum = sum + v[k];
-        psi[c] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
+        psi[pc] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
     }
 }
 
@@ -682,7 +671,7 @@ __global__ void __launch_bounds__(kResBlock) k_dha_residual(SorArgs a) {
         const int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
         CT diag, rhs, sum;
         dha_row<CT>(g, x, y, z, fl, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs, sum);
-        const double r = (double)(rhs + sum - diag * psi[c]);
+        const double r = (double)(rhs + sum - diag * psi[psi_slot(g, c, (uint32_t)((x + y + z) & 1))]);
         ss += r * r;
         n += 1.0;
     }
@@ -978,7 +967,20 @@ __global__ void __launch_bounds__(kFBlock) k_sor_fused(SorArgs a, const CT *src,
 template <typename CT>
 __global__ void k_to_f64(Grid g, const CT *psi, double *out) {
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < g.N) out[c] = (double)psi[c];
+    if (c >= g.N) return;
+    const size_t yz = c / (size_t)g.nx, x = c - yz * (size_t)g.nx;
+    const uint32_t col = (uint32_t)((x + yz % (size_t)g.ny + yz / (size_t)g.ny) & 1);
+    out[c] = (double)psi[psi_slot(g, c, col)];
+}
+
+// psi in cell order (input type TI) into the storage order of the compute type
+template <typename TI, typename CT>
+__global__ void k_psi_pack(Grid g, const TI *in, CT *psi) {
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.N) return;
+    const size_t yz = c / (size_t)g.nx, x = c - yz * (size_t)g.nx;
+    const uint32_t col = (uint32_t)((x + yz % (size_t)g.ny + yz / (size_t)g.ny) & 1);
+    psi[psi_slot(g, c, col)] = (CT)in[c];
 }
 
 template <typename CT>
@@ -990,7 +992,8 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const uint32_t nblk = nxb * nyb * (uint32_t)g.nz;
     // the z-marching interior half-sweep (even nx): tile of wx waves along x
     const int wx = a0.wx == 2 || a0.wx == 4 ? (int)a0.wx : 1;
-    const uint32_t vxb = (uint32_t)((g.nx + wx * kSorWaveX - 1) / (wx * kSorWaveX));
+    const int hx = g.nx / 2;  // entries of one colour per row
+    const uint32_t vxb = (uint32_t)((hx + wx * kSorWaveX - 1) / (wx * kSorWaveX));
     const int tyr = (kSorWaves / wx) * kSorRows;
     const uint32_t vyb = (uint32_t)((g.ny + tyr - 1) / tyr);
     const uint32_t vblk = vxb * vyb * (uint32_t)((g.nz + (int)a0.zc - 1) / (int)a0.zc);
@@ -1013,9 +1016,9 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
                            a.nscratch, nseg, a.nlist);
         hipLaunchKernelGGL((k_nlist_rows<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a);
         if (vec) {
-            const size_t words = (g.N + 31) / 32;
-            hipLaunchKernelGGL(k_interior_bits, dim3((uint32_t)((words + 255) / 256)), dim3(256),
-                               0, s, g, a.flag, a.ibits);
+            const size_t words = sor_ibits_words_per_colour(g.N);
+            hipLaunchKernelGGL(k_interior_bits_split, dim3((uint32_t)((words + 255) / 256)),
+                               dim3(256), 0, s, g, a.flag, a.ibits);
         }
     }
     if (with_res) {
@@ -1085,7 +1088,9 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
     *swapped = 0;
     if (a.g.N == 0) return hipSuccess;
     // the fused iteration is switched off until its plane-ring fix has run
-    // on the device: its flag ring shared 4 slots with the values, so the
+    // on the device (it is also written for the plain cell order of psi,
+    // not the colour-split order of even nx): its flag ring shared 4 slots
+    // with the values, so the
     // black phase read the z- flags of a plane already replaced by the
     // prefetch (a stale obstacle flag then indexed zeta with kNone)
     if (fused) return hipErrorNotSupported;
@@ -1096,6 +1101,29 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
     if (precision == LBMEP_FP64)
         return sor_solve_typed<double>(a, max_iter, check_every, fused, s, swapped);
     return sor_solve_typed<float>(a, max_iter, check_every, fused, s, swapped);
+}
+
+hipError_t launch_potential_pack(int precision, const Grid &g, const void *in, int in_dtype,
+                                 void *psi, hipStream_t s) {
+    if (g.N == 0) return hipSuccess;
+    const uint32_t nb = (uint32_t)((g.N + 255) / 256);
+    const bool in64 = in_dtype == LBMEP_DTYPE_F64;
+    if (precision == LBMEP_FP64) {
+        if (in64)
+            hipLaunchKernelGGL((k_psi_pack<double, double>), dim3(nb), dim3(256), 0, s, g,
+                               static_cast<const double *>(in), static_cast<double *>(psi));
+        else
+            hipLaunchKernelGGL((k_psi_pack<float, double>), dim3(nb), dim3(256), 0, s, g,
+                               static_cast<const float *>(in), static_cast<double *>(psi));
+    } else {
+        if (in64)
+            hipLaunchKernelGGL((k_psi_pack<double, float>), dim3(nb), dim3(256), 0, s, g,
+                               static_cast<const double *>(in), static_cast<float *>(psi));
+        else
+            hipLaunchKernelGGL((k_psi_pack<float, float>), dim3(nb), dim3(256), 0, s, g,
+                               static_cast<const float *>(in), static_cast<float *>(psi));
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_potential_to_f64(int precision, const Grid &g, const void *psi, double *out,

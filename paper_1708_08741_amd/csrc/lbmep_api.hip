@@ -552,8 +552,11 @@ static int set_force_common(lbmep_lattice *L, const void *in, int dtype, int on_
         }
         src = tmp;
     }
-    hipError_t e =
-        launch_convert_force(L->precision, src, dtype, L->force, N, N, Ns, ncomp, L->stream);
+    // psi goes into its storage order (colour-split for even nx)
+    hipError_t e = mode == kForcePotential
+                       ? launch_potential_pack(L->precision, L->g, src, dtype, L->force, L->stream)
+                       : launch_convert_force(L->precision, src, dtype, L->force, N, N, Ns, ncomp,
+                                              L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     dev_free(L, tmp);
     if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
@@ -674,7 +677,8 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
         if (dev_alloc(L, &L->sor_nrow, 2 * compute_bytes(L->precision) *
                                            sor_nlist_entries(L->g.N)) != hipSuccess ||
             dev_alloc(L, (void **)&L->sor_nmask, sor_nlist_entries(L->g.N)) != hipSuccess ||
-            dev_alloc(L, (void **)&L->sor_ibits, 4 * ((L->g.N + 31) / 32)) != hipSuccess)
+            dev_alloc(L, (void **)&L->sor_ibits, 4 * 2 * sor_ibits_words_per_colour(L->g.N)) !=
+                hipSuccess)
             return fail(LBMEP_ENOMEM, "solver boundary rows");
         SorCtl c{};
         c.res0 = c.res = -1.0;
@@ -1092,7 +1096,7 @@ int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches) {
 // ---------------------------------------------------------------------------
 
 namespace {
-const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '2'};
+const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '3'};  // 3: psi in storage order
 
 struct Header {
     char magic[8];

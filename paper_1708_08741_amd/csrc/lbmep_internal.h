@@ -61,6 +61,23 @@ struct Grid {
     size_t Ns;  // population stride (N rounded up to a multiple of 128)
 };
 
+// storage order of the EDL potential psi (Ns values of the compute type).
+// For even nx the cells of the two colours of the red-black order
+// ((x + y + z) & 1) are kept apart: colour k in [k Ns / 2, k Ns / 2 + N / 2),
+// cell c at c >> 1 within its colour (the x-pairs (2i, 2i + 1) of a row hold
+// one cell of each colour, so each colour's row is a contiguous run of
+// nx / 2 values).  A half-sweep of one colour then reads the other colour's
+// array and reads and writes its own, instead of all of psi twice.  For
+// odd nx the plain cell order.
+__host__ __device__ __forceinline__ bool psi_split(const Grid &g) { return (g.nx & 1) == 0; }
+__host__ __device__ __forceinline__ size_t psi_slot(const Grid &g, size_t c, uint32_t colour) {
+    return psi_split(g) ? (size_t)colour * (g.Ns >> 1) + (c >> 1) : c;
+}
+__host__ __device__ __forceinline__ size_t psi_slot_xyz(const Grid &g, int x, int y, int z) {
+    const size_t c = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    return psi_slot(g, c, (uint32_t)((x + y + z) & 1));
+}
+
 // workgroups are dealt to the 8 XCDs round-robin; this remaps them so that
 // consecutive segments of a grid (which share cache lines through their
 // neighbour reads) run on the same XCD and its L2.  A permutation of
@@ -232,7 +249,7 @@ struct SorArgs {
     uint32_t *nscratch;        // per-segment counts / offsets of the list build
     void *nrow;                // per list entry: diag and rhs of the row (2 compute values)
     uint8_t *nmask;            // per list entry: bit k = neighbour k is an unknown
-    uint32_t *ibits;           // bit c: cell c is an interior unknown ((N + 31) / 32 words)
+    uint32_t *ibits;           // per colour, bit e: the colour's entry e is an interior unknown
     uint32_t xcd_swizzle;
     uint32_t zc;               // planes per workgroup of the interior half-sweep (>= 1)
     uint32_t wx;               // waves along x of its workgroup tile (1, 2 or 4)
@@ -242,6 +259,8 @@ constexpr int kSorPartials = 8192;
 constexpr int kNearSeg = 8192;
 inline size_t sor_nlist_entries(size_t N) { return N + 2; }
 inline size_t sor_nscratch_entries(size_t N) { return 4 * ((N + kNearSeg - 1) / kNearSeg) + 2; }
+// interior bitmaps of the two colours (even nx): 32 entries per word
+__host__ __device__ inline size_t sor_ibits_words_per_colour(size_t N) { return (N / 2 + 31) / 32; }
 // one solve on the current map: max_iter iterations of (red, black), with
 // rf > 0 a residual before the first and after every check_every-th (and the
 // last) iteration, stopping at res < rf res0 (the host reads the control
@@ -253,6 +272,10 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
                             bool fused, hipStream_t s, int *swapped);
 hipError_t launch_potential_to_f64(int precision, const Grid &g, const void *psi, double *out,
                                    hipStream_t s);
+// psi given in cell order (LBMEP_DTYPE_F32 / F64, device memory) into the
+// storage order (psi_slot) of the compute type
+hipError_t launch_potential_pack(int precision, const Grid &g, const void *in, int in_dtype,
+                                 void *psi, hipStream_t s);
 
 // deterministic FP64 invariants: partial sums per block, then one block
 hipError_t launch_invariants(int precision, const Grid &g, const void *f, const uint8_t *flag,

@@ -13,7 +13,8 @@
 // 2 b_p - psi_c; walls and non-periodic edges are homogeneous Neumann
 // boundaries (they count psi_c).  Shared by the sweep and the macroscopic
 // read-out; the operation order is fixed, so the FP64 form rounds like a
-// plain CPU evaluation.
+// plain CPU evaluation.  psi is addressed through psi_slot (colour-split
+// order for even nx), with each cell's colour from its own coordinates.
 #pragma once
 #include "lbmep_internal.h"
 
@@ -37,14 +38,15 @@ __device__ __forceinline__ CT psi_bc(const Grid &g, int x, int y, int z, int dx,
     }
     const size_t s = (size_t)v[0] + (size_t)g.nx * ((size_t)v[1] + (size_t)g.ny * (size_t)v[2]);
     if (flag[s] & kWall) return centre;
+    const size_t ps = psi_slot(g, s, (uint32_t)((v[0] + v[1] + v[2]) & 1));
     if (owner) {
         const uint32_t p = owner[s];
         if (p != kNone) {
-            const CT b = zeta ? (CT)zeta[p] : psi[s];
+            const CT b = zeta ? (CT)zeta[p] : psi[ps];
             return CT(2.0) * b - centre;
         }
     }
-    return psi[s];
+    return psi[ps];
 }
 
 // the body force at fluid cell (x, y, z) with flag fl
@@ -54,8 +56,7 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
                                                 const uint32_t *owner, const double *zeta,
                                                 CT keps, CT E0, CT E1, CT E2, CT &f0, CT &f1,
                                                 CT &f2) {
-    const size_t c = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    const CT pc = psi[c];
+    const CT pc = psi[psi_slot_xyz(g, x, y, z)];
     CT g0, g1, g2;
     if (!(fl & kNear)) {
         // every neighbour is a fluid cell inside the grid (periodic wrap)
@@ -66,9 +67,8 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
         CT s0 = CT(0), s1 = CT(0), s2 = CT(0);
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-            const size_t n = (size_t)xs[kCx[q] + 1] +
-                             (size_t)g.nx * ((size_t)ys[kCy[q] + 1] + (size_t)g.ny * (size_t)zs[kCz[q] + 1]);
-            const CT t = (CT)wq(q) * psi[n];
+            const CT t = (CT)wq(q) * psi[psi_slot_xyz(g, xs[kCx[q] + 1], ys[kCy[q] + 1],
+                                                      zs[kCz[q] + 1])];
             if (kCx[q] > 0) s0 = s0 + t;
             if (kCx[q] < 0) s0 = s0 - t;
             if (kCy[q] > 0) s1 = s1 + t;
