@@ -56,19 +56,34 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
                                                 const uint32_t *owner, const double *zeta,
                                                 CT keps, CT E0, CT E1, CT E2, CT &f0, CT &f1,
                                                 CT &f2) {
-    const CT pc = psi[psi_slot_xyz(g, x, y, z)];
-    CT g0, g1, g2;
+    CT pc, g0, g1, g2;
     if (!(fl & kNear)) {
         // every neighbour is a fluid cell inside the grid (periodic wrap)
         const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
         const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
         const int xs[3] = {xm, x, xp}, ys[3] = {ym, y, yp}, zs[3] = {zm, z, zp};
+        // storage slots of the neighbours: a base per row (y', z') and an
+        // offset per column x' (psi_slot written out for the 3 x 3 x 3 block)
+        const bool split = psi_split(g);
+        const size_t half = split ? (g.Ns >> 1) : 0;
+        const size_t rowlen = split ? (size_t)(g.nx >> 1) : (size_t)g.nx;
+        size_t xo[3];
+        uint32_t xpar[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            xo[i] = split ? (size_t)(xs[i] >> 1) : (size_t)xs[i];
+            xpar[i] = (uint32_t)xs[i] & 1u;
+        }
+        auto slot = [&](int i, int j, int k) -> size_t {
+            const size_t rb = rowlen * ((size_t)ys[j] + (size_t)g.ny * (size_t)zs[k]) + xo[i];
+            return split && ((xpar[i] ^ (uint32_t)(ys[j] + zs[k])) & 1u) ? rb + half : rb;
+        };
+        pc = psi[slot(1, 1, 1)];
         CT s0 = CT(0), s1 = CT(0), s2 = CT(0);
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-            const CT t = (CT)wq(q) * psi[psi_slot_xyz(g, xs[kCx[q] + 1], ys[kCy[q] + 1],
-                                                      zs[kCz[q] + 1])];
+            const CT t = (CT)wq(q) * psi[slot(kCx[q] + 1, kCy[q] + 1, kCz[q] + 1)];
             if (kCx[q] > 0) s0 = s0 + t;
             if (kCx[q] < 0) s0 = s0 - t;
             if (kCy[q] > 0) s1 = s1 + t;
@@ -81,6 +96,7 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
         g1 = s1 * CT(3.0);
         g2 = s2 * CT(3.0);
     } else {
+        pc = psi[psi_slot_xyz(g, x, y, z)];
         g0 = (psi_bc(g, x, y, z, 1, 0, 0, psi, flag, owner, zeta, pc) -
               psi_bc(g, x, y, z, -1, 0, 0, psi, flag, owner, zeta, pc)) * CT(0.5);
         g1 = (psi_bc(g, x, y, z, 0, 1, 0, psi, flag, owner, zeta, pc) -
