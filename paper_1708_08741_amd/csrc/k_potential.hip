@@ -20,12 +20,16 @@
 // thread.  Terms are formed in the order x-, x+, y-, y+, z-, z+, so the
 // FP64 kernel rounds like a plain CPU evaluation of the same rows.
 //
+// psi is stored colour-split for even nx (psi_slot: colour k's cells at
+// [k Ns / 2, k Ns / 2 + N / 2), cell c at c >> 1), in cell order for odd nx.
+//
 // Two implementations of an iteration, bitwise identical:
-//   * in use: one launch per colour, in place (each colour streams psi
-//     through HBM once): for even nx k_sor_half_vec, whose workgroups march
-//     through chunks of z planes with the three-plane window in registers
-//     and relax the listed boundary cells in the same grid; for odd nx
-//     k_sor_half, then k_sor_near for the listed cells;
+//   * in use: one launch per colour, in place: for even nx k_sor_half_vec,
+//     whose workgroups march through chunks of z planes with the other
+//     colour's three-plane window in registers (the other colour read once,
+//     the own colour read and written once) and relax the listed boundary
+//     cells in the same grid; for odd nx k_sor_half, then k_sor_near for the
+//     listed cells;
 //   * k_sor_fused (switched off, see launch_sor_solve): one launch per
 //     iteration from psi into a second buffer.  A workgroup owns a 64 x 16 tile of (x, y) and a chunk of z
 //     planes and marches through its planes with rings of planes in LDS:

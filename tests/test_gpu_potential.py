@@ -204,6 +204,22 @@ def test_checkpoint_keeps_the_potential(lb, tmp_path):
     assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all()
 
 
+@pytest.mark.parametrize("shape", [(8, 6, 4), (7, 6, 4), (130, 3, 5), (2, 1, 1), (1, 1, 1)])
+def test_potential_storage_round_trip(lb, shape):
+    """psi goes into its storage order on upload (colour-split for even nx,
+    cell order for odd nx) and comes back in cell order: FP64 bitwise, FP32
+    equal to the float32 rounding of the input."""
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal(shape[::-1])
+    for prec in (lb.FP64, lb.FP32DEV):
+        g = lb.Lattice(shape, precision=prec)
+        g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0))
+        out = g.potential()
+        g.close()
+        want = psi if prec == lb.FP64 else psi.astype(np.float32).astype(np.float64)
+        assert np.array_equal(out.reshape(psi.shape), want), prec
+
+
 def test_set_particles_drops_zeta(lb):
     """The surface potentials belong to the particle table they came with:
     after set_particles the obstacle cells give psi's own value."""
