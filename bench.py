@@ -476,10 +476,10 @@ def main():
             "sor_GBps": round(sor_bytes / (it_ms / 1e3) / 1e9, 1),
             "sor_roofline_frac": round(sor_bytes / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "sor_bytes_per_cell_iteration": 2 * es + 1,
-            "sor_kernel": "k_sor_half_vec: one colour per launch, two per iteration; "
-                          "workgroups of 512 x 4 cells march through chunks of 4 z planes "
-                          "in XCD-contiguous order (interior cells; the listed boundary "
-                          "cells in the same grid)",
+            "sor_kernel": "k_sor_half_vec: one colour per launch, two per iteration, on "
+                          "colour-split psi; tiles of 256 entries (512 cells) x 8 rows "
+                          "march through chunks of 8 z planes in XCD-contiguous order "
+                          "(interior cells; the listed boundary cells in the same grid)",
             "sor_traffic_per_half_sweep": sor_traffic() if es == 4 else None,
             "steps": args.coupled_steps,
         }

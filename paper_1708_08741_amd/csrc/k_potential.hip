@@ -288,10 +288,11 @@ constexpr int kSorWaveX = 64;  // entries (of one colour) of a wave's row segmen
 // workgroup tile: WX waves along x, kSorWaves / WX along y
 template <int WX>
 constexpr int sor_tile_x() { return WX * kSorWaveX; }
-template <int WX>
-constexpr int sor_tile_y() { return (kSorWaves / WX) * kSorRows; }
+template <int WX, int RW>
+constexpr int sor_tile_y() { return (kSorWaves / WX) * RW; }
 
-template <typename CT, int WX>
+// RW: rows per thread (4 or 8)
+template <typename CT, int WX, int RW>
 __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colour, int count,
                                                             uint32_t nxb, uint32_t nyb,
                                                             uint32_t ninterior) {
@@ -319,7 +320,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     // plus the lane's 32-bit entry offset
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wx = w % WX, wy = w / WX;
-    const int y0 = (int)yb * sor_tile_y<WX>() + wy * kSorRows;
+    const int y0 = (int)yb * sor_tile_y<WX, RW>() + wy * RW;
     const int zs = (int)zb * (int)a.zc;
     const int ze = min(zs + (int)a.zc, g.nz);
     const int hx = g.nx >> 1;  // entries of one colour per row
@@ -333,15 +334,15 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     CT *own = psi + (size_t)colour * (g.Ns >> 1);
     const CT *oth = psi + (size_t)(colour ^ 1) * (g.Ns >> 1);
     const uint32_t *bits_c = a.ibits + (size_t)colour * sor_ibits_words_per_colour(g.N);
-    // rows y0 .. y0 + kSorRows - 1 and the two halo rows (in entries),
+    // rows y0 .. y0 + RW - 1 and the two halo rows (in entries),
     // wrapped into the grid (rows a cell needs wrap once; the rows past ny of
     // the last workgroup are the wrapped y + 1 neighbours of its last valid
     // row after the window slides, so they wrap too)
-    size_t ro[kSorRows];
+    size_t ro[RW];
 #pragma unroll
-    for (int r = 0; r < kSorRows; ++r) ro[r] = hxs * (size_t)((y0 + r) % g.ny);
+    for (int r = 0; r < RW; ++r) ro[r] = hxs * (size_t)((y0 + r) % g.ny);
     const size_t rlo = hxs * (size_t)(((y0 - 1) % g.ny + g.ny) % g.ny);
-    const size_t rhi = hxs * (size_t)((y0 + kSorRows) % g.ny);
+    const size_t rhi = hxs * (size_t)((y0 + RW) % g.ny);
     auto plane = [&](const CT *base, int z) -> const CT * {
         const int zw = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
         return base + hxy * (size_t)zw;
@@ -359,15 +360,15 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         return (bits_c[e >> 5] >> (e & 31)) & 1u;
     };
     // window at the first plane
-    CT C[kSorRows + 2], M[kSorRows], P[kSorRows], O[kSorRows];
+    CT C[RW + 2], M[RW], P[RW], O[RW];
     uint32_t F = 0;  // bit r: row r's entry is an interior unknown
     {
         const CT *pz = plane(oth, zs), *pm = plane(oth, zs - 1), *pp = plane(oth, zs + 1);
         const CT *qz = plane(own, zs);
         C[0] = ld(pz + rlo, io);
-        C[kSorRows + 1] = ld(pz + rhi, io);
+        C[RW + 1] = ld(pz + rhi, io);
 #pragma unroll
-        for (int r = 0; r < kSorRows; ++r) {
+        for (int r = 0; r < RW; ++r) {
             C[r + 1] = ld(pz + ro[r], io);
             M[r] = ld(pm + ro[r], io);
             P[r] = ld(pp + ro[r], io);
@@ -384,10 +385,10 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
             // rows, and the new plane ahead and the own entries are loaded
             const CT *pz = plane(oth, z), *pp = plane(oth, z + 1), *qz = plane(own, z);
             C[0] = ld(pz + rlo, io);
-            C[kSorRows + 1] = ld(pz + rhi, io);
+            C[RW + 1] = ld(pz + rhi, io);
             F = 0;
 #pragma unroll
-            for (int r = 0; r < kSorRows; ++r) {
+            for (int r = 0; r < RW; ++r) {
                 M[r] = C[r + 1];
                 C[r + 1] = P[r];
                 P[r] = ld(pp + ro[r], io);
@@ -400,9 +401,9 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         // the two x-neighbours: entries i - 1 + p and i + p of the other
         // colour's row; one is the lane's own, the other the neighbouring
         // lane's (p is uniform per row), or a load at the wave's ends
-        CT xm[kSorRows], xp[kSorRows];
+        CT xm[RW], xp[RW];
 #pragma unroll
-        for (int r = 0; r < kSorRows; ++r) {
+        for (int r = 0; r < RW; ++r) {
             const int p = (colour + y0 + r + z) & 1;
             if (p) {
                 xm[r] = C[r + 1];
@@ -416,7 +417,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
         }
         if (act) {
 #pragma unroll
-            for (int r = 0; r < kSorRows; ++r) {
+            for (int r = 0; r < RW; ++r) {
                 if (y0 + r >= g.ny || !((F >> r) & 1u)) continue;
                 // interior cell: x-, x+, y-, y+, z-, z+
                 const CT nb[6] = {xm[r], xp[r], C[r], C[r + 2], M[r], P[r]};
@@ -996,9 +997,10 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const uint32_t nblk = nxb * nyb * (uint32_t)g.nz;
     // the z-marching interior half-sweep (even nx): tile of wx waves along x
     const int wx = a0.wx == 2 || a0.wx == 4 ? (int)a0.wx : 1;
+    const int rw = a0.rows == 8 ? 8 : 4;
     const int hx = g.nx / 2;  // entries of one colour per row
     const uint32_t vxb = (uint32_t)((hx + wx * kSorWaveX - 1) / (wx * kSorWaveX));
-    const int tyr = (kSorWaves / wx) * kSorRows;
+    const int tyr = (kSorWaves / wx) * rw;
     const uint32_t vyb = (uint32_t)((g.ny + tyr - 1) / tyr);
     const uint32_t vblk = vxb * vyb * (uint32_t)((g.nz + (int)a0.zc - 1) / (int)a0.zc);
     // 2-vector rows: even nx keeps every pair aligned
@@ -1040,15 +1042,19 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
                 if (vec) {
                     // kNearInVec blocks for the boundary list, then the interior blocks
                     const dim3 grid(vblk + kNearInVec), blk(kSorBlock);
-                    if (wx == 4)
-                        hipLaunchKernelGGL((k_sor_half_vec<CT, 4>), grid, blk, 0, s, a, col, col,
-                                           vxb, vyb, vblk);
-                    else if (wx == 2)
-                        hipLaunchKernelGGL((k_sor_half_vec<CT, 2>), grid, blk, 0, s, a, col, col,
-                                           vxb, vyb, vblk);
-                    else
-                        hipLaunchKernelGGL((k_sor_half_vec<CT, 1>), grid, blk, 0, s, a, col, col,
-                                           vxb, vyb, vblk);
+#define LBMEP_SOR_VEC(WX, RW)                                                              \
+    hipLaunchKernelGGL((k_sor_half_vec<CT, WX, RW>), grid, blk, 0, s, a, col, col, vxb, vyb, \
+                       vblk)
+                    if (rw == 8) {
+                        if (wx == 4) LBMEP_SOR_VEC(4, 8);
+                        else if (wx == 2) LBMEP_SOR_VEC(2, 8);
+                        else LBMEP_SOR_VEC(1, 8);
+                    } else {
+                        if (wx == 4) LBMEP_SOR_VEC(4, 4);
+                        else if (wx == 2) LBMEP_SOR_VEC(2, 4);
+                        else LBMEP_SOR_VEC(1, 4);
+                    }
+#undef LBMEP_SOR_VEC
                 } else {
                     hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a,
                                        col, col, nxb, nyb);

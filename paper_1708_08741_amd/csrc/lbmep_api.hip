@@ -334,6 +334,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         if (c == 1 || c == 2 || c == 4) L->sor_wx = c;
     }
     if (const char *e = std::getenv("LBMEP_SOR_XCD")) L->sor_xcd = std::atoi(e) != 0;
+    if (const char *e = std::getenv("LBMEP_SOR_ROWS")) {
+        const int c = std::atoi(e);
+        if (c == 4 || c == 8) L->sor_rows = c;
+    }
     if (const char *e = std::getenv("LBMEP_BLOCK_X")) {
         const int b = std::atoi(e);
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
@@ -633,6 +637,7 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.xcd_swizzle = (uint32_t)L->sor_xcd;
     a.zc = (uint32_t)L->sor_zc;
     a.wx = (uint32_t)L->sor_wx;
+    a.rows = (uint32_t)L->sor_rows;
     return a;
 }
 
