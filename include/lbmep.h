@@ -127,7 +127,8 @@ int lbmep_set_charge_force(lbmep_lattice *L, const void *rho_e, int dtype, const
                            int on_device);
 
 /* Set the electric body force of the double layer computed from the EDL
- * potential psi (N values of dtype, kept in the compute precision) in the
+ * potential psi (N values of dtype in cell order, x fastest; the library
+ * keeps them in the compute precision and in its own storage order) in the
  * sweep itself (Sec. "Computing Electrostatic Forces on Fluid and
  * Particles"): at every fluid cell f_b = rho_e (E - grad psi) with the
  * Debye-Hueckel charge density rho_e = -kappa2_eps * psi (Eq. ChrgDensDHA;
@@ -178,8 +179,8 @@ int lbmep_solve_potential(lbmep_lattice *L, int32_t *iters, double res[2]);
  * Errors: EINVAL (null, no solver configured). */
 int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]);
 
-/* Copy psi (N values, FP64) to host or device memory.  Errors: EINVAL (null,
- * no potential set), ENOMEM, EDEVICE. */
+/* Copy psi (N values, FP64, cell order with x fastest) to host or device
+ * memory.  Errors: EINVAL (null, no potential set), ENOMEM, EDEVICE. */
 int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device);
 
 /* Free-slip faces (Sec. "Lattice Boltzmann Method with Forcing": no-slip
