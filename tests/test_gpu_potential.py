@@ -49,6 +49,10 @@ def _fluid(o):
     ((131, 7, 6), (True, False, True), True, False, 2),
     ((9, 8, 7), (False, False, False), False, False, 3),
     ((1, 1, 1), (True, True, True), False, False, 4),
+    # even nx (colour-split psi) with odd periodic extents: across the wrap a
+    # neighbour has the cell's own colour
+    ((12, 9, 7), (True, True, True), True, True, 5),
+    ((20, 7, 10), (True, True, False), False, True, 6),
 ])
 def test_force_at_rest(lb, oracle_mod, shape, periodic, walls, with_zeta, seed):
     """At rest (rho = 1, u = 0) the read-out velocity is f_b / 2 at fluid
