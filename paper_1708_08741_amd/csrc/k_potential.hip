@@ -222,27 +222,6 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, i
     }
 }
 
-// vector form of the interior half-sweep for even nx: the pairs (x2, x2 + 1)
-// are loaded as one aligned 2-vector for the rows y0 - 1 .. y0 + kSorRows of
-// the plane and the rows y0 .. y0 + kSorRows - 1 of the planes z -+ 1; the
-// x -+ 1 values come from the neighbouring lanes (the wave's end lanes load
-// theirs), the y -+ 1 values from the thread's own neighbouring rows.  Every
-// load and store is a whole coalesced 2-vector; a pair is written only when
-// its cell of this colour is an interior unknown.  Same arithmetic as
-// k_sor_half.
-template <typename CT>
-struct Vec2;
-template <>
-struct Vec2<float> {
-    using T = float2;
-    using M = float __attribute__((ext_vector_type(2)));  // memory access type
-};
-template <>
-struct Vec2<double> {
-    using T = double2;
-    using M = double __attribute__((ext_vector_type(2)));
-};
-
 template <typename CT>
 __device__ __forceinline__ CT lane_shift(CT v, int delta) {
     // value of lane (lane + delta) of the wave

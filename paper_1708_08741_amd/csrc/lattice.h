@@ -85,10 +85,10 @@ struct lbmep_lattice {
     int red_blocks = 0;
     int block_x = 128;
     int cpt = 1;  // cells per thread of the sweep (consecutive rows)
-    int sor_zc = 8;   // planes per workgroup of the SOR's interior half-sweep
+    int sor_zc = 8;   // planes per workgroup of the SOR's interior half-sweep (set per precision)
     int sor_wx = 4;   // waves along x of its workgroup tile (1, 2, 4)
     int sor_xcd = 1;  // XCD-contiguous tile order
-    int sor_rows = 8; // rows per thread of the tile (4, 8)
+    int sor_rows = 8; // rows per thread of the tile (4, 8; set per precision)
     int xcd_swizzle = 1;
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     bool timing = false;

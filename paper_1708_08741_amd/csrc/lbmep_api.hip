@@ -325,6 +325,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         const int c = std::atoi(e);
         if (c == 1 || c == 2) L->cpt = c;
     }
+    // SOR tiles: 8 rows per thread and 8-plane chunks for FP32 psi; FP64 psi
+    // needs twice the registers per row, so 4 and 4 (measured best of each)
+    L->sor_rows = L->precision == LBMEP_FP64 ? 4 : 8;
+    L->sor_zc = L->precision == LBMEP_FP64 ? 4 : 8;
     if (const char *e = std::getenv("LBMEP_SOR_ZC")) {
         const int c = std::atoi(e);
         if (c >= 1 && c <= 1024) L->sor_zc = c;
