@@ -982,7 +982,7 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const int tyr = (kSorWaves / wx) * rw;
     const uint32_t vyb = (uint32_t)((g.ny + tyr - 1) / tyr);
     const uint32_t vblk = vxb * vyb * (uint32_t)((g.nz + (int)a0.zc - 1) / (int)a0.zc);
-    // 2-vector rows: even nx keeps every pair aligned
+    // even nx: psi is colour-split, the z-marching tiles relax the interior
     const bool vec = (g.nx % 2) == 0;
     const int ntx = (g.nx + kFTX - 1) / kFTX, nty = (g.ny + kFTY - 1) / kFTY;
     const int ntz = (g.nz + kFZC - 1) / kFZC;

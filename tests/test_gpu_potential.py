@@ -295,9 +295,9 @@ def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, wit
     """One solve (fixed count, or to a residual reduction checked every 3
     iterations): FP64 psi, iteration count and residual norms equal to the
     oracle's (1e-12); FP32 psi within 1e-5 of max |psi|.  Ragged x extents
-    (odd: the scalar rows; even: the 2-vector rows, over several workgroups
-    and waves per row), walls, particles with and without surface
-    potentials, Neumann edges."""
+    (odd: the scalar rows in cell order; even: the z-marching tiles on the
+    colour-split psi, several tiles per row), walls, particles with and
+    without surface potentials, Neumann edges."""
     psi, fl, X, R, zeta = _sor_case(shape, periodic, walls, n, with_zeta, seed)
     kappa2, omega, iters = 0.3, 1.7, 40
     o = oracle_mod.Oracle(shape, periodic)
