@@ -555,7 +555,10 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_write(Grid g, const uint8_
 
 // the boundary unknowns of one colour, from its list (fixed grid, strided)
 constexpr int kNearGrid = 2048;
-constexpr int kNearInVec = 1024;  // list blocks appended to a vector half-sweep
+// list blocks in a vector half-sweep (default; measured at 512^3 with 4096
+// spheres: 64 / 128 / 256 / 1024 / 8192 blocks -> 0.449 / 0.442 / 0.422 /
+// 0.433 / 0.445 ms per iteration)
+constexpr int kNearInVec = 256;
 
 // global indices of the six D3Q7 neighbours (periodic wrap; a neighbour
 // beyond a non-periodic edge gets the cell itself, never used)
@@ -1020,7 +1023,8 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
             for (int col = 0; col < 2; ++col) {
                 if (vec) {
                     // kNearInVec blocks for the boundary list, then the interior blocks
-                    const dim3 grid(vblk + kNearInVec), blk(kSorBlock);
+                    const uint32_t nlb = a0.near_blocks ? a0.near_blocks : (uint32_t)kNearInVec;
+                    const dim3 grid(vblk + nlb), blk(kSorBlock);
 #define LBMEP_SOR_VEC(WX, RW)                                                              \
     hipLaunchKernelGGL((k_sor_half_vec<CT, WX, RW>), grid, blk, 0, s, a, col, col, vxb, vyb, \
                        vblk)

@@ -89,6 +89,7 @@ struct lbmep_lattice {
     int sor_wx = 4;   // waves along x of its workgroup tile (1, 2, 4)
     int sor_xcd = 1;  // XCD-contiguous tile order
     int sor_rows = 8; // rows per thread of the tile (4, 8; set per precision)
+    int sor_near_blocks = 0;  // workgroups of the SOR's boundary list part (0: default)
     int xcd_swizzle = 1;
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     bool timing = false;

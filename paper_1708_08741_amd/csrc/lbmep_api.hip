@@ -338,6 +338,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         if (c == 1 || c == 2 || c == 4) L->sor_wx = c;
     }
     if (const char *e = std::getenv("LBMEP_SOR_XCD")) L->sor_xcd = std::atoi(e) != 0;
+    if (const char *e = std::getenv("LBMEP_SOR_NEARBLK")) {
+        const int c = std::atoi(e);
+        if (c >= 8 && c <= 65536 && c % 8 == 0) L->sor_near_blocks = c;
+    }
     if (const char *e = std::getenv("LBMEP_SOR_ROWS")) {
         const int c = std::atoi(e);
         if (c == 4 || c == 8) L->sor_rows = c;
@@ -642,6 +646,7 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.zc = (uint32_t)L->sor_zc;
     a.wx = (uint32_t)L->sor_wx;
     a.rows = (uint32_t)L->sor_rows;
+    a.near_blocks = (uint32_t)L->sor_near_blocks;
     return a;
 }
 

@@ -254,6 +254,7 @@ struct SorArgs {
     uint32_t zc;               // planes per workgroup of the interior half-sweep (>= 1)
     uint32_t wx;               // waves along x of its workgroup tile (1, 2 or 4)
     uint32_t rows;             // rows per thread of the tile (4 or 8)
+    uint32_t near_blocks;      // workgroups of the boundary list part (0: default; % 8 == 0)
 };
 constexpr int kSorPartials = 8192;
 // the boundary lists are built per segment of kNearSeg cells
