@@ -378,20 +378,24 @@ def test_sor_plane_chunks_identical(lb, monkeypatch, shape, periodic, n, precisi
     """The interior half-sweep marches each workgroup through a chunk of z
     planes (LBMEP_SOR_ZC planes, the window of three planes in registers):
     every chunk size, workgroup tile (LBMEP_SOR_WX waves along x,
-    LBMEP_SOR_ROWS rows per thread) and block order (LBMEP_SOR_XCD) gives
+    LBMEP_SOR_ROWS rows per thread), block order (LBMEP_SOR_XCD) and
+    workgroup count of the boundary list part (LBMEP_SOR_NEARBLK) gives
     bitwise the same psi -- one plane per
     workgroup, chunks with ragged tails, one chunk over the whole grid --
     with several row segments and tiles with ragged ends, periodic wrap in
     z and y, walls and particles."""
     psi, fl, X, R, zeta = _sor_case(shape, periodic, True, n, True, 11)
     ref = None
-    for zc, wx, xcd, rows in (("1", "1", "0", "4"), ("3", "1", "1", "4"), ("8", "2", "0", "4"),
-                              ("1024", "4", "1", "4"), ("5", "4", "0", "4"), ("8", "1", "1", "4"),
-                              ("4", "4", "1", "8"), ("3", "1", "0", "8"), ("16", "2", "1", "8")):
+    for zc, wx, xcd, rows, nblk in (("1", "1", "0", "4", "8"), ("3", "1", "1", "4", "1024"),
+                                    ("8", "2", "0", "4", "256"), ("1024", "4", "1", "4", "64"),
+                                    ("5", "4", "0", "4", "2048"), ("8", "1", "1", "4", "256"),
+                                    ("4", "4", "1", "8", "8"), ("3", "1", "0", "8", "512"),
+                                    ("16", "2", "1", "8", "256")):
         monkeypatch.setenv("LBMEP_SOR_ZC", zc)
         monkeypatch.setenv("LBMEP_SOR_WX", wx)
         monkeypatch.setenv("LBMEP_SOR_XCD", xcd)
         monkeypatch.setenv("LBMEP_SOR_ROWS", rows)
+        monkeypatch.setenv("LBMEP_SOR_NEARBLK", nblk)
         g = lb.Lattice(shape, periodic, precision=precision)
         g.set_flags(fl)
         g.set_particles(X, R, np.zeros((n, 3)))
