@@ -412,26 +412,125 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     }
 }
 
-// once per solve (even nx): bit e of colour k's bitmap = the cell of colour k
-// at entry e is an interior unknown (neither wall, obstacle nor NEAR); a
-// thread covers the 64 cells of 32 entries of each colour
+// a boundary unknown: a NEAR cell that is neither wall nor obstacle
+__device__ __forceinline__ bool near_unknown(uint8_t f) {
+    return (f & kNear) && !(f & (kWall | kObst));
+}
+
+// once per solve (even nx): bit e of colour k's interior bitmap = the cell of
+// colour k at entry e is an interior unknown (neither wall, obstacle nor
+// NEAR); of its boundary bitmap = that cell is a boundary unknown.  A thread
+// covers the 64 cells of 32 entries of each colour, read as four 16-byte
+// loads (the flag buffer is padded to 4096 cells; entries past N/2 are not
+// taken); a pair (x even, x + 1) has the colours (y + z) & 1 and its flip,
+// and the row parity is recomputed only where the pairs cross into a new row.
 __global__ void __launch_bounds__(256) k_interior_bits_split(Grid g, const uint8_t *flag,
                                                              uint32_t *ibits) {
+    const size_t W = sor_ibits_words_per_colour(g.N);
     const size_t w = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const size_t e0 = w * 32, half = g.N / 2;
-    if (e0 >= half) return;
-    uint32_t b[2] = {0, 0};
+    if (w >= W) return;
+    const size_t e0 = w * 32, half = g.N / 2, c0 = 2 * e0;
+    const uint4 *fp = reinterpret_cast<const uint4 *>(flag + c0);
+    const uint4 q0 = fp[0], q1 = fp[1], q2 = fp[2], q3 = fp[3];
+    const uint32_t fw[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                             q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
     const size_t nx = (size_t)g.nx, ny = (size_t)g.ny;
-    for (int k = 0; k < 32 && e0 + k < half; ++k) {
-        const size_t c = 2 * (e0 + k);  // x even: the pair (c, c + 1) is one row's
-        const size_t yz = c / nx;
-        const uint32_t col = (uint32_t)((yz % ny + yz / ny) & 1);  // colour of c
-        const uint8_t f0 = flag[c], f1 = flag[c + 1];
-        if (!(f0 & (kWall | kObst | kNear))) b[col] |= 1u << k;
-        if (!(f1 & (kWall | kObst | kNear))) b[col ^ 1] |= 1u << k;
+    size_t yz = c0 / nx, x = c0 - yz * nx;
+    uint32_t rp = (uint32_t)((yz % ny + yz / ny) & 1);  // colour of the pair's first cell
+    uint32_t b[2] = {0, 0}, nb[2] = {0, 0};
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        if (e0 + k >= half) break;
+        const uint32_t f0 = (fw[k >> 1] >> (16 * (k & 1))) & 0xffu;
+        const uint32_t f1 = (fw[k >> 1] >> (16 * (k & 1) + 8)) & 0xffu;
+        if (!(f0 & (kWall | kObst | kNear))) b[rp] |= 1u << k;
+        if (!(f1 & (kWall | kObst | kNear))) b[rp ^ 1] |= 1u << k;
+        if (near_unknown((uint8_t)f0)) nb[rp] |= 1u << k;
+        if (near_unknown((uint8_t)f1)) nb[rp ^ 1] |= 1u << k;
+        x += 2;
+        if (x >= nx) {  // nx even: the pairs end exactly at the row end
+            x = 0;
+            ++yz;
+            rp = (uint32_t)((yz % ny + yz / ny) & 1);
+        }
     }
     ibits[w] = b[0];
-    ibits[sor_ibits_words_per_colour(g.N) + w] = b[1];
+    ibits[W + w] = b[1];
+    ibits[2 * W + w] = nb[0];
+    ibits[3 * W + w] = nb[1];
+}
+
+// even nx: the boundary lists from the boundary bitmaps.  A list segment of
+// kNearSeg cells is kNearSeg / 64 words of each colour; one workgroup per
+// segment, one thread per word.
+constexpr int kWordsPerSeg = kNearSeg / 64;
+static_assert(kNearSeg % 64 == 0, "segments of whole words");
+
+// counts of one segment per colour: scratch[2 s + colour]
+__global__ void __launch_bounds__(kWordsPerSeg) k_nlist_count_bits(Grid g, const uint32_t *ibits,
+                                                                   uint32_t *scratch) {
+    const size_t W = sor_ibits_words_per_colour(g.N);
+    const size_t w = (size_t)blockIdx.x * kWordsPerSeg + threadIdx.x;
+    __shared__ uint32_t t[2][kWordsPerSeg];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        t[k][threadIdx.x] = w < W ? (uint32_t)__popc(ibits[(2 + k) * W + w]) : 0u;
+    __syncthreads();
+    for (int h = kWordsPerSeg / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            t[0][threadIdx.x] += t[0][threadIdx.x + h];
+            t[1][threadIdx.x] += t[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        scratch[2 * blockIdx.x] = t[0][0];
+        scratch[2 * blockIdx.x + 1] = t[1][0];
+    }
+}
+
+// each segment writes its boundary unknowns of both colours in increasing
+// cell order: the segment's offset (k_nlist_scan), the set bits of the
+// words before this one, the set bits below each bit
+__global__ void __launch_bounds__(kWordsPerSeg) k_nlist_write_bits(Grid g, const uint32_t *ibits,
+                                                                   const uint32_t *scratch,
+                                                                   uint32_t nseg, uint32_t *list) {
+    const size_t W = sor_ibits_words_per_colour(g.N);
+    const size_t half = g.N / 2 + 1;
+    const uint32_t s = blockIdx.x;
+    const size_t w = (size_t)s * kWordsPerSeg + threadIdx.x;
+    uint32_t word[2];
+    __shared__ uint32_t t[2][kWordsPerSeg];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        word[k] = w < W ? ibits[(2 + k) * W + w] : 0u;
+        t[k][threadIdx.x] = (uint32_t)__popc(word[k]);
+    }
+    __syncthreads();
+    // inclusive Hillis-Steele scan of both colours' counts
+    for (int d = 1; d < kWordsPerSeg; d <<= 1) {
+        const uint32_t v0 = threadIdx.x >= (unsigned)d ? t[0][threadIdx.x - d] : 0u;
+        const uint32_t v1 = threadIdx.x >= (unsigned)d ? t[1][threadIdx.x - d] : 0u;
+        __syncthreads();
+        t[0][threadIdx.x] += v0;
+        t[1][threadIdx.x] += v1;
+        __syncthreads();
+    }
+    const size_t nx = (size_t)g.nx, ny = (size_t)g.ny;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        uint32_t pos = scratch[2 * nseg + 2 * s + k] + t[k][threadIdx.x] - (uint32_t)__popc(word[k]);
+        uint32_t m = word[k];
+        while (m) {
+            const int bit = __ffs(m) - 1;
+            m &= m - 1u;
+            const size_t ce = 2 * (w * 32 + (size_t)bit);  // the entry's even-x cell
+            const size_t yz = ce / nx;
+            const uint32_t rp = (uint32_t)((yz % ny + yz / ny) & 1);
+            list[(k ? half : 0) + pos] = (uint32_t)(rp == (uint32_t)k ? ce : ce + 1);
+            ++pos;
+        }
+    }
 }
 
 // the boundary unknowns (NEAR cells) of each colour, listed once per solve
@@ -449,9 +548,6 @@ __device__ __forceinline__ uint32_t cell_colour(const Grid &g, uint32_t c) {
 constexpr int kNearBlock = 256;
 static_assert(kNearSeg % kNearBlock == 0, "segment = whole block passes");
 
-__device__ __forceinline__ bool near_unknown(uint8_t f) {
-    return (f & kNear) && !(f & (kWall | kObst));
-}
 
 // counts of one segment per colour: scratch[2 s + colour]
 __global__ void __launch_bounds__(kNearBlock) k_nlist_count(Grid g, const uint8_t *flag,
@@ -997,17 +1093,25 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     hipLaunchKernelGGL(k_sor_begin, dim3(1), dim3(64), 0, s, a.ctl);
     if (!fused) {
         const uint32_t nseg = (uint32_t)((g.N + kNearSeg - 1) / kNearSeg);
-        hipLaunchKernelGGL(k_nlist_count, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
-                           a.nscratch);
-        hipLaunchKernelGGL(k_nlist_scan, dim3(1), dim3(1024), 0, s, a.nscratch, nseg, a.ctl);
-        hipLaunchKernelGGL(k_nlist_write, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
-                           a.nscratch, nseg, a.nlist);
-        hipLaunchKernelGGL((k_nlist_rows<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a);
         if (vec) {
+            // one pass over the flags into the bitmaps; the lists from the
+            // boundary bitmaps
             const size_t words = sor_ibits_words_per_colour(g.N);
             hipLaunchKernelGGL(k_interior_bits_split, dim3((uint32_t)((words + 255) / 256)),
                                dim3(256), 0, s, g, a.flag, a.ibits);
+            hipLaunchKernelGGL(k_nlist_count_bits, dim3(nseg), dim3(kWordsPerSeg), 0, s, g,
+                               a.ibits, a.nscratch);
+            hipLaunchKernelGGL(k_nlist_scan, dim3(1), dim3(1024), 0, s, a.nscratch, nseg, a.ctl);
+            hipLaunchKernelGGL(k_nlist_write_bits, dim3(nseg), dim3(kWordsPerSeg), 0, s, g,
+                               a.ibits, a.nscratch, nseg, a.nlist);
+        } else {
+            hipLaunchKernelGGL(k_nlist_count, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
+                               a.nscratch);
+            hipLaunchKernelGGL(k_nlist_scan, dim3(1), dim3(1024), 0, s, a.nscratch, nseg, a.ctl);
+            hipLaunchKernelGGL(k_nlist_write, dim3(nseg), dim3(kNearBlock), 0, s, g, a.flag,
+                               a.nscratch, nseg, a.nlist);
         }
+        hipLaunchKernelGGL((k_nlist_rows<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s, a);
     }
     if (with_res) {
         hipLaunchKernelGGL((k_dha_residual<CT>), dim3(nres), dim3(kResBlock), 0, s, a);

@@ -691,7 +691,7 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
         if (dev_alloc(L, &L->sor_nrow, 2 * compute_bytes(L->precision) *
                                            sor_nlist_entries(L->g.N)) != hipSuccess ||
             dev_alloc(L, (void **)&L->sor_nmask, sor_nlist_entries(L->g.N)) != hipSuccess ||
-            dev_alloc(L, (void **)&L->sor_ibits, 4 * 2 * sor_ibits_words_per_colour(L->g.N)) !=
+            dev_alloc(L, (void **)&L->sor_ibits, 4 * 4 * sor_ibits_words_per_colour(L->g.N)) !=
                 hipSuccess)
             return fail(LBMEP_ENOMEM, "solver boundary rows");
         SorCtl c{};

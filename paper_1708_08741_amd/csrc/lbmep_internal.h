@@ -249,7 +249,8 @@ struct SorArgs {
     uint32_t *nscratch;        // per-segment counts / offsets of the list build
     void *nrow;                // per list entry: diag and rhs of the row (2 compute values)
     uint8_t *nmask;            // per list entry: bit k = neighbour k is an unknown
-    uint32_t *ibits;           // per colour, bit e: the colour's entry e is an interior unknown
+    uint32_t *ibits;           // 4 arrays of (N/2 + 31)/32 words: the interior bitmaps of the
+                               // two colours, then their boundary bitmaps
     uint32_t xcd_swizzle;
     uint32_t zc;               // planes per workgroup of the interior half-sweep (>= 1)
     uint32_t wx;               // waves along x of its workgroup tile (1, 2 or 4)
