@@ -677,6 +677,19 @@ static void kahan_add(double *sum, double *comp, double x) {
     *sum = t;
 }
 
+/* Neumaier's compensated summation (the Kahan-Babuska variant, which also
+ * holds when a term exceeds the running sum) in long double */
+typedef struct {
+    long double s, c;
+} xsum;
+
+static void xsum_add(xsum *a, long double x) {
+    long double t = a->s + x;
+    if (fabsl(a->s) >= fabsl(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
 /* -------------------------------------------------------------------------
  * One time step n -> n+1.
  * ---------------------------------------------------------------------- */
@@ -801,10 +814,10 @@ int orc_set_free_slip(orc_lattice *L, const int faces[6]) {
 static void one_step(orc_lattice *L) {
     const long N = L->N;
     const int nx = L->nx, ny = L->ny, nz = L->nz, np = L->np;
-    /* per z slab and particle: F_dev[3], M_dev[3], K[3], T[3] (see below) */
-    double *Sz = NULL;
+    /* per z slab and particle: compensated sums of F[3] and M[3] */
+    xsum *Sz = NULL;
     int z;
-    if (np > 0) Sz = (double *)calloc((size_t)nz * np * 12, sizeof(double));
+    if (np > 0) Sz = (xsum *)calloc((size_t)nz * np * 6, sizeof(xsum));
 
     /* 0. the EDL potential of this level's map and its body force */
     if (L->potential && L->sor_iters > 0) orc_solve_potential(L, NULL, NULL, NULL);
@@ -852,8 +865,10 @@ static void one_step(orc_lattice *L) {
                         int sx = wrap_coord(x + back[0], nx, L->per[0]);
                         int sy = wrap_coord(y + back[1], ny, L->per[1]);
                         int sz = wrap_coord(z + back[2], nz, L->per[2]);
-                        double r[3], xs[3], us[3], cus, mw, gd, g[3], fq, k;
-                        double *S = Sz + ((size_t)z * np + p) * 12;
+                        double r[3], xs[3], us[3], cus, mw, fq;
+                        long double rl[3], g[3], gm;
+                        xsum *S = Sz + ((size_t)z * np + p) * 6;
+                        int a;
                         lever_arm(L, sx, sy, sz, L->Xn + 3 * p, r);
                         image_centre(L, sx, sy, sz, L->Xn + 3 * p, xs);
                         surface_velocity(L, p, r, us);
@@ -862,48 +877,41 @@ static void one_step(orc_lattice *L) {
                         fq = L->fstar[(long)qb * N + c];
                         /* Eq. LBMMovWall: population q arrives back at x */
                         L->fnew[(long)q * N + c] = fq - mw;
-                        /* Eq. LBMhydrodynForce: g = [2 f* - 2 (w/cs^2) rho0 c.u_s] c,
-                         * summed as [2 (f* - w) - 2 (w/cs^2) rho0 c.u_s] c plus the
-                         * rest-weight part 2 w c = (k/18) c, k = 2 (axis) or 1
-                         * (diagonal).  The rest-weight parts cancel over a closed
-                         * body (link cancellation), so they are summed exactly as
-                         * integers (K = sum k c, T = sum k x_s x c with x_s the
-                         * half-integer cell centre nearest the particle). */
-                        gd = 2.0 * (fq - L->w[qb]) - mw;
-                        g[0] = gd * (double)C[qb][0];
-                        g[1] = gd * (double)C[qb][1];
-                        g[2] = gd * (double)C[qb][2];
-                        k = qb <= 6 ? 2.0 : 1.0;
-                        S[0] += g[0]; S[1] += g[1]; S[2] += g[2];
-                        S[3] += r[1] * g[2] - r[2] * g[1];
-                        S[4] += r[2] * g[0] - r[0] * g[2];
-                        S[5] += r[0] * g[1] - r[1] * g[0];
-                        S[6] += k * (double)C[qb][0];
-                        S[7] += k * (double)C[qb][1];
-                        S[8] += k * (double)C[qb][2];
-                        S[9] += k * (xs[1] * (double)C[qb][2] - xs[2] * (double)C[qb][1]);
-                        S[10] += k * (xs[2] * (double)C[qb][0] - xs[0] * (double)C[qb][2]);
-                        S[11] += k * (xs[0] * (double)C[qb][1] - xs[1] * (double)C[qb][0]);
+                        /* Eq. LBMhydrodynForce: the link hands the particle
+                         * g = [2 f*_qb - 2 (w_qb / c_s^2) rho0 c_qb . u_s] c_qb
+                         * and the torque r x g, r = x_s - X (reading of the
+                         * torque substitution).  The terms (~0.1 each) cancel
+                         * to forces many orders smaller, so the lever arm, the
+                         * terms and their sums are taken in long double with
+                         * compensated summation: F and M are the plain link
+                         * sums to within a few ulps of the result. */
+                        for (a = 0; a < 3; ++a) rl[a] = (long double)xs[a] - (long double)L->Xn[3 * p + a];
+                        gm = 2.0L * (long double)fq - (long double)mw;
+                        for (a = 0; a < 3; ++a) g[a] = gm * (long double)C[qb][a];
+                        for (a = 0; a < 3; ++a) xsum_add(&S[a], g[a]);
+                        xsum_add(&S[3], rl[1] * g[2] - rl[2] * g[1]);
+                        xsum_add(&S[4], rl[2] * g[0] - rl[0] * g[2]);
+                        xsum_add(&S[5], rl[0] * g[1] - rl[1] * g[0]);
                     }
                 }
             }
     }
     {
+        /* slabs in order, each slab's sum and its correction term */
         int p, a;
         for (p = 0; p < np; ++p) {
-            double t[12];
-            const double *X = L->Xn + 3 * p;
-            for (a = 0; a < 12; ++a) {
-                t[a] = 0.0;
-                for (z = 0; z < nz; ++z) t[a] += Sz[((size_t)z * np + p) * 12 + a];
+            xsum t[6];
+            memset(t, 0, sizeof(t));
+            for (z = 0; z < nz; ++z)
+                for (a = 0; a < 6; ++a) {
+                    const xsum *S = Sz + ((size_t)z * np + p) * 6 + a;
+                    xsum_add(&t[a], S->s);
+                    xsum_add(&t[a], S->c);
+                }
+            for (a = 0; a < 3; ++a) {
+                L->F[3 * p + a] = (double)(t[a].s + t[a].c);
+                L->M[3 * p + a] = (double)(t[3 + a].s + t[3 + a].c);
             }
-            /* F = F_dev + K/18, M = M_dev + (T - X x K)/18 */
-            L->F[3 * p + 0] = t[0] + t[6] / 18.0;
-            L->F[3 * p + 1] = t[1] + t[7] / 18.0;
-            L->F[3 * p + 2] = t[2] + t[8] / 18.0;
-            L->M[3 * p + 0] = t[3] + (t[9] - (X[1] * t[8] - X[2] * t[7])) / 18.0;
-            L->M[3 * p + 1] = t[4] + (t[10] - (X[2] * t[6] - X[0] * t[8])) / 18.0;
-            L->M[3 * p + 2] = t[5] + (t[11] - (X[0] * t[7] - X[1] * t[6])) / 18.0;
         }
     }
     free(Sz);
