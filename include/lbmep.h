@@ -305,8 +305,10 @@ int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, 
  * `chunk_steps` steps; requests that arrive meanwhile join at the next chunk.
  * Each request computes exactly what a lattice created with the same
  * configuration and stepped `steps` times computes (Sec. 3.1-3.2, as for
- * lbmep_step): its fields are bitwise identical alone or in any mix; forces
- * and torques differ only by the order of FP64 atomic additions.
+ * lbmep_step): its fields, forces and torques are bitwise identical alone or
+ * in any mix (the per-particle sums are taken in a fixed order: wavefront
+ * sums by DPP row butterflies, then the wavefronts of a workgroup in order,
+ * with no atomics).
  *
  * All lbmep_server_* calls on one server must come from one thread at a time.
  * Progress (completion, admission, enqueueing) happens inside

@@ -1110,7 +1110,7 @@ int lbmep_get_timing(lbmep_lattice *L, double *total_ms, int64_t *launches) {
 // ---------------------------------------------------------------------------
 
 namespace {
-const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '3'};  // 3: psi in storage order
+const char kMagic[8] = {'L', 'B', 'M', 'E', 'P', 'c', 'k', '4'};  // 4: psi in cell order, FP64
 
 struct Header {
     char magic[8];
@@ -1196,8 +1196,20 @@ int lbmep_save_state(lbmep_lattice *L, const char *path) {
         for (size_t i = 0; i < N; ++i) fl[i] = (fl[i] & kWall) ? LBMEP_WALL : LBMEP_FLUID;
         ok = ok && std::fwrite(fl.data(), 1, N, fp) == N;
     }
-    // force (compute precision)
-    if (ok && L->force_mode != kForceNone) {
+    // force (compute precision); the potential psi in cell order as FP64
+    // (its storage order, colour-split for even nx, spans Ns/2 + N/2 slots
+    // of a colour, not the first N)
+    if (ok && L->force_mode == kForcePotential) {
+        double *d = nullptr;
+        std::vector<double> buf(N);
+        ok = dev_alloc(L, (void **)&d, N * sizeof(double)) == hipSuccess;
+        ok = ok && launch_potential_to_f64(L->precision, L->g, L->force, d, L->stream) == hipSuccess &&
+             hipMemcpyAsync(buf.data(), d, N * sizeof(double), hipMemcpyDeviceToHost, L->stream) ==
+                 hipSuccess &&
+             hipStreamSynchronize(L->stream) == hipSuccess;
+        if (d) dev_free(L, d);
+        ok = ok && std::fwrite(buf.data(), 8, N, fp) == N;
+    } else if (ok && L->force_mode != kForceNone) {
         const int nc = L->force_mode == kForceDense ? 3 : 1;
         std::vector<char> buf(N * compute_bytes(L->precision));
         for (int k = 0; k < nc && ok; ++k) {
@@ -1255,7 +1267,8 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
     std::vector<uint8_t> fl(N);
     ok = ok && std::fread(fl.data(), 1, N, fp) == N;
     const int nc = h.force_mode == kForceDense ? 3 : (h.force_mode == kForceNone ? 0 : 1);
-    std::vector<char> force(nc * N * compute_bytes(L->precision));
+    const size_t fbytes = h.force_mode == kForcePotential ? 8 : compute_bytes(L->precision);
+    std::vector<char> force(nc * N * fbytes);
     ok = ok && std::fread(force.data(), 1, force.size(), fp) == force.size();
     const size_t es = storage_bytes(L->precision);
     std::vector<char> pdf(Q * N * es);
@@ -1285,10 +1298,23 @@ int lbmep_load_state(lbmep_lattice *L, const char *path) {
             if (dev_alloc(L, (void **)&L->force, need) != hipSuccess) return fail(LBMEP_ENOMEM, "force");
             L->force_bytes = need;
         }
-        const size_t cb = N * compute_bytes(L->precision);
-        for (int k = 0; k < nc; ++k)
-            HIP_TRY(hipMemcpy((char *)L->force + k * Ns * compute_bytes(L->precision),
-                              force.data() + k * cb, cb, hipMemcpyHostToDevice));
+        if (h.force_mode == kForcePotential) {
+            // psi from cell order into its storage order
+            double *d = nullptr;
+            if (dev_alloc(L, (void **)&d, N * sizeof(double)) != hipSuccess)
+                return fail(LBMEP_ENOMEM, "psi staging");
+            hipError_t e = hipMemcpy(d, force.data(), N * sizeof(double), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = launch_potential_pack(L->precision, L->g, d, LBMEP_DTYPE_F64, L->force, L->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+            dev_free(L, d);
+            if (e != hipSuccess) return fail(LBMEP_EDEVICE, hipGetErrorString(e));
+        } else {
+            const size_t cb = N * compute_bytes(L->precision);
+            for (int k = 0; k < nc; ++k)
+                HIP_TRY(hipMemcpy((char *)L->force + k * Ns * compute_bytes(L->precision),
+                                  force.data() + k * cb, cb, hipMemcpyHostToDevice));
+        }
     }
     L->force_mode = h.force_mode;
     for (int k = 0; k < 3; ++k) L->E[k] = h.E[k];

@@ -21,8 +21,9 @@
 // releases the lattice's memory to the arena.
 //
 // The arithmetic is that of the single-lattice path (the same device code):
-// a simulation's fields are bitwise the same alone and in any mix; the
-// per-particle sums use FP64 atomics, whose order may differ.
+// a simulation's fields, forces and torques are bitwise the same alone and
+// in any mix (the per-particle sums are fixed-order wavefront and workgroup
+// sums, no atomics).
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -15,7 +15,8 @@
 // next to the particle with the directions that hit it), so the particle's
 // position and velocities are uniform, no owner look-up is needed, and
 // force and torque are summed over the wavefront in a fixed order (DPP row
-// butterflies) and stored without atomics or barriers.  Links to wall cells
+// butterflies), the wavefronts' sums are combined in wavefront order through
+// LDS after one barrier, and the result is stored without atomics.  Links to wall cells
 // come from a list built when the walls are set.
 #pragma once
 #include "sweep_impl.h"

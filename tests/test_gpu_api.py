@@ -131,6 +131,26 @@ def test_gpu_invariants_momentum_bookkeeping(lb):
         assert np.allclose(i1[1:] - i0[1:], sfb - F[0], rtol=0, atol=1e-16 * n ** 3)
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_nonfinite_populations_reported(lb, precision):
+    """lbmep_get_invariants returns LBMEP_ENONFINITE when a population is
+    NaN or infinite (a NaN planted through a device buffer, which
+    lbmep_set_pdfs does not scan), and the library stays usable."""
+    import torch
+    shape = (12, 10, 8)
+    g = lb.Lattice(shape, precision=precision)
+    g.init_equilibrium()
+    f = torch.from_numpy(g.get_pdfs()).cuda()
+    f[7, 3, 4, 5] = float("nan")
+    g.set_pdfs(f.reshape(-1))
+    with pytest.raises(lb.LbmepError) as ei:
+        g.invariants()
+    assert ei.value.code == lb.ENONFINITE
+    g.init_equilibrium()
+    assert np.isfinite(g.invariants()).all()
+    g.close()
+
+
 def test_macro_of_solid_cells(lb):
     """Obstacle cells report rho0 and their rigid-body surface velocity, wall
     cells rho0 and zero velocity."""

@@ -208,6 +208,39 @@ def test_checkpoint_keeps_the_potential(lb, tmp_path):
     assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all()
 
 
+@pytest.mark.parametrize("prec", ["fp32dev", "fp64"])
+def test_checkpoint_restores_all_of_psi_into_a_used_lattice(lb, tmp_path, prec):
+    """Loading into a lattice that already holds another potential: every
+    value of psi comes from the file (even nx, so psi is colour-split, and
+    N = 117040 is not a multiple of 128, so a colour's slots run past N):
+    potential() and the continued run are bitwise the uninterrupted run."""
+    P = {"fp32dev": lb.FP32DEV, "fp64": lb.FP64}[prec]
+    q = _edl_inputs()
+    nx, ny, nz = SHAPE
+    assert nx % 2 == 0 and (nx * ny * nz) % 128 != 0
+    g = _edl_lattice(lb, P, q)
+    g.step(5)
+    path = str(tmp_path / "pot2.ck")
+    g.save(path)
+    psi_saved = g.potential()
+    g.step(6)
+    ref = (g.get_pdfs(), g.potential(), g.ft())
+    g.close()
+    # a lattice with another potential and another state, then load
+    rng = np.random.default_rng(99)
+    other = dict(q)
+    other["psi"] = 0.3 * rng.standard_normal(SHAPE[::-1])
+    h = _edl_lattice(lb, P, other)
+    h.step(3)
+    h.load(path)
+    assert (h.potential() == psi_saved).all()
+    h.step(6)
+    out = (h.get_pdfs(), h.potential(), h.ft())
+    h.close()
+    assert (out[0] == ref[0]).all() and (out[1] == ref[1]).all()
+    assert (out[2][0] == ref[2][0]).all() and (out[2][1] == ref[2][1]).all()
+
+
 @pytest.mark.parametrize("shape", [(8, 6, 4), (7, 6, 4), (130, 3, 5), (2, 1, 1), (1, 1, 1)])
 def test_potential_storage_round_trip(lb, shape):
     """psi goes into its storage order on upload (colour-split for even nx,
