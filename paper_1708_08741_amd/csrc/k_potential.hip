@@ -24,22 +24,15 @@
 // [k Ns / 2, k Ns / 2 + N / 2), cell c at c >> 1), in cell order for odd nx.
 //
 // Two implementations of an iteration, bitwise identical:
-//   * in use: one launch per colour, in place: for even nx k_sor_half_vec,
-//     whose workgroups march through chunks of z planes with the other
-//     colour's three-plane window in registers (the other colour read once,
-//     the own colour read and written once) and relax the listed boundary
-//     cells in the same grid; for odd nx k_sor_half, then k_sor_near for the
-//     listed cells;
-//   * k_sor_fused (switched off, see launch_sor_solve): one launch per
-//     iteration from psi into a second buffer.  A workgroup owns a 64 x 16 tile of (x, y) and a chunk of z
-//     planes and marches through its planes with rings of planes in LDS:
-//     the old values of a plane with a two-cell halo, then the new red
-//     values of that plane on a one-cell halo ring (from old black
-//     neighbours), then the new black values of the plane behind it (from
-//     the new red values around it).  Halo values are recomputed from the
-//     same old values by every workgroup that needs them, so the result is
-//     the red-black sweep exactly, read once and written once per
-//     iteration.
+//   * one pass per iteration (even nx, rows of up to 2048 cells; the
+//     default): k_sor_march from psi into a second buffer, every cell of
+//     both colours in one z-march (see k_sor_march);
+//   * one launch per colour, in place: for even nx k_sor_half_vec, whose
+//     workgroups march through chunks of z planes with the other colour's
+//     three-plane window in registers (the other colour read once, the own
+//     colour read and written once) and relax the listed boundary cells in
+//     the same grid; for odd nx k_sor_half, then k_sor_near for the listed
+//     cells.
 //
 // The residual's L2 norm is the root mean square over the unknowns, summed
 // in a fixed order (per-thread strided sums, a block tree, one block over
@@ -108,7 +101,10 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
         // Dirichlet value of an obstacle neighbour: zeta of its particle,
         // or psi's value there
         bv[k] = pv[k];
-        if (zeta && !edge[k] && (fs[k] & kObst) && !(fs[k] & kWall)) bv[k] = (CT)zeta[owner[s[k]]];
+        if (zeta && !edge[k] && (fs[k] & kObst) && !(fs[k] & kWall)) {
+            const uint32_t po = owner[s[k]];
+            if (po != kNone) bv[k] = (CT)zeta[po];
+        }
     }
     uint8_t um = 0;
 #pragma unroll
@@ -229,7 +225,8 @@ __device__ __forceinline__ CT lane_shift(CT v, int delta) {
 }
 
 template <typename CT>
-__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb);
+__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb,
+                              const CT *src, CT *dst);
 
 // a wave-uniform global pointer, made opaque to the optimiser: loads then
 // take it as a scalar base plus the lane's 32-bit offset, instead of a
@@ -284,7 +281,8 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     // colour
     const uint32_t nnb = gridDim.x - ninterior;
     if (blockIdx.x < nnb) {
-        sor_near_part<CT>(a, colour, blockIdx.x, nnb);
+        sor_near_part<CT>(a, colour, blockIdx.x, nnb, static_cast<const CT *>(a.psi),
+                          static_cast<CT *>(a.psi));
         return;
     }
     const Grid &g = a.g;
@@ -458,6 +456,8 @@ __global__ void __launch_bounds__(256) k_interior_bits_split(Grid g, const uint8
     ibits[W + w] = b[1];
     ibits[2 * W + w] = nb[0];
     ibits[3 * W + w] = nb[1];
+    // both colours' interior words side by side, for the one-pass iteration
+    reinterpret_cast<uint2 *>(ibits + 4 * W)[w] = make_uint2(b[0], b[1]);
 }
 
 // even nx: the boundary lists from the boundary bitmaps.  A list segment of
@@ -701,14 +701,15 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_rows(SorArgs a) {
 }
 
 // the colour's listed boundary cells, entries strided over nb blocks of
-// kNearBlock threads (this block: b0)
+// kNearBlock threads (this block: b0); neighbours and old values from src,
+// new values into dst (the same buffer in the in-place half-sweeps)
 template <typename CT>
-__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb) {
+__device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_t nb,
+                              const CT *src, CT *dst) {
     const Grid &g = a.g;
     const uint32_t n = a.ctl->nnear[colour];
     const size_t base = colour ? g.N / 2 + 1 : 0;
     const CT *rows = static_cast<const CT *>(a.nrow);
-    CT *psi = static_cast<CT *>(a.psi);
     const CT om = (CT)a.omega;
     for (uint32_t i = b0 * kNearBlock + threadIdx.x; i < n; i += nb * kNearBlock) {
         const uint32_t c = a.nlist[base + i];
@@ -720,21 +721,22 @@ __device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_
         CT v[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            v[k] = (mask >> k) & 1 ? psi[psi_slot(g, s[k], (uint32_t)colour ^ 1u)] : CT(0);
+            v[k] = (mask >> k) & 1 ? src[psi_slot(g, s[k], (uint32_t)colour ^ 1u)] : CT(0);
         const size_t pc = psi_slot(g, c, (uint32_t)colour);
-        const CT own = psi[pc];
+        const CT own = src[pc];
         CT sum = CT(0);
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             if ((mask >> k) & 1) sum = sum + v[k];
-        psi[pc] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
+        dst[pc] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
     }
 }
 
 template <typename CT>
-__global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour) {
+__global__ void __launch_bounds__(kNearBlock) k_sor_near(SorArgs a, int colour, const CT *src,
+                                                         CT *dst) {
     if (a.ctl->done) return;
-    sor_near_part<CT>(a, colour, blockIdx.x, gridDim.x);
+    sor_near_part<CT>(a, colour, blockIdx.x, gridDim.x, src, dst);
 }
 
 // residual: per-thread strided sums of r^2 and of the unknowns, a block tree,
@@ -806,244 +808,374 @@ __global__ void __launch_bounds__(kResBlock) k_dha_finalize(SorArgs a, int npart
     }
 }
 
-// relaxation of unknown cell (x, y, z) with flag fl and old value own.
-// get(k) is the current value and flg(k) the flag of the neighbour in
-// direction k (x-, x+, y-, y+, z-, z+); at(k) its global index (only taken
-// for an obstacle neighbour).  Same terms in the same order as dha_row.
-template <typename CT, typename Get, typename Flg, typename At>
-__device__ __forceinline__ CT relax(const SorArgs &a, int x, int y, int z, uint8_t fl, CT own,
-                                    const CT *psi_old, Get get, Flg flg, At at) {
-    const Grid &g = a.g;
-    CT diag = CT(6.0) + (CT)a.kappa2, rhs = CT(0), sum = CT(0);
-    if (!(fl & kNear)) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) sum = sum + get(k);
-    } else {
-        const int lo[3] = {x == 0, y == 0, z == 0};
-        const int hi[3] = {x == g.nx - 1, y == g.ny - 1, z == g.nz - 1};
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int ax = k >> 1;
-            const bool up = k & 1;
-            if ((up ? hi[ax] : lo[ax]) && !g.per[ax]) {
-                diag = diag - CT(1.0);
-                continue;
-            }
-            const uint8_t fs = flg(k);
-            if (fs & kWall) {
-                diag = diag - CT(1.0);
-            } else if (fs & kObst) {
-                // obstacle cells never change: the old buffer holds b
-                const size_t s = at(k);
-                const CT b = a.zeta ? (CT)a.zeta[a.owner[s]] : psi_old[s];
-                diag = diag + CT(1.0);
-                rhs = rhs + CT(2.0) * b;
-            } else {
-                sum = sum + get(k);
-            }
-        }
-    }
-    const CT om = (CT)a.omega;
-    return (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
-}
+// ---------------------------------------------------------------------------
+// One red-black iteration in one pass (even nx, rows of at most 2048 cells).
+// Buffer A holds iterate n and is only read; buffer B receives iterate
+// n + 1, every cell of it.  A workgroup holds whole rows (every entry of both
+// colours) of RW consecutive y and marches through a chunk of z planes.  At
+// step z it forms the new red values of plane z + 1 on its rows and one halo
+// row on each side (from A) and the new black values of plane z on its rows
+// from the new red values of planes z - 1, z, z + 1, and writes its rows of
+// both into B.  Same-coloured cells are never neighbours, so every value is
+// formed from the operands of the in-place red-black sweep, in the same
+// order: the result is bitwise that sweep's.  A is read once per iteration
+// (the halo rows, re-read by the neighbouring tiles, mostly from L2) and B
+// written once.
+// Rows are formed from per-solve codes (k_sor_prepare): an interior unknown's
+// code is implied by its interior bit (1 bit per cell, always read); the
+// 16-bit code of any other cell is read only when its bit is clear.  With
+// surface potentials, the obstacle cells hold their particle's zeta during
+// the solve (k_sor_prepare / k_dirichlet_restore), so a Dirichlet value is
+// the neighbour's value like any other.
+// The x-neighbours come from the neighbouring lane (DPP wavefront rotate)
+// and, at the ends of a wavefront, from the end values that every wavefront
+// leaves in LDS (double-buffered by step parity: one barrier per step).
+constexpr int kMarchMaxWaves = 16;  // rows of up to 2048 cells
 
-constexpr int kFTX = 64, kFTY = 16, kFZC = 32, kFBlock = 256;
-constexpr int kOW = kFTX + 4, kOH = kFTY + 4;  // old planes: two-cell halo
-constexpr int kRW = kFTX + 2, kRH = kFTY + 2;  // new red values: one-cell halo
-constexpr int kNLoad = (kOH * kOW + kFBlock - 1) / kFBlock;              // 6
-constexpr int kNRed = (kRH * (kRW / 2) + kFBlock - 1) / kFBlock;         // 3
-constexpr int kNBlack = kFTY * kFTX / kFBlock;                           // 4
-static_assert(kFTX == 64 && kFBlock % kFTX == 0, "black phase: one row of 64 per 64 threads");
-
-// v wrapped once into [0, len) on a periodic axis; ok = false outside a
-// non-periodic edge and for positions more than one period away (halo
-// slots of a tile wider than the grid, which no cell needs)
-__device__ __forceinline__ int wrap_axis_or(int v, int len, int per, bool &ok) {
-    if (v < 0 || v >= len) {
-        if (!per) {
-            ok = false;
-            return 0;
-        }
-        v = v < 0 ? v + len : v - len;
-        if (v < 0 || v >= len) {
-            ok = false;
-            return 0;
-        }
-    }
-    ok = true;
-    return v;
-}
-
-// global index of the neighbour in direction k of in-grid cell (x, y, z)
-__device__ __forceinline__ size_t neighbour_index(const Grid &g, int x, int y, int z, int k) {
-    int v[3] = {x, y, z};
-    const int len[3] = {g.nx, g.ny, g.nz};
-    const int ax = k >> 1;
-    v[ax] += (k & 1) ? 1 : -1;
-    if (v[ax] < 0) v[ax] += len[ax];
-    if (v[ax] >= len[ax]) v[ax] -= len[ax];
-    return (size_t)v[0] + (size_t)g.nx * ((size_t)v[1] + (size_t)g.ny * (size_t)v[2]);
-}
-
-// one red-black iteration src -> dst (see the file comment).  Per-thread
-// in-plane offsets are fixed for the whole column of planes; plane j + 2 is
-// fetched into registers while plane j is relaxed.  In-plane offsets are
-// 32-bit (nx ny < 2^31, checked by the launcher).
 template <typename CT>
-__global__ void __launch_bounds__(kFBlock) k_sor_fused(SorArgs a, const CT *src, CT *dst,
-                                                        int ntx, int nty) {
+__device__ __forceinline__ CT dpp_rot(CT v, int ctrl);
+template <>
+__device__ __forceinline__ float dpp_rot<float>(float v, int ctrl) {
+    // ctrl is a constant at every call site after inlining
+    return ctrl == 0x13C ? __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false))
+                         : __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+template <>
+__device__ __forceinline__ double dpp_rot<double>(double v, int ctrl) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo, hi;
+    if (ctrl == 0x13C) {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x13C, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x13C, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x134, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x134, 0xF, 0xF, false);
+    }
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) |
+                                            (unsigned long long)(uint32_t)lo));
+}
+// value of lane l - 1 (wave_ror:1) and of lane l + 1 (wave_rol:1)
+template <typename CT>
+__device__ __forceinline__ CT lane_prev(CT v) { return dpp_rot<CT>(v, 0x13C); }
+template <typename CT>
+__device__ __forceinline__ CT lane_next(CT v) { return dpp_rot<CT>(v, 0x134); }
+
+// code of an interior unknown: an unknown whose six neighbours are unknowns
+// (and the word of an entry whose two cells are)
+constexpr uint32_t kCodeInterior = 0x8000u;
+constexpr uint32_t kCodePairInterior = 0x80008000u;
+
+// the row of a cell from its code (see sor_code), its old value and its
+// six neighbours' values in the order x-, x+, y-, y+, z-, z+; the terms in
+// dha_row's order (adding 0 where dha_row adds nothing changes no bit)
+template <typename CT>
+__device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6], CT om, CT om1,
+                                         CT diag0) {
+    if (code == kCodeInterior) {
+        CT sum = CT(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sum = sum + nb[k];
+        return om1 * own + om * ((CT(0) + sum) / diag0);
+    }
+    CT diag = diag0, rhs = CT(0), sum = CT(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint32_t t = (code >> (2 * k)) & 3u;
+        diag = diag + (t == 1u ? CT(-1.0) : (t == 2u ? CT(1.0) : CT(0.0)));
+        rhs = rhs + (t == 2u ? CT(2.0) * nb[k] : CT(0.0));
+        sum = sum + (t == 0u ? nb[k] : CT(0.0));
+    }
+    const CT nw = om1 * own + om * ((rhs + sum) / diag);
+    return (code & 0x8000u) ? nw : own;
+}
+
+template <typename CT, int RW>
+__global__ void __launch_bounds__(1024) k_sor_march(SorArgs a, const CT *A, CT *B, uint32_t nyb,
+                                                    uint32_t zc) {
     if (a.ctl->done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
-    __shared__ CT s_old[4][kOH * kOW];
-    __shared__ uint8_t s_fl[5][kOH * kOW];  // the black phase still reads plane j - 2's
-    __shared__ CT s_rn[3][kRH * kRW];
+    // end values of each wavefront's rows: [step parity][row][wavefront][first, last]
+    __shared__ CT e_old[2][RW + 2][kMarchMaxWaves][2];  // black, old, plane z + 1
+    __shared__ CT e_new[2][RW][kMarchMaxWaves][2];      // red, new, plane z + 1
     const Grid &g = a.g;
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int tx = (int)(lb % (uint32_t)ntx);
-    const int ty = (int)((lb / (uint32_t)ntx) % (uint32_t)nty);
-    const int tz = (int)(lb / ((uint32_t)ntx * (uint32_t)nty));
-    const int X0 = tx * kFTX, Y0 = ty * kFTY, Z0 = tz * kFZC;
-    const int Z1 = min(Z0 + kFZC, g.nz);
-    const int nx = g.nx;
-    const size_t nxy = (size_t)g.nx * (size_t)g.ny;
-    const int tid = threadIdx.x;
-
-    // load slots: in-plane offset (-1: outside a non-periodic edge)
-    int loff[kNLoad];
+    const uint32_t zb = lb / nyb, yb = lb - zb * nyb;  // neighbouring y-blocks share an XCD
+    const int y0 = (int)yb * RW;
+    const int zs = (int)(zb * zc), ze = min(zs + (int)zc, g.nz);
+    const int hx = g.nx >> 1;  // entries of one colour per row
+    const int nw = (int)(blockDim.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = 64 * w + lane;
+    const bool act = i < hx;
+    const uint32_t ic = act ? (uint32_t)i : (uint32_t)(hx - 1);  // in-range entry for the rest
+    const int lw = min(63, hx - 1 - 64 * w);                      // last lane holding an entry
+    const int wl = (w + nw - 1) % nw, wr = (w + 1) % nw;          // wavefronts holding i - 1, i + 1
+    const size_t hxs = (size_t)hx, hxy = hxs * (size_t)g.ny, half = g.Ns >> 1;
+    const CT *Ar = A, *Ab = A + half;  // colour 0 (red) and colour 1 (black)
+    CT *Br = B, *Bb = B + half;
+    const uint2 *mb = reinterpret_cast<const uint2 *>(a.ibits + 4 * sor_ibits_words_per_colour(g.N));
+    const uint32_t *codes = a.codes;
+    // rows -2 .. RW + 1 of the tile: wrapped y and entry offset
+    int yr[RW + 4];
+    size_t ro_[RW + 4];
 #pragma unroll
-    for (int m = 0; m < kNLoad; ++m) {
-        const int i = tid + m * kFBlock;
-        loff[m] = -1;
-        if (i < kOH * kOW) {
-            const int r = i / kOW, c = i - r * kOW;
-            bool okx, oky;
-            const int gx = wrap_axis_or(X0 - 2 + c, g.nx, g.per[0], okx);
-            const int gy = wrap_axis_or(Y0 - 2 + r, g.ny, g.per[1], oky);
-            if (okx && oky) loff[m] = gx + nx * gy;
+    for (int k = 0; k < RW + 4; ++k) {
+        int y = (y0 + k - 2) % g.ny;
+        if (y < 0) y += g.ny;
+        yr[k] = y;
+        ro_[k] = hxs * (size_t)y;
+    }
+    auto zwrap = [&](int z) {
+        int v = z % g.nz;
+        return v < 0 ? v + g.nz : v;
+    };
+    const uint32_t io = ic * (uint32_t)sizeof(CT), ico = ic * 4u;
+    auto ld = [&](const CT *row) -> CT {
+        return *reinterpret_cast<GlobalPtr<const CT>>(
+            uniform_ptr(reinterpret_cast<const char *>(row)) + io);
+    };
+    auto ldc = [&](size_t e0) -> uint32_t {  // the code pair of the lane's entry in row e0
+        return *reinterpret_cast<GlobalPtr<const uint32_t>>(
+            uniform_ptr(reinterpret_cast<const char *>(codes + e0)) + ico);
+    };
+    auto st = [&](CT *row, CT v) {
+        *reinterpret_cast<GlobalPtr<CT>>(uniform_ptr(reinterpret_cast<char *>(row)) + io) = v;
+    };
+    // interior bits of the lane's entry in row k of plane z: red into bit kr
+    // of rb, black into bit kb of bb
+    auto bits = [&](int z, int k, uint32_t &rb, int kr, uint32_t &bb, int kb) {
+        const uint32_t e = (uint32_t)(hxy * (size_t)zwrap(z) + ro_[k]) + ic;
+        const uint2 m = mb[e >> 5];
+        rb |= ((m.x >> (e & 31)) & 1u) << kr;
+        if (kb >= 0) bb |= ((m.y >> (e & 31)) & 1u) << kb;
+    };
+    const CT om = (CT)a.omega, om1 = CT(1.0) - om;
+    const CT diag0 = CT(6.0) + (CT)a.kappa2;
+
+    // windows: black old of planes z (rows -1..RW), z + 1 (rows -2..RW+1),
+    // z + 2 (rows -1..RW); red new of planes z - 1 (rows 0..RW-1), z and
+    // z + 1 (rows -1..RW)
+    CT Bo0[RW + 2], Bo1[RW + 4], Bo2[RW + 2], Rm[RW], R0[RW + 2], R1[RW + 2];
+    // interior bits: red of plane z + 1, black of planes z and z + 1
+    uint32_t rb1 = 0, bb0 = 0, bb1 = 0;
+    {
+        const CT *p0 = Ab + hxy * (size_t)zwrap(zs - 2), *p1 = Ab + hxy * (size_t)zwrap(zs - 1);
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) {
+            Bo0[r] = ld(p0 + ro_[r + 1]);
+            Bo1[r + 1] = ld(p1 + ro_[r + 1]);
+            bits(zs - 1, r + 1, rb1, r, bb1, r >= 1 && r <= RW ? r - 1 : -1);
+        }
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) R0[r] = CT(0);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) Rm[r] = CT(0);
+    }
+    for (int z = zs - 2; z < ze; ++z) {
+        const int par = (z - zs + 2) & 1;
+        const int zw = zwrap(z), zw1 = zwrap(z + 1);
+        const size_t pz = hxy * (size_t)zw, pz1 = hxy * (size_t)zw1, pz2 = hxy * (size_t)zwrap(z + 2);
+        // plane z + 2 of the black window, the two outer rows of plane z + 1,
+        // the red old values of plane z + 1, the bits of plane z + 2, and the
+        // code words of the cells to be relaxed that are not interior
+        // unknowns (as loaded: the colour is taken apart at its use, so that
+        // the conditional loads need no wait here)
+        Bo1[0] = ld(Ab + pz1 + ro_[0]);
+        Bo1[RW + 3] = ld(Ab + pz1 + ro_[RW + 3]);
+        CT Ro1[RW + 2];
+        uint32_t Cr[RW + 2], Cb[RW];
+        uint32_t rb2 = 0, bb2 = 0;
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) {
+            Bo2[r] = ld(Ab + pz2 + ro_[r + 1]);
+            Ro1[r] = ld(Ar + pz1 + ro_[r + 1]);
+            Cr[r] = kCodePairInterior;
+            if (!((rb1 >> r) & 1u)) Cr[r] = ldc(pz1 + ro_[r + 1]);
+            bits(z + 2, r + 1, rb2, r, bb2, r >= 1 && r <= RW ? r - 1 : -1);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            Cb[r] = kCodePairInterior;
+            if (z >= zs && !((bb0 >> r) & 1u)) Cb[r] = ldc(pz + ro_[r + 2]);
+        }
+        // end values of the black rows of plane z + 1
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) {
+            if (lane == 0) e_old[par][r][w][0] = Bo1[r + 1];
+            if (lane == lw) e_old[par][r][w][1] = Bo1[r + 1];
+        }
+        __syncthreads();
+        // new red values of plane z + 1, rows -1 .. RW (index r = row + 1)
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) {
+            const int p = (yr[r + 1] + zw1) & 1;  // the red cell of entry i is x = 2i + p
+            const CT own = Bo1[r + 1];
+            const CT prv = lane_prev(own), nxt = lane_next(own);
+            CT xm = p ? own : prv, xp = p ? nxt : own;
+            if (!p && lane == 0) xm = e_old[par][r][wl][1];
+            if (p && lane == lw) xp = e_old[par][r][wr][0];
+            const CT nb[6] = {xm, xp, Bo1[r], Bo1[r + 2], Bo0[r], Bo2[r]};
+            R1[r] = relax_code<CT>(Cr[r] & 0xFFFFu, Ro1[r], nb, om, om1, diag0);
+        }
+        if (act && z + 1 >= zs && z + 1 < ze) {
+#pragma unroll
+            for (int r = 1; r <= RW; ++r) st(Br + pz1 + ro_[r + 1], R1[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (lane == 0) e_new[par][r][w][0] = R1[r + 1];
+            if (lane == lw) e_new[par][r][w][1] = R1[r + 1];
+        }
+        // new black values of plane z, rows 0 .. RW - 1, from the new red
+        // values of planes z - 1, z, z + 1 (the end values of plane z were
+        // left in LDS at the previous step)
+        if (z >= zs) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int p = (1 + yr[r + 2] + zw) & 1;  // the black cell of entry i
+                const CT own = R0[r + 1];
+                const CT prv = lane_prev(own), nxt = lane_next(own);
+                CT xm = p ? own : prv, xp = p ? nxt : own;
+                if (!p && lane == 0) xm = e_new[par ^ 1][r][wl][1];
+                if (p && lane == lw) xp = e_new[par ^ 1][r][wr][0];
+                const CT nb[6] = {xm, xp, R0[r], R0[r + 2], Rm[r], R1[r + 1]};
+                const CT v = relax_code<CT>(Cb[r] >> 16, Bo0[r + 1], nb, om, om1, diag0);
+                if (act) st(Bb + pz + ro_[r + 2], v);
+            }
+        }
+        // slide the windows one plane up
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) {
+            Bo0[r] = Bo1[r + 1];
+            Bo1[r + 1] = Bo2[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) Rm[r] = R0[r + 1];
+#pragma unroll
+        for (int r = 0; r < RW + 2; ++r) R0[r] = R1[r];
+        rb1 = rb2;
+        bb0 = bb1;
+        bb1 = bb2;
+    }
+}
+
+// the code of cell (x, y, z) for the one-pass iteration (both colours of an
+// entry share one word, colour 0 low).  Bit 15: the cell is an unknown;
+// bits 2k, 2k + 1: how its neighbour in direction k (x-, x+, y-, y+, z-,
+// z+) enters its row, as in dha_row: 0 an unknown (its value is summed), 1 a
+// wall or beyond a non-periodic edge (homogeneous Neumann: diag - 1), 2 an
+// obstacle cell (Dirichlet on the shared face: diag + 1, rhs + 2 b).  Walls
+// and obstacle cells: 0.
+__device__ __forceinline__ uint32_t sor_code(const Grid &g, const uint8_t *flag, int x, int y,
+                                             int z) {
+    const size_t nx = (size_t)g.nx, nxy = (size_t)g.nx * (size_t)g.ny;
+    if (flag[(size_t)x + nx * (size_t)y + nxy * (size_t)z] & (kWall | kObst)) return 0u;
+    uint32_t code = 0x8000u;
+    const int len[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int v[3] = {x, y, z};
+        const int ax = k >> 1;
+        v[ax] += (k & 1) ? 1 : -1;
+        if (v[ax] < 0 || v[ax] >= len[ax]) {
+            if (!g.per[ax]) {
+                code |= 1u << (2 * k);
+                continue;
+            }
+            v[ax] = v[ax] < 0 ? v[ax] + len[ax] : v[ax] - len[ax];
+        }
+        const uint8_t fs = flag[(size_t)v[0] + nx * (size_t)v[1] + nxy * (size_t)v[2]];
+        if (fs & kWall) code |= 1u << (2 * k);
+        else if (fs & kObst) code |= 2u << (2 * k);
+    }
+    return code;
+}
+
+// once per solve, 16 cells (8 entries) per thread, read as one 16-byte load
+// of the flags (padded to 4096 cells; nx even, so an entry never straddles a
+// row): the code word of every entry with a cell that is not an interior
+// unknown (the only words k_sor_march reads), and, with surface potentials,
+// zeta into the obstacle cells (their own values kept in save and put back
+// by k_dirichlet_restore after the solve)
+template <typename CT>
+__global__ void __launch_bounds__(256) k_sor_prepare(SorArgs a, CT *psi, CT *save, int dirichlet) {
+    const Grid &g = a.g;
+    const size_t c0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (c0 >= g.N) return;
+    const uint4 q = *reinterpret_cast<const uint4 *>(a.flag + c0);
+    const uint32_t fw[4] = {q.x, q.y, q.z, q.w};
+    const uint32_t any = 0x01010101u * (uint32_t)(kWall | kObst | kNear);
+    if (!((fw[0] | fw[1] | fw[2] | fw[3]) & any)) return;  // interior unknowns: codes implied
+    const size_t nx = (size_t)g.nx, hx = nx >> 1;
+    size_t yz = c0 / nx;
+    int x = (int)(c0 - yz * nx);
+    int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
+    for (int k = 0; k < 8; ++k) {
+        const size_t c = c0 + 2 * (size_t)k;
+        if (c >= g.N) break;
+        const uint32_t fp = (fw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;  // cells x, x + 1
+        if ((fp | (fp >> 8)) & (uint32_t)(kWall | kObst | kNear)) {
+            const int pr = (y + z) & 1;  // the red cell of the entry is x + pr
+            const uint32_t cr = sor_code(g, a.flag, x + pr, y, z);
+            const uint32_t cb = sor_code(g, a.flag, x + 1 - pr, y, z);
+            const size_t e = c >> 1;
+            a.codes[e] = cr | (cb << 16);
+            if (dirichlet) {
+                for (int m = 0; m < 2; ++m) {
+                    const uint8_t fl = (uint8_t)(fp >> (8 * m));
+                    if (!(fl & kObst) || (fl & kWall)) continue;
+                    const uint32_t p = a.owner[c + (size_t)m];
+                    if (p == kNone) continue;
+                    // cell x + m has colour (x + m + y + z) & 1
+                    const size_t sl = (size_t)((x + m + y + z) & 1) * (g.Ns >> 1) + e;
+                    save[sl] = psi[sl];
+                    psi[sl] = (CT)a.zeta[p];
+                }
+            }
+        }
+        x += 2;
+        if (x >= g.nx) {
+            x = 0;
+            if (++y == g.ny) {
+                y = 0;
+                ++z;
+            }
         }
     }
-    auto exists = [&](int j, int &jw) {
-        bool ok;
-        jw = wrap_axis_or(j, g.nz, g.per[2], ok);
-        return ok;
-    };
-    // plane j of the old values and flags, through registers into its LDS
-    // slot (cells outside a non-periodic edge read as walls: never relaxed,
-    // never taken as neighbour values)
-    CT pv[kNLoad];
-    uint8_t fv[kNLoad];
-    bool pok = false;
-    auto fetch = [&](int j) {
-        int jw;
-        pok = exists(j, jw);
-        const size_t base = nxy * (size_t)jw;
-#pragma unroll
-        for (int m = 0; m < kNLoad; ++m) {
-            pv[m] = CT(0);
-            fv[m] = kWall;
-            if (pok && loff[m] >= 0) {
-                pv[m] = src[base + (size_t)loff[m]];
-                fv[m] = a.flag[base + (size_t)loff[m]];
-            }
-        }
-    };
-    auto fslot = [&](int j) { return (j - Z0 + 10) % 5; };
-    auto stash = [&](int j) {
-        const int sl = (j - Z0 + 8) & 3, sf = fslot(j);
-#pragma unroll
-        for (int m = 0; m < kNLoad; ++m) {
-            const int i = tid + m * kFBlock;
-            if (i < kOH * kOW) {
-                s_old[sl][i] = pv[m];
-                s_fl[sf][i] = fv[m];
-            }
-        }
-    };
+}
 
-    fetch(Z0 - 2);
-    stash(Z0 - 2);
-    fetch(Z0 - 1);
-    stash(Z0 - 1);
-    fetch(Z0);
-    stash(Z0);
-    __syncthreads();
-    // step j: fetch plane j + 2, relax the red cells of plane j (old planes
-    // j - 1 .. j + 1), put plane j + 2 into the value slot plane j - 2 held
-    // and into the flag slot of plane j - 3 (the black phase reads the flags
-    // of planes j - 2 .. j), then relax the black cells of plane j - 1 (new
-    // red planes j - 2 .. j)
-    for (int j = Z0 - 1; j <= Z1; ++j) {
-        const bool ahead = j + 2 <= Z1 + 1;
-        if (ahead) fetch(j + 2);
-        // new red values of plane j on the tile and a one-cell ring
-        int jw;
-        if (exists(j, jw)) {
-            const CT *om = s_old[(j - 1 - Z0 + 8) & 3], *o0 = s_old[(j - Z0 + 8) & 3],
-                     *op = s_old[(j + 1 - Z0 + 8) & 3];
-            const uint8_t *fm = s_fl[fslot(j - 1)], *f0 = s_fl[fslot(j)], *fp = s_fl[fslot(j + 1)];
-            CT *rn = s_rn[(j - Z0 + 6) % 3];
-#pragma unroll
-            for (int m = 0; m < kNRed; ++m) {
-                const int i = tid + m * kFBlock;
-                if (i >= kRH * (kRW / 2)) break;
-                const int r = i / (kRW / 2), k = i - r * (kRW / 2);
-                const int c = 2 * k + ((X0 + Y0 + r + j) & 1);  // (x + y + z) even
-                const int O = (r + 1) * kOW + (c + 1);          // in the old planes
-                const uint8_t fl = f0[O];
-                if (fl & (kWall | kObst)) continue;  // also outside a non-periodic edge
-                const int gx = X0 - 1 + c < 0 ? X0 - 1 + c + g.nx
-                               : X0 - 1 + c >= g.nx ? X0 - 1 + c - g.nx : X0 - 1 + c;
-                const int gy = Y0 - 1 + r < 0 ? Y0 - 1 + r + g.ny
-                               : Y0 - 1 + r >= g.ny ? Y0 - 1 + r - g.ny : Y0 - 1 + r;
-                const int nb[4] = {O - 1, O + 1, O - kOW, O + kOW};
-                rn[r * kRW + c] = relax<CT>(
-                    a, gx, gy, jw, fl, o0[O], src,
-                    [&](int d) { return d < 4 ? o0[nb[d]] : d == 4 ? om[O] : op[O]; },
-                    [&](int d) { return d < 4 ? f0[nb[d]] : d == 4 ? fm[O] : fp[O]; },
-                    [&](int d) { return neighbour_index(g, gx, gy, jw, d); });
+// after the solve: the obstacle cells' own values back into both buffers
+// (the result is in either); same walk as k_sor_prepare
+template <typename CT>
+__global__ void __launch_bounds__(256) k_dirichlet_restore(SorArgs a, CT *p0, CT *p1, const CT *save) {
+    const Grid &g = a.g;
+    const size_t c0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 16;
+    if (c0 >= g.N) return;
+    const uint4 q = *reinterpret_cast<const uint4 *>(a.flag + c0);
+    const uint32_t fw[4] = {q.x, q.y, q.z, q.w};
+    const uint32_t ob = 0x01010101u * (uint32_t)kObst;
+    if (!((fw[0] | fw[1] | fw[2] | fw[3]) & ob)) return;
+    const size_t nx = (size_t)g.nx;
+    size_t yz = c0 / nx;
+    int x = (int)(c0 - yz * nx);
+    int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
+    for (int k = 0; k < 16; ++k) {
+        const size_t c = c0 + (size_t)k;
+        if (c >= g.N) break;
+        const uint8_t fl = (uint8_t)(fw[k >> 2] >> (8 * (k & 3)));
+        if ((fl & kObst) && !(fl & kWall) && a.owner[c] != kNone) {
+            const size_t sl = (size_t)((x + y + z) & 1) * (g.Ns >> 1) + (c >> 1);
+            p0[sl] = save[sl];
+            p1[sl] = save[sl];
+        }
+        if (++x == g.nx) {
+            x = 0;
+            if (++y == g.ny) {
+                y = 0;
+                ++z;
             }
         }
-        if (ahead) stash(j + 2);
-        __syncthreads();
-        // plane j - 1 of the tile: new black values from the new red ones,
-        // new red values, unchanged boundary cells
-        const int jj = j - 1;
-        if (jj >= Z0) {
-            int jjw;
-            exists(jj, jjw);
-            const CT *o0 = s_old[(jj - Z0 + 8) & 3];
-            const uint8_t *fm = s_fl[fslot(jj - 1)], *f0 = s_fl[fslot(jj)],
-                          *fp = s_fl[fslot(jj + 1)];
-            const CT *rm = s_rn[(jj - 1 - Z0 + 6) % 3], *r0 = s_rn[(jj - Z0 + 6) % 3],
-                     *rp = s_rn[(jj + 1 - Z0 + 6) % 3];
-            const size_t base = nxy * (size_t)jjw;
-            const int c = tid % kFTX;
-            const int gx = X0 + c;
-#pragma unroll
-            for (int m = 0; m < kNBlack; ++m) {
-                const int r = tid / kFTX + m * (kFBlock / kFTX);
-                const int gy = Y0 + r;
-                if (gx >= g.nx || gy >= g.ny) continue;
-                const int O = (r + 2) * kOW + (c + 2), Rr = (r + 1) * kRW + (c + 1);
-                const uint8_t fl = f0[O];
-                CT out;
-                if (fl & (kWall | kObst)) {
-                    out = o0[O];
-                } else if (((gx + gy + jjw) & 1) == 0) {
-                    out = r0[Rr];
-                } else {
-                    const int nr[4] = {Rr - 1, Rr + 1, Rr - kRW, Rr + kRW};
-                    const int nb[4] = {O - 1, O + 1, O - kOW, O + kOW};
-                    out = relax<CT>(
-                        a, gx, gy, jjw, fl, o0[O], src,
-                        [&](int d) { return d < 4 ? r0[nr[d]] : d == 4 ? rm[Rr] : rp[Rr]; },
-                        [&](int d) { return d < 4 ? f0[nb[d]] : d == 4 ? fm[O] : fp[O]; },
-                        [&](int d) { return neighbour_index(g, gx, gy, jjw, d); });
-                }
-                dst[base + (size_t)(gx + nx * gy)] = out;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -1083,15 +1215,37 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const uint32_t vblk = vxb * vyb * (uint32_t)((g.nz + (int)a0.zc - 1) / (int)a0.zc);
     // even nx: psi is colour-split, the z-marching tiles relax the interior
     const bool vec = (g.nx % 2) == 0;
-    const int ntx = (g.nx + kFTX - 1) / kFTX, nty = (g.ny + kFTY - 1) / kFTY;
-    const int ntz = (g.nz + kFZC - 1) / kFZC;
-    const uint32_t nfused = (uint32_t)ntx * (uint32_t)nty * (uint32_t)ntz;
+    // one pass per iteration: even nx, whole rows in one workgroup, a second
+    // buffer; rows per thread: the largest of mrw, mrw / 2, ... dividing ny
+    const bool march = fused && vec && hx <= 64 * kMarchMaxWaves && a0.psi2 != nullptr;
+    // windows of more than 4 rows per thread spill
+    int mrw = a0.mrw >= 4 ? 4 : (a0.mrw >= 2 ? 2 : 1);
+    while (g.ny % mrw) mrw >>= 1;
+    const uint32_t mzc = a0.mzc >= 1 ? a0.mzc : 16u;
+    const uint32_t myb = (uint32_t)(g.ny / mrw);
+    const uint32_t mblk = myb * (uint32_t)((g.nz + (int)mzc - 1) / (int)mzc);
+    const uint32_t mthreads = 64u * (uint32_t)((hx + 63) / 64);
     const size_t rblk = (g.N + kResBlock - 1) / kResBlock;
     const int nres = (int)(rblk < (size_t)(kSorPartials / 2) ? rblk : (size_t)(kSorPartials / 2));
     const bool with_res = a0.rf > 0.0;
     SorArgs a = a0;  // a.psi: the buffer holding the current iterate
     hipLaunchKernelGGL(k_sor_begin, dim3(1), dim3(64), 0, s, a.ctl);
-    if (!fused) {
+    const bool dirichlet = march && a0.zeta && a0.owner;  // obstacle cells hold zeta meanwhile
+    const uint32_t ncb = (uint32_t)((g.N + 16 * 256 - 1) / (16 * 256));
+    if (march) {
+        // what k_sor_march assumes of its launch: whole rows in one workgroup
+        // (at most kMarchMaxWaves wavefronts), rows per thread dividing ny
+        if (mthreads > 64u * kMarchMaxWaves || hx < 1 || g.ny % mrw != 0 || myb < 1 || !a0.codes ||
+            (dirichlet && !a0.save))
+            return hipErrorInvalidValue;
+        // the interior bits (one pass over the flags) and the codes of the rows
+        const size_t words = sor_ibits_words_per_colour(g.N);
+        hipLaunchKernelGGL(k_interior_bits_split, dim3((uint32_t)((words + 255) / 256)), dim3(256),
+                           0, s, g, a.flag, a.ibits);
+        hipLaunchKernelGGL((k_sor_prepare<CT>), dim3(ncb), dim3(256), 0, s, a,
+                           static_cast<CT *>(a0.psi), static_cast<CT *>(a0.save),
+                           dirichlet ? 1 : 0);
+    } else {
         const uint32_t nseg = (uint32_t)((g.N + kNearSeg - 1) / kNearSeg);
         if (vec) {
             // one pass over the flags into the bitmaps; the lists from the
@@ -1118,11 +1272,17 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
         hipLaunchKernelGGL(k_dha_finalize, dim3(1), dim3(kResBlock), 0, s, a, nres, 1);
     }
     for (int it = 1; it <= max_iter; ++it) {
-        if (fused) {
-            void *next = a.psi == a0.psi ? a0.psi2 : a0.psi;
-            hipLaunchKernelGGL((k_sor_fused<CT>), dim3(nfused), dim3(kFBlock), 0, s, a,
-                               static_cast<const CT *>(a.psi), static_cast<CT *>(next), ntx, nty);
-            a.psi = next;
+        if (march) {
+            const CT *src = static_cast<const CT *>(a.psi);
+            CT *dst = static_cast<CT *>(a.psi == a0.psi ? a0.psi2 : a0.psi);
+#define LBMEP_SOR_MARCH(RW)                                                                  \
+    hipLaunchKernelGGL((k_sor_march<CT, RW>), dim3(mblk), dim3(mthreads), 0, s, a, src, dst, myb, \
+                       mzc)
+            if (mrw == 4) LBMEP_SOR_MARCH(4);
+            else if (mrw == 2) LBMEP_SOR_MARCH(2);
+            else LBMEP_SOR_MARCH(1);
+#undef LBMEP_SOR_MARCH
+            a.psi = dst;
         } else {
             for (int col = 0; col < 2; ++col) {
                 if (vec) {
@@ -1146,7 +1306,8 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
                     hipLaunchKernelGGL((k_sor_half<CT>), dim3(nblk), dim3(kSorBlock), 0, s, a,
                                        col, col, nxb, nyb);
                     hipLaunchKernelGGL((k_sor_near<CT>), dim3(kNearGrid), dim3(kNearBlock), 0, s,
-                                       a, col);
+                                       a, col, static_cast<const CT *>(a.psi),
+                                       static_cast<CT *>(a.psi));
                 }
             }
         }
@@ -1162,11 +1323,17 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
             if (done) break;
         }
     }
+    // the obstacle cells' own values back, in both buffers (the result is in
+    // either)
+    if (dirichlet)
+        hipLaunchKernelGGL((k_dirichlet_restore<CT>), dim3(ncb), dim3(256), 0, s, a,
+                           static_cast<CT *>(a0.psi), static_cast<CT *>(a0.psi2),
+                           static_cast<const CT *>(a0.save));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the fused iterations alternate buffers: which one holds the result
+    // the one-pass iterations alternate buffers: which one holds the result
     *swapped = 0;
-    if (fused) {
+    if (march) {
         int32_t iters = max_iter;
         if (with_res) {
             e = hipMemcpyAsync(&iters, &a.ctl->iters, sizeof iters, hipMemcpyDeviceToHost, s);
@@ -1184,17 +1351,8 @@ hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int c
                             bool fused, hipStream_t s, int *swapped) {
     *swapped = 0;
     if (a.g.N == 0) return hipSuccess;
-    // the fused iteration is switched off until its plane-ring fix has run
-    // on the device (it is also written for the plain cell order of psi,
-    // not the colour-split order of even nx): its flag ring shared 4 slots
-    // with the values, so the
-    // black phase read the z- flags of a plane already replaced by the
-    // prefetch (a stale obstacle flag then indexed zeta with kNone)
-    if (fused) return hipErrorNotSupported;
     if (a.zc < 1) return hipErrorInvalidValue;
     if (fused && !a.psi2) return hipErrorInvalidValue;
-    // the fused kernel keeps 32-bit in-plane offsets
-    if ((size_t)a.g.nx * (size_t)a.g.ny >= ((size_t)1 << 31)) fused = false;
     if (precision == LBMEP_FP64)
         return sor_solve_typed<double>(a, max_iter, check_every, fused, s, swapped);
     return sor_solve_typed<float>(a, max_iter, check_every, fused, s, swapped);

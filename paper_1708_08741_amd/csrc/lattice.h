@@ -78,9 +78,11 @@ struct lbmep_lattice {
     void *sor_nrow = nullptr;          // per list entry: diag, rhs (compute precision)
     uint8_t *sor_nmask = nullptr;      // per list entry: unknown neighbours
     uint32_t *sor_ibits = nullptr;     // interior unknowns, one bit per cell
-    void *psi2 = nullptr;      // second psi buffer of the fused SOR iteration
+    void *psi2 = nullptr;      // second psi buffer of the one-pass SOR iteration
+    void *sor_save = nullptr;  // one-pass SOR: obstacle cells' values while they hold zeta
+    uint32_t *sor_codes = nullptr;  // one-pass SOR: row codes of both colours per entry
     size_t psi2_bytes = 0;
-    bool sor_fused = false;    // fused iteration (switched off: one launch per colour)
+    bool sor_fused = false;    // one-pass iteration (even nx, rows of up to 2048 cells)
     double *red = nullptr;
     int red_blocks = 0;
     int block_x = 128;
@@ -90,6 +92,8 @@ struct lbmep_lattice {
     int sor_xcd = 1;  // XCD-contiguous tile order
     int sor_rows = 8; // rows per thread of the tile (4, 8; set per precision)
     int sor_near_blocks = 0;  // workgroups of the SOR's boundary list part (0: default)
+    int sor_mzc = 16; // planes per workgroup of the one-pass SOR iteration
+    int sor_mrw = 4;  // rows per thread of the one-pass SOR iteration (set per precision)
     int xcd_swizzle = 1;
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     bool timing = false;
@@ -114,6 +118,10 @@ int fail(int code, const std::string &msg);
 
 size_t round_up(size_t n, size_t m);
 size_t storage_bytes(int precision);
+// stride (in elements) between the arrays of two populations: N rounded up
+// to 128 plus a pad that staggers the 19 arrays against the HBM channel
+// interleave
+size_t population_stride(size_t N, int precision);
 size_t compute_bytes(int precision);
 bool finite_all(const double *p, size_t n);
 int check_config(const lbmep_config *cfg);

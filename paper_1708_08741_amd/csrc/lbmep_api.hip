@@ -34,6 +34,22 @@ size_t storage_bytes(int precision) {
     return precision == LBMEP_FP64 ? 8 : (precision == LBMEP_FP32DEV ? 4 : 2);
 }
 
+// With a stride of exactly N = 2^k elements, the 19 source and 19
+// destination streams of the sweep start at the same offset modulo every
+// power of two, so the same cell of every population maps to the same HBM
+// channel and bank; at 512^3 the pull pattern then moves ~7 % less data per
+// second than with the arrays staggered.  The pad (in elements, a multiple
+// of 128 so that the colour-split potential's halves stay aligned) is the
+// best of a measured sweep per storage size (LBMEP_POP_PAD overrides it).
+size_t population_stride(size_t N, int precision) {
+    size_t pad = precision == LBMEP_FP64 ? 256 : 2048;
+    if (const char *e = std::getenv("LBMEP_POP_PAD")) {
+        const long v = std::atol(e);
+        if (v >= 0) pad = round_up((size_t)v, 128);
+    }
+    return round_up(N, 128) + pad;
+}
+
 size_t compute_bytes(int precision) { return precision == LBMEP_FP64 ? 8 : 4; }
 
 bool finite_all(const double *p, size_t n) {
@@ -181,7 +197,7 @@ void free_particles(lbmep_lattice *L) {
 size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
                      int force_mode) {
     const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
-    const size_t Ns = round_up(N, 128);
+    const size_t Ns = population_stride(N, cfg->precision);
     size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
     b += round_up(N, 4096) + 4 * round_up(N, 4096) + 4 * N;      // flags, wall masks, wall list
     if (n_particles > 0) {
@@ -275,6 +291,8 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->sor_nmask);
     dev_free(L, L->sor_ibits);
     dev_free(L, L->psi2);
+    dev_free(L, L->sor_save);
+    dev_free(L, L->sor_codes);
     free_particles(L);
     for (hipEvent_t e : L->ev) hipEventDestroy(e);
     delete L;
@@ -301,7 +319,7 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     g.nz = cfg->nz;
     for (int k = 0; k < 3; ++k) g.per[k] = cfg->periodic[k] ? 1 : 0;
     g.N = (size_t)g.nx * g.ny * g.nz;
-    g.Ns = round_up(g.N, 128);
+    g.Ns = population_stride(g.N, cfg->precision);
     // Eq. kinVisc: nu = (tau - 1/2) c_s^2; lambda_e = -1/tau (Sec. 3.1); the
     // odd rate from Lambda = (1/s_e - 1/2)(1/s_o - 1/2), s = -lambda
     L->tau = cfg->nu * 3.0 + 0.5;
@@ -319,7 +337,12 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     // stores (every value is read once and written once per step);
     // LBMEP_BLOCK_X, LBMEP_CPT, LBMEP_XCD_SWIZZLE and LBMEP_SWEEP_NT override
     // the defaults for launch-shape sweeps
-    L->block_x = 128;
+    // measured at 512^3 (4096 spheres): FP32 is fastest with 256-cell
+    // segments in hardware order (every XCD streams the same planes: 5.45
+    // against 5.11 TB/s with XCD-contiguous 128-cell segments); FP16 with
+    // 256-cell segments in XCD-contiguous order; FP64 with 128-cell ones
+    L->block_x = L->precision == LBMEP_FP64 ? 128 : 256;
+    L->xcd_swizzle = L->precision != LBMEP_FP32DEV;
     L->cpt = 1;
     if (const char *e = std::getenv("LBMEP_CPT")) {
         const int c = std::atoi(e);
@@ -341,6 +364,16 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     if (const char *e = std::getenv("LBMEP_SOR_NEARBLK")) {
         const int c = std::atoi(e);
         if (c >= 8 && c <= 65536 && c % 8 == 0) L->sor_near_blocks = c;
+    }
+    // one-pass SOR iteration: rows per thread and planes per workgroup
+    L->sor_mrw = 4;
+    if (const char *e = std::getenv("LBMEP_SOR_MRW")) {
+        const int c = std::atoi(e);
+        if (c == 1 || c == 2 || c == 4 || c == 8) L->sor_mrw = c;
+    }
+    if (const char *e = std::getenv("LBMEP_SOR_MZC")) {
+        const int c = std::atoi(e);
+        if (c >= 1 && c <= 1024) L->sor_mzc = c;
     }
     if (const char *e = std::getenv("LBMEP_SOR_ROWS")) {
         const int c = std::atoi(e);
@@ -647,6 +680,10 @@ static SorArgs sor_args(const lbmep_lattice *L) {
     a.wx = (uint32_t)L->sor_wx;
     a.rows = (uint32_t)L->sor_rows;
     a.near_blocks = (uint32_t)L->sor_near_blocks;
+    a.codes = L->sor_codes;
+    a.save = L->sor_save;
+    a.mzc = (uint32_t)L->sor_mzc;
+    a.mrw = (uint32_t)L->sor_mrw;
     return a;
 }
 
@@ -691,24 +728,30 @@ int lbmep_set_potential_solver(lbmep_lattice *L, double kappa2, double omega, in
         if (dev_alloc(L, &L->sor_nrow, 2 * compute_bytes(L->precision) *
                                            sor_nlist_entries(L->g.N)) != hipSuccess ||
             dev_alloc(L, (void **)&L->sor_nmask, sor_nlist_entries(L->g.N)) != hipSuccess ||
-            dev_alloc(L, (void **)&L->sor_ibits, 4 * 4 * sor_ibits_words_per_colour(L->g.N)) !=
+            dev_alloc(L, (void **)&L->sor_ibits, 6 * 4 * sor_ibits_words_per_colour(L->g.N)) !=
                 hipSuccess)
             return fail(LBMEP_ENOMEM, "solver boundary rows");
         SorCtl c{};
         c.res0 = c.res = -1.0;
         HIP_TRY(hipMemcpy(L->sor_ctl, &c, sizeof c, hipMemcpyHostToDevice));
     }
-    // one launch per colour; the fused iteration is switched off
-    L->sor_fused = false;
+    // one pass per iteration where it applies (even nx, rows of up to 2048
+    // cells), else one launch per colour; LBMEP_SOR_FUSED=0 forces the latter
+    L->sor_fused = L->g.nx % 2 == 0 && L->g.nx <= 2048;
+    if (const char *e = std::getenv("LBMEP_SOR_FUSED")) L->sor_fused = L->sor_fused && std::atoi(e) != 0;
     const size_t need = L->g.Ns * compute_bytes(L->precision);
     if (L->sor_fused && L->psi2_bytes < need) {
         dev_free(L, L->psi2);
-        L->psi2 = nullptr;
+        dev_free(L, L->sor_save);
+        L->psi2 = L->sor_save = nullptr;
         L->psi2_bytes = 0;
-        if (dev_alloc(L, &L->psi2, need) != hipSuccess)
+        if (dev_alloc(L, &L->psi2, need) != hipSuccess || dev_alloc(L, &L->sor_save, need) != hipSuccess)
             return fail(LBMEP_ENOMEM, "second potential buffer");
         L->psi2_bytes = need;
     }
+    if (L->sor_fused && !L->sor_codes &&
+        dev_alloc(L, (void **)&L->sor_codes, 4 * (L->g.N / 2 + 1)) != hipSuccess)
+        return fail(LBMEP_ENOMEM, "solver row codes");
     L->sor_kappa2 = kappa2;
     L->sor_omega = omega;
     L->sor_iters = max_iter;

@@ -249,13 +249,18 @@ struct SorArgs {
     uint32_t *nscratch;        // per-segment counts / offsets of the list build
     void *nrow;                // per list entry: diag and rhs of the row (2 compute values)
     uint8_t *nmask;            // per list entry: bit k = neighbour k is an unknown
-    uint32_t *ibits;           // 4 arrays of (N/2 + 31)/32 words: the interior bitmaps of the
-                               // two colours, then their boundary bitmaps
+    uint32_t *ibits;           // 6 arrays of (N/2 + 31)/32 words: the interior bitmaps of the
+                               // two colours, their boundary bitmaps, then the two interior
+                               // bitmaps interleaved word by word
     uint32_t xcd_swizzle;
     uint32_t zc;               // planes per workgroup of the interior half-sweep (>= 1)
     uint32_t wx;               // waves along x of its workgroup tile (1, 2 or 4)
     uint32_t rows;             // rows per thread of the tile (4 or 8)
     uint32_t near_blocks;      // workgroups of the boundary list part (0: default; % 8 == 0)
+    uint32_t *codes;           // one-pass iteration: per entry the codes of its two cells
+    void *save;                // one-pass iteration: obstacle cells' values (Ns compute values)
+    uint32_t mzc;              // planes per workgroup of the one-pass iteration (>= 1)
+    uint32_t mrw;              // rows per thread of the one-pass iteration (1, 2, 4)
 };
 constexpr int kSorPartials = 8192;
 // the boundary lists are built per segment of kNearSeg cells
@@ -267,10 +272,10 @@ __host__ __device__ inline size_t sor_ibits_words_per_colour(size_t N) { return 
 // one solve on the current map: max_iter iterations of (red, black), with
 // rf > 0 a residual before the first and after every check_every-th (and the
 // last) iteration, stopping at res < rf res0 (the host reads the control
-// block every 64 iterations and stops launching once it is done).  fused:
-// one launch per iteration from psi into psi2 and back; *swapped = 1 when
-// the result ends in psi2 (the caller swaps the buffers).  Otherwise one
-// launch per colour in place.
+// block every 64 iterations and stops launching once it is done).  fused
+// (even nx, rows of up to 2048 cells): one pass per iteration from psi into
+// psi2 and back; *swapped = 1 when the result ends in psi2 (the caller swaps
+// the buffers).  Otherwise one launch per colour in place.
 hipError_t launch_sor_solve(int precision, const SorArgs &a, int max_iter, int check_every,
                             bool fused, hipStream_t s, int *swapped);
 hipError_t launch_potential_to_f64(int precision, const Grid &g, const void *psi, double *out,

@@ -141,7 +141,7 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 
 bool small_offsets(const lbmep_config &c) {
     const size_t N = (size_t)c.nx * c.ny * c.nz;
-    const size_t Ns = round_up(N, 128);
+    const size_t Ns = population_stride(N, c.precision);
     return 2 * Ns * storage_bytes(c.precision) < (size_t(1) << 32) && 4 * Ns < (size_t(1) << 32);
 }
 

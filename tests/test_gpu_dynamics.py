@@ -2,11 +2,14 @@
 (Alg. "Electrophoresis Algorithm", last block: the step's hydrodynamic force
 and torque plus q E of the applied field move the spheres).
 
-Bars: maps bit-exact; FP64 positions, velocities, angular velocities,
-fields, forces and torques within 1e-12 relative (the hydrodynamic sums
-differ from the oracle's only in summation order); FP32 deviation storage
-within the tolerances of the prescribed-motion runs, with velocities and
-positions relative to the largest velocity change.
+Bars: maps bit-exact; FP64 velocities, angular velocities, fields, forces
+and torques within 1e-12 relative, positions within 1e-12 of the distance
+a particle can travel in the run (steps x max |U|: X is integrated from U,
+so its error is the velocity error accumulated over the steps; the
+hydrodynamic sums differ from the oracle's by rounding, the oracle summing
+the plain link terms in long double, the library the deviation part in
+FP64 and the rest-weight part exactly); FP32 deviation storage within the
+tolerances of the prescribed-motion runs.
 """
 import numpy as np
 import pytest
@@ -25,7 +28,7 @@ def lb():
     return lbmep
 
 
-def _compare(o, g, prec, lbm, tol_f, label):
+def _compare(o, g, prec, lbm, tol_f, label, steps):
     fo, oo = o.map()
     fg, og = g.map()
     assert (fg == fo).all() and (og == oo).all(), label
@@ -39,7 +42,7 @@ def _compare(o, g, prec, lbm, tol_f, label):
     sU = np.abs(Uo).max()
     sW = max(np.abs(Wo).max(), 1e-30)
     sF = np.abs(F_o).max()
-    err = dict(X=np.abs(Xg - Xo).max() / sU, U=np.abs(Ug - Uo).max() / sU,
+    err = dict(X=np.abs(Xg - Xo).max() / (steps * sU), U=np.abs(Ug - Uo).max() / sU,
                W=np.abs(Wg - Wo).max() / sW, F=np.abs(F_g - F_o).max() / sF,
                M=np.abs(M_g - M_o).max() / np.abs(M_o).max(),
                u=np.abs(u_g - u_o)[:, fluid].max() / np.abs(u_o[:, fluid]).max(),
@@ -108,7 +111,7 @@ def test_free_charged_spheres(lb, oracle_mod, precision):
     g.set_particles(c["X"], c["R"], c["U"], c["W"])
     g.set_dynamics(c["rho_p"], c["q"], c["E"])
     g.step(steps)
-    _compare(o, g, prec, lb, TOL64 if precision == "fp64" else TOL32, precision)
+    _compare(o, g, prec, lb, TOL64 if precision == "fp64" else TOL32, precision, steps)
     g.close()
 
 
@@ -149,7 +152,7 @@ def test_electrophoresis_loop(lb, oracle_mod, precision):
     g.set_dynamics(1.2, q, E)
     g.init_equilibrium()
     g.step(steps)
-    _compare(o, g, prec, lb, TOL64 if precision == "fp64" else TOL32, precision)
+    _compare(o, g, prec, lb, TOL64 if precision == "fp64" else TOL32, precision, steps)
     psi_o, psi_g = o.potential(), g.potential()
     assert np.abs(psi_g - psi_o).max() <= (1e-12 if prec == lb.FP64 else 1e-5) * np.abs(psi_o).max()
     g.close()

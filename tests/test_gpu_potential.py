@@ -361,25 +361,32 @@ def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, wit
                 assert r0_g == -1.0 and r_g == -1.0
 
 
-@pytest.mark.parametrize("shape,periodic,n,rf", [
-    ((130, 34, 70), (False, True, True), 6, 0.0),
-    ((64, 16, 32), (True, True, True), 3, 0.0),
-    ((66, 18, 34), (True, True, True), 4, 1e-3),
-    ((7, 5, 3), (False, False, False), 1, 0.0),
-    ((2, 2, 2), (True, True, True), 0, 0.0),
-    ((1, 1, 1), (False, False, False), 0, 0.0),
+@pytest.mark.parametrize("shape,periodic,n,rf,mzc,mrw", [
+    ((130, 34, 70), (False, True, True), 6, 0.0, "16", "8"),
+    ((64, 16, 32), (True, True, True), 3, 0.0, "5", "8"),
+    ((66, 18, 34), (True, True, True), 4, 1e-3, "16", "8"),   # ny = 18: 2 rows per thread
+    ((256, 12, 10), (True, True, False), 5, 0.0, "3", "8"),   # ny = 12: 4 rows per thread
+    ((2048, 4, 6), (True, True, True), 3, 0.0, "4", "4"),     # 16 wavefronts per row
+    ((2050, 4, 6), (True, True, True), 3, 0.0, "16", "8"),    # rows too long: two launches
+    ((18, 6, 20), (False, False, False), 2, 0.0, "1", "2"),
+    ((130, 35, 9), (True, False, False), 4, 0.0, "16", "8"),  # odd ny: one row per thread
+    ((7, 5, 3), (False, False, False), 1, 0.0, "16", "8"),    # odd nx: cell order
+    ((2, 2, 2), (True, True, True), 0, 0.0, "16", "8"),
+    ((1, 1, 1), (False, False, False), 0, 0.0, "16", "8"),
 ])
-@pytest.mark.skip(reason="fused SOR iteration switched off: a plane-ring slot overwrite (z- flags "
-                         "of the black phase) faulted the GPU; fixed in the source, not yet run")
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sor_fused_equals_two_pass(lb, monkeypatch, shape, periodic, n, rf, precision):
-    """The fused iteration (one launch, tiles of 64 x 16 with plane rings,
-    chunks of 32 planes, two buffers) gives bitwise the psi of the in-place
-    one-launch-per-colour form: several tiles and chunks with ragged tails,
-    periodic wrap of the halos, walls, particles, tiny grids; odd and even
-    iteration counts, with and without a residual stop."""
+def test_sor_one_pass_equals_two_pass(lb, monkeypatch, shape, periodic, n, rf, mzc, mrw, precision):
+    """The one-pass iteration (a z-march from psi into a second buffer
+    between the red and black boundary lists) gives bitwise the psi and the
+    iteration count of the in-place one-launch-per-colour form: chunks of 1,
+    3, 4, 5 and 16 planes with ragged tails, 1, 2, 4 and 8 rows per thread,
+    1 to 16 wavefronts per row, periodic wrap of every halo, walls,
+    particles with and without surface potentials, non-periodic edges, tiny
+    grids; odd and even iteration counts, with and without a residual stop."""
     psi, fl, X, R, zeta = _sor_case(shape, periodic, True, n, True, 9)
     out = {}
+    monkeypatch.setenv("LBMEP_SOR_MZC", mzc)
+    monkeypatch.setenv("LBMEP_SOR_MRW", mrw)
     for fused in ("1", "0"):
         monkeypatch.setenv("LBMEP_SOR_FUSED", fused)
         res = []
@@ -387,7 +394,7 @@ def test_sor_fused_equals_two_pass(lb, monkeypatch, shape, periodic, n, rf, prec
             g = lb.Lattice(shape, periodic, precision=precision)
             g.set_flags(fl)
             g.set_particles(X, R, np.zeros((n, 3)))
-            g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta)
+            g.set_potential_force(psi, KEPS, (0.0, 0.0, 0.0), zeta if iters == 7 else None)
             g.set_potential_solver(0.3, 1.7, iters, rf, 2)
             st = g.solve_potential()
             res.append((st, g.potential()))
@@ -418,6 +425,7 @@ def test_sor_plane_chunks_identical(lb, monkeypatch, shape, periodic, n, precisi
     with several row segments and tiles with ragged ends, periodic wrap in
     z and y, walls and particles."""
     psi, fl, X, R, zeta = _sor_case(shape, periodic, True, n, True, 11)
+    monkeypatch.setenv("LBMEP_SOR_FUSED", "0")  # the in-place half-sweeps
     ref = None
     for zc, wx, xcd, rows, nblk in (("1", "1", "0", "4", "8"), ("3", "1", "1", "4", "1024"),
                                     ("8", "2", "0", "4", "256"), ("1024", "4", "1", "4", "64"),
