@@ -42,6 +42,10 @@ SWEEP_KERNEL = {"fp32dev": "k_sweep<float, 2, unsigned int, 4, 1>",
                 "fp64": "k_sweep<double, 2, unsigned int, 4, 1>",
                 "fp16dev": "k_sweep<__half, 2, unsigned int, 3, 1>"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "sweep_impl.h")
+# the sweep's launch shape (segment width, block order, population stride) is
+# set in the API source: counters taken on other settings do not apply
+LAUNCH_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "lbmep_api.hip")
+SERVE_FULL = os.path.join(ROOT, "profiles", "serving_2000_requests_fp32.json")
 
 
 def log(*a):
@@ -49,15 +53,19 @@ def log(*a):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in (KERNEL_SRC, LAUNCH_SRC):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 SOR_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "k_potential.hip")
 
 
 def sor_traffic():
-    """HBM bytes per FP32 interior half-sweep from the committed counter
-    summary, if it was taken on the current SOR source; else None."""
+    """HBM bytes of one FP32 one-pass SOR iteration (k_sor_march) from the
+    committed counter summary, if it was taken on the current SOR source;
+    else None."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -66,7 +74,7 @@ def sor_traffic():
     if d.get("sor_kernel_sha") != sha:
         return None
     for k, e in d.get("other_kernels", {}).items():
-        if k.startswith("k_sor_half_vec<float"):
+        if k.startswith("k_sor_march<float"):
             return e.get("hbm_bytes_per_launch")
     return None
 
@@ -165,62 +173,181 @@ def run_coupled(wl, precision, steps, warmup, sor_iters, kappa=0.5):
     e1.record(stream)
     torch.cuda.synchronize()
     solve_ms = e0.elapsed_time(e1) / solves
+    shape = L.solver_shape()
     L.close()
     torch.cuda.empty_cache()
-    return dict(step_ms=step_ms, solve_ms=solve_ms)
+    return dict(step_ms=step_ms, solve_ms=solve_ms, shape=shape)
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle on a bounded sample: the 128^3 sub-run of the same
-    workload shape (64 moving R=4 spheres, same force construction).
-    Returns the baseline record and the oracle state (for the error check)."""
+def _time_oracle(wl, steps, repeats, threads):
+    """Median wall time per step of the oracle on workload wl (after a
+    5-step warm-up), with the given OpenMP thread count."""
+    from oracle import oracle as O
+    O.set_num_threads(threads)
+    o = O.from_workload(wl)
+    o.step(5)
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        o.step(steps)
+        ts.append((time.perf_counter() - t0) / steps)
+    fl, _ = o.map()
+    nfluid = int(((fl == O.FLUID) | (fl == O.NEAR)).sum())
+    o.close()
+    return float(np.median(ts)), nfluid
+
+
+def cpu_baseline():
+    """The FP64 oracle on bounded samples of the two 128^3 configurations:
+    the sub-run of the 512^3 suspension (64 moving R=4 spheres, charge force)
+    and the channel (walls y=0,127, 64 moving R=6 spheres), each on every
+    host core and on one core; median of 3 timed repeats after a 5-step
+    warm-up.  `value` is the all-core rate on the sub-run (the headline
+    workload's shape)."""
     from oracle import oracle as O
     from paper_1708_08741_amd import workloads as W
 
-    wl = W.suspension_subrun(precision="fp64")
-    o = O.from_workload(wl)
-    t0 = time.perf_counter()
-    o.step(3)
-    per = (time.perf_counter() - t0) / 3
-    n = max(2, int(target_s / per))
-    t0 = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t0
-    cells = wl.ncells
-    rec = {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
+    cores = O.num_threads()
+    out = {}
+    for name, wl in (("subrun128", W.suspension_subrun(precision="fp64")),
+                     ("channel128", W.channel_spheres())):
+        for label, threads, steps in (("all_cores", cores, 10), ("one_core", 1, 2)):
+            per, nfluid = _time_oracle(wl, steps, 3, threads)
+            out[f"{name}_{label}"] = {"MLUPS": round(wl.ncells / per / 1e6, 3),
+                                      "MFLUPS": round(nfluid / per / 1e6, 3),
+                                      "threads": threads, "steps_timed": steps}
+            log(f"[bench] oracle {name} {label}: {out[f'{name}_{label}']}")
+    O.set_num_threads(cores)
+    rec = {"value": out["subrun128_all_cores"]["MLUPS"], "unit": "MLUPS", "cores": cores,
            "kind": "oracle",
-           "sample": f"128^3 periodic sub-run, 64 moving R=4 spheres, charge force, FP64, "
-                     f"{n} steps timed ({dt:.1f} s) after 3 untimed"}
-    return rec, wl, o, n + 3
+           "sample": "128^3 periodic sub-run (64 moving R=4 spheres, charge force), FP64, median "
+                     "of 3 x 10 steps after 5 warm-up steps, all host cores; also 1 core and the "
+                     "128^3 channel (64 moving R=6 spheres), see 'samples'",
+           "samples": out,
+           "paper_context_MFLUPS_per_16_core_node": 61.2}
+    return rec
 
 
-def precision_errors(wl, o, steps):
-    """Errors of the GPU FP64 / FP32-dev / FP16-dev runs of the oracle's
-    sub-run after the same number of steps (relative to max |u| over fluid
-    cells and max |F_p|; |drho| absolute; torque relative to max|F| R)."""
+def precision_errors(steps=500):
+    """Errors of the GPU FP64 / FP32-dev / FP16-dev runs of the 128^3
+    sub-run against the FP64 oracle after the configuration's 500 steps
+    (relative to max |u| over fluid cells and max |F_p|; |drho| absolute;
+    torque relative to max |F| R; FP64 mass and momentum sums: mass relative,
+    momentum relative to N_fluid max |u|)."""
     from oracle import oracle as O
     from paper_1708_08741_amd import lbmep as lb
+    from paper_1708_08741_amd import workloads as W
 
+    wl = W.suspension_subrun(precision="fp64", steps=steps)
+    o = O.from_workload(wl)
+    t0 = time.perf_counter()
+    o.step(steps)
+    log(f"[bench] oracle sub-run, {steps} steps: {time.perf_counter() - t0:.1f} s")
     rho_o, u_o = o.macro()
     F_o, M_o = o.ft()
     fl, _ = o.map()
+    inv_o = o.invariants()
+    o.close()
     fluid = (fl == O.FLUID) | (fl == O.NEAR)
     umax = np.abs(u_o[:, fluid]).max()
     sF = np.linalg.norm(F_o, axis=1).max()
+    scale_P = fluid.sum() * umax
     out = {"steps": steps, "workload": "128^3 sub-run (64 moving R=4 spheres)"}
     for p in ("fp64", "fp32dev", "fp16dev"):
         g = lb.from_workload(wl, precision=p)
         g.step(steps)
         rho_g, u_g = g.macro()
         F_g, M_g = g.ft()
+        inv_g = g.invariants()
         out[p] = {
             "u_rel": float(np.abs(u_g - u_o)[:, fluid].max() / umax),
             "rho_abs": float(np.abs(rho_g - rho_o)[fluid].max()),
             "F_rel": float(np.linalg.norm(F_g - F_o, axis=1).max() / sF),
             "M_rel": float(np.linalg.norm(M_g - M_o, axis=1).max() / (sF * 4.0)),
+            "mass_drift_rel": float(abs(inv_g[0] - inv_o[0]) / inv_o[0]),
+            "momentum_drift_rel": float(np.abs(inv_g[1:] - inv_o[1:]).max() / scale_P),
         }
         g.close()
     return out
+
+
+def fullsize_vs_fp64(wl, steps=500):
+    """FP32-dev and FP16-dev against GPU-FP64 on the full 512^3 suspension
+    after `steps` steps: u (relative to max |u| of the FP64 run over fluid
+    cells), rho (absolute), F (relative to max |F_p|), M (relative to max
+    |F| R) and the FP64 mass / momentum sums; compared on the device."""
+    import torch
+
+    from paper_1708_08741_amd import lbmep as lb
+
+    dev = torch.device("cuda")
+    n = wl.ncells
+    res = {}
+    ref = None
+    for p in ("fp64", "fp32dev", "fp16dev"):
+        L = lb.from_workload(wl, precision=p)
+        L.step(steps)
+        rho = torch.empty(n, dtype=torch.float64, device=dev)
+        u = torch.empty(3 * n, dtype=torch.float64, device=dev)
+        L.macro_device(rho, u)
+        F, M = L.ft()
+        inv = L.invariants()
+        if ref is None:
+            fl, _ = L.map()
+            fluid = torch.from_numpy(((fl == lb.FLUID) | (fl == lb.NEAR)).reshape(-1)).to(dev)
+            del fl
+            umax = u.view(3, n)[:, fluid].abs().max().item()
+            ref = dict(rho=rho, u=u, F=F, M=M, inv=inv, fluid=fluid, umax=umax,
+                       nfluid=int(fluid.sum().item()))
+        else:
+            fluid = ref["fluid"]
+            sF = np.linalg.norm(ref["F"], axis=1).max()
+            res[p] = {
+                "u_rel": (u - ref["u"]).view(3, n)[:, fluid].abs().max().item() / ref["umax"],
+                "rho_abs": (rho - ref["rho"])[fluid].abs().max().item(),
+                "F_rel": float(np.linalg.norm(F - ref["F"], axis=1).max() / sF),
+                "M_rel": float(np.linalg.norm(M - ref["M"], axis=1).max() / (sF * 4.0)),
+                "mass_drift_rel": float(abs(inv[0] - ref["inv"][0]) / ref["inv"][0]),
+                "momentum_drift_rel": float(np.abs(inv[1:] - ref["inv"][1:]).max() /
+                                            (ref["nfluid"] * ref["umax"])),
+            }
+            del rho, u
+        L.close()
+        torch.cuda.empty_cache()
+        log(f"[bench] {p} {steps} steps at full size done")
+    res["steps"] = steps
+    res["workload"] = "512^3 suspension (4096 moving R=4 spheres), against the GPU FP64 run"
+    del ref
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_reference_gbps(gib=4.0, iters=10):
+    """Achievable HBM bandwidth: the library's reference copy (16-byte lanes,
+    streaming stores) of `gib` GiB, bytes read + written per second."""
+    import torch
+
+    from paper_1708_08741_amd import lbmep as lb
+
+    nbytes = int(gib * 2 ** 30) // 16 * 16
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lb.copy_reference(dst, src, stream.cuda_stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(iters):
+        lb.copy_reference(dst, src, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    assert torch.equal(dst[:1024], src[:1024])
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
 def _serving_inputs(r):
@@ -389,6 +516,14 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (the reference "
                          "kernel that scales HBM byte counters)")
+    ap.add_argument("--copy-gib", type=float, default=4.0,
+                    help="size of the reference copy that measures the achievable bandwidth "
+                         "(0 = skip)")
+    ap.add_argument("--fullsize-steps", type=int, default=500,
+                    help="steps of the full-size FP32-dev / FP16-dev against FP64 comparison "
+                         "(0 = skip)")
+    ap.add_argument("--error-steps", type=int, default=500,
+                    help="steps of the sub-run compared with the FP64 oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this "
@@ -409,17 +544,22 @@ def main():
     log(f"[bench] inputs ready in {time.perf_counter() - t0:.1f} s")
 
     if args.copy_calibration > 0:
-        # an elementwise copy (y = x + 1) of 1 GiB float32 arrays: 1 GiB
-        # read and 1 GiB written per launch
+        # the reference copy of args.copy_calibration GiB: that many bytes
+        # read and written per launch (scales the HBM byte counters)
+        from paper_1708_08741_amd import lbmep as lbc
         nbytes = int(args.copy_calibration * 2 ** 30) // 16 * 16
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            torch.add(src, 1.0, out=dst)
+            lbc.copy_reference(dst, src)
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {nbytes} bytes read and written per launch")
         del src, dst
         torch.cuda.empty_cache()
+    copy_gbps = None
+    if args.copy_gib > 0:
+        copy_gbps = copy_reference_gbps(args.copy_gib)
+        log(f"[bench] reference copy ({args.copy_gib} GiB, 16-byte lanes): {copy_gbps:.0f} GB/s")
 
     res = run_gpu(wl, args.precision, args.steps, args.warmup)
     cells = wl.ncells
@@ -468,6 +608,14 @@ def main():
         es = 4 if args.precision != "fp64" else 8
         sor_bytes = (2 * es + 1) * cells  # psi read and written once, one flag byte
         it_ms = r["solve_ms"] / args.sor_iters
+        one, rows, planes, waves = r["shape"]
+        if one:
+            label = (f"k_sor_march: one pass per iteration on colour-split psi, from one buffer "
+                     f"into the other; workgroups of {waves} wavefronts hold whole rows, "
+                     f"{rows} rows per thread, marching through chunks of {planes} z planes")
+        else:
+            label = (f"k_sor_half_vec: one colour per launch, two per iteration, {rows} rows "
+                     f"per thread, chunks of {planes} z planes")
         coupled = {
             "MLUPS": round(cells / (r["step_ms"] / 1e3) / 1e6, 1),
             "ms_per_step": round(r["step_ms"], 4),
@@ -476,22 +624,29 @@ def main():
             "sor_GBps": round(sor_bytes / (it_ms / 1e3) / 1e9, 1),
             "sor_roofline_frac": round(sor_bytes / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "sor_bytes_per_cell_iteration": 2 * es + 1,
-            "sor_kernel": "k_sor_half_vec: one colour per launch, two per iteration, on "
-                          "colour-split psi; tiles of 256 entries (512 cells) x 8 rows "
-                          "march through chunks of 8 z planes in XCD-contiguous order "
-                          "(interior cells; the listed boundary cells in the same grid)",
-            "sor_traffic_per_half_sweep": sor_traffic() if es == 4 else None,
+            "sor_byte_model": "ideal: psi read once and written once plus one flag byte per cell; "
+                              "the one-pass kernel reads psi once (plus halo rows), writes it "
+                              "once, and reads 2 bits per cell plus the codes of non-interior "
+                              "cells instead of the flag byte",
+            "sor_kernel": label,
+            "sor_traffic_per_iteration": sor_traffic() if es == 4 and one else None,
             "steps": args.coupled_steps,
         }
         log(f"[bench] coupled step: {coupled}")
 
+    fullsize = None
+    if args.fullsize_steps > 0:
+        log(f"[bench] FP32-dev / FP16-dev against FP64 at full size, {args.fullsize_steps} steps")
+        fullsize = fullsize_vs_fp64(wl, args.fullsize_steps)
+        log(f"[bench] full-size errors: {fullsize}")
+
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle sample")
-        cpu, swl, o, n_o = cpu_baseline()
-        log("[bench] GPU precisions against the oracle sample")
-        errors = precision_errors(swl, o, n_o)
+        log("[bench] timing the CPU oracle samples")
+        cpu = cpu_baseline()
+        log(f"[bench] GPU precisions against the oracle sub-run ({args.error_steps} steps)")
+        errors = precision_errors(args.error_steps)
         log(f"[bench] errors: {errors}")
 
     serving = None
@@ -499,6 +654,14 @@ def main():
         log("[bench] serving leg")
         serving = serving_bench(args.serve_requests, args.serve_sat_requests, args.serve_load,
                                 args.serve_budget_gib, args.serve_slots, args.serve_chunk)
+        serving["note"] = (f"a bounded sample of {args.serve_requests} Poisson arrivals; the full "
+                           f"configuration (2000 requests) is run with --serve-requests 2000, its "
+                           f"record in 'full_configuration_run'")
+        try:
+            serving["full_configuration_run"] = json.load(open(SERVE_FULL))
+            serving["full_configuration_run"]["file"] = os.path.relpath(SERVE_FULL, ROOT)
+        except (OSError, ValueError):
+            serving["full_configuration_run"] = None
         log(f"[bench] serving: {serving}")
 
     traffic = traffic_for(args.precision)
@@ -526,14 +689,20 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_note": "HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / "
+                            "WRITE_SIZE summary (profiles/), used only when it was taken on the "
+                            "current sweep and launch sources; not measured in this run",
             "kernel": SWEEP_KERNEL.get(args.precision, "k_sweep"),
             "kernel_ms": round(res["kernel_ms"], 4),
             "bytes_per_cell": bpc,
+            "achievable_copy_GBps": round(copy_gbps, 1) if copy_gbps else None,
+            "frac_of_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
         },
         "cpu_baseline": cpu,
         "variants": variants,
         "coupled_electrophoresis_step": coupled,
         "errors_vs_fp64_oracle": errors,
+        "fullsize_vs_gpu_fp64": fullsize,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

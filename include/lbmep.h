@@ -179,6 +179,14 @@ int lbmep_solve_potential(lbmep_lattice *L, int32_t *iters, double res[2]);
  * Errors: EINVAL (null, no solver configured). */
 int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]);
 
+/* How a solve of L iterates (for labels of measurements): shape[0] = 1 for
+ * the one-pass iteration (even nx, rows of at most 2048 cells), 0 for one
+ * in-place launch per colour; shape[1] = rows per thread and shape[2] =
+ * planes per workgroup of the one-pass iteration (of the in-place
+ * half-sweep otherwise); shape[3] = wavefronts per row (one-pass) or per
+ * tile along x (in-place).  Errors: EINVAL (null, no solver configured). */
+int lbmep_get_solver_shape(const lbmep_lattice *L, int32_t shape[4]);
+
 /* Copy psi (N values, FP64, cell order with x fastest) to host or device
  * memory.  Errors: EINVAL (null, no potential set), ENOMEM, EDEVICE. */
 int lbmep_get_potential(lbmep_lattice *L, double *psi, int on_device);
@@ -291,6 +299,15 @@ int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n);
  * dynamics (8 n).  Errors: EINVAL. */
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
                     size_t *bytes);
+
+/* Measurement aid (not part of the method): copy `bytes` from src to dst,
+ * both device memory, with 16-byte lanes and streaming stores, enqueued on
+ * `stream` (a hipStream_t, NULL = the default stream) and asynchronous.  Its
+ * rate is the achievable HBM bandwidth the sweep's roofline fraction is read
+ * against, beside the 8 TB/s peak.  The caller owns both buffers.  Errors:
+ * EINVAL (null pointer, pointers or size not multiples of 16 bytes),
+ * EDEVICE. */
+int lbmep_copy_reference(void *dst, const void *src, size_t bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of independent simulations on one GPU.

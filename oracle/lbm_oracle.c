@@ -1073,6 +1073,14 @@ void orc_get_positions(const orc_lattice *L, double *X) {
     if (L->np > 0) memcpy(X, L->Xn, sizeof(double) * 3 * L->np);
 }
 
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

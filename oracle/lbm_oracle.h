@@ -77,6 +77,8 @@ void orc_get_bookkeeping(const orc_lattice *L, double out[11]);
 /* particle centres of the current time level (wrapped) */
 void orc_get_positions(const orc_lattice *L, double *X);
 int orc_num_threads(void);
+/* set the OpenMP thread count of later calls (timing on 1 core or all) */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

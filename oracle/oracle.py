@@ -83,6 +83,7 @@ def lib():
         L.orc_get_bookkeeping.argtypes = [P, dp]
         L.orc_get_positions.argtypes = [P, dp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -280,6 +281,10 @@ class Oracle:
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 def from_workload(wl):

@@ -410,6 +410,32 @@ hipError_t launch_invariants(int precision, const Grid &g, const void *f, const 
     return hipGetLastError();
 }
 
+// the achievable-bandwidth reference: a plain copy in 16-byte lanes with
+// streaming (non-temporal) stores, one element per thread (measured faster
+// than a grid-strided loop over fewer workgroups: 6.3 against 5.2 TB/s)
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                size_t n, size_t base) {
+    const size_t i = base + (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint4 v = src[i];
+    __builtin_nontemporal_store(v.x, &dst[i].x);
+    __builtin_nontemporal_store(v.y, &dst[i].y);
+    __builtin_nontemporal_store(v.z, &dst[i].z);
+    __builtin_nontemporal_store(v.w, &dst[i].w);
+}
+
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    // at most 2^31 - 1 workgroups per launch
+    const size_t per = (size_t)0x7FFFFFFF * 256;
+    for (size_t base = 0; base < n; base += per) {
+        const size_t m = n - base < per ? n - base : per;
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n, base);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_export_flags(const Grid &g, const uint8_t *flag, uint8_t *out, hipStream_t s) {
     hipLaunchKernelGGL(k_export_flags, dim3((unsigned)((g.N + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, g, flag, out);

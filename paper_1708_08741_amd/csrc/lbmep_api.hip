@@ -253,6 +253,14 @@ int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, 
     return LBMEP_OK;
 }
 
+int lbmep_copy_reference(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(LBMEP_EINVAL, "null pointer");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | bytes) & 15u)
+        return fail(LBMEP_EINVAL, "pointers and size must be multiples of 16 bytes");
+    HIP_TRY(launch_copy16(src, dst, bytes, (hipStream_t)stream));
+    return LBMEP_OK;
+}
+
 int lbmep_destroy(lbmep_lattice *L) { return destroy_lattice(L, true); }
 
 int lbmep_create(const lbmep_config *cfg, lbmep_lattice **out) {
@@ -793,6 +801,26 @@ int lbmep_get_solver_stats(lbmep_lattice *L, int32_t *iters, double res[2]) {
     *iters = c.iters;
     res[0] = c.res0;
     res[1] = c.res;
+    return LBMEP_OK;
+}
+
+int lbmep_get_solver_shape(const lbmep_lattice *L, int32_t shape[4]) {
+    if (!L || !shape) return fail(LBMEP_EINVAL, "null argument");
+    if (!L->sor_set) return fail(LBMEP_EINVAL, "no potential solver configured");
+    const bool one = L->sor_fused && L->g.nx % 2 == 0 && L->g.nx <= 2048;
+    if (one) {
+        int rw = L->sor_mrw >= 4 ? 4 : (L->sor_mrw >= 2 ? 2 : 1);  // as the solve picks it
+        while (L->g.ny % rw) rw >>= 1;
+        shape[0] = 1;
+        shape[1] = rw;
+        shape[2] = L->sor_mzc;
+        shape[3] = (L->g.nx / 2 + 63) / 64;
+    } else {
+        shape[0] = 0;
+        shape[1] = L->g.nx % 2 == 0 ? L->sor_rows : 4;
+        shape[2] = L->g.nx % 2 == 0 ? L->sor_zc : 1;
+        shape[3] = L->g.nx % 2 == 0 ? L->sor_wx : 1;
+    }
     return LBMEP_OK;
 }
 

@@ -327,6 +327,7 @@ hipError_t launch_finalize_ft(int np, const double *acc, const double *X, double
                               hipStream_t s);
 // map read-out in the ABI encoding
 hipError_t launch_export_flags(const Grid &g, const uint8_t *flag, uint8_t *out, hipStream_t s);
+hipError_t launch_copy16(const void *src, void *dst, size_t bytes, hipStream_t s);
 // user flags -> internal wall bits (clears OBST/NEAR)
 hipError_t launch_import_flags(const Grid &g, const uint8_t *in, uint8_t *flag, hipStream_t s);
 

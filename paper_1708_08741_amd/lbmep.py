@@ -99,6 +99,7 @@ _SIGS = {
                                                   ctypes.c_int32]),
     "lbmep_solve_potential": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_solver_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
+    "lbmep_get_solver_shape": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbmep_get_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_set_dynamics": (ctypes.c_int, [_P, ctypes.c_double, _P, _D]),
     "lbmep_set_free_slip": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -120,6 +121,8 @@ _SIGS = {
     "lbmep_get_particle_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbmep_footprint": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbmep_copy_reference": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]),
     "lbmep_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig),
                                            ctypes.POINTER(ctypes.c_void_p)]),
     "lbmep_server_destroy": (ctypes.c_int, [_P]),
@@ -194,6 +197,16 @@ def make_config(shape, periodic=(True, True, True), nu=1.0 / 6.0, magic=3.0 / 16
     c.reserved = 0
     c.stream = stream
     return c
+
+
+def copy_reference(dst, src, stream=None):
+    """The achievable-bandwidth reference copy (lbmep_copy_reference) of two
+    equally sized device tensors; asynchronous on `stream` (a hipStream_t
+    handle, None = the default stream)."""
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= n
+    _check(lib().lbmep_copy_reference(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                      n, ctypes.c_void_p(stream or 0)))
 
 
 def footprint(shape, precision=FP64, n_particles=0, with_charge=False, r_max=8.0, **kw):
@@ -315,6 +328,12 @@ class Lattice:
         res = np.zeros(2)
         _check(lib().lbmep_get_solver_stats(self._h, ctypes.byref(it), _dp(res)))
         return it.value, float(res[0]), float(res[1])
+
+    def solver_shape(self):
+        """(one_pass, rows per thread, planes per workgroup, wavefronts)."""
+        out = (ctypes.c_int32 * 4)()
+        _check(lib().lbmep_get_solver_shape(self._h, out))
+        return tuple(int(v) for v in out)
 
     def potential(self, out=None):
         nx, ny, nz = self.shape

@@ -151,6 +151,34 @@ def test_nonfinite_populations_reported(lb, precision):
     g.close()
 
 
+def test_copy_reference(lb):
+    """The achievable-bandwidth reference copy moves the bytes exactly and
+    rejects sizes and pointers that are not multiples of 16 bytes."""
+    import torch
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    lb.copy_reference(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    assert lb.lib().lbmep_copy_reference(None, None, 16, None) == lb.EINVAL
+    assert lb.lib().lbmep_copy_reference(dst.data_ptr(), src.data_ptr() + 4, 64, None) == lb.EINVAL
+    assert lb.lib().lbmep_copy_reference(dst.data_ptr(), src.data_ptr(), 24, None) == lb.EINVAL
+
+
+def test_solver_shape(lb):
+    """The solver reports the one-pass iteration where it applies (even nx,
+    rows of at most 2048 cells) and the in-place half-sweeps otherwise."""
+    for shape, one in (((64, 12, 8), 1), ((63, 12, 8), 0), ((2050, 4, 4), 0)):
+        g = lb.Lattice(shape, (True, True, True) if shape[0] % 2 == 0 else (False, True, True))
+        g.set_potential_force(np.zeros(shape[::-1]), 1e-3, (0.0, 0.0, 0.0))
+        g.set_potential_solver(0.2, 1.7, 2)
+        sh = g.solver_shape()
+        assert sh[0] == one, (shape, sh)
+        if one:
+            assert shape[1] % sh[1] == 0 and sh[3] == (shape[0] // 2 + 63) // 64
+        g.close()
+
+
 def test_macro_of_solid_cells(lb):
     """Obstacle cells report rho0 and their rigid-body surface velocity, wall
     cells rho0 and zero velocity."""
