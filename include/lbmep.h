@@ -300,6 +300,20 @@ int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n);
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
                     size_t *bytes);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops): the sums of lbmep_get_invariants, out[0] = sum rho,
+ * out[1..3] = sum c f over the fluid cells, written to `out`, 4 doubles in
+ * DEVICE memory owned by the caller, enqueued on the lattice's stream and
+ * asynchronous (no host synchronisation, no check for NaN/Inf: the caller
+ * reads the values).  Same kernels and order as lbmep_get_invariants, so the
+ * same bits.  Allocates nothing: its per-workgroup partial sums live in a
+ * static device array of 5 * 4096 + 4 doubles (164 KiB) per GPU, held until
+ * the process ends and shared by every call on that GPU, so calls that
+ * overlap in time on one GPU (other streams or threads) race.  Grids needing
+ * more than 4096 partial blocks are rejected (none do: the reduction uses at
+ * most 4096).  Errors: EINVAL (null, device index >= 64), EDEVICE. */
+int lbmep_get_invariants_noalloc(lbmep_lattice *L, double *out);
+
 /* Measurement aid (not part of the method): copy `bytes` from src to dst,
  * both device memory, with 16-byte lanes and streaming stores, enqueued on
  * `stream` (a hipStream_t, NULL = the default stream) and asynchronous.  Its

@@ -17,7 +17,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbmep.so")
 
 SOURCES = ["k_stream_f64.hip", "k_stream_lp.hip", "k_particles.hip", "k_fields.hip", "k_potential.hip",
-           "lbmep_api.hip", "lbmep_server.hip"]
+           "lbmep_api.hip", "lbmep_server.hip", "lbmep_noalloc.hip"]
 
 # no floating-point contraction anywhere: the FP64 sweep and the particle
 # mapping evaluate the operation sequence of a plain CPU implementation, and

@@ -100,6 +100,7 @@ _SIGS = {
     "lbmep_solve_potential": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_solver_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "lbmep_get_solver_shape": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "lbmep_get_invariants_noalloc": (ctypes.c_int, [_P, ctypes.c_void_p]),
     "lbmep_get_potential": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lbmep_set_dynamics": (ctypes.c_int, [_P, ctypes.c_double, _P, _D]),
     "lbmep_set_free_slip": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -425,6 +426,12 @@ class Lattice:
         out = np.zeros(4)
         _check(lib().lbmep_get_invariants(self._h, _dp(out)))
         return out
+
+    def invariants_noalloc(self, out):
+        """lbmep_get_invariants_noalloc: the FP64 sums into `out` (a device
+        tensor of 4 float64), asynchronous on the lattice's stream."""
+        assert out.is_cuda and out.dtype.itemsize == 8 and out.numel() >= 4
+        _check(lib().lbmep_get_invariants_noalloc(self._h, ctypes.c_void_p(out.data_ptr())))
 
     def set_timing(self, enable=True):
         _check(lib().lbmep_set_timing(self._h, 1 if enable else 0))
