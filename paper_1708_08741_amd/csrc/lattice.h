@@ -95,6 +95,7 @@ struct lbmep_lattice {
     int sor_mzc = 16; // planes per workgroup of the one-pass SOR iteration
     int sor_mrw = 4;  // rows per thread of the one-pass SOR iteration (set per precision)
     int xcd_swizzle = 1;
+    int xpair = 1;    // FP16 sweep: two cells per thread along x where the grid allows it
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     bool timing = false;
     std::vector<hipEvent_t> ev;

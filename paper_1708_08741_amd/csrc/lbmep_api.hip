@@ -123,6 +123,31 @@ int remap_all(lbmep_lattice *L) {
     return LBMEP_OK;
 }
 
+// constants of the FP32-compute collision (see TrtF32), rounded once from
+// FP64 products
+TrtF32 trt_f32_constants(const lbmep_lattice *L) {
+    const double kc = L->precision == LBMEP_FP16DEV ? (double)kHalfScale : 1.0;
+    const double le = L->le, lo = L->lo, ae = L->ae, ao = L->ao;
+    const double w0 = 1.0 / 3.0, wk[2] = {1.0 / 18.0, 1.0 / 36.0};
+    TrtF32 t;
+    t.hle = (float)(0.5 * le);
+    t.le = (float)le;
+    t.b15 = (float)(1.5 / kc);
+    t.lw0 = (float)(le * w0);
+    t.m0 = (float)(3.0 * ae * w0 / kc);
+    for (int k = 0; k < 2; ++k) {
+        t.lw[k] = (float)(le * wk[k]);
+        t.m[k] = (float)(3.0 * ae * wk[k] / kc);
+        t.k1[k] = (float)(4.5 * le * wk[k] / kc);
+        t.k3[k] = (float)(9.0 * ae * wk[k] / kc);
+        t.hlo[k] = (float)(lo * 3.0 * wk[k]);
+        t.k4[k] = (float)(3.0 * ao * wk[k]);
+    }
+    t.fscale = (float)kc;
+    for (int k = 0; k < 3; ++k) t.Ec[k] = (float)L->E[k] * (float)kc;
+    return t;
+}
+
 SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     SweepArgs a;
     a.g = L->g;
@@ -144,9 +169,11 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.lo = L->lo;
     a.ae = L->ae;
     a.ao = L->ao;
+    a.tf = trt_f32_constants(L);
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
     a.slip = L->slip;
+    a.xpair = L->xpair;
     a.keps = L->keps;
     a.zeta = L->force_mode == kForcePotential ? L->zeta : nullptr;
     a.np = L->np;
@@ -395,6 +422,9 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     // measured at 512^3: hints on the stores only are fastest for FP32 and
     // FP64 storage (the loads' one-element overlaps along x then hit L2);
     // FP16 gains from hints on the loads as well
+    // FP16: two cells per thread along x (LBMEP_SWEEP_PAIR=0: one)
+    L->xpair = 1;
+    if (const char *e = std::getenv("LBMEP_SWEEP_PAIR")) L->xpair = std::atoi(e) != 0;
     L->sweep_nt = L->precision == LBMEP_FP16DEV ? 1 : 2;
     if (const char *e = std::getenv("LBMEP_SWEEP_NT")) {
         const int v = std::atoi(e);

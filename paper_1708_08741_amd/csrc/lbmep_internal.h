@@ -88,6 +88,22 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t lb, uint32_t nblk) {
 }
 
 // arguments of the fused stream-collide sweep
+// constants of the FP32-compute TRT collision (FP32 and FP16 storage), set
+// on the host from lambda_e, lambda_o and the compute unit kC of the storage
+// (values are deviations times kC: 1 for FP32, 2^22 for FP16 storage).  Per
+// weight class k (w = 1/18 for the axis, 1/36 for the diagonal directions):
+//   lw = le w, m = 3 ae w / kC, k1 = 9/2 le w / kC, k3 = 9 ae w / kC,
+//   hlo = lo / 6 (axis), lo / 12 (diagonal), k4 = 3 ao w
+struct TrtF32 {
+    float hle;      // le / 2
+    float le;       // le (rest population)
+    float b15;      // 3/2 / kC
+    float lw0, m0;  // le w_0, 3 ae w_0 / kC
+    float lw[2], m[2], k1[2], k3[2], hlo[2], k4[2];
+    float fscale;   // kC: a body force in compute units
+    float Ec[3];    // charge force: the field times kC
+};
+
 struct SweepArgs {
     Grid g;
     const void *src;
@@ -106,9 +122,11 @@ struct SweepArgs {
     double keps;       // potential: kappa^2 eps_e (rho_e = -keps psi)
     const double *zeta; // potential: per-particle boundary value, or null
     double le, lo, ae, ao;  // lambda_e, lambda_o, 1 + lambda_e/2, 1 + lambda_o/2
+    TrtF32 tf;              // the same rates for the FP32-compute collision
     int nxb;                // x-segments per row (set by the launcher)
     int xcd_swizzle;        // 1: map consecutive segments onto one XCD
     int slip;               // free-slip faces: bit 2a + side (a = axis, side 1 = high)
+    int xpair;              // FP16: two cells per thread along x where the grid allows it
     int np;                 // particles
     uint32_t pcap;          // link-list capacity per particle
     const uint2 *plist;     // per particle: (cell, directions into the particle)

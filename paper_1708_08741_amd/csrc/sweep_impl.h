@@ -20,8 +20,9 @@
 // The template is instantiated in two translation units, k_stream_f64.hip
 // (FP64) and k_stream_lp.hip (FP32 / FP16 deviation storage), both compiled
 // without floating-point contraction: the FP64 sweep evaluates exactly the
-// operation sequence of a plain CPU implementation, and every sweep mode
-// rounds identically.
+// operation sequence of a plain CPU implementation; the FP32-compute sweep
+// (FP32 and FP16 storage) uses the rearranged collision of collide_f32 with
+// explicit FMAs; either way every sweep mode rounds identically.
 // Byte offsets are 32-bit (global loads/stores with a scalar base) whenever a
 // population array is smaller than 4 GiB.
 #pragma once
@@ -50,6 +51,12 @@ struct Storage<double> {
     static __device__ __forceinline__ double devval(double v, int q) { return v - wq(q); }
     // f^eq(rho0 = 1, u) of population q (Eq. fequ_Incompr_SRT) as stored
     static __device__ __forceinline__ double feq(int q, double d) { return wq(q) * (1.0 + 1.0 * d); }
+    // the sweep's compute units are the stored values themselves
+    static __device__ __forceinline__ double lc(const double *p) { return load(p); }
+    static __device__ __forceinline__ double lc_nt(const double *p) { return load_nt(p); }
+    static __device__ __forceinline__ void sc(double *p, double v) { store(p, v); }
+    static __device__ __forceinline__ void sc_nt(double *p, double v) { store_nt(p, v); }
+    static __device__ __forceinline__ double feq_c(int q, double d) { return feq(q, d); }
 };
 
 // FP32: deviations f - w_q
@@ -66,6 +73,12 @@ struct Storage<float> {
     }
     static __device__ __forceinline__ double devval(float v, int q) { return (double)v; }
     static __device__ __forceinline__ float feq(int q, double d) { return (float)(wq(q) * d); }
+    // compute units: the deviations themselves
+    static __device__ __forceinline__ float lc(const float *p) { return load(p); }
+    static __device__ __forceinline__ float lc_nt(const float *p) { return load_nt(p); }
+    static __device__ __forceinline__ void sc(float *p, float v) { store(p, v); }
+    static __device__ __forceinline__ void sc_nt(float *p, float v) { store_nt(p, v); }
+    static __device__ __forceinline__ float feq_c(int q, double d) { return feq(q, d); }
 };
 
 // FP16: deviations scaled by 2^22
@@ -90,6 +103,21 @@ struct Storage<__half> {
     // rounded to the storage format, as a stored and re-loaded value would be
     static __device__ __forceinline__ float feq(int q, double d) {
         return __half2float(__float2half_rn((float)(wq(q) * d) * kHalfScale)) * kHalfInvScale;
+    }
+    // compute units: deviations times 2^22, the stored half values widened
+    // (loads and stores convert only; the power-of-two scale is exact)
+    static __device__ __forceinline__ float lc(const __half *p) { return __half2float(*p); }
+    static __device__ __forceinline__ float lc_nt(const __half *p) {
+        const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+        return __half2float(__ushort_as_half(b));
+    }
+    static __device__ __forceinline__ void sc(__half *p, float v) { *p = __float2half_rn(v); }
+    static __device__ __forceinline__ void sc_nt(__half *p, float v) {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)),
+                                    reinterpret_cast<unsigned short *>(p));
+    }
+    static __device__ __forceinline__ float feq_c(int q, double d) {
+        return __half2float(__float2half_rn((float)(wq(q) * d) * kHalfScale));
     }
 };
 
@@ -158,20 +186,21 @@ enum { kPull = 0,     // gather f* of the previous level, refill, collide
        kPullNTS = 4   // as kPull, stores with streaming hints
 };
 
-// load / store of one stored population, with the streaming hint in kPullNT
+// load / store of one stored population in compute units, with the
+// streaming hint in kPullNT
 template <int MODE, typename ST>
 __device__ __forceinline__ typename Storage<ST>::CT pop_load(const ST *p) {
     if constexpr (MODE == kPullNT)
-        return Storage<ST>::load_nt(p);
+        return Storage<ST>::lc_nt(p);
     else
-        return Storage<ST>::load(p);
+        return Storage<ST>::lc(p);
 }
 template <int MODE, typename ST>
 __device__ __forceinline__ void pop_store(ST *p, typename Storage<ST>::CT v) {
     if constexpr (MODE == kPullNT || MODE == kPullNTS)
-        Storage<ST>::store_nt(p, v);
+        Storage<ST>::sc_nt(p, v);
     else
-        Storage<ST>::store(p, v);
+        Storage<ST>::sc(p, v);
 }
 
 // the TRT collision of one opposite pair (q, q+1) with the forcing term
@@ -201,6 +230,99 @@ __device__ __forceinline__ void collide_pair(CT (&v)[Q], CT rho, CT ux, CT uy, C
     }
     v[q] = fq;
     v[qb] = fqb;
+}
+
+// FP32 compute (FP32 and FP16 storage): the TRT collision with the Luo
+// forcing term (Eq. LBMcollideStep with Eq. EqPDF_TRT, Eq. LBE_forcetermLuo
+// and Eq. modified_velocity) rearranged to fewer operations.  With the pair
+// sum s = f_q + f_qbar and difference d = f_q - f_qbar, the update of an
+// opposite pair is f_q <- f_q + (E + O), f_qbar <- f_qbar + (E - O) with
+//   E = le/2 s - G_k - (c.u)(9/2 le w (c.u) - 9 ae w (c.F))
+//   O = le/2 d - 3 lo w (c.u) + 3 ao w (c.F)
+//     = lo/6 (3 d - c.u) + ao/6 (c.F)      (axis, w = 1/18)
+//     = lo/12 (6 d - c.u) + ao/12 (c.F)    (diagonal, w = 1/36)
+// and G_k = le w (rho - 3/2 u.u) + 3 ae w u.F per weight class; the rest
+// population becomes f_0 + (le f_0 - G_0).  The increments are added to the
+// loaded values (the unit part of the update stays exact), and in the odd
+// part d and c.u enter with exact integer weights, so the momentum the
+// collision changes, lo (j - u) + ao F, has no bias from the rounding of the
+// rates.  Algebraically the textbook form; the rounding differs (FMA,
+// regrouped sums).  rho and j = sum c f come from the same pair sums and
+// differences.  Values are in compute units (see TrtF32).
+template <int q, bool FORCED>
+__device__ __forceinline__ void trt_pair_f32(float (&v)[Q], const TrtF32 &t, float s, float d,
+                                             float ux, float uy, float uz, float fx, float fy,
+                                             float fz, float G) {
+    constexpr int qb = q + 1;
+    constexpr int k = q <= 6 ? 0 : 1;  // weight class: axis / diagonal
+    const float cu = cdot<q>(ux, uy, uz);
+    const float D = __builtin_fmaf(k == 0 ? 3.0f : 6.0f, d, -cu);
+    float E, O;
+    if constexpr (FORCED) {
+        const float cf = cdot<q>(fx, fy, fz);
+        const float h = __builtin_fmaf(t.k1[k], cu, -(t.k3[k] * cf));
+        E = __builtin_fmaf(t.hle, s, -__builtin_fmaf(cu, h, G));
+        O = __builtin_fmaf(t.hlo[k], D, t.k4[k] * cf);
+    } else {
+        E = __builtin_fmaf(t.hle, s, -__builtin_fmaf(cu, t.k1[k] * cu, G));
+        O = t.hlo[k] * D;
+    }
+    v[q] = v[q] + (E + O);
+    v[qb] = v[qb] + (E - O);
+}
+
+template <bool FORCED>
+__device__ __forceinline__ void collide_f32(float (&v)[Q], const TrtF32 &t, float fx, float fy,
+                                            float fz) {
+    // directions 2p+1, 2p+2 are opposite; the first of each pair points
+    // along +x for p = 0, 3, 4, 5, 6, along +y for p = 1, 3, 7, 8 and -y for
+    // p = 4, along +z for p = 2, 5, 7 and -z for p = 6, 8
+    static_assert(kCx[1] == 1 && kCx[7] == 1 && kCx[9] == 1 && kCx[11] == 1 && kCx[13] == 1 &&
+                  kCx[3] == 0 && kCx[5] == 0 && kCx[15] == 0 && kCx[17] == 0, "x layout");
+    static_assert(kCy[3] == 1 && kCy[7] == 1 && kCy[9] == -1 && kCy[15] == 1 && kCy[17] == 1 &&
+                  kCy[1] == 0 && kCy[5] == 0 && kCy[11] == 0 && kCy[13] == 0, "y layout");
+    static_assert(kCz[5] == 1 && kCz[11] == 1 && kCz[13] == -1 && kCz[15] == 1 && kCz[17] == -1 &&
+                  kCz[1] == 0 && kCz[3] == 0 && kCz[7] == 0 && kCz[9] == 0, "z layout");
+    static_assert(opp(1) == 2 && opp(7) == 8 && opp(17) == 18, "pairs");
+    float s[9], d[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        s[p] = v[2 * p + 1] + v[2 * p + 2];
+        d[p] = v[2 * p + 1] - v[2 * p + 2];
+    }
+    float rho = v[0];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) rho += s[p];
+    const float jx = (((d[0] + d[3]) + d[4]) + d[5]) + d[6];
+    const float jy = (((d[1] + d[3]) - d[4]) + d[7]) + d[8];
+    const float jz = (((d[2] + d[5]) - d[6]) + d[7]) - d[8];
+    // Eq. modified_velocity: u = j + F/2 (rho0 = 1)
+    const float ux = FORCED ? __builtin_fmaf(0.5f, fx, jx) : jx;
+    const float uy = FORCED ? __builtin_fmaf(0.5f, fy, jy) : jy;
+    const float uz = FORCED ? __builtin_fmaf(0.5f, fz, jz) : jz;
+    const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    const float base = __builtin_fmaf(-t.b15, uu, rho);
+    float G0, G1, G2;
+    if constexpr (FORCED) {
+        const float ufb = __builtin_fmaf(ux, fx, __builtin_fmaf(uy, fy, uz * fz));
+        G0 = __builtin_fmaf(t.m0, ufb, t.lw0 * base);
+        G1 = __builtin_fmaf(t.m[0], ufb, t.lw[0] * base);
+        G2 = __builtin_fmaf(t.m[1], ufb, t.lw[1] * base);
+    } else {
+        G0 = t.lw0 * base;
+        G1 = t.lw[0] * base;
+        G2 = t.lw[1] * base;
+    }
+    v[0] = v[0] + __builtin_fmaf(t.le, v[0], -G0);
+    trt_pair_f32<1, FORCED>(v, t, s[0], d[0], ux, uy, uz, fx, fy, fz, G1);
+    trt_pair_f32<3, FORCED>(v, t, s[1], d[1], ux, uy, uz, fx, fy, fz, G1);
+    trt_pair_f32<5, FORCED>(v, t, s[2], d[2], ux, uy, uz, fx, fy, fz, G1);
+    trt_pair_f32<7, FORCED>(v, t, s[3], d[3], ux, uy, uz, fx, fy, fz, G2);
+    trt_pair_f32<9, FORCED>(v, t, s[4], d[4], ux, uy, uz, fx, fy, fz, G2);
+    trt_pair_f32<11, FORCED>(v, t, s[5], d[5], ux, uy, uz, fx, fy, fz, G2);
+    trt_pair_f32<13, FORCED>(v, t, s[6], d[6], ux, uy, uz, fx, fy, fz, G2);
+    trt_pair_f32<15, FORCED>(v, t, s[7], d[7], ux, uy, uz, fx, fy, fz, G2);
+    trt_pair_f32<17, FORCED>(v, t, s[8], d[8], ux, uy, uz, fx, fy, fz, G2);
 }
 
 #define LBMEP_FOR_Q18(M) \
@@ -261,7 +383,7 @@ __device__ __forceinline__ void slip_fix(const SweepArgs &a, int x, int y, int z
         case 6: p = mirror_dir(q, 6); break;
         default: p = mirror_dir(q, 7); break;
     }
-    v = Storage<ST>::load(static_cast<const ST *>(a.src) + (size_t)p * a.g.Ns + sc);
+    v = Storage<ST>::lc(static_cast<const ST *>(a.src) + (size_t)p * a.g.Ns + sc);
 }
 
 // loaded inputs of one cell
@@ -296,7 +418,7 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
     if constexpr (MODE == kLocal) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            c.v[q] = T::load(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
+            c.v[q] = T::lc(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
     } else {
         // source rows (y - c_y, z - c_z) and columns x - c_x, wrapped on
         // periodic axes; beyond a non-periodic edge: not ok
@@ -361,16 +483,29 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
                 re = __builtin_nontemporal_load(rp);
             else
                 re = *rp;
-            c.fb0 = re * (CT)a.E[0];
-            c.fb1 = re * (CT)a.E[1];
-            c.fb2 = re * (CT)a.E[2];
+            if constexpr (sizeof(CT) == 4) {
+                // the field in compute units (exact power-of-two scale)
+                c.fb0 = re * a.tf.Ec[0];
+                c.fb1 = re * a.tf.Ec[1];
+                c.fb2 = re * a.tf.Ec[2];
+            } else {
+                c.fb0 = re * (CT)a.E[0];
+                c.fb1 = re * (CT)a.E[1];
+                c.fb2 = re * (CT)a.E[2];
+            }
+        }
+        if constexpr (sizeof(ST) == 2 && (FMODE == kForceDense || FMODE == kForcePotential)) {
+            c.fb0 *= a.tf.fscale;
+            c.fb1 *= a.tf.fscale;
+            c.fb2 *= a.tf.fscale;
         }
     }
 }
 
 // refill (if uncovered), collide, store, bounce-back slots and momentum
 // exchange of one loaded cell
-template <typename ST, int FMODE, typename OFF, int MODE>
+// (STORE = false: leave the post-collision values in c.v for the caller)
+template <typename ST, int FMODE, typename OFF, int MODE, bool STORE = true>
 __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, int z,
                                             CellIn<typename Storage<ST>::CT> &c) {
     using T = Storage<ST>;
@@ -401,7 +536,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
-                v[q] = (CT)T::feq(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5);
+                v[q] = (CT)T::feq_c(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5);
             }
         }
     }
@@ -428,18 +563,21 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const double cu = ((double)kCx[q] * u0 + (double)kCy[q] * u1) + (double)kCz[q] * u2;
-                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, si * es),
-                         (CT)T::feq(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5));
+                T::sc(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, si * es),
+                      (CT)T::feq_c(q, (cu * 3.0 + (cu * cu) * 4.5) - uu * 1.5));
             }
         }
         if (act) {
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                T::store(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+                T::sc(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
         }
     } else {
         // the collision runs on every lane; only the stores are restricted
         // to fluid cells
+        if constexpr (sizeof(CT) == 4) {
+            collide_f32<FMODE != kForceNone>(v, a.tf, c.fb0, c.fb1, c.fb2);
+        } else {
         const CT fb0 = c.fb0, fb1 = c.fb1, fb2 = c.fb2;
 
         // moments (Eq. MacroscopVel), in q order
@@ -487,12 +625,15 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
         collide_pair<13>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
         collide_pair<15>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
         collide_pair<17>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
+        }
 
-        if (act) {
-            // aligned store of the post-collision state
+        if constexpr (STORE) {
+            if (act) {
+                // aligned store of the post-collision state
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                pop_store<MODE, ST>(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+                for (int q = 0; q < Q; ++q)
+                    pop_store<MODE, ST>(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
+            }
         }
     }
 }
@@ -523,6 +664,174 @@ template <typename ST, int FMODE, typename OFF, int MODE, int CPT>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     sweep_segment<ST, FMODE, OFF, MODE, CPT>(a, lb);
+}
+
+// FP16 storage, two cells (x, x + 1) per thread along x (x even; nx even,
+// periodic x, no free-slip face): each population of the pair is one 4-byte
+// load (the two cells' gathered values are adjacent in the source row; for
+// c_x = +-1 the word starts at an odd element, a 2-byte aligned access), so a
+// wavefront moves 256 bytes per load instead of 128 and the loads in flight
+// per wavefront double.  The lanes whose pair straddles the row's periodic
+// seam patch the wrapped half with a 2-byte load.  The two cells are then
+// collided one after the other, exactly as the one-cell sweep collides them,
+// and stored as one 4-byte word per population (2 bytes where only one of
+// the two is a fluid cell).
+__device__ __forceinline__ uint32_t ld_u32(const char *p) {
+    uint32_t v;
+    __builtin_memcpy(&v, p, 4);
+    return v;
+}
+__device__ __forceinline__ uint32_t ld_u16(const char *p) {
+    uint16_t v;
+    __builtin_memcpy(&v, p, 2);
+    return v;
+}
+// a stored half and its value in compute units (deviation times 2^22)
+__device__ __forceinline__ float h16(uint32_t b) {
+    return __half2float(__ushort_as_half((unsigned short)b));
+}
+__device__ __forceinline__ uint32_t to_h16(float v) {
+    return (uint32_t)__half_as_ushort(__float2half_rn(v));
+}
+
+template <int q>
+__device__ __forceinline__ uint32_t gather_pair(const char *src, uint32_t pst, uint32_t cb,
+                                                const uint32_t rows[3][3], const bool rok[3][3],
+                                                uint32_t xb, bool seam_lo, bool seam_hi,
+                                                uint32_t last_b) {
+    constexpr int qb = opp(q);
+    constexpr int lo = q < qb ? q : qb;
+    constexpr int cx = kCx[q];
+    const char *base = src + (size_t)lo * pst;
+    const uint32_t own = (uint32_t)(qb - lo) * pst + cb;  // the pair's own q-bar values
+    if (!rok[kCy[q] + 1][kCz[q] + 1]) return ld_u32(base + own);  // beyond a non-periodic edge
+    const uint32_t row = (uint32_t)(q - lo) * pst + rows[kCy[q] + 1][kCz[q] + 1];
+    if constexpr (cx == 0) {
+        return ld_u32(base + row + xb);
+    } else {
+        // sources x - c_x, x + 1 - c_x: adjacent, starting 2 bytes off the pair
+        const bool seam = cx > 0 ? seam_lo : seam_hi;
+        uint32_t v = ld_u32(base + (seam ? own : row + xb - (uint32_t)(2 * cx)));
+        // at the seam the pair's sources are the row's last and first cells
+        // (x = 0, c_x = 1: x - 1 wraps; x + 1 = nx - 1, c_x = -1: x + 2 wraps)
+        if (seam) v = ld_u16(base + row + last_b) | (ld_u16(base + row) << 16);
+        return v;
+    }
+}
+
+template <int FMODE, int MODE>
+__device__ __forceinline__ void load_pair_h(const SweepArgs &a, int x, int y, int z, bool valid,
+                                            CellIn<float> &c0, CellIn<float> &c1) {
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const uint32_t pst = (uint32_t)a.g.Ns * 2u;
+    const int xc = valid ? x : 0, yc = valid ? y : 0;
+    const uint32_t ci = (uint32_t)xc + (uint32_t)nx * ((uint32_t)yc + (uint32_t)ny * (uint32_t)z);
+    const uint32_t cb = ci * 2u;
+    const uint32_t fp = ld_u16(reinterpret_cast<const char *>(a.flag) + ci);
+    c0.fl = valid ? (uint8_t)fp : kWall;
+    c1.fl = valid ? (uint8_t)(fp >> 8) : kWall;
+    uint32_t rows[3][3];
+    bool rok[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int ys = yc - (j - 1), zs = z - (k - 1);
+            bool ok = true;
+            if (ys < 0 || ys >= ny) {
+                if (a.g.per[1]) ys = ys < 0 ? ys + ny : ys - ny; else { ok = false; ys = yc; }
+            }
+            if (zs < 0 || zs >= nz) {
+                if (a.g.per[2]) zs = zs < 0 ? zs + nz : zs - nz; else { ok = false; zs = z; }
+            }
+            rows[j][k] = (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * (uint32_t)zs) * 2u;
+            rok[j][k] = ok;
+        }
+    const uint32_t xb = (uint32_t)xc * 2u, last_b = (uint32_t)(nx - 1) * 2u;
+    const bool seam_lo = xc == 0, seam_hi = xc + 2 == nx;
+    const char *src = static_cast<const char *>(a.src);
+    uint32_t p[Q];
+    p[0] = ld_u32(src + cb);
+#define LBMEP_GPAIR(q) p[q] = gather_pair<q>(src, pst, cb, rows, rok, xb, seam_lo, seam_hi, last_b);
+    LBMEP_FOR_Q18(LBMEP_GPAIR)
+#undef LBMEP_GPAIR
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        c0.v[q] = h16(p[q] & 0xFFFFu);
+        c1.v[q] = h16(p[q] >> 16);
+    }
+    c0.fb0 = c0.fb1 = c0.fb2 = 0.f;
+    c1.fb0 = c1.fb1 = c1.fb2 = 0.f;
+    const float *force = static_cast<const float *>(a.force);
+    if constexpr (FMODE == kForceDense) {
+        const size_t fs = a.g.Ns;
+        const float2 f0 = *reinterpret_cast<const float2 *>(force + ci);
+        const float2 f1 = *reinterpret_cast<const float2 *>(force + fs + ci);
+        const float2 f2 = *reinterpret_cast<const float2 *>(force + 2 * fs + ci);
+        const float k = a.tf.fscale;
+        c0.fb0 = f0.x * k; c1.fb0 = f0.y * k;
+        c0.fb1 = f1.x * k; c1.fb1 = f1.y * k;
+        c0.fb2 = f2.x * k; c1.fb2 = f2.y * k;
+    } else if constexpr (FMODE == kForceCharge) {
+        const float2 re = *reinterpret_cast<const float2 *>(force + ci);
+        c0.fb0 = re.x * a.tf.Ec[0];
+        c0.fb1 = re.x * a.tf.Ec[1];
+        c0.fb2 = re.x * a.tf.Ec[2];
+        c1.fb0 = re.y * a.tf.Ec[0];
+        c1.fb1 = re.y * a.tf.Ec[1];
+        c1.fb2 = re.y * a.tf.Ec[2];
+    } else if constexpr (FMODE == kForcePotential) {
+        if (valid && !(c0.fl & (kWall | kObst)))
+            potential_force<float>(a.g, x, y, z, c0.fl, force, a.flag, a.owner, a.zeta, (float)a.keps,
+                                   (float)a.E[0], (float)a.E[1], (float)a.E[2], c0.fb0, c0.fb1, c0.fb2);
+        if (valid && !(c1.fl & (kWall | kObst)))
+            potential_force<float>(a.g, x + 1, y, z, c1.fl, force, a.flag, a.owner, a.zeta,
+                                   (float)a.keps, (float)a.E[0], (float)a.E[1], (float)a.E[2],
+                                   c1.fb0, c1.fb1, c1.fb2);
+        const float k = a.tf.fscale;
+        c0.fb0 *= k; c0.fb1 *= k; c0.fb2 *= k;
+        c1.fb0 *= k; c1.fb1 *= k; c1.fb2 *= k;
+    }
+}
+
+template <int FMODE, int MODE>
+__global__ void __launch_bounds__(512) k_sweep_pair_h(SweepArgs a) {
+    const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
+    const int y = (int)(row % (uint32_t)a.g.ny), z = (int)(row / (uint32_t)a.g.ny);
+    const int x = 2 * ((int)xb * (int)blockDim.x + (int)threadIdx.x);
+    const bool valid = x < a.g.nx;
+    CellIn<float> c0, c1;
+    load_pair_h<FMODE, MODE>(a, x, y, z, valid, c0, c1);
+    const bool act0 = !(c0.fl & (kWall | kObst)), act1 = !(c1.fl & (kWall | kObst));
+    finish_cell<__half, FMODE, uint32_t, MODE, false>(a, x, y, z, c0);
+    uint32_t h[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) h[q] = to_h16(c0.v[q]);
+    finish_cell<__half, FMODE, uint32_t, MODE, false>(a, x + 1, y, z, c1);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) h[q] |= to_h16(c1.v[q]) << 16;
+    if (!act0 && !act1) return;
+    const size_t pst = a.g.Ns * 2;
+    const uint32_t ci = (uint32_t)x + (uint32_t)a.g.nx * ((uint32_t)y + (uint32_t)a.g.ny * (uint32_t)z);
+    char *dst = static_cast<char *>(a.dst) + (size_t)ci * 2;
+    if (act0 && act1) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            uint32_t *d = reinterpret_cast<uint32_t *>(dst + (size_t)q * pst);  // 4-byte aligned: x even
+            if constexpr (MODE == kPullNT || MODE == kPullNTS)
+                __builtin_nontemporal_store(h[q], d);
+            else
+                *d = h[q];
+        }
+    } else {
+        // one fluid cell: its 2 bytes only (the solid cell's values stay)
+        const int k = act0 ? 0 : 1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            *reinterpret_cast<unsigned short *>(dst + (size_t)q * pst + 2 * k) =
+                (unsigned short)(h[q] >> (16 * k));
+    }
 }
 
 // the gather sweep of several lattices in one dispatch
@@ -559,6 +868,29 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     // 32-bit byte offsets when two population arrays fit in 4 GiB (the
     // gather addresses an opposite pair from one base)
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
+    if constexpr (sizeof(ST) == 2) {
+        // FP16: two cells per thread along x where the grid allows it
+        if (a.xpair && small && cpt == 1 && a.g.nx % 2 == 0 && a.g.per[0] && !a.slip &&
+            (mode == kPull || mode == kPullNT || mode == kPullNTS)) {
+            a.nxb = (a.g.nx / 2 + block_x - 1) / block_x;
+            const size_t nb = (size_t)a.nxb * a.g.ny * a.g.nz;
+            const dim3 grid((unsigned)nb, 1, 1), block(block_x, 1, 1);
+#define LBMEP_PAIR(MD, FM) hipLaunchKernelGGL((k_sweep_pair_h<FM, MD>), grid, block, 0, s, a)
+#define LBMEP_PAIR_F(MD)                                                     \
+    do {                                                                     \
+        if (force_mode == kForceNone) LBMEP_PAIR(MD, kForceNone);            \
+        else if (force_mode == kForceDense) LBMEP_PAIR(MD, kForceDense);     \
+        else if (force_mode == kForceCharge) LBMEP_PAIR(MD, kForceCharge);   \
+        else LBMEP_PAIR(MD, kForcePotential);                                \
+    } while (0)
+            if (mode == kPullNT) LBMEP_PAIR_F(kPullNT);
+            else if (mode == kPullNTS) LBMEP_PAIR_F(kPullNTS);
+            else LBMEP_PAIR_F(kPull);
+#undef LBMEP_PAIR_F
+#undef LBMEP_PAIR
+            return hipGetLastError();
+        }
+    }
     if (!small || mode == kReadout) cpt = 1;
     a.nxb = (a.g.nx + block_x - 1) / block_x;
     const size_t nblocks = (size_t)a.nxb * ((a.g.ny + cpt - 1) / cpt) * a.g.nz;
