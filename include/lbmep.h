@@ -293,10 +293,13 @@ int lbmep_get_particle_count(const lbmep_lattice *L, int32_t *n);
 
 /* Device bytes held by a lattice of this configuration with n particles of
  * radius at most r_max and a charge force or none (used for admission by
- * footprint).  Not counted: a potential solver (lbmep_set_potential_solver
- * adds 4 N + 9 N (FP32) / 17 N (FP64) + N / 8 bytes for the boundary lists,
- * their rows and the interior bitmask) and the per-particle charges of the
- * dynamics (8 n).  Errors: EINVAL. */
+ * footprint).  With moving particles this includes the next level's link
+ * lists of the overlapped step, n (8 (2 ceil(r_max) + 3)^3 + 4).  Not
+ * counted: a potential solver (lbmep_set_potential_solver adds about 23 N
+ * bytes with FP32 psi, 39 N with FP64 psi: boundary lists and their rows,
+ * interior bitmaps, and for the one-pass iteration (even nx) a second psi
+ * buffer, a saved copy of psi and per-entry row codes) and the per-particle
+ * charges of the dynamics (8 n).  Errors: EINVAL. */
 int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, int with_charge,
                     size_t *bytes);
 

@@ -249,9 +249,10 @@ __global__ void k_classify_all(Grid g, uint8_t *flag, uint32_t *wallmask, const 
 }
 
 // state bits of a box plus a one-cell halo, staged in LDS for the
-// classification (boxes up to kHaloCells cells; larger ones use the global
-// path): solid (wall, obstacle of the new map, or beyond a non-periodic
-// edge), obstacle cell of this particle, obstacle cell, wall cell
+// classification (boxes up to the staging capacity, at most kHaloCells
+// cells; larger ones use the global path): solid (wall, obstacle of the new
+// map, or beyond a non-periodic edge), obstacle cell of this particle,
+// obstacle cell, wall cell
 constexpr int kHaloCells = 32768;
 constexpr uint8_t kHSolid = 1, kHMine = 2, kHObst = 4, kHWall = 8;
 
@@ -262,7 +263,8 @@ constexpr uint8_t kHSolid = 1, kHMine = 2, kHObst = 4, kHWall = 8;
 __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
                                                   const double *Xold, const double *Xnew,
                                                   uint8_t *flag, const uint32_t *owner_new,
-                                                  const uint32_t *owner_old, uint8_t *solid) {
+                                                  const uint32_t *owner_old, uint8_t *solid,
+                                                  int cap) {
     __shared__ uint32_t wcnt[kBoxThreads / 64][8];
     const Grid &g = pa.g;
     const double R = pa.R[p];
@@ -287,7 +289,7 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
     uint32_t base = 0;
     const int hx = b.cnt[0] + 2, hy = b.cnt[1] + 2, hz = b.cnt[2] + 2;
     const int hn = hx * hy * hz;
-    const bool staged = n > 0 && hn <= kHaloCells;
+    const bool staged = n > 0 && hn <= cap;
     if (staged) {
         const int len[3] = {g.nx, g.ny, g.nz};
         // four halo cells per thread and pass, their loads issued together
@@ -425,11 +427,15 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
     if (threadIdx.x == 0) pa.pcount[p] = base < pa.pcap ? base : pa.pcap;
 }
 
-__global__ void __launch_bounds__(kBoxThreads)
+// the staging array is dynamic LDS of pa.halo_cap bytes, sized for the
+// largest particle: a 32 KiB array for R = 4 boxes of < 5 KiB would hold the
+// CU to 5 workgroups
+__global__ void __launch_bounds__(kBoxThreads, 6)
     k_classify_boxes(ParticleArgs pa, const double *Xold, const double *Xnew, uint8_t *flag,
                      const uint32_t *owner_new, const uint32_t *owner_old) {
-    __shared__ uint8_t solid[kHaloCells];
-    classify_particle(pa, blockIdx.x, Xold, Xnew, flag, owner_new, owner_old, solid);
+    extern __shared__ uint8_t solid[];
+    classify_particle(pa, blockIdx.x, Xold, Xnew, flag, owner_new, owner_old, solid,
+                      (int)pa.halo_cap);
 }
 
 // compact list, in cell order, of the cells with a wall link (wall-link mask
@@ -543,7 +549,7 @@ __global__ void __launch_bounds__(kBoxThreads) k_classify_packed(PackTable t) {
     const ParticleArgs pa = d->pa;
     const int co = (int)(t.state[e] >> 1), b = 1 - co;
     classify_particle(pa, (int)(blockIdx.x - t.start[e]), d->Xheld[co], d->Xheld[b], d->flag,
-                      d->owner[b], d->owner[co], solid);
+                      d->owner[b], d->owner[co], solid, kHaloCells);
 }
 
 // F = F_dev + K/18 and M = M_dev + (T - X x K)/18 from the per-particle
@@ -612,6 +618,12 @@ int wall_list_blocks(const Grid &g) { return (int)((g.N + kListChunk - 1) / kLis
 int wall_list_tiles(const Grid &g) { return (wall_list_blocks(g) + kTile - 1) / kTile; }
 size_t wall_list_scratch(const Grid &g) {
     return (size_t)wall_list_blocks(g) + (size_t)wall_list_tiles(g) + 64;
+}
+
+uint32_t halo_capacity(double r_max) {
+    const double e = 2.0 * std::ceil(r_max) + 9.0;
+    const double c = e * e * e;
+    return c > (double)kHaloCells ? (uint32_t)kHaloCells : (uint32_t)c;
 }
 
 uint32_t link_capacity(double r_max) {
@@ -697,8 +709,8 @@ hipError_t launch_classify_boxes(const ParticleArgs &pa, const double *Xold, con
                                  uint8_t *flag, const uint32_t *owner_new,
                                  const uint32_t *owner_old, hipStream_t s) {
     if (pa.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify_boxes, dim3(pa.np), dim3(kBoxThreads), 0, s, pa, Xold, Xnew,
-                       flag, owner_new, owner_old);
+    hipLaunchKernelGGL(k_classify_boxes, dim3(pa.np), dim3(kBoxThreads), pa.halo_cap, s, pa,
+                       Xold, Xnew, flag, owner_new, owner_old);
     return hipGetLastError();
 }
 

@@ -39,9 +39,13 @@ struct lbmep_lattice {
     uint32_t *wall_count = nullptr;   // their number (device)
     uint32_t *wall_scratch = nullptr; // per-block counts of the list scan
     bool has_walls = false;           // any WALL cell (sizes the wall pass)
-    uint2 *plist = nullptr;           // per particle: link list of the current map
-    uint32_t *pcount = nullptr;       // per particle: list length
+    // per particle: link lists (and their lengths) of the current level and,
+    // with overlapped stepping, of the next level
+    uint2 *plist_buf[2] = {nullptr, nullptr};
+    uint32_t *pcount_buf[2] = {nullptr, nullptr};
+    int lcur = 0;                     // list buffer of the current level
     uint32_t pcap = 0;                // list capacity per particle
+    uint32_t halo_cap = 0;            // LDS bytes of the classification's staged box
     size_t plist_entries = 0;         // allocated entries
     uint32_t *owner[2] = {nullptr, nullptr};
     double *Xheld[2] = {nullptr, nullptr};  // positions of the level each map holds
@@ -95,8 +99,15 @@ struct lbmep_lattice {
     int sor_mzc = 16; // planes per workgroup of the one-pass SOR iteration
     int sor_mrw = 4;  // rows per thread of the one-pass SOR iteration (set per precision)
     int xcd_swizzle = 1;
-    int xpair = 1;    // FP16 sweep: two cells per thread along x where the grid allows it
+    int sweep_lds = 0;  // sweep: dynamic LDS bytes per workgroup (caps its workgroups per CU)
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
+    // overlapped stepping (moving particles, prescribed kinematics): the
+    // kinematics, mapping and classification of level n + 1 run on a second
+    // stream during the exchange of level n
+    bool overlap = false;
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_sweep = nullptr, ev_chain = nullptr;
+    bool chain_pending = false;
     bool timing = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -128,7 +139,7 @@ bool finite_all(const double *p, size_t n);
 int check_config(const lbmep_config *cfg);
 // device bytes of a lattice (what lbmep_footprint reports)
 size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
-                     int force_mode);
+                     int force_mode, bool overlap);
 
 hipError_t dev_alloc(lbmep_lattice *L, void **p, size_t bytes);
 void dev_free(lbmep_lattice *L, void *p);

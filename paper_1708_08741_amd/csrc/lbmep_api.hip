@@ -94,16 +94,18 @@ ParticleArgs particle_args(const lbmep_lattice *L) {
     pa.R = L->R;
     pa.U = L->U;
     pa.W = L->W;
-    pa.plist = L->plist;
-    pa.pcount = L->pcount;
+    pa.plist = L->plist_buf[L->lcur];
+    pa.pcount = L->pcount_buf[L->lcur];
     pa.pcap = L->pcap;
+    pa.halo_cap = L->halo_cap;
     return pa;
 }
 
-// map the particles at `level` into both owner buffers, classify the grid,
+// map the particles at `level` into every owner buffer, classify the grid,
 // list the cells with wall links, and write the particles' link lists
 int remap_all(lbmep_lattice *L) {
     hipStream_t s = L->stream;
+    L->lcur = 0;
     const ParticleArgs pa = particle_args(L);
     if (L->np > 0) {
         for (int b = 0; b < 2; ++b) {
@@ -173,13 +175,13 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
     a.slip = L->slip;
-    a.xpair = L->xpair;
+    a.lds = (uint32_t)L->sweep_lds;
     a.keps = L->keps;
     a.zeta = L->force_mode == kForcePotential ? L->zeta : nullptr;
     a.np = L->np;
     a.pcap = L->pcap;
-    a.plist = L->plist;
-    a.pcount = L->pcount;
+    a.plist = L->plist_buf[L->lcur];
+    a.pcount = L->pcount_buf[L->lcur];
     a.wlist = L->wall_list;
     a.wcount = L->wall_count;
     return a;
@@ -191,7 +193,10 @@ void advance_state(lbmep_lattice *L) {
     L->ft_buf = L->cur_owner;
     L->cur = 1 - L->cur;
     L->pmode = true;
-    if (L->np > 0 && L->cfg.move_particles) L->cur_owner = 1 - L->cur_owner;
+    if (L->np > 0 && L->cfg.move_particles) {
+        L->cur_owner = 1 - L->cur_owner;
+        if (L->overlap) L->lcur ^= 1;
+    }
     L->level += 1;
 }
 
@@ -213,16 +218,20 @@ void free_particles(lbmep_lattice *L) {
     dev_free(L, L->U);
     dev_free(L, L->W);
     dev_free(L, L->FM);
-    dev_free(L, L->Xheld[0]);
-    dev_free(L, L->Xheld[1]);
-    dev_free(L, L->pcount);
-    L->X0 = L->R = L->U = L->W = L->FM = L->Xheld[0] = L->Xheld[1] = nullptr;
-    L->pcount = nullptr;
+    for (int b = 0; b < 2; ++b) {
+        dev_free(L, L->Xheld[b]);
+        L->Xheld[b] = nullptr;
+    }
+    for (int b = 0; b < 2; ++b) {
+        dev_free(L, L->pcount_buf[b]);
+        L->pcount_buf[b] = nullptr;
+    }
+    L->X0 = L->R = L->U = L->W = L->FM = nullptr;
     L->np_cap = 0;
 }
 
 size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
-                     int force_mode) {
+                     int force_mode, bool overlap) {
     const size_t N = (size_t)cfg->nx * cfg->ny * cfg->nz;
     const size_t Ns = population_stride(N, cfg->precision);
     size_t b = 2 * (size_t)Q * Ns * storage_bytes(cfg->precision);  // two population grids
@@ -230,6 +239,8 @@ size_t lattice_bytes(const lbmep_config *cfg, int32_t n_particles, double r_max,
     if (n_particles > 0) {
         b += 2 * 4 * N + (size_t)n_particles * (16 + 6 * 3) * 8;  // maps, particle table
         b += (size_t)n_particles * (8 * (size_t)link_capacity(r_max) + 4);  // link lists
+        if (overlap)  // overlapped stepping: the next level's link lists
+            b += (size_t)n_particles * (8 * (size_t)link_capacity(r_max) + 4);
     }
     if (force_mode == kForceDense) b += 3 * Ns * compute_bytes(cfg->precision);
     if (force_mode == kForceCharge || force_mode == kForcePotential)
@@ -276,7 +287,8 @@ int lbmep_footprint(const lbmep_config *cfg, int32_t n_particles, double r_max, 
     if (rc) return rc;
     if (!bytes || n_particles < 0 || !(r_max >= 0.0) || !std::isfinite(r_max))
         return fail(LBMEP_EINVAL, "bad footprint arguments");
-    *bytes = lattice_bytes(cfg, n_particles, r_max, with_charge ? kForceCharge : kForceNone);
+    *bytes = lattice_bytes(cfg, n_particles, r_max, with_charge ? kForceCharge : kForceNone,
+                           n_particles > 0 && cfg->move_particles);
     return LBMEP_OK;
 }
 
@@ -303,6 +315,12 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     if (!L) return LBMEP_OK;
     hipSetDevice(L->cfg.device);
     if (sync) hipStreamSynchronize(L->stream);
+    if (L->stream2) {
+        hipStreamSynchronize(L->stream2);
+        hipStreamDestroy(L->stream2);
+        hipEventDestroy(L->ev_sweep);
+        hipEventDestroy(L->ev_chain);
+    }
     dev_free(L, L->f[0]);
     dev_free(L, L->f[1]);
     dev_free(L, L->flag);
@@ -310,9 +328,8 @@ int destroy_lattice(lbmep_lattice *L, bool sync) {
     dev_free(L, L->wall_list);
     dev_free(L, L->wall_count);
     dev_free(L, L->wall_scratch);
-    dev_free(L, L->plist);
-    dev_free(L, L->owner[0]);
-    dev_free(L, L->owner[1]);
+    for (int b = 0; b < 2; ++b) dev_free(L, L->plist_buf[b]);
+    for (int b = 0; b < 2; ++b) dev_free(L, L->owner[b]);
     dev_free(L, L->force);
     dev_free(L, L->red);
     dev_free(L, L->zeta);
@@ -347,6 +364,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     L->heap = heap;
     L->cfg = *cfg;
     L->stream = (hipStream_t)cfg->stream;
+    // overlapped stepping for a lattice of its own with moving particles
+    // (LBMEP_STEP_OVERLAP=0: every step in one stream, for comparisons)
+    L->overlap = heap == nullptr && cfg->move_particles;
+    if (const char *e = std::getenv("LBMEP_STEP_OVERLAP")) L->overlap = L->overlap && std::atoi(e) != 0;
     L->precision = cfg->precision;
     Grid &g = L->g;
     g.nx = cfg->nx;
@@ -422,9 +443,18 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     // measured at 512^3: hints on the stores only are fastest for FP32 and
     // FP64 storage (the loads' one-element overlaps along x then hit L2);
     // FP16 gains from hints on the loads as well
-    // FP16: two cells per thread along x (LBMEP_SWEEP_PAIR=0: one)
-    L->xpair = 1;
-    if (const char *e = std::getenv("LBMEP_SWEEP_PAIR")) L->xpair = std::atoi(e) != 0;
+    // workgroups per CU of the sweep capped by a dynamic LDS allocation per
+    // workgroup (the kernel uses none of it; 160 KiB of LDS per CU).  Measured
+    // at 512^3: FP32 is fastest with 3 workgroups of 256 threads per CU (3
+    // waves per SIMD; 3.72 against 3.82 ms uncapped), FP64 with 4 of 128 (2
+    // waves per SIMD; 7.80 against 7.92 ms), FP16 uncapped.
+    // LBMEP_SWEEP_WGCU (workgroups per CU, 0: no cap) overrides it
+    int wgcu = L->precision == LBMEP_FP32DEV ? 3 : L->precision == LBMEP_FP64 ? 4 : 0;
+    if (const char *e = std::getenv("LBMEP_SWEEP_WGCU")) {
+        const int w = std::atoi(e);
+        if (w >= 0 && w <= 32) wgcu = w;
+    }
+    L->sweep_lds = wgcu > 0 ? (160 * 1024) / wgcu / 16 * 16 : 0;
     L->sweep_nt = L->precision == LBMEP_FP16DEV ? 1 : 2;
     if (const char *e = std::getenv("LBMEP_SWEEP_NT")) {
         const int v = std::atoi(e);
@@ -531,18 +561,21 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(L->stream));
     if (n > 0 && !L->owner[0]) {
-        if (dev_alloc(L, (void **)&L->owner[0], 4 * L->g.N) != hipSuccess ||
-            dev_alloc(L, (void **)&L->owner[1], 4 * L->g.N) != hipSuccess)
-            return fail(LBMEP_ENOMEM, "owner field allocation failed");
+        for (int b = 0; b < 2; ++b)
+            if (dev_alloc(L, (void **)&L->owner[b], 4 * L->g.N) != hipSuccess)
+                return fail(LBMEP_ENOMEM, "owner field allocation failed");
     }
+    const int nlists = L->overlap ? 2 : 1;
     if ((size_t)n > L->np_cap) {
         free_particles(L);
         const size_t b = 3 * (size_t)n * sizeof(double);
         bool ok = dev_alloc(L, (void **)&L->X0, b) == hipSuccess && dev_alloc(L, (void **)&L->U, b) == hipSuccess &&
                   dev_alloc(L, (void **)&L->W, b) == hipSuccess && dev_alloc(L, (void **)&L->R, b / 3) == hipSuccess &&
-                  dev_alloc(L, (void **)&L->FM, 6 * b) == hipSuccess && dev_alloc(L, (void **)&L->Xheld[0], b) == hipSuccess &&
-                  dev_alloc(L, (void **)&L->Xheld[1], b) == hipSuccess &&
-                  dev_alloc(L, (void **)&L->pcount, 4 * (size_t)n) == hipSuccess;
+                  dev_alloc(L, (void **)&L->FM, 6 * b) == hipSuccess;
+        for (int r = 0; r < 2; ++r)
+            ok = ok && dev_alloc(L, (void **)&L->Xheld[r], b) == hipSuccess;
+        for (int r = 0; r < nlists; ++r)
+            ok = ok && dev_alloc(L, (void **)&L->pcount_buf[r], 4 * (size_t)n) == hipSuccess;
         if (!ok) {
             free_particles(L);
             L->np = 0;
@@ -555,16 +588,20 @@ int lbmep_set_particles(lbmep_lattice *L, int32_t n, const double *X, const doub
     for (int i = 0; i < n; ++i) rmax = R[i] > rmax ? R[i] : rmax;
     const uint32_t pcap = n > 0 ? link_capacity(rmax) : 0;
     if ((size_t)n * pcap > L->plist_entries) {
-        dev_free(L, L->plist);
-        L->plist = nullptr;
         L->plist_entries = 0;
-        if (dev_alloc(L, (void **)&L->plist, (size_t)n * pcap * sizeof(uint2)) != hipSuccess) {
-            L->np = 0;
-            return fail(LBMEP_ENOMEM, "link list allocation failed");
+        for (int r = 0; r < 2; ++r) {
+            dev_free(L, L->plist_buf[r]);
+            L->plist_buf[r] = nullptr;
         }
+        for (int r = 0; r < nlists; ++r)
+            if (dev_alloc(L, (void **)&L->plist_buf[r], (size_t)n * pcap * sizeof(uint2)) != hipSuccess) {
+                L->np = 0;
+                return fail(LBMEP_ENOMEM, "link list allocation failed");
+            }
         L->plist_entries = (size_t)n * pcap;
     }
     L->pcap = pcap;
+    L->halo_cap = n > 0 ? halo_capacity(rmax) : 0;
     // boundary values of the potential and the dynamics belong to the
     // particle table they were given with
     dev_free(L, L->zeta);
@@ -1013,7 +1050,17 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
     hipStream_t s = L->stream;
     const ParticleArgs pa = particle_args(L);
     const bool solve = L->force_mode == kForcePotential && L->sor_set && L->sor_iters > 0;
+    // overlapped stepping: prescribed kinematics (the next level's positions
+    // do not depend on this step's forces)
+    const bool ov = L->overlap && L->np > 0 && L->cfg.move_particles && !L->dynamic;
+    if (ov && !L->stream2) {
+        HIP_TRY(hipStreamCreateWithFlags(&L->stream2, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&L->ev_sweep, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&L->ev_chain, hipEventDisableTiming));
+    }
     for (int32_t it = 0; it < nsteps; ++it) {
+        // the sweep needs the flags, map and lists of its level
+        if (ov && L->chain_pending) HIP_TRY(hipStreamWaitEvent(s, L->ev_chain, 0));
         // the EDL potential of this level's map, before the collision that
         // uses its force
         if (solve) {
@@ -1041,6 +1088,7 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
                                             : kSweepPull;
         HIP_TRY(launch_sweep(L->precision, mode, L->force_mode, a, L->block_x, L->cpt, s));
         if (L->timing) HIP_TRY(hipEventRecord(e1, s));
+        if (ov) HIP_TRY(hipEventRecord(L->ev_sweep, s));
         // bounce-back slots and momentum exchange next to solid cells
         HIP_TRY(launch_near(L->precision, a, near_wall_blocks(L->g, L->has_walls), s));
         if (L->dynamic && L->np > 0) {
@@ -1063,13 +1111,39 @@ int lbmep_step(lbmep_lattice *L, int32_t nsteps) {
         if (L->np > 0 && L->cfg.move_particles) {
             // kinematics, re-mapping and classification of the next level
             const int b = 1 - L->cur_owner;
-            // clear the map buffer b held two levels back, move to level + 1
-            HIP_TRY(launch_advance(pa, L->level + 1, L->Xheld[b], L->owner[b], s));
-            HIP_TRY(launch_map_set(pa, L->Xheld[b], L->flag, L->owner[b], s));
-            HIP_TRY(launch_classify_boxes(pa, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
-                                          L->owner[b], L->owner[L->cur_owner], s));
+            // the next level's link lists: the other buffer when overlapped
+            ParticleArgs pn = pa;
+            pn.plist = L->plist_buf[L->overlap ? L->lcur ^ 1 : L->lcur];
+            pn.pcount = L->pcount_buf[L->overlap ? L->lcur ^ 1 : L->lcur];
+            if (ov) {
+                // on the second stream once the sweep has read the previous
+                // map, the positions and the flags, while the exchange runs
+                // (it reads the current link lists, positions and
+                // post-collision state only): clear the map held two levels
+                // back, map and classify the next level
+                hipStream_t s2 = L->stream2;
+                HIP_TRY(hipStreamWaitEvent(s2, L->ev_sweep, 0));
+                HIP_TRY(launch_advance(pn, L->level + 1, L->Xheld[b], L->owner[b], s2));
+                HIP_TRY(launch_map_set(pn, L->Xheld[b], L->flag, L->owner[b], s2));
+                HIP_TRY(launch_classify_boxes(pn, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
+                                              L->owner[b], L->owner[L->cur_owner], s2));
+                HIP_TRY(hipEventRecord(L->ev_chain, s2));
+                L->chain_pending = true;
+            } else {
+                // clear the map buffer b held two levels back, move to
+                // level + 1
+                HIP_TRY(launch_advance(pn, L->level + 1, L->Xheld[b], L->owner[b], s));
+                HIP_TRY(launch_map_set(pn, L->Xheld[b], L->flag, L->owner[b], s));
+                HIP_TRY(launch_classify_boxes(pn, L->Xheld[L->cur_owner], L->Xheld[b], L->flag,
+                                              L->owner[b], L->owner[L->cur_owner], s));
+            }
         }
         advance_state(L);
+    }
+    // later work on the lattice's stream follows the last classification
+    if (L->chain_pending) {
+        HIP_TRY(hipStreamWaitEvent(s, L->ev_chain, 0));
+        L->chain_pending = false;
     }
     return LBMEP_OK;
 }

@@ -126,7 +126,7 @@ struct SweepArgs {
     int nxb;                // x-segments per row (set by the launcher)
     int xcd_swizzle;        // 1: map consecutive segments onto one XCD
     int slip;               // free-slip faces: bit 2a + side (a = axis, side 1 = high)
-    int xpair;              // FP16: two cells per thread along x where the grid allows it
+    uint32_t lds;           // dynamic LDS bytes per sweep workgroup (caps the waves per CU; 0: none)
     int np;                 // particles
     uint32_t pcap;          // link-list capacity per particle
     const uint2 *plist;     // per particle: (cell, directions into the particle)
@@ -154,11 +154,16 @@ struct ParticleArgs {
     uint2 *plist;      // link lists written by the classification
     uint32_t *pcount;
     uint32_t pcap;
+    uint32_t halo_cap; // LDS bytes of the classification's staged box (one per cell)
 };
 
 // link-list capacity per particle for radii up to r_max: the cells whose
 // centre lies within one cell (per axis) of the ball, (2 ceil(R) + 3)^3
 uint32_t link_capacity(double r_max);
+// LDS bytes that stage the classification box of a particle of radius up to
+// r_max moving less than one cell per step, with its halo: (2 ceil(R) + 9)^3,
+// at most 32768 (larger boxes are classified from global memory)
+uint32_t halo_capacity(double r_max);
 
 // ---------------------------------------------------------------------------
 // Packed launches: one dispatch runs a kernel of the step for several

@@ -180,7 +180,7 @@ hipEvent_t get_event(lbmep_server *S) {
 size_t request_footprint(const lbmep_config &c, int32_t n, double r_max, bool charge, bool flags,
                          bool keep_fields) {
     const size_t N = (size_t)c.nx * c.ny * c.nz;
-    size_t b = lattice_bytes(&c, n, r_max, charge ? kForceCharge : kForceNone);
+    size_t b = lattice_bytes(&c, n, r_max, charge ? kForceCharge : kForceNone, false);
     b += 32 * Arena::kAlign;                 // alignment of the lattice's arrays
     b += round_up(sizeof(LatticeDev), Arena::kAlign);
     // staging of the inputs during set-up

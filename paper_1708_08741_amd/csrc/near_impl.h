@@ -10,14 +10,15 @@
 // slots are free); a link to an obstacle cell of particle p adds
 // [2 f*_q - 2 w_q rho0 c_q.u_s / c_s^2] c_q to F_p and r x (that) to M_p.
 //
-// Work distribution: one wavefront per particle (four per workgroup) walks
-// 64 entries at a time of the particle's link list, direction by direction (written by the classification: the fluid cells
-// next to the particle with the directions that hit it), so the particle's
-// position and velocities are uniform, no owner look-up is needed, and
-// force and torque are summed over the wavefront in a fixed order (DPP row
-// butterflies), the wavefronts' sums are combined in wavefront order through
-// LDS after one barrier, and the result is stored without atomics.  Links to wall cells
-// come from a list built when the walls are set.
+// Work distribution: one workgroup per particle walks the particle's link
+// list (written by the classification: the fluid cells next to the particle
+// with the directions that hit it), one link per lane in direction-major
+// order, so the particle's position and velocities are uniform, no owner
+// look-up is needed, and force and torque are summed over each wavefront in
+// a fixed order (DPP row butterflies), the wavefronts' sums are combined in
+// wavefront order through LDS after one barrier, and the result is stored
+// without atomics.  Links to wall cells come from a list built when the
+// walls are set.
 #pragma once
 #include "sweep_impl.h"
 
@@ -103,17 +104,20 @@ __device__ __forceinline__ typename Storage<ST>::CT load_fstar(const SweepArgs &
     return Storage<ST>::load(at<ST>(base, (OFF)c * (OFF)sizeof(ST)));
 }
 
-// One link of particle p at compile-time direction q: the bounce-back slot
-// and the momentum exchange into the lane's sums.
-template <int q, typename ST, typename OFF>
-__device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, int x, int y, int z,
+// One link of particle p in direction q (1..18, known at run time): the
+// bounce-back slot and the momentum exchange into the lane's sums.
+template <typename ST, typename OFF>
+__device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, int q,
                                               const double Xp[3], const double Up[3],
                                               const double Wp[3], double acc[kAcc]) {
     using T = Storage<ST>;
     using CT = typename T::CT;
-    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
     const Grid &g = a.g;
-    int sx = x + cx, sy = y + cy, sz = z + cz;
+    const int nx = g.nx, ny = g.ny;
+    const int cx = dir_comp(kPackCx, q), cy = dir_comp(kPackCy, q), cz = dir_comp(kPackCz, q);
+    int sx = (int)(c % (uint32_t)nx) + cx;
+    int sy = (int)((c / (uint32_t)nx) % (uint32_t)ny) + cy;
+    int sz = (int)(c / ((uint32_t)nx * (uint32_t)ny)) + cz;
     wrap_axis(sx, g.nx, g.per[0]);  // an obstacle cell: always inside
     wrap_axis(sy, g.ny, g.per[1]);
     wrap_axis(sz, g.nz, g.per[2]);
@@ -125,9 +129,11 @@ __device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, in
     const double us0 = Up[0] + (Wp[1] * r2 - Wp[2] * r1);
     const double us1 = Up[1] + (Wp[2] * r0 - Wp[0] * r2);
     const double us2 = Up[2] + (Wp[0] * r1 - Wp[1] * r0);
-    const double cus = cdot<q>(us0, us1, us2);
+    // c_q . u_s with unit components: the zero terms add exact zeros
+    const double cus = ((double)cx * us0 + (double)cy * us1) + (double)cz * us2;
+    const double w = q <= 6 ? wq(1) : wq(7);
     // 2 (w_q / c_s^2) rho0 c_q . u_s (Eq. LBMMovWall)
-    const double mw = 2.0 * wq(q) * 3.0 * cus;
+    const double mw = 2.0 * w * 3.0 * cus;
     // [2 f*_q - 2 (w_q/c_s^2) rho0 c_q . u_s] c_q (Eq. LBMhydrodynForce),
     // summed as [2 (f*_q - w_q) - ...] c_q plus the rest-weight part
     // 2 w_q c_q = (k/18) c_q (k = 2 axis, 1 diagonal), whose sum cancels
@@ -138,7 +144,7 @@ __device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, in
     const double g0 = cx == 0 ? 0.0 : (cx > 0 ? gm : -gm);
     const double g1 = cy == 0 ? 0.0 : (cy > 0 ? gm : -gm);
     const double g2 = cz == 0 ? 0.0 : (cz > 0 ? gm : -gm);
-    constexpr double k = q <= 6 ? 2.0 : 1.0;
+    const double k = q <= 6 ? 2.0 : 1.0;
     const double xs0 = image_coord((double)sx + 0.5, Xp[0], g.nx, g.per[0]);
     const double xs1 = image_coord((double)sy + 0.5, Xp[1], g.ny, g.per[1]);
     const double xs2 = image_coord((double)sz + 0.5, Xp[2], g.nz, g.per[2]);
@@ -158,22 +164,28 @@ __device__ __forceinline__ void particle_link(const SweepArgs &a, uint32_t c, in
     store_slot<ST, OFF>(a, q, s, fq, mw);
 }
 
-// All links of particle p (its list from the classification: cells with the
-// directions whose neighbour is an obstacle cell of p), one wavefront: the
-// bounce-back slots and the momentum exchange, summed over the wavefront in
-// a fixed order and stored (no atomics: the result does not depend on
-// scheduling).  The lanes take 64 consecutive list entries (neighbouring
-// cells along x) and walk the directions in the same order, so each load
-// and store instruction touches consecutive addresses of one population.
 // waves per particle in the exchange kernel (a 256-thread workgroup)
 constexpr int kNearWaves = 4;
+constexpr int kNearThreads = 64 * kNearWaves;
+// list entries per pass: their links (at most 18 each) are staged in LDS
+constexpr int kNearEntries = 128;
 
+// All links of particle p (its list from the classification: cells with the
+// directions whose neighbour is an obstacle cell of p), one workgroup: the
+// bounce-back slots and the momentum exchange, summed in a fixed order and
+// stored (no atomics: the result does not depend on scheduling).  The
+// workgroup takes 128 list entries per pass and lays their links out
+// direction by direction (per direction in list order, i.e. neighbouring
+// cells along x), then works through them 256 at a time, one link per lane:
+// every lane does useful work whatever the links per cell, and neighbouring
+// lanes load and store neighbouring values of one population.
 template <typename ST, typename OFF>
 __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
-    const int lane = (int)__lane_id();
-    const int wave = (int)(threadIdx.x / 64);
-    const Grid &g = a.g;
-    const int nx = g.nx, ny = g.ny;
+    __shared__ uint32_t lcell[kNearEntries * (Q - 1)];
+    __shared__ uint8_t lq[kNearEntries * (Q - 1)];
+    __shared__ uint32_t qcnt[2][Q];  // per direction: links of each half of the pass
+    __shared__ double part[kNearWaves][kAcc];
+    const int tid = (int)threadIdx.x, lane = (int)__lane_id(), wave = tid / 64;
     const uint2 *list = a.plist + (size_t)p * a.pcap;
     const uint32_t n = a.pcount[p];
     const double Xp[3] = {a.Xc[3 * (size_t)p], a.Xc[3 * (size_t)p + 1], a.Xc[3 * (size_t)p + 2]};
@@ -182,22 +194,40 @@ __device__ __forceinline__ void near_particle(const SweepArgs &a, uint32_t p) {
     double acc[kAcc];
 #pragma unroll
     for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
-    // the waves of the workgroup take every kNearWaves-th chunk of 64 entries
-    for (uint32_t i0 = 64u * (uint32_t)wave; i0 < n; i0 += 64u * kNearWaves) {
-        const uint32_t i = i0 + (uint32_t)lane;
-        uint2 e = make_uint2(0u, 0u);
-        if (i < n) e = list[i];
-        const uint32_t c = e.x, mask = e.y;
-        const int x = (int)(c % (uint32_t)nx);
-        const int y = (int)((c / (uint32_t)nx) % (uint32_t)ny);
-        const int z = (int)(c / ((uint32_t)nx * (uint32_t)ny));
-#define LBMEP_PLINK(q) \
-    if (mask & (1u << ((q)-1))) particle_link<q, ST, OFF>(a, c, x, y, z, Xp, Up, Wp, acc);
-        LBMEP_FOR_Q18(LBMEP_PLINK)
-#undef LBMEP_PLINK
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (uint32_t e0 = 0; e0 < n; e0 += kNearEntries) {
+        // waves 0 and 1 hold the pass's entries (one per lane); per direction
+        // a ballot gives each lane its rank and each wave its count
+        const uint32_t i = e0 + (uint32_t)tid;
+        const bool mine = wave < 2 && i < n;
+        const uint2 e = mine ? list[i] : make_uint2(0u, 0u);
+        uint32_t rank[Q - 1];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const unsigned long long b = __ballot((e.y >> (q - 1)) & 1u);
+            rank[q - 1] = (uint32_t)__popcll(b & below);
+            if (lane == 0 && wave < 2) qcnt[wave][q] = (uint32_t)__popcll(b);
+        }
+        __syncthreads();
+        // links in direction-major order: direction q starts after all links
+        // of the lower directions, wave 1's after wave 0's
+        uint32_t start = 0, total = 0;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const uint32_t off = start + (wave == 1 ? qcnt[0][q] : 0u);
+            if (mine && ((e.y >> (q - 1)) & 1u)) {
+                lcell[off + rank[q - 1]] = e.x;
+                lq[off + rank[q - 1]] = (uint8_t)q;
+            }
+            start += qcnt[0][q] + qcnt[1][q];
+        }
+        total = start;
+        __syncthreads();
+        for (uint32_t k = (uint32_t)tid; k < total; k += kNearThreads)
+            particle_link<ST, OFF>(a, lcell[k], (int)lq[k], Xp, Up, Wp, acc);
+        __syncthreads();  // lcell, lq and qcnt are rewritten by the next pass
     }
     // wave sums, then the waves' sums in wave order: a fixed order
-    __shared__ double part[kNearWaves][kAcc];
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) {
         const double t = wave_sum_f64(acc[k]);

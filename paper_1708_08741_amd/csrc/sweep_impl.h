@@ -386,6 +386,15 @@ __device__ __forceinline__ void slip_fix(const SweepArgs &a, int x, int y, int z
     v = Storage<ST>::lc(static_cast<const ST *>(a.src) + (size_t)p * a.g.Ns + sc);
 }
 
+// store population q of a cell at byte offset cb; addressed from the base of
+// its opposite pair like the gather (a uniform base plus a 32-bit offset)
+template <int q, int MODE, typename ST, typename OFF>
+__device__ __forceinline__ void store_pop(void *dst, OFF pst, OFF cb, typename Storage<ST>::CT v) {
+    constexpr int lo = q == 0 ? 0 : (q < opp(q) ? q : opp(q));
+    char *base = static_cast<char *>(dst) + (size_t)lo * pst;
+    pop_store<MODE, ST>(at<ST>(base, (OFF)(q - lo) * pst + cb), v);
+}
+
 // loaded inputs of one cell
 template <typename CT>
 struct CellIn {
@@ -502,10 +511,8 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
     }
 }
 
-// refill (if uncovered), collide, store, bounce-back slots and momentum
-// exchange of one loaded cell
-// (STORE = false: leave the post-collision values in c.v for the caller)
-template <typename ST, int FMODE, typename OFF, int MODE, bool STORE = true>
+// refill (if uncovered), collide and store one loaded cell
+template <typename ST, int FMODE, typename OFF, int MODE>
 __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, int z,
                                             CellIn<typename Storage<ST>::CT> &c) {
     using T = Storage<ST>;
@@ -627,13 +634,12 @@ __device__ __forceinline__ void finish_cell(const SweepArgs &a, int x, int y, in
         collide_pair<17>(v, rho, ux, uy, uz, uu, ufb, fb0, fb1, fb2, le, lo, ae, ao, forced);
         }
 
-        if constexpr (STORE) {
-            if (act) {
-                // aligned store of the post-collision state
-#pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    pop_store<MODE, ST>(at<ST>(static_cast<char *>(a.dst) + (size_t)q * pst, cb), v[q]);
-            }
+        if (act) {
+            // aligned store of the post-collision state
+#define LBMEP_STORE(q) store_pop<q, MODE, ST, OFF>(a.dst, pst, cb, v[q]);
+            LBMEP_STORE(0)
+            LBMEP_FOR_Q18(LBMEP_STORE)
+#undef LBMEP_STORE
         }
     }
 }
@@ -664,174 +670,6 @@ template <typename ST, int FMODE, typename OFF, int MODE, int CPT>
 __global__ void __launch_bounds__(512) k_sweep(SweepArgs a) {
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     sweep_segment<ST, FMODE, OFF, MODE, CPT>(a, lb);
-}
-
-// FP16 storage, two cells (x, x + 1) per thread along x (x even; nx even,
-// periodic x, no free-slip face): each population of the pair is one 4-byte
-// load (the two cells' gathered values are adjacent in the source row; for
-// c_x = +-1 the word starts at an odd element, a 2-byte aligned access), so a
-// wavefront moves 256 bytes per load instead of 128 and the loads in flight
-// per wavefront double.  The lanes whose pair straddles the row's periodic
-// seam patch the wrapped half with a 2-byte load.  The two cells are then
-// collided one after the other, exactly as the one-cell sweep collides them,
-// and stored as one 4-byte word per population (2 bytes where only one of
-// the two is a fluid cell).
-__device__ __forceinline__ uint32_t ld_u32(const char *p) {
-    uint32_t v;
-    __builtin_memcpy(&v, p, 4);
-    return v;
-}
-__device__ __forceinline__ uint32_t ld_u16(const char *p) {
-    uint16_t v;
-    __builtin_memcpy(&v, p, 2);
-    return v;
-}
-// a stored half and its value in compute units (deviation times 2^22)
-__device__ __forceinline__ float h16(uint32_t b) {
-    return __half2float(__ushort_as_half((unsigned short)b));
-}
-__device__ __forceinline__ uint32_t to_h16(float v) {
-    return (uint32_t)__half_as_ushort(__float2half_rn(v));
-}
-
-template <int q>
-__device__ __forceinline__ uint32_t gather_pair(const char *src, uint32_t pst, uint32_t cb,
-                                                const uint32_t rows[3][3], const bool rok[3][3],
-                                                uint32_t xb, bool seam_lo, bool seam_hi,
-                                                uint32_t last_b) {
-    constexpr int qb = opp(q);
-    constexpr int lo = q < qb ? q : qb;
-    constexpr int cx = kCx[q];
-    const char *base = src + (size_t)lo * pst;
-    const uint32_t own = (uint32_t)(qb - lo) * pst + cb;  // the pair's own q-bar values
-    if (!rok[kCy[q] + 1][kCz[q] + 1]) return ld_u32(base + own);  // beyond a non-periodic edge
-    const uint32_t row = (uint32_t)(q - lo) * pst + rows[kCy[q] + 1][kCz[q] + 1];
-    if constexpr (cx == 0) {
-        return ld_u32(base + row + xb);
-    } else {
-        // sources x - c_x, x + 1 - c_x: adjacent, starting 2 bytes off the pair
-        const bool seam = cx > 0 ? seam_lo : seam_hi;
-        uint32_t v = ld_u32(base + (seam ? own : row + xb - (uint32_t)(2 * cx)));
-        // at the seam the pair's sources are the row's last and first cells
-        // (x = 0, c_x = 1: x - 1 wraps; x + 1 = nx - 1, c_x = -1: x + 2 wraps)
-        if (seam) v = ld_u16(base + row + last_b) | (ld_u16(base + row) << 16);
-        return v;
-    }
-}
-
-template <int FMODE, int MODE>
-__device__ __forceinline__ void load_pair_h(const SweepArgs &a, int x, int y, int z, bool valid,
-                                            CellIn<float> &c0, CellIn<float> &c1) {
-    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const uint32_t pst = (uint32_t)a.g.Ns * 2u;
-    const int xc = valid ? x : 0, yc = valid ? y : 0;
-    const uint32_t ci = (uint32_t)xc + (uint32_t)nx * ((uint32_t)yc + (uint32_t)ny * (uint32_t)z);
-    const uint32_t cb = ci * 2u;
-    const uint32_t fp = ld_u16(reinterpret_cast<const char *>(a.flag) + ci);
-    c0.fl = valid ? (uint8_t)fp : kWall;
-    c1.fl = valid ? (uint8_t)(fp >> 8) : kWall;
-    uint32_t rows[3][3];
-    bool rok[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            int ys = yc - (j - 1), zs = z - (k - 1);
-            bool ok = true;
-            if (ys < 0 || ys >= ny) {
-                if (a.g.per[1]) ys = ys < 0 ? ys + ny : ys - ny; else { ok = false; ys = yc; }
-            }
-            if (zs < 0 || zs >= nz) {
-                if (a.g.per[2]) zs = zs < 0 ? zs + nz : zs - nz; else { ok = false; zs = z; }
-            }
-            rows[j][k] = (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * (uint32_t)zs) * 2u;
-            rok[j][k] = ok;
-        }
-    const uint32_t xb = (uint32_t)xc * 2u, last_b = (uint32_t)(nx - 1) * 2u;
-    const bool seam_lo = xc == 0, seam_hi = xc + 2 == nx;
-    const char *src = static_cast<const char *>(a.src);
-    uint32_t p[Q];
-    p[0] = ld_u32(src + cb);
-#define LBMEP_GPAIR(q) p[q] = gather_pair<q>(src, pst, cb, rows, rok, xb, seam_lo, seam_hi, last_b);
-    LBMEP_FOR_Q18(LBMEP_GPAIR)
-#undef LBMEP_GPAIR
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        c0.v[q] = h16(p[q] & 0xFFFFu);
-        c1.v[q] = h16(p[q] >> 16);
-    }
-    c0.fb0 = c0.fb1 = c0.fb2 = 0.f;
-    c1.fb0 = c1.fb1 = c1.fb2 = 0.f;
-    const float *force = static_cast<const float *>(a.force);
-    if constexpr (FMODE == kForceDense) {
-        const size_t fs = a.g.Ns;
-        const float2 f0 = *reinterpret_cast<const float2 *>(force + ci);
-        const float2 f1 = *reinterpret_cast<const float2 *>(force + fs + ci);
-        const float2 f2 = *reinterpret_cast<const float2 *>(force + 2 * fs + ci);
-        const float k = a.tf.fscale;
-        c0.fb0 = f0.x * k; c1.fb0 = f0.y * k;
-        c0.fb1 = f1.x * k; c1.fb1 = f1.y * k;
-        c0.fb2 = f2.x * k; c1.fb2 = f2.y * k;
-    } else if constexpr (FMODE == kForceCharge) {
-        const float2 re = *reinterpret_cast<const float2 *>(force + ci);
-        c0.fb0 = re.x * a.tf.Ec[0];
-        c0.fb1 = re.x * a.tf.Ec[1];
-        c0.fb2 = re.x * a.tf.Ec[2];
-        c1.fb0 = re.y * a.tf.Ec[0];
-        c1.fb1 = re.y * a.tf.Ec[1];
-        c1.fb2 = re.y * a.tf.Ec[2];
-    } else if constexpr (FMODE == kForcePotential) {
-        if (valid && !(c0.fl & (kWall | kObst)))
-            potential_force<float>(a.g, x, y, z, c0.fl, force, a.flag, a.owner, a.zeta, (float)a.keps,
-                                   (float)a.E[0], (float)a.E[1], (float)a.E[2], c0.fb0, c0.fb1, c0.fb2);
-        if (valid && !(c1.fl & (kWall | kObst)))
-            potential_force<float>(a.g, x + 1, y, z, c1.fl, force, a.flag, a.owner, a.zeta,
-                                   (float)a.keps, (float)a.E[0], (float)a.E[1], (float)a.E[2],
-                                   c1.fb0, c1.fb1, c1.fb2);
-        const float k = a.tf.fscale;
-        c0.fb0 *= k; c0.fb1 *= k; c0.fb2 *= k;
-        c1.fb0 *= k; c1.fb1 *= k; c1.fb2 *= k;
-    }
-}
-
-template <int FMODE, int MODE>
-__global__ void __launch_bounds__(512) k_sweep_pair_h(SweepArgs a) {
-    const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t xb = lb % (uint32_t)a.nxb, row = lb / (uint32_t)a.nxb;
-    const int y = (int)(row % (uint32_t)a.g.ny), z = (int)(row / (uint32_t)a.g.ny);
-    const int x = 2 * ((int)xb * (int)blockDim.x + (int)threadIdx.x);
-    const bool valid = x < a.g.nx;
-    CellIn<float> c0, c1;
-    load_pair_h<FMODE, MODE>(a, x, y, z, valid, c0, c1);
-    const bool act0 = !(c0.fl & (kWall | kObst)), act1 = !(c1.fl & (kWall | kObst));
-    finish_cell<__half, FMODE, uint32_t, MODE, false>(a, x, y, z, c0);
-    uint32_t h[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) h[q] = to_h16(c0.v[q]);
-    finish_cell<__half, FMODE, uint32_t, MODE, false>(a, x + 1, y, z, c1);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) h[q] |= to_h16(c1.v[q]) << 16;
-    if (!act0 && !act1) return;
-    const size_t pst = a.g.Ns * 2;
-    const uint32_t ci = (uint32_t)x + (uint32_t)a.g.nx * ((uint32_t)y + (uint32_t)a.g.ny * (uint32_t)z);
-    char *dst = static_cast<char *>(a.dst) + (size_t)ci * 2;
-    if (act0 && act1) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            uint32_t *d = reinterpret_cast<uint32_t *>(dst + (size_t)q * pst);  // 4-byte aligned: x even
-            if constexpr (MODE == kPullNT || MODE == kPullNTS)
-                __builtin_nontemporal_store(h[q], d);
-            else
-                *d = h[q];
-        }
-    } else {
-        // one fluid cell: its 2 bytes only (the solid cell's values stay)
-        const int k = act0 ? 0 : 1;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-            *reinterpret_cast<unsigned short *>(dst + (size_t)q * pst + 2 * k) =
-                (unsigned short)(h[q] >> (16 * k));
-    }
 }
 
 // the gather sweep of several lattices in one dispatch
@@ -868,36 +706,13 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     // 32-bit byte offsets when two population arrays fit in 4 GiB (the
     // gather addresses an opposite pair from one base)
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
-    if constexpr (sizeof(ST) == 2) {
-        // FP16: two cells per thread along x where the grid allows it
-        if (a.xpair && small && cpt == 1 && a.g.nx % 2 == 0 && a.g.per[0] && !a.slip &&
-            (mode == kPull || mode == kPullNT || mode == kPullNTS)) {
-            a.nxb = (a.g.nx / 2 + block_x - 1) / block_x;
-            const size_t nb = (size_t)a.nxb * a.g.ny * a.g.nz;
-            const dim3 grid((unsigned)nb, 1, 1), block(block_x, 1, 1);
-#define LBMEP_PAIR(MD, FM) hipLaunchKernelGGL((k_sweep_pair_h<FM, MD>), grid, block, 0, s, a)
-#define LBMEP_PAIR_F(MD)                                                     \
-    do {                                                                     \
-        if (force_mode == kForceNone) LBMEP_PAIR(MD, kForceNone);            \
-        else if (force_mode == kForceDense) LBMEP_PAIR(MD, kForceDense);     \
-        else if (force_mode == kForceCharge) LBMEP_PAIR(MD, kForceCharge);   \
-        else LBMEP_PAIR(MD, kForcePotential);                                \
-    } while (0)
-            if (mode == kPullNT) LBMEP_PAIR_F(kPullNT);
-            else if (mode == kPullNTS) LBMEP_PAIR_F(kPullNTS);
-            else LBMEP_PAIR_F(kPull);
-#undef LBMEP_PAIR_F
-#undef LBMEP_PAIR
-            return hipGetLastError();
-        }
-    }
     if (!small || mode == kReadout) cpt = 1;
     a.nxb = (a.g.nx + block_x - 1) / block_x;
     const size_t nblocks = (size_t)a.nxb * ((a.g.ny + cpt - 1) / cpt) * a.g.nz;
     const dim3 block(block_x, 1, 1);
     const dim3 grid((unsigned)nblocks, 1, 1);
 #define LBMEP_LAUNCH(MD, FM, OFF, C) \
-    hipLaunchKernelGGL((k_sweep<ST, FM, OFF, MD, C>), grid, block, 0, s, a)
+    hipLaunchKernelGGL((k_sweep<ST, FM, OFF, MD, C>), grid, block, a.lds, s, a)
 #define LBMEP_BY_FORCE(MD, OFF, C)                                           \
     do {                                                                     \
         if (force_mode == kForceNone) LBMEP_LAUNCH(MD, kForceNone, OFF, C);      \

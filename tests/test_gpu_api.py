@@ -231,14 +231,18 @@ def test_empty_particle_table_and_zero_steps(lb):
 @pytest.mark.parametrize("precision", [0, 1, 2])
 def test_sweep_variants_identical(lb, monkeypatch, precision):
     """Launch-shape variants of the sweep (streaming hints on / off, one or
-    two cells per thread, XCD block order) compute bitwise the same run."""
+    two cells per thread, XCD block order, workgroups per CU capped) and the
+    step with the next level's mapping on a second stream or in one stream
+    compute bitwise the same run."""
     ref = None
-    for env in [dict(), dict(LBMEP_SWEEP_PAIR="0"), dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1"),
+    for env in [dict(), dict(LBMEP_STEP_OVERLAP="0"), dict(LBMEP_SWEEP_WGCU="0"),
+                dict(LBMEP_SWEEP_WGCU="5"),
+                dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1"),
                 dict(LBMEP_SWEEP_NT="2"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
                 dict(LBMEP_SWEEP_NT="1", LBMEP_CPT="2"), dict(LBMEP_SWEEP_NT="2", LBMEP_CPT="2"),
                 dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
         for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X",
-                  "LBMEP_SWEEP_PAIR"):
+                  "LBMEP_SWEEP_WGCU", "LBMEP_STEP_OVERLAP"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
@@ -251,50 +255,3 @@ def test_sweep_variants_identical(lb, monkeypatch, precision):
         else:
             assert (out[0] == ref[0]).all(), env
             assert (out[1][0] == ref[1][0]).all() and (out[1][1] == ref[1][1]).all(), env
-
-
-@pytest.mark.parametrize("shape,periodic,walls,force", [
-    ((40, 36, 32), (True, True, True), False, "charge"),
-    ((24, 10, 12), (True, False, False), True, "dense"),
-    ((2, 3, 4), (True, True, False), False, "dense"),
-    ((130, 6, 5), (True, False, True), True, "potential"),
-    ((66, 8, 6), (True, True, True), False, "none"),
-])
-def test_fp16_pair_sweep_equals_one_cell(lb, monkeypatch, shape, periodic, walls, force):
-    """FP16 storage: the sweep with two cells per thread along x (4-byte
-    loads of adjacent gathered values, the row's periodic seam patched per
-    lane) gives bitwise the populations and forces of the one-cell sweep:
-    moving spheres, walls, non-periodic y / z edges, a 2-cell-wide grid (both
-    seams in one lane), every force mode."""
-    rng = np.random.default_rng(17)
-    nx, ny, nz = shape
-    fl = (rng.random((nz, ny, nx)) < (0.06 if walls else 0.0)).astype(np.uint8)
-    n = 3 if min(shape) >= 6 else 0
-    X = np.column_stack([rng.uniform(0, nx, n), rng.uniform(0, ny, n), rng.uniform(0, nz, n)])
-    R = rng.uniform(1.3, 2.2, n)
-    # FP16 deviations (scaled by 2^22) hold |f - w_q| < 0.0156: sphere speeds
-    # of 0.005 keep the bounce-back terms well inside that range
-    U = rng.uniform(-0.005, 0.005, size=(n, 3))
-    rho_e = (1e-3 * rng.standard_normal(shape[::-1])).astype(np.float32)
-    fb = (1e-5 * rng.standard_normal((3,) + shape[::-1])).astype(np.float32)
-    psi = (0.05 * rng.standard_normal(shape[::-1])).astype(np.float32)
-    out = {}
-    for pair in ("1", "0"):
-        monkeypatch.setenv("LBMEP_SWEEP_PAIR", pair)
-        g = lb.Lattice(shape, periodic, precision=lb.FP16DEV, move_particles=True)
-        g.set_flags(fl)
-        if force == "charge":
-            g.set_charge_force(rho_e, (1e-2, -5e-3, 2e-3))
-        elif force == "dense":
-            g.set_force(fb)
-        elif force == "potential":
-            g.set_potential_force(psi, 1e-3, (1e-2, 0.0, 0.0))
-        g.init_equilibrium()
-        g.set_particles(X, R, U)
-        g.step(13)
-        out[pair] = (g.get_pdfs(), g.ft())
-        g.close()
-    a, b = out["1"], out["0"]
-    assert np.isfinite(b[0]).all()
-    assert (a[0] == b[0]).all()
-    assert (a[1][0] == b[1][0]).all() and (a[1][1] == b[1][1]).all()

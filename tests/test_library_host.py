@@ -107,6 +107,10 @@ def test_footprint(shape, prec, np_, charge):
         assert lb.footprint(shape, prec, np_, charge, r_max=8.0) - b == np_ * 8 * (19 ** 3 - 11 ** 3)
     if shape == (512, 512, 512) and prec == lb.FP32DEV:
         assert 20.4e9 < b < 24e9  # fits one MI355X (288 GB) many times over
+    if np_:
+        # moving particles: the next level's link lists of the overlapped step
+        bm = lb.footprint(shape, prec, np_, charge, r_max=4.0, move_particles=True)
+        assert bm - b == links
 
 
 @pytest.mark.parametrize("kw", [
