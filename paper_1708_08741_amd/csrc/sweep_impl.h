@@ -345,19 +345,26 @@ __device__ __forceinline__ typename Storage<ST>::CT gather(const void *src, OFF 
     return pop_load<MODE, ST>(at<ST>(base, ok ? nb : own));
 }
 
-// free-slip faces: population q of a cell whose source x - c_q lies beyond a
-// free-slip face (along the axes of mask) comes from the tangential
-// neighbour s' (x - c_q with those components set back to x's) in the
-// mirrored direction, unless s' is a wall or obstacle cell or a crossed face
-// is no-slip (then the gather's half-way bounce-back stands).  Rare: only
-// cells on a free-slip face run this.
+// Free-slip faces: a population that a face cell x gathers from beyond a
+// free-slip face (direction q, source x - c_q outside along the axes of
+// mask) comes from the tangential neighbour s' (x - c_q with those
+// components set back to x's) in the direction p = q mirrored across the
+// crossed axes, unless s' is a wall or obstacle cell or a crossed face is
+// no-slip (then the half-way bounce-back stands).  Beyond a non-periodic
+// edge the gather reads slot q-bar of x itself, which no other gather reads;
+// slot p of s' is likewise read only through the reflection of (s', q2),
+// q2 = q-bar mirrored across the same axes, whose partner is (x, q).  So the
+// reflection is a swap of the two slots, made once per pair before a gather
+// of the state by a pass over the face cells; the gather itself keeps no
+// branch for it.
 template <int q, typename ST>
-__device__ __forceinline__ void slip_fix(const SweepArgs &a, int x, int y, int z,
-                                         typename Storage<ST>::CT &v) {
-    constexpr int cx = kCx[q], cy = kCy[q], cz = kCz[q];
+__device__ __forceinline__ void slip_pair(const SweepArgs &a, const int (&o)[3], size_t c,
+                                          int ax, int side) {
+    constexpr int cq[3] = {kCx[q], kCy[q], kCz[q]};
+    // the pass of face (ax, side) takes the directions that cross it
+    if (cq[ax] == 0 || (side == 0) != (cq[ax] > 0)) return;
     const int len[3] = {a.g.nx, a.g.ny, a.g.nz};
-    int s[3] = {x - cx, y - cy, z - cz};
-    const int o[3] = {x, y, z};
+    int s[3] = {o[0] - cq[0], o[1] - cq[1], o[2] - cq[2]};
     int mask = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -370,20 +377,46 @@ __device__ __forceinline__ void slip_fix(const SweepArgs &a, int x, int y, int z
         mask |= 1 << k;
         s[k] = o[k];
     }
-    if (!mask) return;
-    const size_t sc = (size_t)s[0] + (size_t)a.g.nx * ((size_t)s[1] + (size_t)a.g.ny * (size_t)s[2]);
-    if (a.flag[sc] & (kWall | kObst)) return;
-    int p = q;
+    // a pair that crosses an edge or corner is taken by its lowest axis
+    if (mask & ((1 << ax) - 1)) return;
+    int p = q, q2 = q;
     switch (mask) {
-        case 1: p = mirror_dir(q, 1); break;
-        case 2: p = mirror_dir(q, 2); break;
-        case 3: p = mirror_dir(q, 3); break;
-        case 4: p = mirror_dir(q, 4); break;
-        case 5: p = mirror_dir(q, 5); break;
-        case 6: p = mirror_dir(q, 6); break;
-        default: p = mirror_dir(q, 7); break;
+        case 1: p = mirror_dir(q, 1); q2 = mirror_dir(opp(q), 1); break;
+        case 2: p = mirror_dir(q, 2); q2 = mirror_dir(opp(q), 2); break;
+        case 3: p = mirror_dir(q, 3); q2 = mirror_dir(opp(q), 3); break;
+        case 4: p = mirror_dir(q, 4); q2 = mirror_dir(opp(q), 4); break;
+        case 5: p = mirror_dir(q, 5); q2 = mirror_dir(opp(q), 5); break;
+        case 6: p = mirror_dir(q, 6); q2 = mirror_dir(opp(q), 6); break;
+        default: p = mirror_dir(q, 7); q2 = mirror_dir(opp(q), 7); break;
     }
-    v = Storage<ST>::lc(static_cast<const ST *>(a.src) + (size_t)p * a.g.Ns + sc);
+    const size_t sc = (size_t)s[0] + (size_t)a.g.nx * ((size_t)s[1] + (size_t)a.g.ny * (size_t)s[2]);
+    // normal incidence (s' = x, p = q-bar): the bounce-back is the reflection;
+    // otherwise the pair is swapped by its smaller (cell, direction)
+    if (sc * Q + (size_t)q2 <= c * Q + (size_t)q) return;
+    if ((a.flag[c] | a.flag[sc]) & (kWall | kObst)) return;
+    ST *f = static_cast<ST *>(const_cast<void *>(a.src));
+    ST *u = f + (size_t)opp(q) * a.g.Ns + c;
+    ST *v = f + (size_t)p * a.g.Ns + sc;
+    const ST t = *u;
+    *u = *v;
+    *v = t;
+}
+
+// one thread per cell of free-slip face (ax, side)
+template <typename ST>
+__global__ void __launch_bounds__(256) k_slip_swap(SweepArgs a, int ax, int side) {
+    const int len[3] = {a.g.nx, a.g.ny, a.g.nz};
+    const int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)len[a1] * (size_t)len[a2]) return;
+    int o[3];
+    o[ax] = side ? len[ax] - 1 : 0;
+    o[a1] = (int)(i % (size_t)len[a1]);
+    o[a2] = (int)(i / (size_t)len[a1]);
+    const size_t c = (size_t)o[0] + (size_t)a.g.nx * ((size_t)o[1] + (size_t)a.g.ny * (size_t)o[2]);
+#define LBMEP_SLIP(q) slip_pair<q, ST>(a, o, c, ax, side);
+    LBMEP_FOR_Q18(LBMEP_SLIP)
+#undef LBMEP_SLIP
 }
 
 // store population q of a cell at byte offset cb; addressed from the base of
@@ -464,14 +497,6 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
 #define LBMEP_GATHER(q) c.v[q] = gather<q, ST, OFF, MODE>(a.src, pst, es, cb, rows, rok, xs, xok);
         LBMEP_FOR_Q18(LBMEP_GATHER)
 #undef LBMEP_GATHER
-        if (a.slip && valid &&
-            (((a.slip & 1) && x == 0) || ((a.slip & 2) && x == nx - 1) ||
-             ((a.slip & 4) && y == 0) || ((a.slip & 8) && y == ny - 1) ||
-             ((a.slip & 16) && z == 0) || ((a.slip & 32) && z == nz - 1))) {
-#define LBMEP_SLIP(q) slip_fix<q, ST>(a, x, y, z, c.v[q]);
-            LBMEP_FOR_Q18(LBMEP_SLIP)
-#undef LBMEP_SLIP
-        }
     }
     c.fb0 = c.fb1 = c.fb2 = CT(0);
     if constexpr (MODE != kReadout) {
@@ -706,6 +731,18 @@ hipError_t launch_typed(int mode, int force_mode, SweepArgs a, int block_x, int 
     // 32-bit byte offsets when two population arrays fit in 4 GiB (the
     // gather addresses an opposite pair from one base)
     const bool small = 2 * a.g.Ns * sizeof(ST) < (size_t(1) << 32) && 4 * a.g.Ns < (size_t(1) << 32);
+    if (a.slip && mode != kLocal) {
+        // free-slip faces: the reflected values into the slots the gather
+        // reads beyond those faces
+        const int len[3] = {a.g.nx, a.g.ny, a.g.nz};
+        for (int f = 0; f < 6; ++f) {
+            if (!(a.slip & (1 << f))) continue;
+            const int ax = f / 2;
+            const size_t cells = (size_t)len[ax == 0 ? 1 : 0] * (size_t)len[ax == 2 ? 1 : 2];
+            hipLaunchKernelGGL((k_slip_swap<ST>), dim3((unsigned)((cells + 255) / 256)), dim3(256), 0,
+                               s, a, ax, f & 1);
+        }
+    }
     if (!small || mode == kReadout) cpt = 1;
     a.nxb = (a.g.nx + block_x - 1) / block_x;
     const size_t nblocks = (size_t)a.nxb * ((a.g.ny + cpt - 1) / cpt) * a.g.nz;
