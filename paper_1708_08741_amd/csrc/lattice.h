@@ -99,7 +99,7 @@ struct lbmep_lattice {
     int sor_mzc = 16; // planes per workgroup of the one-pass SOR iteration
     int sor_mrw = 4;  // rows per thread of the one-pass SOR iteration (set per precision)
     int xcd_swizzle = 1;
-    int sweep_lds = 0;  // sweep: dynamic LDS bytes per workgroup (caps its workgroups per CU)
+    int sweep_wgcu = -1;  // sweep: workgroups per CU (0: no cap, -1: per precision and force)
     int sweep_nt = 2;  // streaming hints of the sweep: 0 none, 1 loads + stores, 2 stores
     // overlapped stepping (moving particles, prescribed kinematics): the
     // kinematics, mapping and classification of level n + 1 run on a second

@@ -175,7 +175,16 @@ SweepArgs sweep_args_state(const lbmep_lattice *L, int cur, int co) {
     a.nxb = 0;
     a.xcd_swizzle = L->xcd_swizzle;
     a.slip = L->slip;
-    a.lds = (uint32_t)L->sweep_lds;
+    // measured at 512^3 (4096 moving spheres, two repeats): a cap of 4
+    // workgroups per CU is fastest for FP32 (3.56-3.71 ms; 3: 4.1-4.5, none:
+    // 3.56-3.84) and FP64 (7.03-7.21 ms; none: 7.19-8.06) with a charge or
+    // dense force; FP16 and the force from the potential (its neighbour
+    // reads of psi want every wave: 4.4-4.6 ms uncapped, 5.8-6.2 with 4) run
+    // best uncapped
+    int wgcu = L->sweep_wgcu;
+    if (wgcu < 0)
+        wgcu = L->force_mode == kForcePotential || L->precision == LBMEP_FP16DEV ? 0 : 4;
+    a.lds = wgcu > 0 ? (uint32_t)((160 * 1024) / wgcu / 16 * 16) : 0u;
     a.keps = L->keps;
     a.zeta = L->force_mode == kForcePotential ? L->zeta : nullptr;
     a.np = L->np;
@@ -444,17 +453,14 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     // FP64 storage (the loads' one-element overlaps along x then hit L2);
     // FP16 gains from hints on the loads as well
     // workgroups per CU of the sweep capped by a dynamic LDS allocation per
-    // workgroup (the kernel uses none of it; 160 KiB of LDS per CU).  Measured
-    // at 512^3: FP32 is fastest with 3 workgroups of 256 threads per CU (3
-    // waves per SIMD; 3.72 against 3.82 ms uncapped), FP64 with 4 of 128 (2
-    // waves per SIMD; 7.80 against 7.92 ms), FP16 uncapped.
-    // LBMEP_SWEEP_WGCU (workgroups per CU, 0: no cap) overrides it
-    int wgcu = L->precision == LBMEP_FP32DEV ? 3 : L->precision == LBMEP_FP64 ? 4 : 0;
+    // workgroup (the kernel uses none of it; 160 KiB of LDS per CU), set per
+    // force mode in sweep_args_state; LBMEP_SWEEP_WGCU (workgroups per CU, 0:
+    // no cap) overrides it
+    L->sweep_wgcu = -1;
     if (const char *e = std::getenv("LBMEP_SWEEP_WGCU")) {
         const int w = std::atoi(e);
-        if (w >= 0 && w <= 32) wgcu = w;
+        if (w >= 0 && w <= 32) L->sweep_wgcu = w;
     }
-    L->sweep_lds = wgcu > 0 ? (160 * 1024) / wgcu / 16 * 16 : 0;
     L->sweep_nt = L->precision == LBMEP_FP16DEV ? 1 : 2;
     if (const char *e = std::getenv("LBMEP_SWEEP_NT")) {
         const int v = std::atoi(e);
