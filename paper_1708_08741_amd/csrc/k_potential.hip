@@ -14,7 +14,8 @@
 // 2 b_p - psi_i) and a wall or beyond-edge neighbour is a homogeneous
 // Neumann boundary (it counts psi_i).  A half-sweep relaxes every unknown of
 // one colour ((x + y + z) & 1) with
-//     psi_i <- (1 - omega) psi_i + omega (rhs_i + sum) / diag_i;
+//     psi_i <- (1 - omega) psi_i + omega (rhs_i + sum) / diag_i
+// (in FP32 the quotient as a product with the reciprocal, see sor_quot);
 // same-coloured cells are never neighbours (even extents along periodic
 // axes), so a half-sweep is order-free and each cell is written by one
 // thread.  Terms are formed in the order x-, x+, y-, y+, z-, z+, so the
@@ -44,6 +45,15 @@ namespace {
 
 constexpr int kSorBlock = 256;
 constexpr int kResBlock = 256;
+
+// (rhs + sum) / diag of a relaxation: the exact quotient in FP64 (the
+// rounding of a plain CPU evaluation); in FP32 the product with the
+// reciprocal, which for the interior rows is a constant of the launch (one
+// multiplication instead of a correctly rounded division, within one
+// rounding of it).  Every FP32 form of an iteration uses it, so they stay
+// bitwise equal to each other.
+__device__ __forceinline__ double sor_quot(double x, double diag) { return x / diag; }
+__device__ __forceinline__ float sor_quot(float x, float diag) { return x * (1.0f / diag); }
 
 // row of unknown cell (x, y, z) with flag fl: diag, rhs and the sum over
 // unknown neighbours.  Next to boundaries, the six neighbour flags and
@@ -208,7 +218,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, i
 #pragma unroll
             for (int k = 0; k < 6; ++k) sum = sum + v[r][k];
             const CT old = p ? pair[r][1] : pair[r][0];
-            const CT nw = (CT(1.0) - om) * old + om * ((rhs + sum) / diag);
+            const CT nw = (CT(1.0) - om) * old + om * sor_quot(rhs + sum, diag);
             if (p) pair[r][1] = nw;
             else pair[r][0] = nw;
         }
@@ -402,7 +412,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
 #pragma unroll
                 for (int k = 0; k < 6; ++k) sum = sum + nb[k];
                 const CT rhs = CT(0);
-                const CT nw = (CT(1.0) - om) * O[r] + om * ((rhs + sum) / diag);
+                const CT nw = (CT(1.0) - om) * O[r] + om * sor_quot(rhs + sum, diag);
                 *reinterpret_cast<GlobalPtr<CT>>(
                     uniform_ptr(reinterpret_cast<char *>(qz + ro[r])) + io) = nw;
             }
@@ -728,7 +738,7 @@ __device__ void sor_near_part(const SorArgs &a, int colour, uint32_t b0, uint32_
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             if ((mask >> k) & 1) sum = sum + v[k];
-        dst[pc] = (CT(1.0) - om) * own + om * ((rhs + sum) / diag);
+        dst[pc] = (CT(1.0) - om) * own + om * sor_quot(rhs + sum, diag);
     }
 }
 
@@ -875,7 +885,7 @@ __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6
         CT sum = CT(0);
 #pragma unroll
         for (int k = 0; k < 6; ++k) sum = sum + nb[k];
-        return om1 * own + om * ((CT(0) + sum) / diag0);
+        return om1 * own + om * sor_quot(CT(0) + sum, diag0);
     }
     CT diag = diag0, rhs = CT(0), sum = CT(0);
 #pragma unroll
@@ -885,18 +895,18 @@ __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6
         rhs = rhs + (t == 2u ? CT(2.0) * nb[k] : CT(0.0));
         sum = sum + (t == 0u ? nb[k] : CT(0.0));
     }
-    const CT nw = om1 * own + om * ((rhs + sum) / diag);
+    const CT nw = om1 * own + om * sor_quot(rhs + sum, diag);
     return (code & 0x8000u) ? nw : own;
 }
 
-template <typename CT, int RW>
-__global__ void __launch_bounds__(1024) k_sor_march(SorArgs a, const CT *A, CT *B, uint32_t nyb,
-                                                    uint32_t zc) {
+template <typename CT, int RW, int MAXW>
+__global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A, CT *B, uint32_t nyb,
+                                                         uint32_t zc) {
     if (a.ctl->done) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->iters += 1;
     // end values of each wavefront's rows: [step parity][row][wavefront][first, last]
-    __shared__ CT e_old[2][RW + 2][kMarchMaxWaves][2];  // black, old, plane z + 1
-    __shared__ CT e_new[2][RW][kMarchMaxWaves][2];      // red, new, plane z + 1
+    __shared__ CT e_old[2][RW + 2][MAXW][2];  // black, old, plane z + 1
+    __shared__ CT e_new[2][RW][MAXW][2];      // red, new, plane z + 1
     const Grid &g = a.g;
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t zb = lb / nyb, yb = lb - zb * nyb;  // neighbouring y-blocks share an XCD
@@ -1218,13 +1228,16 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     // one pass per iteration: even nx, whole rows in one workgroup, a second
     // buffer; rows per thread: the largest of mrw, mrw / 2, ... dividing ny
     const bool march = fused && vec && hx <= 64 * kMarchMaxWaves && a0.psi2 != nullptr;
-    // windows of more than 4 rows per thread spill
+    const uint32_t mthreads = 64u * (uint32_t)((hx + 63) / 64);
+    // windows of more than 4 rows per thread spill in a kernel bounded for
+    // 1024 threads; bounded for 256 (rows of up to 512 cells) 8 rows fit in
+    // 130 VGPRs, but at 3 waves per SIMD the march ran slower (512^3 FP32:
+    // 0.453 against 0.377 ms per iteration)
     int mrw = a0.mrw >= 4 ? 4 : (a0.mrw >= 2 ? 2 : 1);
     while (g.ny % mrw) mrw >>= 1;
     const uint32_t mzc = a0.mzc >= 1 ? a0.mzc : 16u;
     const uint32_t myb = (uint32_t)(g.ny / mrw);
     const uint32_t mblk = myb * (uint32_t)((g.nz + (int)mzc - 1) / (int)mzc);
-    const uint32_t mthreads = 64u * (uint32_t)((hx + 63) / 64);
     const size_t rblk = (g.N + kResBlock - 1) / kResBlock;
     const int nres = (int)(rblk < (size_t)(kSorPartials / 2) ? rblk : (size_t)(kSorPartials / 2));
     const bool with_res = a0.rf > 0.0;
@@ -1275,12 +1288,12 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
         if (march) {
             const CT *src = static_cast<const CT *>(a.psi);
             CT *dst = static_cast<CT *>(a.psi == a0.psi ? a0.psi2 : a0.psi);
-#define LBMEP_SOR_MARCH(RW)                                                                  \
-    hipLaunchKernelGGL((k_sor_march<CT, RW>), dim3(mblk), dim3(mthreads), 0, s, a, src, dst, myb, \
-                       mzc)
-            if (mrw == 4) LBMEP_SOR_MARCH(4);
-            else if (mrw == 2) LBMEP_SOR_MARCH(2);
-            else LBMEP_SOR_MARCH(1);
+#define LBMEP_SOR_MARCH(RW, W)                                                                 \
+    hipLaunchKernelGGL((k_sor_march<CT, RW, W>), dim3(mblk), dim3(mthreads), 0, s, a, src, dst, \
+                       myb, mzc)
+            if (mrw == 4) LBMEP_SOR_MARCH(4, kMarchMaxWaves);
+            else if (mrw == 2) LBMEP_SOR_MARCH(2, kMarchMaxWaves);
+            else LBMEP_SOR_MARCH(1, kMarchMaxWaves);
 #undef LBMEP_SOR_MARCH
             a.psi = dst;
         } else {
