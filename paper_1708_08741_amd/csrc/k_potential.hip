@@ -117,18 +117,25 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
         }
     }
     uint8_t um = 0;
+    int nd = 0, nn = 0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         if (edge[k] || (fs[k] & kWall)) {
-            diag = diag - CT(1.0);  // homogeneous Neumann (edge or wall)
+            // homogeneous Neumann (edge or wall)
+            if constexpr (sizeof(CT) == 8) diag = diag - CT(1.0);
+            ++nn;
         } else if (fs[k] & kObst) {
-            diag = diag + CT(1.0);  // Dirichlet on the shared face
+            // Dirichlet on the shared face
+            if constexpr (sizeof(CT) == 8) diag = diag + CT(1.0);
+            ++nd;
             rhs = rhs + CT(2.0) * bv[k];
         } else {
             sum = sum + pv[k];
             um |= (uint8_t)(1u << k);
         }
     }
+    // FP32: the face count added to 6 + kappa^2 at once (see relax_code)
+    if constexpr (sizeof(CT) == 4) diag = diag + (CT)(nd - nn);
     if (unknown) *unknown = um;
 }
 
@@ -887,11 +894,18 @@ __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6
         for (int k = 0; k < 6; ++k) sum = sum + nb[k];
         return om1 * own + om * sor_quot(CT(0) + sum, diag0);
     }
+    // diag = 6 + kappa^2 + (Dirichlet faces) - (Neumann faces): in FP64 the
+    // +-1 of each face in direction order (a plain CPU evaluation's
+    // rounding), in FP32 the face count added at once, as dha_row does for
+    // FP32 (two popcounts instead of a select chain per direction); rhs and
+    // sum add their terms in direction order (a skipped term adds an exact 0)
     CT diag = diag0, rhs = CT(0), sum = CT(0);
+    if constexpr (sizeof(CT) == 4)
+        diag = diag0 + (CT)(__builtin_popcount(code & 0xAAAu) - __builtin_popcount(code & 0x555u));
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const uint32_t t = (code >> (2 * k)) & 3u;
-        diag = diag + (t == 1u ? CT(-1.0) : (t == 2u ? CT(1.0) : CT(0.0)));
+        if constexpr (sizeof(CT) == 8) diag = diag + (t == 1u ? CT(-1.0) : (t == 2u ? CT(1.0) : CT(0.0)));
         rhs = rhs + (t == 2u ? CT(2.0) * nb[k] : CT(0.0));
         sum = sum + (t == 0u ? nb[k] : CT(0.0));
     }
