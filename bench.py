@@ -40,7 +40,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_collide_512.json")
 # charge force, 32-bit offsets, streaming-hint mode, one cell per thread)
 SWEEP_KERNEL = {"fp32dev": "k_sweep<float, 2, unsigned int, 4, 1>",
                 "fp64": "k_sweep<double, 2, unsigned int, 4, 1>",
-                "fp16dev": "k_sweep<__half, 2, unsigned int, 3, 1>"}
+                "fp16dev": "k_sweep<__half, 2, unsigned int, 4, 1>"}
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_08741_amd", "csrc", "sweep_impl.h")
 # the sweep's launch shape (segment width, block order, population stride) is
 # set in the API source: counters taken on other settings do not apply

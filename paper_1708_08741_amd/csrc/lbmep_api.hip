@@ -402,12 +402,14 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
     // stores (every value is read once and written once per step);
     // LBMEP_BLOCK_X, LBMEP_CPT, LBMEP_XCD_SWIZZLE and LBMEP_SWEEP_NT override
     // the defaults for launch-shape sweeps
-    // measured at 512^3 (4096 spheres): FP32 is fastest with 256-cell
-    // segments in hardware order (every XCD streams the same planes: 5.45
-    // against 5.11 TB/s with XCD-contiguous 128-cell segments); FP16 with
-    // 256-cell segments in XCD-contiguous order; FP64 with 128-cell ones
-    L->block_x = L->precision == LBMEP_FP64 ? 128 : 256;
-    L->xcd_swizzle = L->precision != LBMEP_FP32DEV;
+    // measured at 512^3 (4096 spheres; segment width x block order x hints,
+    // then repeated): FP32 is fastest with 256-cell segments in hardware
+    // order (every XCD streams the same planes; 3.71 ms, XCD-contiguous 256:
+    // 4.05-4.13), FP16 with 512-cell segments in hardware order (1.99 ms in
+    // three repeats against 2.16-2.21 with 256 XCD-contiguous), FP64 with
+    // 128-cell segments in XCD-contiguous order (7.75 ms; hardware 7.86)
+    L->block_x = L->precision == LBMEP_FP64 ? 128 : L->precision == LBMEP_FP16DEV ? 512 : 256;
+    L->xcd_swizzle = L->precision == LBMEP_FP64;
     L->cpt = 1;
     if (const char *e = std::getenv("LBMEP_CPT")) {
         const int c = std::atoi(e);
@@ -449,9 +451,10 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         if (b >= 64 && b <= 512 && b % 64 == 0) L->block_x = b;
     }
     if (const char *e = std::getenv("LBMEP_XCD_SWIZZLE")) L->xcd_swizzle = std::atoi(e) != 0;
-    // measured at 512^3: hints on the stores only are fastest for FP32 and
-    // FP64 storage (the loads' one-element overlaps along x then hit L2);
-    // FP16 gains from hints on the loads as well
+    // measured at 512^3: hints on the stores only are fastest for every
+    // storage type (the loads' one-element overlaps along x then hit L2;
+    // FP16 with 512-cell segments: 1.99 against 2.02-2.06 ms with hints on
+    // the loads too)
     // workgroups per CU of the sweep capped by a dynamic LDS allocation per
     // workgroup (the kernel uses none of it; 160 KiB of LDS per CU), set per
     // force mode in sweep_args_state; LBMEP_SWEEP_WGCU (workgroups per CU, 0:
@@ -461,7 +464,7 @@ int create_lattice(const lbmep_config *cfg, DevHeap *heap, lbmep_lattice **out) 
         const int w = std::atoi(e);
         if (w >= 0 && w <= 32) L->sweep_wgcu = w;
     }
-    L->sweep_nt = L->precision == LBMEP_FP16DEV ? 1 : 2;
+    L->sweep_nt = 2;
     if (const char *e = std::getenv("LBMEP_SWEEP_NT")) {
         const int v = std::atoi(e);
         if (v >= 0 && v <= 2) L->sweep_nt = v;

@@ -703,9 +703,8 @@ __global__ void __launch_bounds__(kPackBlockX) k_sweep_packed(PackTable t) {
     const uint32_t gb = t.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int e = pack_find(t, gb);
     const SweepArgs a = t.d[e]->sweep[t.state[e]];
-    // streaming hints as in the single-lattice default: stores only, and
-    // loads too for FP16 storage
-    constexpr int MODE = sizeof(ST) == 2 ? kPullNT : kPullNTS;
+    // streaming hints as in the single-lattice default: stores only
+    constexpr int MODE = kPullNTS;
     sweep_segment<ST, FMODE, uint32_t, MODE, 1>(a, gb - t.start[e]);
 }
 

@@ -240,7 +240,8 @@ def test_sweep_variants_identical(lb, monkeypatch, precision):
                 dict(LBMEP_SWEEP_NT="0"), dict(LBMEP_SWEEP_NT="1"),
                 dict(LBMEP_SWEEP_NT="2"), dict(LBMEP_SWEEP_NT="0", LBMEP_CPT="2"),
                 dict(LBMEP_SWEEP_NT="1", LBMEP_CPT="2"), dict(LBMEP_SWEEP_NT="2", LBMEP_CPT="2"),
-                dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256")]:
+                dict(LBMEP_XCD_SWIZZLE="0", LBMEP_BLOCK_X="256"),
+                dict(LBMEP_XCD_SWIZZLE="1", LBMEP_BLOCK_X="512")]:
         for k in ("LBMEP_SWEEP_NT", "LBMEP_CPT", "LBMEP_XCD_SWIZZLE", "LBMEP_BLOCK_X",
                   "LBMEP_SWEEP_WGCU", "LBMEP_STEP_OVERLAP"):
             monkeypatch.delenv(k, raising=False)
