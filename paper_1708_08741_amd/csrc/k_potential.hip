@@ -853,20 +853,21 @@ template <typename CT>
 __device__ __forceinline__ CT dpp_rot(CT v, int ctrl);
 template <>
 __device__ __forceinline__ float dpp_rot<float>(float v, int ctrl) {
-    // ctrl is a constant at every call site after inlining
-    return ctrl == 0x13C ? __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x13C, 0xF, 0xF, false))
-                         : __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+    // ctrl is a constant at every call site after inlining; a wavefront
+    // rotate has a source lane for every lane, so no old value is needed
+    return ctrl == 0x13C ? __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x13C, 0xF, 0xF, false))
+                         : __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
 }
 template <>
 __device__ __forceinline__ double dpp_rot<double>(double v, int ctrl) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     int lo, hi;
     if (ctrl == 0x13C) {
-        lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x13C, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x13C, 0xF, 0xF, false);
+        lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x13C, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x13C, 0xF, 0xF, false);
     } else {
-        lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x134, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x134, 0xF, 0xF, false);
+        lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x134, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x134, 0xF, 0xF, false);
     }
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) |
                                             (unsigned long long)(uint32_t)lo));
@@ -887,7 +888,7 @@ constexpr uint32_t kCodePairInterior = 0x80008000u;
 // dha_row's order (adding 0 where dha_row adds nothing changes no bit)
 template <typename CT>
 __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6], CT om, CT om1,
-                                         CT diag0) {
+                                         CT diag0, const float *rd) {
     if (code == kCodeInterior) {
         CT sum = CT(0);
 #pragma unroll
@@ -896,12 +897,11 @@ __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6
     }
     // diag = 6 + kappa^2 + (Dirichlet faces) - (Neumann faces): in FP64 the
     // +-1 of each face in direction order (a plain CPU evaluation's
-    // rounding), in FP32 the face count added at once, as dha_row does for
-    // FP32 (two popcounts instead of a select chain per direction); rhs and
+    // rounding); in FP32 the face count added at once, as dha_row does for
+    // FP32, and sor_quot's reciprocal of it read from the table rd (the 13
+    // correctly rounded values, so the same bits as the division); rhs and
     // sum add their terms in direction order (a skipped term adds an exact 0)
     CT diag = diag0, rhs = CT(0), sum = CT(0);
-    if constexpr (sizeof(CT) == 4)
-        diag = diag0 + (CT)(__builtin_popcount(code & 0xAAAu) - __builtin_popcount(code & 0x555u));
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const uint32_t t = (code >> (2 * k)) & 3u;
@@ -909,7 +909,13 @@ __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6
         rhs = rhs + (t == 2u ? CT(2.0) * nb[k] : CT(0.0));
         sum = sum + (t == 0u ? nb[k] : CT(0.0));
     }
-    const CT nw = om1 * own + om * sor_quot(rhs + sum, diag);
+    CT nw;
+    if constexpr (sizeof(CT) == 4) {
+        const int k = 6 + __builtin_popcount(code & 0xAAAu) - __builtin_popcount(code & 0x555u);
+        nw = om1 * own + om * ((rhs + sum) * rd[k]);
+    } else {
+        nw = om1 * own + om * sor_quot(rhs + sum, diag);
+    }
     return (code & 0x8000u) ? nw : own;
 }
 
@@ -921,6 +927,8 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
     // end values of each wavefront's rows: [step parity][row][wavefront][first, last]
     __shared__ CT e_old[2][RW + 2][MAXW][2];  // black, old, plane z + 1
     __shared__ CT e_new[2][RW][MAXW][2];      // red, new, plane z + 1
+    __shared__ float rd[16];                  // FP32: the reciprocals of the diagonals
+    if (threadIdx.x < 13) rd[threadIdx.x] = a.rdiag[threadIdx.x];  // read after a barrier
     const Grid &g = a.g;
     const uint32_t lb = a.xcd_swizzle ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t zb = lb / nyb, yb = lb - zb * nyb;  // neighbouring y-blocks share an XCD
@@ -1040,7 +1048,7 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
             if (!p && lane == 0) xm = e_old[par][r][wl][1];
             if (p && lane == lw) xp = e_old[par][r][wr][0];
             const CT nb[6] = {xm, xp, Bo1[r], Bo1[r + 2], Bo0[r], Bo2[r]};
-            R1[r] = relax_code<CT>(Cr[r] & 0xFFFFu, Ro1[r], nb, om, om1, diag0);
+            R1[r] = relax_code<CT>(Cr[r] & 0xFFFFu, Ro1[r], nb, om, om1, diag0, rd);
         }
         if (act && z + 1 >= zs && z + 1 < ze) {
 #pragma unroll
@@ -1064,7 +1072,7 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
                 if (!p && lane == 0) xm = e_new[par ^ 1][r][wl][1];
                 if (p && lane == lw) xp = e_new[par ^ 1][r][wr][0];
                 const CT nb[6] = {xm, xp, R0[r], R0[r + 2], Rm[r], R1[r + 1]};
-                const CT v = relax_code<CT>(Cb[r] >> 16, Bo0[r + 1], nb, om, om1, diag0);
+                const CT v = relax_code<CT>(Cb[r] >> 16, Bo0[r + 1], nb, om, om1, diag0, rd);
                 if (act) st(Bb + pz + ro_[r + 2], v);
             }
         }
@@ -1116,89 +1124,86 @@ __device__ __forceinline__ uint32_t sor_code(const Grid &g, const uint8_t *flag,
     return code;
 }
 
-// once per solve, 16 cells (8 entries) per thread, read as one 16-byte load
-// of the flags (padded to 4096 cells; nx even, so an entry never straddles a
-// row): the code word of every entry with a cell that is not an interior
-// unknown (the only words k_sor_march reads), and, with surface potentials,
-// zeta into the obstacle cells (their own values kept in save and put back
-// by k_dirichlet_restore after the solve)
+// sor_code of a cell with no neighbour across a grid face (x, y, z all
+// strictly inside): the six neighbours at fixed offsets, no wrap or edge
+__device__ __forceinline__ uint32_t sor_code_inner(const uint8_t *f, ptrdiff_t nx, ptrdiff_t nxy) {
+    if (f[0] & (kWall | kObst)) return 0u;
+    const uint8_t fs[6] = {f[-1], f[1], f[-nx], f[nx], f[-nxy], f[nxy]};
+    uint32_t code = 0x8000u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (fs[k] & kWall) code |= 1u << (2 * k);
+        else if (fs[k] & kObst) code |= 2u << (2 * k);
+    }
+    return code;
+}
+
+// once per solve, one thread per entry (the cells x = 2i, 2i + 1 of a row;
+// grid: entries of a row along x, then y and z), its two flags read as one
+// 2-byte load: the code word of every entry with a cell that is not an
+// interior unknown (the only words k_sor_march reads), and, with surface
+// potentials, zeta into the obstacle cells (their own values kept in save
+// and put back by k_dirichlet_restore after the solve).  A thread near a
+// sphere does a few dozen instructions, so the wavefronts that have one
+// stay short (512^3 with 4096 spheres: 16 cells per thread with a 64-bit
+// index decomposition took 0.53 ms)
 template <typename CT>
 __global__ void __launch_bounds__(256) k_sor_prepare(SorArgs a, CT *psi, CT *save, int dirichlet) {
     const Grid &g = a.g;
-    const size_t c0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 16;
-    if (c0 >= g.N) return;
-    const uint4 q = *reinterpret_cast<const uint4 *>(a.flag + c0);
-    const uint32_t fw[4] = {q.x, q.y, q.z, q.w};
-    const uint32_t any = 0x01010101u * (uint32_t)(kWall | kObst | kNear);
-    if (!((fw[0] | fw[1] | fw[2] | fw[3]) & any)) return;  // interior unknowns: codes implied
-    const size_t nx = (size_t)g.nx, hx = nx >> 1;
-    size_t yz = c0 / nx;
-    int x = (int)(c0 - yz * nx);
-    int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
-    for (int k = 0; k < 8; ++k) {
-        const size_t c = c0 + 2 * (size_t)k;
-        if (c >= g.N) break;
-        const uint32_t fp = (fw[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;  // cells x, x + 1
-        if ((fp | (fp >> 8)) & (uint32_t)(kWall | kObst | kNear)) {
-            const int pr = (y + z) & 1;  // the red cell of the entry is x + pr
-            const uint32_t cr = sor_code(g, a.flag, x + pr, y, z);
-            const uint32_t cb = sor_code(g, a.flag, x + 1 - pr, y, z);
-            const size_t e = c >> 1;
-            a.codes[e] = cr | (cb << 16);
-            if (dirichlet) {
-                for (int m = 0; m < 2; ++m) {
-                    const uint8_t fl = (uint8_t)(fp >> (8 * m));
-                    if (!(fl & kObst) || (fl & kWall)) continue;
-                    const uint32_t p = a.owner[c + (size_t)m];
-                    if (p == kNone) continue;
-                    // cell x + m has colour (x + m + y + z) & 1
-                    const size_t sl = (size_t)((x + m + y + z) & 1) * (g.Ns >> 1) + e;
-                    save[sl] = psi[sl];
-                    psi[sl] = (CT)a.zeta[p];
-                }
-            }
-        }
-        x += 2;
-        if (x >= g.nx) {
-            x = 0;
-            if (++y == g.ny) {
-                y = 0;
-                ++z;
-            }
+    const int hx = g.nx >> 1;
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i >= hx) return;
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    const size_t e = ((size_t)z * (size_t)g.ny + (size_t)y) * (size_t)hx + (size_t)i;
+    const size_t c = 2 * e;
+    const uint32_t fp = *reinterpret_cast<const uint16_t *>(a.flag + c);  // cells x, x + 1
+    if (!((fp | (fp >> 8)) & (uint32_t)(kWall | kObst | kNear))) return;  // codes implied
+    const int x = 2 * i;
+    const int pr = (y + z) & 1;  // the red cell of the entry is x + pr
+    const bool inner = x > 0 && x + 1 < g.nx - 1 && y > 0 && y < g.ny - 1 && z > 0 && z < g.nz - 1;
+    uint32_t cr, cb;
+    if (inner) {
+        const ptrdiff_t nx = g.nx, nxy = (ptrdiff_t)g.nx * g.ny;
+        cr = sor_code_inner(a.flag + c + pr, nx, nxy);
+        cb = sor_code_inner(a.flag + c + 1 - pr, nx, nxy);
+    } else {
+        cr = sor_code(g, a.flag, x + pr, y, z);
+        cb = sor_code(g, a.flag, x + 1 - pr, y, z);
+    }
+    a.codes[e] = cr | (cb << 16);
+    if (dirichlet) {
+        for (int m = 0; m < 2; ++m) {
+            const uint8_t fl = (uint8_t)(fp >> (8 * m));
+            if (!(fl & kObst) || (fl & kWall)) continue;
+            const uint32_t p = a.owner[c + (size_t)m];
+            if (p == kNone) continue;
+            // cell x + m has colour (x + m + y + z) & 1
+            const size_t sl = (size_t)((x + m + y + z) & 1) * (g.Ns >> 1) + e;
+            save[sl] = psi[sl];
+            psi[sl] = (CT)a.zeta[p];
         }
     }
 }
 
 // after the solve: the obstacle cells' own values back into both buffers
-// (the result is in either); same walk as k_sor_prepare
+// (the result is in either); same grid as k_sor_prepare
 template <typename CT>
 __global__ void __launch_bounds__(256) k_dirichlet_restore(SorArgs a, CT *p0, CT *p1, const CT *save) {
     const Grid &g = a.g;
-    const size_t c0 = ((size_t)blockIdx.x * 256 + threadIdx.x) * 16;
-    if (c0 >= g.N) return;
-    const uint4 q = *reinterpret_cast<const uint4 *>(a.flag + c0);
-    const uint32_t fw[4] = {q.x, q.y, q.z, q.w};
-    const uint32_t ob = 0x01010101u * (uint32_t)kObst;
-    if (!((fw[0] | fw[1] | fw[2] | fw[3]) & ob)) return;
-    const size_t nx = (size_t)g.nx;
-    size_t yz = c0 / nx;
-    int x = (int)(c0 - yz * nx);
-    int y = (int)(yz % (size_t)g.ny), z = (int)(yz / (size_t)g.ny);
-    for (int k = 0; k < 16; ++k) {
-        const size_t c = c0 + (size_t)k;
-        if (c >= g.N) break;
-        const uint8_t fl = (uint8_t)(fw[k >> 2] >> (8 * (k & 3)));
-        if ((fl & kObst) && !(fl & kWall) && a.owner[c] != kNone) {
-            const size_t sl = (size_t)((x + y + z) & 1) * (g.Ns >> 1) + (c >> 1);
+    const int hx = g.nx >> 1;
+    const int i = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (i >= hx) return;
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    const size_t e = ((size_t)z * (size_t)g.ny + (size_t)y) * (size_t)hx + (size_t)i;
+    const size_t c = 2 * e;
+    const uint32_t fp = *reinterpret_cast<const uint16_t *>(a.flag + c);
+    if (!((fp | (fp >> 8)) & (uint32_t)kObst)) return;
+    for (int m = 0; m < 2; ++m) {
+        const uint8_t fl = (uint8_t)(fp >> (8 * m));
+        if ((fl & kObst) && !(fl & kWall) && a.owner[c + (size_t)m] != kNone) {
+            const size_t sl = (size_t)((2 * i + m + y + z) & 1) * (g.Ns >> 1) + e;
             p0[sl] = save[sl];
             p1[sl] = save[sl];
-        }
-        if (++x == g.nx) {
-            x = 0;
-            if (++y == g.ny) {
-                y = 0;
-                ++z;
-            }
         }
     }
 }
@@ -1256,9 +1261,19 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     const int nres = (int)(rblk < (size_t)(kSorPartials / 2) ? rblk : (size_t)(kSorPartials / 2));
     const bool with_res = a0.rf > 0.0;
     SorArgs a = a0;  // a.psi: the buffer holding the current iterate
+    {
+        // 1 / diag for the 13 diagonals of FP32 rows (IEEE division in
+        // single precision, as the kernels' own)
+        const float d0 = 6.0f + (float)a0.kappa2;
+        for (int k = 0; k < 13; ++k) {
+            volatile float d = d0 + (float)(k - 6);
+            a.rdiag[k] = 1.0f / d;
+        }
+    }
     hipLaunchKernelGGL(k_sor_begin, dim3(1), dim3(64), 0, s, a.ctl);
     const bool dirichlet = march && a0.zeta && a0.owner;  // obstacle cells hold zeta meanwhile
-    const uint32_t ncb = (uint32_t)((g.N + 16 * 256 - 1) / (16 * 256));
+    // per-solve passes over the entries: rows of hx entries, then y and z
+    const dim3 egrid((uint32_t)((hx + 255) / 256), (uint32_t)g.ny, (uint32_t)g.nz);
     if (march) {
         // what k_sor_march assumes of its launch: whole rows in one workgroup
         // (at most kMarchMaxWaves wavefronts), rows per thread dividing ny
@@ -1269,7 +1284,7 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
         const size_t words = sor_ibits_words_per_colour(g.N);
         hipLaunchKernelGGL(k_interior_bits_split, dim3((uint32_t)((words + 255) / 256)), dim3(256),
                            0, s, g, a.flag, a.ibits);
-        hipLaunchKernelGGL((k_sor_prepare<CT>), dim3(ncb), dim3(256), 0, s, a,
+        hipLaunchKernelGGL((k_sor_prepare<CT>), egrid, dim3(256), 0, s, a,
                            static_cast<CT *>(a0.psi), static_cast<CT *>(a0.save),
                            dirichlet ? 1 : 0);
     } else {
@@ -1353,7 +1368,7 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     // the obstacle cells' own values back, in both buffers (the result is in
     // either)
     if (dirichlet)
-        hipLaunchKernelGGL((k_dirichlet_restore<CT>), dim3(ncb), dim3(256), 0, s, a,
+        hipLaunchKernelGGL((k_dirichlet_restore<CT>), egrid, dim3(256), 0, s, a,
                            static_cast<CT *>(a0.psi), static_cast<CT *>(a0.psi2),
                            static_cast<const CT *>(a0.save));
     hipError_t e = hipGetLastError();

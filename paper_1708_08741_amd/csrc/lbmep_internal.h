@@ -284,6 +284,7 @@ struct SorArgs {
     void *save;                // one-pass iteration: obstacle cells' values (Ns compute values)
     uint32_t mzc;              // planes per workgroup of the one-pass iteration (>= 1)
     uint32_t mrw;              // rows per thread of the one-pass iteration (1, 2, 4)
+    float rdiag[13];           // FP32: 1 / (6 + kappa^2 + k), k = -6 .. 6, correctly rounded
 };
 constexpr int kSorPartials = 8192;
 // the boundary lists are built per segment of kNearSeg cells

@@ -49,6 +49,39 @@ __device__ __forceinline__ CT psi_bc(const Grid &g, int x, int y, int z, int dx,
     return psi[ps];
 }
 
+// grad psi of a cell that is not NEAR (Eq. ElPotGradComp): the centre
+// value and the w_q-weighted sums over the 18 neighbours, divided by the
+// rest weight 1/3, in the fixed order; val(dx, dy, dz) is psi at the
+// neighbour (x + dx, y + dy, z + dz).  Every caller uses this one form.
+template <typename CT, typename V>
+__device__ __forceinline__ void psi_grad_inner(V &&val, CT &pc, CT &g0, CT &g1, CT &g2) {
+    pc = val(0, 0, 0);
+    CT s0 = CT(0), s1 = CT(0), s2 = CT(0);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        const CT t = (CT)wq(q) * val(kCx[q], kCy[q], kCz[q]);
+        if (kCx[q] > 0) s0 = s0 + t;
+        if (kCx[q] < 0) s0 = s0 - t;
+        if (kCy[q] > 0) s1 = s1 + t;
+        if (kCy[q] < 0) s1 = s1 - t;
+        if (kCz[q] > 0) s2 = s2 + t;
+        if (kCz[q] < 0) s2 = s2 - t;
+    }
+    g0 = s0 * CT(3.0);
+    g1 = s1 * CT(3.0);
+    g2 = s2 * CT(3.0);
+}
+
+// f_b = rho_e (E_ext - grad psi), rho_e = -kappa^2 eps_e psi (Eq. ChrgDensDHA)
+template <typename CT>
+__device__ __forceinline__ void edl_force(CT pc, CT g0, CT g1, CT g2, CT keps, CT E0, CT E1,
+                                          CT E2, CT &f0, CT &f1, CT &f2) {
+    const CT rho_e = -(keps * pc);
+    f0 = rho_e * (E0 - g0);
+    f1 = rho_e * (E1 - g1);
+    f2 = rho_e * (E2 - g2);
+}
+
 // the body force at fluid cell (x, y, z) with flag fl
 template <typename CT>
 __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int z, uint8_t fl,
@@ -79,22 +112,8 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
             const size_t rb = rowlen * ((size_t)ys[j] + (size_t)g.ny * (size_t)zs[k]) + xo[i];
             return split && ((xpar[i] ^ (uint32_t)(ys[j] + zs[k])) & 1u) ? rb + half : rb;
         };
-        pc = psi[slot(1, 1, 1)];
-        CT s0 = CT(0), s1 = CT(0), s2 = CT(0);
-#pragma unroll
-        for (int q = 1; q < Q; ++q) {
-            const CT t = (CT)wq(q) * psi[slot(kCx[q] + 1, kCy[q] + 1, kCz[q] + 1)];
-            if (kCx[q] > 0) s0 = s0 + t;
-            if (kCx[q] < 0) s0 = s0 - t;
-            if (kCy[q] > 0) s1 = s1 + t;
-            if (kCy[q] < 0) s1 = s1 - t;
-            if (kCz[q] > 0) s2 = s2 + t;
-            if (kCz[q] < 0) s2 = s2 - t;
-        }
-        // divided by the rest weight 1/3
-        g0 = s0 * CT(3.0);
-        g1 = s1 * CT(3.0);
-        g2 = s2 * CT(3.0);
+        psi_grad_inner<CT>([&](int dx, int dy, int dz) { return psi[slot(dx + 1, dy + 1, dz + 1)]; },
+                           pc, g0, g1, g2);
     } else {
         pc = psi[psi_slot_xyz(g, x, y, z)];
         g0 = (psi_bc(g, x, y, z, 1, 0, 0, psi, flag, owner, zeta, pc) -
@@ -104,10 +123,7 @@ __device__ __forceinline__ void potential_force(const Grid &g, int x, int y, int
         g2 = (psi_bc(g, x, y, z, 0, 0, 1, psi, flag, owner, zeta, pc) -
               psi_bc(g, x, y, z, 0, 0, -1, psi, flag, owner, zeta, pc)) * CT(0.5);
     }
-    const CT rho_e = -(keps * pc);
-    f0 = rho_e * (E0 - g0);
-    f1 = rho_e * (E1 - g1);
-    f2 = rho_e * (E2 - g2);
+    edl_force<CT>(pc, g0, g1, g2, keps, E0, E1, E2, f0, f1, f2);
 }
 
 }  // namespace lbmep

@@ -457,15 +457,17 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
     else
         fl = *flp;
     c.fl = valid ? fl : kWall;
+    // source rows (y - c_y, z - c_z) and columns x - c_x, wrapped on
+    // periodic axes; beyond a non-periodic edge: not ok (pull modes)
+    OFF rows[3][3];
+    bool rok[3][3];
+    OFF xs[3];
+    bool xok[3];
     if constexpr (MODE == kLocal) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             c.v[q] = T::lc(at<ST>(static_cast<const char *>(a.src) + (size_t)q * pst, cb));
     } else {
-        // source rows (y - c_y, z - c_z) and columns x - c_x, wrapped on
-        // periodic axes; beyond a non-periodic edge: not ok
-        OFF rows[3][3];
-        bool rok[3][3];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -481,8 +483,6 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
                 rows[j][k] = (OFF)nx * ((OFF)ys + (OFF)ny * (OFF)zs) * es;
                 rok[j][k] = ok;
             }
-        OFF xs[3];
-        bool xok[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             int xq = xc - (i - 1);
@@ -506,10 +506,31 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
             c.fb1 = *at<CT>(a.force, fo + fs);
             c.fb2 = *at<CT>(a.force, fo + 2 * fs);
         } else if constexpr (FMODE == kForcePotential) {
-            if (valid && !(fl & (kWall | kObst)))
+            if (MODE != kLocal && psi_split(a.g) && valid && !(fl & (kWall | kObst | kNear))) {
+                // colour-split psi (even nx), every neighbour a fluid cell
+                // inside the grid: the stencil's slots from the gather's
+                // wrapped rows and columns (row (y', z') starts at entry
+                // nx / 2 (y' + ny z'), column x' is entry x' / 2, the
+                // colour-1 half at Ns / 2); the colour of the neighbour
+                // (x, y, z) + (dx, dy, dz) is the cell's own xor the parity
+                // of dx + dy + dz (periodic extents are even)
+                const OFF half = (OFF)(a.g.Ns >> 1) * (OFF)sizeof(CT);
+                const OFF cs = (OFF)(((xc + yc + z) & 1) ? half : 0), co = half - cs;
+                auto val = [&](int dx, int dy, int dz) -> CT {
+                    const OFF ob = rows[1 - dy][1 - dz] / (2 * es) * (OFF)sizeof(CT) +
+                                   xs[1 - dx] / (2 * es) * (OFF)sizeof(CT) +
+                                   (((dx + dy + dz) & 1) ? co : cs);
+                    return *at<CT>(a.force, ob);
+                };
+                CT pc, g0, g1, g2;
+                psi_grad_inner<CT>(val, pc, g0, g1, g2);
+                edl_force<CT>(pc, g0, g1, g2, (CT)a.keps, (CT)a.E[0], (CT)a.E[1], (CT)a.E[2],
+                              c.fb0, c.fb1, c.fb2);
+            } else if (valid && !(fl & (kWall | kObst))) {
                 potential_force<CT>(a.g, x, y, z, fl, static_cast<const CT *>(a.force), a.flag,
                                     a.owner, a.zeta, (CT)a.keps, (CT)a.E[0], (CT)a.E[1],
                                     (CT)a.E[2], c.fb0, c.fb1, c.fb2);
+            }
         } else if constexpr (FMODE == kForceCharge) {
             const CT *rp = at<CT>(a.force, ci * (OFF)sizeof(CT));
             CT re;
