@@ -64,16 +64,54 @@ __device__ __forceinline__ Box ball_box(const Grid &g, const double *X, double R
     return b;
 }
 
-// the i-th cell of a box (wrapped on periodic axes); false if empty
+// floor(i / d) for i >= 0, d >= 1, with rd ~ 1 / d: the product in single
+// precision is within a few units of the quotient, the integer corrections
+// make it exact (an integer division is a long instruction sequence)
+__device__ __forceinline__ int div_exact(int i, int d, float rd) {
+    int q = (int)((float)i * rd);
+    int r = i - q * d;
+    while (r < 0) {
+        --q;
+        r += d;
+    }
+    while (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
+// v wrapped into [0, len): box coordinates lie within one period of the
+// grid, so one addition or subtraction does it (the remainder otherwise)
+__device__ __forceinline__ int wrap_axis(int v, int len) {
+    if (v < 0) v += len;
+    else if (v >= len) v -= len;
+    if (v < 0 || v >= len) v = ((v % len) + len) % len;
+    return v;
+}
+
+// box-relative coordinates (ix, iy, iz) of the i-th cell of a box of
+// cx x cy x ... cells (rcx, rcy: reciprocals of cx, cy)
+__device__ __forceinline__ void box_split(int i, int cx, int cy, float rcx, float rcy, int &ix,
+                                          int &iy, int &iz) {
+    const int q = div_exact(i, cx, rcx);
+    ix = i - q * cx;
+    iz = div_exact(q, cy, rcy);
+    iy = q - iz * cy;
+}
+
+// the i-th cell of a box (wrapped on periodic axes)
 __device__ __forceinline__ void box_cell(const Grid &g, const Box &b, int i, int &x, int &y,
                                          int &z) {
     const int cx = b.cnt[0], cy = b.cnt[1];
-    x = b.lo[0] + i % cx;
-    y = b.lo[1] + (i / cx) % cy;
-    z = b.lo[2] + i / (cx * cy);
-    if (g.per[0]) x = ((x % g.nx) + g.nx) % g.nx;
-    if (g.per[1]) y = ((y % g.ny) + g.ny) % g.ny;
-    if (g.per[2]) z = ((z % g.nz) + g.nz) % g.nz;
+    int ix, iy, iz;
+    box_split(i, cx, cy, 1.0f / (float)cx, 1.0f / (float)cy, ix, iy, iz);
+    x = b.lo[0] + ix;
+    y = b.lo[1] + iy;
+    z = b.lo[2] + iz;
+    if (g.per[0]) x = wrap_axis(x, g.nx);
+    if (g.per[1]) y = wrap_axis(y, g.ny);
+    if (g.per[2]) z = wrap_axis(z, g.nz);
 }
 
 __device__ __forceinline__ size_t cell_of(const Grid &g, int x, int y, int z) {
@@ -290,6 +328,8 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
     const int hx = b.cnt[0] + 2, hy = b.cnt[1] + 2, hz = b.cnt[2] + 2;
     const int hn = hx * hy * hz;
     const bool staged = n > 0 && hn <= cap;
+    const float rhx = 1.0f / (float)hx, rhy = 1.0f / (float)hy;
+    const float rcx = 1.0f / (float)b.cnt[0], rcy = 1.0f / (float)b.cnt[1];
     if (staged) {
         const int len[3] = {g.nx, g.ny, g.nz};
         // four halo cells per thread and pass, their loads issued together
@@ -301,12 +341,13 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-                int v[3] = {b.lo[0] - 1 + i % hx, b.lo[1] - 1 + (i / hx) % hy,
-                            b.lo[2] - 1 + i / (hx * hy)};
+                int ix, iy, iz;
+                box_split(i, hx, hy, rhx, rhy, ix, iy, iz);
+                int v[3] = {b.lo[0] - 1 + ix, b.lo[1] - 1 + iy, b.lo[2] - 1 + iz};
                 bool out = i >= hn;
                 for (int k = 0; k < 3; ++k) {
                     if (v[k] < 0 || v[k] >= len[k]) {
-                        if (g.per[k]) v[k] = ((v[k] % len[k]) + len[k]) % len[k]; else out = true;
+                        if (g.per[k]) v[k] = wrap_axis(v[k], len[k]); else out = true;
                     }
                 }
                 in[u] = !out;
@@ -350,14 +391,16 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
             fl[j] = 0;
             fluid[j] = false;
             if (i >= n) continue;
-            int x, y, z;
-            box_cell(g, b, i, x, y, z);
+            int ix, iy, iz;
+            box_split(i, b.cnt[0], b.cnt[1], rcx, rcy, ix, iy, iz);
+            int x = b.lo[0] + ix, y = b.lo[1] + iy, z = b.lo[2] + iz;
+            if (g.per[0]) x = wrap_axis(x, g.nx);
+            if (g.per[1]) y = wrap_axis(y, g.ny);
+            if (g.per[2]) z = wrap_axis(z, g.nz);
             const size_t c = cell_of(g, x, y, z);
             cells[j] = (uint32_t)c;
             if (staged) {
                 // the cell itself is in the staged box: no global re-reads
-                const int ix = i % b.cnt[0], iy = (i / b.cnt[0]) % b.cnt[1],
-                          iz = i / (b.cnt[0] * b.cnt[1]);
                 const int h = (ix + 1) + hx * ((iy + 1) + hy * (iz + 1));
                 const uint8_t me = solid[h];
                 if (me & kHWall) {

@@ -958,9 +958,15 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
         yr[k] = y;
         ro_[k] = hxs * (size_t)y;
     }
-    auto zwrap = [&](int z) {
-        int v = z % g.nz;
-        return v < 0 ? v + g.nz : v;
+    auto zwrap = [&](int z) {  // z within two planes of the grid: one step
+        int v = z;
+        if (v < 0) v += g.nz;
+        else if (v >= g.nz) v -= g.nz;
+        if (v < 0 || v >= g.nz) {
+            v %= g.nz;
+            if (v < 0) v += g.nz;
+        }
+        return v;
     };
     const uint32_t io = ic * (uint32_t)sizeof(CT), ico = ic * 4u;
     auto ld = [&](const CT *row) -> CT {
