@@ -872,6 +872,16 @@ __device__ __forceinline__ double dpp_rot<double>(double v, int ctrl) {
     return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) |
                                             (unsigned long long)(uint32_t)lo));
 }
+// bitwise select: b where the lane's mask m is all ones, a where it is zero
+// (a bit operation, so a load feeding b is not moved under a lane branch)
+__device__ __forceinline__ float sel_lane(float a, float b, uint32_t m) {
+    return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+}
+__device__ __forceinline__ double sel_lane(double a, double b, uint32_t m) {
+    const unsigned long long mm = ((unsigned long long)m << 32) | m;
+    return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(a) & ~mm) |
+                                            ((unsigned long long)__double_as_longlong(b) & mm)));
+}
 // value of lane l - 1 (wave_ror:1) and of lane l + 1 (wave_rol:1)
 template <typename CT>
 __device__ __forceinline__ CT lane_prev(CT v) { return dpp_rot<CT>(v, 0x13C); }
@@ -889,7 +899,12 @@ constexpr uint32_t kCodePairInterior = 0x80008000u;
 template <typename CT>
 __device__ __forceinline__ CT relax_code(uint32_t code, CT own, const CT (&nb)[6], CT om, CT om1,
                                          CT diag0, const float *rd) {
-    if (code == kCodeInterior) {
+    // the interior form when every lane of the wavefront holds an interior
+    // unknown (a uniform branch); otherwise the general form for all lanes,
+    // which for an interior code adds the same terms in the same order
+    // (zeros where the interior form adds nothing) and divides by the same
+    // diagonal, so the lanes' bits do not depend on their neighbours
+    if (__ballot(code != kCodeInterior) == 0ull) {
         CT sum = CT(0);
 #pragma unroll
         for (int k = 0; k < 6; ++k) sum = sum + nb[k];
@@ -943,6 +958,7 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
     const uint32_t ic = act ? (uint32_t)i : (uint32_t)(hx - 1);  // in-range entry for the rest
     const int lw = min(63, hx - 1 - 64 * w);                      // last lane holding an entry
     const int wl = (w + nw - 1) % nw, wr = (w + 1) % nw;          // wavefronts holding i - 1, i + 1
+    const uint32_t m_0 = lane == 0 ? ~0u : 0u, m_lw = lane == lw ? ~0u : 0u;  // lane masks
     const size_t hxs = (size_t)hx, hxy = hxs * (size_t)g.ny, half = g.Ns >> 1;
     const CT *Ar = A, *Ab = A + half;  // colour 0 (red) and colour 1 (black)
     CT *Br = B, *Bb = B + half;
@@ -980,10 +996,10 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
     auto st = [&](CT *row, CT v) {
         *reinterpret_cast<GlobalPtr<CT>>(uniform_ptr(reinterpret_cast<char *>(row)) + io) = v;
     };
-    // interior bits of the lane's entry in row k of plane z: red into bit kr
-    // of rb, black into bit kb of bb
-    auto bits = [&](int z, int k, uint32_t &rb, int kr, uint32_t &bb, int kb) {
-        const uint32_t e = (uint32_t)(hxy * (size_t)zwrap(z) + ro_[k]) + ic;
+    // interior bits of the lane's entry in row k of the plane at entry
+    // offset pzo: red into bit kr of rb, black into bit kb of bb
+    auto bits = [&](size_t pzo, int k, uint32_t &rb, int kr, uint32_t &bb, int kb) {
+        const uint32_t e = (uint32_t)(pzo + ro_[k]) + ic;
         const uint2 m = mb[e >> 5];
         rb |= ((m.x >> (e & 31)) & 1u) << kr;
         if (kb >= 0) bb |= ((m.y >> (e & 31)) & 1u) << kb;
@@ -1003,7 +1019,7 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
         for (int r = 0; r < RW + 2; ++r) {
             Bo0[r] = ld(p0 + ro_[r + 1]);
             Bo1[r + 1] = ld(p1 + ro_[r + 1]);
-            bits(zs - 1, r + 1, rb1, r, bb1, r >= 1 && r <= RW ? r - 1 : -1);
+            bits(hxy * (size_t)zwrap(zs - 1), r + 1, rb1, r, bb1, r >= 1 && r <= RW ? r - 1 : -1);
         }
 #pragma unroll
         for (int r = 0; r < RW + 2; ++r) R0[r] = CT(0);
@@ -1030,18 +1046,24 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
             Ro1[r] = ld(Ar + pz1 + ro_[r + 1]);
             Cr[r] = kCodePairInterior;
             if (!((rb1 >> r) & 1u)) Cr[r] = ldc(pz1 + ro_[r + 1]);
-            bits(z + 2, r + 1, rb2, r, bb2, r >= 1 && r <= RW ? r - 1 : -1);
+            bits(pz2, r + 1, rb2, r, bb2, r >= 1 && r <= RW ? r - 1 : -1);
         }
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
             Cb[r] = kCodePairInterior;
             if (z >= zs && !((bb0 >> r) & 1u)) Cb[r] = ldc(pz + ro_[r + 2]);
         }
-        // end values of the black rows of plane z + 1
+        // end values of the black rows of plane z + 1 (lane 0 the first, lane
+        // lw the last; one lane holds both when the wavefront has one entry)
+        if (lw == 0) {
+            if (lane == 0) {
 #pragma unroll
-        for (int r = 0; r < RW + 2; ++r) {
-            if (lane == 0) e_old[par][r][w][0] = Bo1[r + 1];
-            if (lane == lw) e_old[par][r][w][1] = Bo1[r + 1];
+                for (int r = 0; r < RW + 2; ++r) e_old[par][r][w][0] = e_old[par][r][w][1] = Bo1[r + 1];
+            }
+        } else if (lane == 0 || lane == lw) {
+            const int side = lane == 0 ? 0 : 1;
+#pragma unroll
+            for (int r = 0; r < RW + 2; ++r) e_old[par][r][w][side] = Bo1[r + 1];
         }
         __syncthreads();
         // new red values of plane z + 1, rows -1 .. RW (index r = row + 1)
@@ -1049,10 +1071,17 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
         for (int r = 0; r < RW + 2; ++r) {
             const int p = (yr[r + 1] + zw1) & 1;  // the red cell of entry i is x = 2i + p
             const CT own = Bo1[r + 1];
-            const CT prv = lane_prev(own), nxt = lane_next(own);
-            CT xm = p ? own : prv, xp = p ? nxt : own;
-            if (!p && lane == 0) xm = e_old[par][r][wl][1];
-            if (p && lane == lw) xp = e_old[par][r][wr][0];
+            // p is uniform: one rotate, and the value beyond the wavefront's
+            // end (one LDS word, read by every lane) for lane 0's x- (p = 0)
+            // or lane lw's x+ (p = 1)
+            CT xm, xp;
+            if (p) {
+                xm = own;
+                xp = sel_lane(lane_next(own), e_old[par][r][wr][0], m_lw);
+            } else {
+                xm = sel_lane(lane_prev(own), e_old[par][r][wl][1], m_0);
+                xp = own;
+            }
             const CT nb[6] = {xm, xp, Bo1[r], Bo1[r + 2], Bo0[r], Bo2[r]};
             R1[r] = relax_code<CT>(Cr[r] & 0xFFFFu, Ro1[r], nb, om, om1, diag0, rd);
         }
@@ -1060,10 +1089,15 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
 #pragma unroll
             for (int r = 1; r <= RW; ++r) st(Br + pz1 + ro_[r + 1], R1[r]);
         }
+        if (lw == 0) {
+            if (lane == 0) {
 #pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            if (lane == 0) e_new[par][r][w][0] = R1[r + 1];
-            if (lane == lw) e_new[par][r][w][1] = R1[r + 1];
+                for (int r = 0; r < RW; ++r) e_new[par][r][w][0] = e_new[par][r][w][1] = R1[r + 1];
+            }
+        } else if (lane == 0 || lane == lw) {
+            const int side = lane == 0 ? 0 : 1;
+#pragma unroll
+            for (int r = 0; r < RW; ++r) e_new[par][r][w][side] = R1[r + 1];
         }
         // new black values of plane z, rows 0 .. RW - 1, from the new red
         // values of planes z - 1, z, z + 1 (the end values of plane z were
@@ -1073,10 +1107,14 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
             for (int r = 0; r < RW; ++r) {
                 const int p = (1 + yr[r + 2] + zw) & 1;  // the black cell of entry i
                 const CT own = R0[r + 1];
-                const CT prv = lane_prev(own), nxt = lane_next(own);
-                CT xm = p ? own : prv, xp = p ? nxt : own;
-                if (!p && lane == 0) xm = e_new[par ^ 1][r][wl][1];
-                if (p && lane == lw) xp = e_new[par ^ 1][r][wr][0];
+                CT xm, xp;
+                if (p) {
+                    xm = own;
+                    xp = sel_lane(lane_next(own), e_new[par ^ 1][r][wr][0], m_lw);
+                } else {
+                    xm = sel_lane(lane_prev(own), e_new[par ^ 1][r][wl][1], m_0);
+                    xp = own;
+                }
                 const CT nb[6] = {xm, xp, R0[r], R0[r + 2], Rm[r], R1[r + 1]};
                 const CT v = relax_code<CT>(Cb[r] >> 16, Bo0[r + 1], nb, om, om1, diag0, rd);
                 if (act) st(Bb + pz + ro_[r + 2], v);
