@@ -1026,10 +1026,12 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
 #pragma unroll
         for (int r = 0; r < RW; ++r) Rm[r] = CT(0);
     }
+    // wrapped planes z, z + 1, z + 2 and their entry offsets, carried from
+    // step to step
+    int zw = zwrap(zs - 2), zw1 = zwrap(zs - 1), zw2 = zwrap(zs);
+    size_t pz = hxy * (size_t)zw, pz1 = hxy * (size_t)zw1, pz2 = hxy * (size_t)zw2;
     for (int z = zs - 2; z < ze; ++z) {
         const int par = (z - zs + 2) & 1;
-        const int zw = zwrap(z), zw1 = zwrap(z + 1);
-        const size_t pz = hxy * (size_t)zw, pz1 = hxy * (size_t)zw1, pz2 = hxy * (size_t)zwrap(z + 2);
         // plane z + 2 of the black window, the two outer rows of plane z + 1,
         // the red old values of plane z + 1, the bits of plane z + 2, and the
         // code words of the cells to be relaxed that are not interior
@@ -1133,6 +1135,12 @@ __global__ void __launch_bounds__(64 * MAXW) k_sor_march(SorArgs a, const CT *A,
         rb1 = rb2;
         bb0 = bb1;
         bb1 = bb2;
+        zw = zw1;
+        zw1 = zw2;
+        pz = pz1;
+        pz1 = pz2;
+        if (++zw2 == g.nz) zw2 = 0;
+        pz2 = hxy * (size_t)zw2;
     }
 }
 
