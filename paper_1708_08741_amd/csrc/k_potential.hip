@@ -1176,11 +1176,10 @@ __device__ __forceinline__ uint32_t sor_code(const Grid &g, const uint8_t *flag,
     return code;
 }
 
-// sor_code of a cell with no neighbour across a grid face (x, y, z all
-// strictly inside): the six neighbours at fixed offsets, no wrap or edge
-__device__ __forceinline__ uint32_t sor_code_inner(const uint8_t *f, ptrdiff_t nx, ptrdiff_t nxy) {
-    if (f[0] & (kWall | kObst)) return 0u;
-    const uint8_t fs[6] = {f[-1], f[1], f[-nx], f[nx], f[-nxy], f[nxy]};
+// the code of a cell that is an unknown or not, from its own flag and its
+// six neighbours' flags in the order x-, x+, y-, y+, z-, z+ (as sor_code)
+__device__ __forceinline__ uint32_t code_of_flags(uint32_t self, const uint32_t (&fs)[6]) {
+    if (self & (kWall | kObst)) return 0u;
     uint32_t code = 0x8000u;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -1190,72 +1189,171 @@ __device__ __forceinline__ uint32_t sor_code_inner(const uint8_t *f, ptrdiff_t n
     return code;
 }
 
-// once per solve, one thread per entry (the cells x = 2i, 2i + 1 of a row;
-// grid: entries of a row along x, then y and z), its two flags read as one
-// 2-byte load: the code word of every entry with a cell that is not an
-// interior unknown (the only words k_sor_march reads), and, with surface
-// potentials, zeta into the obstacle cells (their own values kept in save
-// and put back by k_dirichlet_restore after the solve).  A thread near a
-// sphere does a few dozen instructions, so the wavefronts that have one
-// stay short (512^3 with 4096 spheres: 16 cells per thread with a 64-bit
-// index decomposition took 0.53 ms)
-template <typename CT>
+// once per solve: the code word of every entry (the cells x = 2i, 2i + 1 of
+// a row) with a cell that is not an interior unknown (the only words
+// k_sor_march reads), and, with surface potentials, zeta into the obstacle
+// cells (their own values kept in save and put back by k_dirichlet_restore
+// after the solve).  A thread takes one entry in PR consecutive rows
+// (grid: entries of a row along x, groups of rows, planes) and issues each
+// phase's loads together -- the two flags of every row, the neighbour flags
+// of every boundary entry away from the grid faces, the owners, then zeta
+// and psi -- so a wavefront waits a few memory round trips, not a few per
+// row.  Measured at 512^3 with 4096 spheres (a one-iteration solve): 2 rows
+// per thread 0.740 ms, 1 row 0.762, 4 rows 0.745, 8 rows (124 VGPRs)
+// 0.871; the restore, with far fewer registers, is fastest with 8 (0.13
+// against 0.19 ms with 1); 16 cells per thread with a 64-bit index
+// decomposition took 0.53 ms for the prepare alone
+constexpr int kPrepareRows = 2;
+constexpr int kPrepRows = 8;  // rows per thread of k_dirichlet_restore
+template <typename CT, int PR>
 __global__ void __launch_bounds__(256) k_sor_prepare(SorArgs a, CT *psi, CT *save, int dirichlet) {
     const Grid &g = a.g;
     const int hx = g.nx >> 1;
     const int i = (int)(blockIdx.x * 256 + threadIdx.x);
     if (i >= hx) return;
-    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-    const size_t e = ((size_t)z * (size_t)g.ny + (size_t)y) * (size_t)hx + (size_t)i;
-    const size_t c = 2 * e;
-    const uint32_t fp = *reinterpret_cast<const uint16_t *>(a.flag + c);  // cells x, x + 1
-    if (!((fp | (fp >> 8)) & (uint32_t)(kWall | kObst | kNear))) return;  // codes implied
+    const int y0 = (int)blockIdx.y * PR, z = (int)blockIdx.z;
+    const int nr = min(PR, g.ny - y0);  // rows of this thread (>= 1)
     const int x = 2 * i;
-    const int pr = (y + z) & 1;  // the red cell of the entry is x + pr
-    const bool inner = x > 0 && x + 1 < g.nx - 1 && y > 0 && y < g.ny - 1 && z > 0 && z < g.nz - 1;
-    uint32_t cr, cb;
-    if (inner) {
-        const ptrdiff_t nx = g.nx, nxy = (ptrdiff_t)g.nx * g.ny;
-        cr = sor_code_inner(a.flag + c + pr, nx, nxy);
-        cb = sor_code_inner(a.flag + c + 1 - pr, nx, nxy);
-    } else {
-        cr = sor_code(g, a.flag, x + pr, y, z);
-        cb = sor_code(g, a.flag, x + 1 - pr, y, z);
+    const size_t e0 = ((size_t)z * (size_t)g.ny + (size_t)y0) * (size_t)hx + (size_t)i;
+    const uint32_t bnd = kWall | kObst | kNear;
+    uint32_t fp[PR];  // cells x (low byte), x + 1
+#pragma unroll
+    for (int k = 0; k < PR; ++k)
+        fp[k] = k < nr ? *reinterpret_cast<const uint16_t *>(a.flag + 2 * (e0 + (size_t)k * hx)) : 0u;
+    // neighbour flags of the boundary entries with no neighbour across a
+    // grid face: x - 1, x + 2 (bytes), the pairs in rows y -+ 1 and planes
+    // z -+ 1
+    const bool xzin = x > 0 && x + 1 < g.nx - 1 && z > 0 && z < g.nz - 1;
+    const ptrdiff_t nx = g.nx, nxy = (ptrdiff_t)g.nx * g.ny;
+    uint32_t nf[PR][6];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+        const int y = y0 + k;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) nf[k][d] = 0u;
+        if (k < nr && ((fp[k] | (fp[k] >> 8)) & bnd) && xzin && y > 0 && y < g.ny - 1) {
+            const uint8_t *c = a.flag + 2 * (e0 + (size_t)k * hx);
+            nf[k][0] = c[-1];
+            nf[k][1] = c[2];
+            nf[k][2] = *reinterpret_cast<const uint16_t *>(c - nx);
+            nf[k][3] = *reinterpret_cast<const uint16_t *>(c + nx);
+            nf[k][4] = *reinterpret_cast<const uint16_t *>(c - nxy);
+            nf[k][5] = *reinterpret_cast<const uint16_t *>(c + nxy);
+        }
     }
-    a.codes[e] = cr | (cb << 16);
-    if (dirichlet) {
+    // the obstacle cells' owners (surface potentials)
+    uint32_t ow[PR][2];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+#pragma unroll
         for (int m = 0; m < 2; ++m) {
-            const uint8_t fl = (uint8_t)(fp >> (8 * m));
-            if (!(fl & kObst) || (fl & kWall)) continue;
-            const uint32_t p = a.owner[c + (size_t)m];
-            if (p == kNone) continue;
-            // cell x + m has colour (x + m + y + z) & 1
-            const size_t sl = (size_t)((x + m + y + z) & 1) * (g.Ns >> 1) + e;
-            save[sl] = psi[sl];
-            psi[sl] = (CT)a.zeta[p];
+            const uint32_t fl = (fp[k] >> (8 * m)) & 0xFFu;
+            ow[k][m] = kNone;
+            if (dirichlet && k < nr && (fl & kObst) && !(fl & kWall))
+                ow[k][m] = a.owner[2 * (e0 + (size_t)k * hx) + (size_t)m];
+        }
+    }
+    // the codes
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+        const int y = y0 + k;
+        if (k >= nr || !((fp[k] | (fp[k] >> 8)) & bnd)) continue;
+        const int pr = (y + z) & 1;  // the red cell of the entry is x + pr
+        uint32_t cl, ch;             // codes of cells x and x + 1
+        if (xzin && y > 0 && y < g.ny - 1) {
+            const uint32_t f0 = fp[k] & 0xFFu, f1 = fp[k] >> 8;
+            const uint32_t fs0[6] = {nf[k][0], f1, nf[k][2] & 0xFFu, nf[k][3] & 0xFFu,
+                                     nf[k][4] & 0xFFu, nf[k][5] & 0xFFu};
+            const uint32_t fs1[6] = {f0, nf[k][1], nf[k][2] >> 8, nf[k][3] >> 8, nf[k][4] >> 8,
+                                     nf[k][5] >> 8};
+            cl = code_of_flags(f0, fs0);
+            ch = code_of_flags(f1, fs1);
+        } else {
+            cl = sor_code(g, a.flag, x, y, z);
+            ch = sor_code(g, a.flag, x + 1, y, z);
+        }
+        const uint32_t cr = pr ? ch : cl, cb = pr ? cl : ch;
+        a.codes[e0 + (size_t)k * hx] = cr | (cb << 16);
+    }
+    if (!dirichlet) return;
+    // zeta into the obstacle cells, their values into save
+    CT zv[PR][2], pv[PR][2];
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            zv[k][m] = pv[k][m] = CT(0);
+            if (ow[k][m] != kNone) {
+                const size_t e = e0 + (size_t)k * hx;
+                // cell x + m has colour (x + m + y + z) & 1
+                const size_t sl = (size_t)((x + m + y0 + k + z) & 1) * (g.Ns >> 1) + e;
+                zv[k][m] = (CT)a.zeta[ow[k][m]];
+                pv[k][m] = psi[sl];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (ow[k][m] != kNone) {
+                const size_t e = e0 + (size_t)k * hx;
+                const size_t sl = (size_t)((x + m + y0 + k + z) & 1) * (g.Ns >> 1) + e;
+                save[sl] = pv[k][m];
+                psi[sl] = zv[k][m];
+            }
         }
     }
 }
 
 // after the solve: the obstacle cells' own values back into both buffers
-// (the result is in either); same grid as k_sor_prepare
+// (the result is in either); same grid and phases as k_sor_prepare
 template <typename CT>
 __global__ void __launch_bounds__(256) k_dirichlet_restore(SorArgs a, CT *p0, CT *p1, const CT *save) {
     const Grid &g = a.g;
     const int hx = g.nx >> 1;
     const int i = (int)(blockIdx.x * 256 + threadIdx.x);
     if (i >= hx) return;
-    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-    const size_t e = ((size_t)z * (size_t)g.ny + (size_t)y) * (size_t)hx + (size_t)i;
-    const size_t c = 2 * e;
-    const uint32_t fp = *reinterpret_cast<const uint16_t *>(a.flag + c);
-    if (!((fp | (fp >> 8)) & (uint32_t)kObst)) return;
-    for (int m = 0; m < 2; ++m) {
-        const uint8_t fl = (uint8_t)(fp >> (8 * m));
-        if ((fl & kObst) && !(fl & kWall) && a.owner[c + (size_t)m] != kNone) {
-            const size_t sl = (size_t)((2 * i + m + y + z) & 1) * (g.Ns >> 1) + e;
-            p0[sl] = save[sl];
-            p1[sl] = save[sl];
+    const int y0 = (int)blockIdx.y * kPrepRows, z = (int)blockIdx.z;
+    const int nr = min(kPrepRows, g.ny - y0);
+    const int x = 2 * i;
+    const size_t e0 = ((size_t)z * (size_t)g.ny + (size_t)y0) * (size_t)hx + (size_t)i;
+    uint32_t fp[kPrepRows];
+#pragma unroll
+    for (int k = 0; k < kPrepRows; ++k)
+        fp[k] = k < nr ? *reinterpret_cast<const uint16_t *>(a.flag + 2 * (e0 + (size_t)k * hx)) : 0u;
+    uint32_t ow[kPrepRows][2];
+#pragma unroll
+    for (int k = 0; k < kPrepRows; ++k) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const uint32_t fl = (fp[k] >> (8 * m)) & 0xFFu;
+            ow[k][m] = kNone;
+            if (k < nr && (fl & kObst) && !(fl & kWall))
+                ow[k][m] = a.owner[2 * (e0 + (size_t)k * hx) + (size_t)m];
+        }
+    }
+    CT sv[kPrepRows][2];
+#pragma unroll
+    for (int k = 0; k < kPrepRows; ++k) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            sv[k][m] = CT(0);
+            if (ow[k][m] != kNone) {
+                const size_t sl = (size_t)((x + m + y0 + k + z) & 1) * (g.Ns >> 1) + e0 + (size_t)k * hx;
+                sv[k][m] = save[sl];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPrepRows; ++k) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (ow[k][m] != kNone) {
+                const size_t sl = (size_t)((x + m + y0 + k + z) & 1) * (g.Ns >> 1) + e0 + (size_t)k * hx;
+                p0[sl] = sv[k][m];
+                p1[sl] = sv[k][m];
+            }
         }
     }
 }
@@ -1325,7 +1423,8 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
     hipLaunchKernelGGL(k_sor_begin, dim3(1), dim3(64), 0, s, a.ctl);
     const bool dirichlet = march && a0.zeta && a0.owner;  // obstacle cells hold zeta meanwhile
     // per-solve passes over the entries: rows of hx entries, then y and z
-    const dim3 egrid((uint32_t)((hx + 255) / 256), (uint32_t)g.ny, (uint32_t)g.nz);
+    const dim3 egrid((uint32_t)((hx + 255) / 256), (uint32_t)((g.ny + kPrepRows - 1) / kPrepRows),
+                     (uint32_t)g.nz);
     if (march) {
         // what k_sor_march assumes of its launch: whole rows in one workgroup
         // (at most kMarchMaxWaves wavefronts), rows per thread dividing ny
@@ -1336,9 +1435,9 @@ hipError_t sor_solve_typed(const SorArgs &a0, int max_iter, int check_every, boo
         const size_t words = sor_ibits_words_per_colour(g.N);
         hipLaunchKernelGGL(k_interior_bits_split, dim3((uint32_t)((words + 255) / 256)), dim3(256),
                            0, s, g, a.flag, a.ibits);
-        hipLaunchKernelGGL((k_sor_prepare<CT>), egrid, dim3(256), 0, s, a,
-                           static_cast<CT *>(a0.psi), static_cast<CT *>(a0.save),
-                           dirichlet ? 1 : 0);
+        const dim3 pgrid(egrid.x, (uint32_t)((g.ny + kPrepareRows - 1) / kPrepareRows), egrid.z);
+        hipLaunchKernelGGL((k_sor_prepare<CT, kPrepareRows>), pgrid, dim3(256), 0, s, a,
+                           static_cast<CT *>(a0.psi), static_cast<CT *>(a0.save), dirichlet ? 1 : 0);
     } else {
         const uint32_t nseg = (uint32_t)((g.N + kNearSeg - 1) / kNearSeg);
         if (vec) {

@@ -367,6 +367,8 @@ def test_sor_solve_matches_oracle(lb, oracle_mod, shape, periodic, walls, n, wit
     ((66, 18, 34), (True, True, True), 4, 1e-3, "16", "8"),   # ny = 18: 2 rows per thread
     ((256, 12, 10), (True, True, False), 5, 0.0, "3", "8"),   # ny = 12: 4 rows per thread
     ((2048, 4, 6), (True, True, True), 3, 0.0, "4", "4"),     # 16 wavefronts per row
+    ((128, 24, 22), (False, True, True), 5, 1e-3, "7", "4"),  # walls in every row
+    ((384, 8, 12), (True, True, True), 4, 0.0, "5", "4"),     # 3 wavefronts per row
     ((2050, 4, 6), (True, True, True), 3, 0.0, "16", "8"),    # rows too long: two launches
     ((18, 6, 20), (False, False, False), 2, 0.0, "1", "2"),
     ((130, 35, 9), (True, False, False), 4, 0.0, "16", "8"),  # odd ny: one row per thread
