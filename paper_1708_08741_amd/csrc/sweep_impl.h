@@ -506,14 +506,18 @@ __device__ __forceinline__ void load_cell(const SweepArgs &a, int x, int y, int 
             c.fb1 = *at<CT>(a.force, fo + fs);
             c.fb2 = *at<CT>(a.force, fo + 2 * fs);
         } else if constexpr (FMODE == kForcePotential) {
-            if (MODE != kLocal && psi_split(a.g) && valid && !(fl & (kWall | kObst | kNear))) {
-                // colour-split psi (even nx), every neighbour a fluid cell
-                // inside the grid: the stencil's slots from the gather's
-                // wrapped rows and columns (row (y', z') starts at entry
-                // nx / 2 (y' + ny z'), column x' is entry x' / 2, the
-                // colour-1 half at Ns / 2); the colour of the neighbour
-                // (x, y, z) + (dx, dy, dz) is the cell's own xor the parity
-                // of dx + dy + dz (periodic extents are even)
+            // colour-split psi (even nx) with even extents along the
+            // periodic y and z axes, so a neighbour across a wrap keeps the
+            // colour parity of its unwrapped place
+            const bool split_even = psi_split(a.g) && (!a.g.per[1] || a.g.ny % 2 == 0) &&
+                                    (!a.g.per[2] || a.g.nz % 2 == 0);
+            if (MODE != kLocal && split_even && valid && !(fl & (kWall | kObst | kNear))) {
+                // every neighbour a fluid cell inside the grid: the
+                // stencil's slots from the gather's wrapped rows and columns
+                // (row (y', z') starts at entry nx / 2 (y' + ny z'), column
+                // x' is entry x' / 2, the colour-1 half at Ns / 2); the
+                // colour of the neighbour (x, y, z) + (dx, dy, dz) is the
+                // cell's own xor the parity of dx + dy + dz
                 const OFF half = (OFF)(a.g.Ns >> 1) * (OFF)sizeof(CT);
                 const OFF cs = (OFF)(((xc + yc + z) & 1) ? half : 0), co = half - cs;
                 auto val = [&](int dx, int dy, int dz) -> CT {

@@ -93,6 +93,48 @@ def test_force_at_rest(lb, oracle_mod, shape, periodic, walls, with_zeta, seed):
         g.close()
 
 
+@pytest.mark.parametrize("shape,periodic,seed", [
+    ((16, 10, 8), (True, True, True), 21),    # even periodic extents: the sweep's fast stencil
+    ((12, 9, 7), (True, True, True), 22),     # odd periodic ny, nz: across a wrap a neighbour
+    ((20, 7, 10), (True, True, False), 23),   # keeps the cell's colour
+])
+def test_force_in_the_sweep(lb, oracle_mod, shape, periodic, seed):
+    """A few collisions with the force from a random potential (random walls,
+    spheres with a surface potential): the sweep's force agrees with the
+    oracle, on even nx with even and with odd periodic extents (the
+    precisions' tolerances of u relative to max |u| and of rho)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    psi = 0.05 * rng.standard_normal((nz, ny, nx))
+    fl = (rng.random((nz, ny, nx)) < 0.05).astype(np.uint8)
+    X = np.column_stack([rng.uniform(0, nx, 2), rng.uniform(0, ny, 2), rng.uniform(0, nz, 2)])
+    R = rng.uniform(1.2, 2.0, 2)
+    zeta = rng.uniform(-0.1, 0.1, 2)
+    E = (1e-2, -2e-2, 5e-3)
+    steps = 4
+    o = oracle_mod.Oracle(shape, periodic)
+    o.set_flags(fl)
+    o.set_particles(X, R, np.zeros((2, 3)), moving=False)
+    o.set_potential_force(psi, KEPS, E, zeta)
+    o.init_equilibrium()
+    o.step(steps)
+    rho_o, u_o = o.macro()
+    fluid = _fluid(o)
+    s = np.abs(u_o[:, fluid]).max()
+    assert s > 0
+    for prec, name in ((lb.FP64, "fp64"), (lb.FP32DEV, "fp32dev")):
+        g = lb.Lattice(shape, periodic, precision=prec)
+        g.set_flags(fl)
+        g.set_particles(X, R, np.zeros((2, 3)))
+        g.set_potential_force(psi.astype(np.float64 if prec == lb.FP64 else np.float32), KEPS, E, zeta)
+        g.init_equilibrium()
+        g.step(steps)
+        rho_g, u_g = g.macro()
+        g.close()
+        assert np.abs(u_g - u_o)[:, fluid].max() <= TOLS[name]["u"] * s, name
+        assert np.abs(rho_g - rho_o)[fluid].max() <= TOLS[name]["rho"], name
+
+
 SHAPE, PER = (70, 44, 38), (True, False, True)
 
 
