@@ -264,7 +264,7 @@ __device__ __forceinline__ uint8_t classify_cell(const Grid &g, int x, int y, in
                 }
                 if (solid) mask |= 1u << (q - 1);
             }
-            f = mask ? kNear : 0;
+            f = (mask ? kNear : 0) | ((mask & kFaceDirs) ? kNear7 : 0);
             if (owner_old && owner_old[c] != kNone) f |= kUncov;
         }
     }
@@ -415,7 +415,7 @@ __device__ __forceinline__ void classify_particle(const ParticleArgs &pa, int p,
                         if (sv & kHSolid) mask |= 1u << (q - 1);
                         if (sv & kHMine) pm |= 1u << (q - 1);
                     }
-                    fl[j] = mask ? kNear : 0;
+                    fl[j] = (mask ? kNear : 0) | ((mask & kFaceDirs) ? kNear7 : 0);
                     pms[j] = pm;
                     fluid[j] = true;
                 }

@@ -83,8 +83,8 @@ __device__ __forceinline__ void dha_row(const Grid &g, int x, int y, int z, uint
     // the six neighbours have the other colour (even extents along periodic
     // axes; a neighbour beyond a non-periodic edge is never read)
     const uint32_t oc = (uint32_t)((x + y + z + 1) & 1);
-    if (!(fl & kNear)) {
-        // every neighbour is an unknown inside the grid (periodic wrap)
+    if (!(fl & kNear7)) {
+        // every face neighbour is an unknown inside the grid (periodic wrap)
 #pragma unroll
         for (int k = 0; k < 6; ++k) sum = sum + psi[psi_slot(g, s[k], oc)];
         if (unknown) *unknown = 63;
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, i
     CT v[kSorRows][6];
 #pragma unroll
     for (int r = 0; r < kSorRows; ++r) {
-        if (fl[r] & (kWall | kObst | kNear)) continue;
+        if (fl[r] & (kWall | kObst | kNear7)) continue;
         const uint32_t x = xs[r];
         const int y = y0 + r;
         const uint32_t xm = x == 0 ? (uint32_t)g.nx - 1 : x - 1;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half(SorArgs a, int colour, i
         const int y = y0 + r;
         if (y >= g.ny) continue;
         const uint32_t p = xs[r] - (uint32_t)x2;
-        if (!(fl[r] & (kWall | kObst | kNear))) {
+        if (!(fl[r] & (kWall | kObst | kNear7))) {
             // interior cell; boundary cells are relaxed from the list
             const CT diag = CT(6.0) + (CT)a.kappa2, rhs = CT(0);
             CT sum = CT(0);
@@ -427,14 +427,17 @@ __global__ void __launch_bounds__(kSorBlock) k_sor_half_vec(SorArgs a, int colou
     }
 }
 
-// a boundary unknown: a NEAR cell that is neither wall nor obstacle
+// a boundary unknown: a cell with a solid face neighbour (kNear7) that is
+// neither wall nor obstacle; a NEAR cell whose solid neighbours are all
+// diagonal has the interior row (the D3Q7 stencil sees only faces)
 __device__ __forceinline__ bool near_unknown(uint8_t f) {
-    return (f & kNear) && !(f & (kWall | kObst));
+    return (f & kNear7) && !(f & (kWall | kObst));
 }
 
 // once per solve (even nx): bit e of colour k's interior bitmap = the cell of
 // colour k at entry e is an interior unknown (neither wall, obstacle nor
-// NEAR); of its boundary bitmap = that cell is a boundary unknown.  A thread
+// next to a solid face neighbour); of its boundary bitmap = that cell is a
+// boundary unknown.  A thread
 // covers the 64 cells of 32 entries of each colour, read as four 16-byte
 // loads (the flag buffer is padded to 4096 cells; entries past N/2 are not
 // taken); a pair (x even, x + 1) has the colours (y + z) & 1 and its flip,
@@ -458,8 +461,8 @@ __global__ void __launch_bounds__(256) k_interior_bits_split(Grid g, const uint8
         if (e0 + k >= half) break;
         const uint32_t f0 = (fw[k >> 1] >> (16 * (k & 1))) & 0xffu;
         const uint32_t f1 = (fw[k >> 1] >> (16 * (k & 1) + 8)) & 0xffu;
-        if (!(f0 & (kWall | kObst | kNear))) b[rp] |= 1u << k;
-        if (!(f1 & (kWall | kObst | kNear))) b[rp ^ 1] |= 1u << k;
+        if (!(f0 & (kWall | kObst | kNear7))) b[rp] |= 1u << k;
+        if (!(f1 & (kWall | kObst | kNear7))) b[rp ^ 1] |= 1u << k;
         if (near_unknown((uint8_t)f0)) nb[rp] |= 1u << k;
         if (near_unknown((uint8_t)f1)) nb[rp ^ 1] |= 1u << k;
         x += 2;
@@ -708,7 +711,7 @@ __global__ void __launch_bounds__(kNearBlock) k_nlist_rows(SorArgs a) {
             const int z = (int)(yz / (uint32_t)g.ny), y = (int)(yz - (uint32_t)z * (uint32_t)g.ny);
             CT diag, rhs, sum;
             uint8_t mask;
-            dha_row<CT>(g, x, y, z, kNear, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs,
+            dha_row<CT>(g, x, y, z, kNear | kNear7, psi, a.flag, a.owner, a.zeta, (CT)a.kappa2, diag, rhs,
                         sum, &mask);
             rows[2 * (base + i)] = diag;
             rows[2 * (base + i) + 1] = rhs;
@@ -1215,7 +1218,7 @@ __global__ void __launch_bounds__(256) k_sor_prepare(SorArgs a, CT *psi, CT *sav
     const int nr = min(PR, g.ny - y0);  // rows of this thread (>= 1)
     const int x = 2 * i;
     const size_t e0 = ((size_t)z * (size_t)g.ny + (size_t)y0) * (size_t)hx + (size_t)i;
-    const uint32_t bnd = kWall | kObst | kNear;
+    const uint32_t bnd = kWall | kObst | kNear7;
     uint32_t fp[PR];  // cells x (low byte), x + 1
 #pragma unroll
     for (int k = 0; k < PR; ++k)

@@ -36,8 +36,13 @@ __host__ __device__ constexpr double wq(int q) {
 }
 
 // cell flag bits (internal encoding of LBMEP_WALL / OBST / NEAR); kUncov
-// marks a fluid cell that was an obstacle cell at the previous time level
-constexpr uint8_t kWall = 1, kObst = 2, kNear = 4, kUncov = 8;
+// marks a fluid cell that was an obstacle cell at the previous time level;
+// kNear7 (set with kNear) a fluid cell with a face neighbour (q = 1..6)
+// that is a wall or obstacle cell or lies beyond a non-periodic edge: the
+// cells whose Debye-Hueckel row is not the interior one
+constexpr uint8_t kWall = 1, kObst = 2, kNear = 4, kUncov = 8, kNear7 = 16;
+// bits q - 1 of a direction mask for the face directions q = 1..6
+constexpr uint32_t kFaceDirs = 0x3Fu;
 // owner value of a cell no particle covers
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
