@@ -157,6 +157,35 @@ def test_map_moving_many_steps(lb, oracle_mod):
     assert _rel(Fg, Fo) <= TOL and _rel(Mg, Mo) <= TOL
 
 
+@pytest.mark.parametrize("shape,periodic", [
+    ((12, 10, 14), (True, True, True)),
+    ((13, 12, 9), (True, False, True)),
+])
+def test_map_large_spheres_moving(lb, oracle_mod, shape, periodic):
+    """Spheres as wide as the grid or reaching well past a face (boxes that
+    span a whole periodic axis, boxes that wrap, a box cut by non-periodic
+    edges), moving: flags and owners bit-identical to the oracle after every
+    step, and the fields within the FP64 tolerance."""
+    nx, ny, nz = shape
+    X = np.array([[0.4, 0.6, 0.3], [nx - 0.7, ny / 2.0, nz - 0.2], [nx / 2.0, ny - 0.5, 1.1]])
+    R = np.array([5.6, 3.2, 2.1])
+    U = np.array([[-0.08, 0.05, 0.06], [0.07, -0.04, 0.09], [0.05, 0.08, -0.07]])
+    Wv = np.array([[0.0, 0.01, 0.0], [0.0, 0.0, 0.02], [0.01, 0.0, 0.0]])
+    o, g = _pair(lb, oracle_mod, shape, periodic, moving=True)
+    for Lt in (o, g):
+        Lt.init_equilibrium()
+    o.set_particles(X, R, U, Wv, moving=True)
+    g.set_particles(X, R, U, Wv)
+    for k in range(25):
+        o.step(1)
+        g.step(1)
+        fo, oo = o.map()
+        fg, og = g.map()
+        assert (fo == fg).all(), k
+        assert (oo == og).all(), k
+    _compare_fields(o, g)
+
+
 # ---------------------------------------------------------------------------
 # the named workloads
 # ---------------------------------------------------------------------------
